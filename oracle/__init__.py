@@ -1,0 +1,150 @@
+"""CAFS reference oracle (test infrastructure only).
+
+Thin ctypes wrapper around ``liboracle.so`` built from ``cafs_oracle.cpp``.
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package; the GPU library never does, and shares no code with it.
+
+Report fields follow the dispatcher of Alg. 3 and the reconstruction of Alg. 4
+of the CAFS paper: the Chao1 estimate (Alg. 2), the path label, the tiny-count
+miss flag, the bucket count M (Eq. Msize), the spill size in elements and the
+exact number of distinct keys.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cafs_oracle.cpp")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+PATHS = ("MONOTONE", "SMALL_N", "TINY", "HIGH_K", "MAIN", "GUARD")
+REPORT_FIELDS = ("k_hat", "u", "f1", "f2", "n_samples", "stride", "saturated",
+                 "path", "tiny_miss", "table_M", "spill_elems", "k_exact")
+ESTIMATE_FIELDS = REPORT_FIELDS[:7]
+
+
+def build(force=False):
+    """Compile the oracle with g++ (plain C++17, no GPU code)."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["g++", "-std=c++17", "-O2", "-fPIC", "-shared",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        p, u64 = ctypes.c_void_p, ctypes.c_uint64
+        for name in ("oracle_sort_i64", "oracle_sort_u64"):
+            getattr(lib, name).argtypes = [p, u64, p]
+            getattr(lib, name).restype = None
+        for name in ("oracle_counts_i64", "oracle_counts_u64"):
+            getattr(lib, name).argtypes = [p, u64, p, p]
+            getattr(lib, name).restype = u64
+        for name in ("oracle_is_monotone_i64", "oracle_is_monotone_u64"):
+            getattr(lib, name).argtypes = [p, u64]
+            getattr(lib, name).restype = ctypes.c_int
+        for name in ("oracle_estimate", "oracle_report_i64", "oracle_report_u64"):
+            getattr(lib, name).argtypes = [p, u64, p]
+            getattr(lib, name).restype = None
+        lib.oracle_sample_keys.argtypes = [p, u64, p]
+        lib.oracle_sample_keys.restype = u64
+        lib.oracle_table_M.argtypes = [u64, u64]
+        lib.oracle_table_M.restype = u64
+        lib.oracle_hash.argtypes = [u64, u64]
+        lib.oracle_hash.restype = u64
+        lib.oracle_spill.argtypes = [p, u64, u64]
+        lib.oracle_spill.restype = u64
+        _lib = lib
+    return _lib
+
+
+def _arr(x, dtype):
+    a = np.ascontiguousarray(x)
+    if a.dtype != dtype:
+        if a.dtype.itemsize != 8 or a.dtype.kind not in "iu":
+            raise TypeError("oracle takes 64-bit integer arrays")
+        a = a.view(dtype)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data if a.size else None
+
+
+def sort(x, dtype=np.int64):
+    """Sorted copy of ``x`` (nondecreasing in ``dtype``'s order)."""
+    a = _arr(x, dtype)
+    y = np.empty_like(a)
+    fn = _load().oracle_sort_i64 if a.dtype == np.int64 else _load().oracle_sort_u64
+    fn(_ptr(a), a.size, _ptr(y))
+    return y
+
+
+def counts(x, dtype=np.int64):
+    """(uniq, counts) of ``x`` with ``uniq`` ascending in ``dtype``'s order."""
+    a = _arr(x, dtype)
+    uniq = np.empty_like(a)
+    cnt = np.empty(a.size, dtype=np.uint64)
+    fn = _load().oracle_counts_i64 if a.dtype == np.int64 else _load().oracle_counts_u64
+    k = fn(_ptr(a), a.size, _ptr(uniq), _ptr(cnt))
+    return uniq[:k].copy(), cnt[:k].copy()
+
+
+def is_monotone(x, dtype=np.int64):
+    a = _arr(x, dtype)
+    fn = _load().oracle_is_monotone_i64 if a.dtype == np.int64 else _load().oracle_is_monotone_u64
+    return bool(fn(_ptr(a), a.size))
+
+
+def estimate(x):
+    """Chao1 estimate over 1024 strided samples (Alg. 2), as a dict."""
+    a = _arr(x, np.uint64)
+    out = np.zeros(7, dtype=np.uint64)
+    _load().oracle_estimate(_ptr(a), a.size, _ptr(out))
+    return {k: int(v) for k, v in zip(ESTIMATE_FIELDS, out)}
+
+
+def sample_keys(x):
+    a = _arr(x, np.uint64)
+    keys = np.empty(1024, dtype=np.uint64)
+    k = _load().oracle_sample_keys(_ptr(a), a.size, _ptr(keys))
+    return keys[:k].copy()
+
+
+def table_M(k_hat, n):
+    """Bucket count of Eq. Msize (cap 4, clamped to [8, bit_ceil(N/4)])."""
+    return int(_load().oracle_table_M(int(k_hat), int(n)))
+
+
+def hash_bucket(v, M):
+    """Eq. hash: top log2(M) bits of v * 0x9E3779B97F4A7C15 mod 2^64."""
+    return int(_load().oracle_hash(int(v) & (2**64 - 1), int(M)))
+
+
+def spill(x, M):
+    """Literal bucket simulation (Alg. 1 + RLE): spilled element count."""
+    a = _arr(x, np.uint64)
+    return int(_load().oracle_spill(_ptr(a), a.size, int(M)))
+
+
+def report(x, dtype=np.int64):
+    """Full dispatcher report (Alg. 3 + Alg. 4) as a dict with a path name."""
+    a = _arr(x, dtype)
+    out = np.zeros(12, dtype=np.uint64)
+    fn = _load().oracle_report_i64 if a.dtype == np.int64 else _load().oracle_report_u64
+    fn(_ptr(a), a.size, _ptr(out))
+    r = {k: int(v) for k, v in zip(REPORT_FIELDS, out)}
+    r["path"] = PATHS[r["path"]]
+    return r

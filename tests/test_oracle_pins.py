@@ -1,0 +1,307 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here re-derives a value with the oracle's own code: expected values
+come from a library routine (numpy / Python sorting), brute force, closed
+forms worked by hand from the paper's definitions, numbers the paper prints
+(tests/golden/paper_values.json), or a Poisson model.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from tests import crafted
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+I64_MIN, I64_MAX = -(1 << 63), (1 << 63) - 1
+U64_MAX = (1 << 64) - 1
+
+
+# --------------------------------------------------------------------------
+# Output and counts: library sort, brute force, invariants (Sec. 3.1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [np.int64, np.uint64])
+@pytest.mark.parametrize("n,k,dist,pal", [
+    (0, 1, "uniform", "random"), (1, 1, "uniform", "random"), (7, 3, "uniform", "random"),
+    (1000, 200, "uniform", "random"), (100000, 200, "zipf", "random"),
+    (50000, 50000, "uniform", "random"), (20000, 1000, "uniform", "codes"),
+    (30000, 17, "runs", "ap"), (30000, 40, "almost_sorted", "random"),
+])
+def test_sort_equals_numpy_sort(dtype, n, k, dist, pal):
+    x = gen.column(n, k, dist=dist, palette=pal, dtype=dtype)
+    y = oracle.sort(x, dtype)
+    assert y.dtype == dtype
+    np.testing.assert_array_equal(y, np.sort(x, kind="stable"))
+
+
+@pytest.mark.parametrize("dtype", [np.int64, np.uint64])
+def test_counts_equal_unique(dtype):
+    x = gen.column(200000, 3000, dist="zipf", s=1.1, dtype=dtype)
+    uniq, cnt = oracle.counts(x, dtype)
+    u_ref, c_ref = np.unique(x, return_counts=True)
+    np.testing.assert_array_equal(uniq, u_ref)
+    np.testing.assert_array_equal(cnt, c_ref.astype(np.uint64))
+    assert int(cnt.sum()) == x.size
+    r = oracle.report(x, dtype)
+    assert r["k_exact"] == u_ref.size
+
+
+def test_bruteforce_small_alphabets():
+    """All arrays of length <= 6 over a 5-letter alphabet of extreme values:
+    output == Python's sorted(); counts == run lengths; MONOTONE iff sorted.
+    """
+    alph = {
+        np.int64: [I64_MIN, -1, 0, 1, I64_MAX],
+        np.uint64: [0, 1, (1 << 63) - 1, 1 << 63, U64_MAX],
+    }
+    for dtype, letters in alph.items():
+        for n in range(0, 7):
+            for tup in itertools.product(letters, repeat=n):
+                x = np.array(tup, dtype=dtype)
+                exp = sorted(tup)
+                assert oracle.sort(x, dtype).tolist() == exp
+                uniq, cnt = oracle.counts(x, dtype)
+                runs = [(k, len(list(g))) for k, g in itertools.groupby(exp)]
+                assert uniq.tolist() == [k for k, _ in runs]
+                assert cnt.tolist() == [c for _, c in runs]
+                r = oracle.report(x, dtype)
+                mono = list(tup) == exp
+                assert r["path"] == ("MONOTONE" if mono else "SMALL_N")
+                assert r["k_exact"] == len(runs)
+
+
+# --------------------------------------------------------------------------
+# IsMonotone and the dispatch order (Alg. 3): crafted T1 / T2
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [0, 1, 2047, 2048, 1000000])
+def test_t1_sorted_is_monotone(n):
+    x, exp = crafted.t1_sorted(n)
+    assert oracle.report(x.view(np.int64))["path"] == "MONOTONE"
+
+
+def test_t1_signedness():
+    # [-1, 0] is nondecreasing in signed order; the same bits in unsigned order
+    # are [2^64-1, 0], which is not.
+    x = np.array([-1, 0], dtype=np.int64)
+    assert oracle.is_monotone(x, np.int64)
+    assert not oracle.is_monotone(x.view(np.uint64), np.uint64)
+    assert oracle.report(x, np.int64)["path"] == "MONOTONE"
+    assert oracle.report(x.view(np.uint64), np.uint64)["path"] == "SMALL_N"
+
+
+def test_t2_small_n_cut():
+    x, _ = crafted.t2_unsorted(2047)
+    r = oracle.report(x.view(np.int64))
+    assert r["path"] == "SMALL_N" and r["n_samples"] == 0
+    x, _ = crafted.t2_unsorted(2048)
+    r = oracle.report(x.view(np.int64))
+    assert r["path"] != "SMALL_N" and r["stride"] == 2 and r["n_samples"] == 1024
+
+
+# --------------------------------------------------------------------------
+# Chao1 over strided samples (Alg. 2, Eq. chao1): closed forms
+# --------------------------------------------------------------------------
+
+def test_estimate_all_equal():
+    e = oracle.estimate(np.full(5000, 42, dtype=np.uint64))
+    # one distinct value seen 1024 times: u = 1, f1 = f2 = 0, K^ = 1 + 0
+    assert e == dict(k_hat=1, u=1, f1=0, f2=0, n_samples=1024, stride=4, saturated=0)
+
+
+def test_estimate_saturates():
+    # stride 4 and 1024 distinct values at the sampled positions: u = s -> K^ = N
+    x = np.zeros(4096, dtype=np.uint64)
+    x[0::4] = np.arange(1, 1025, dtype=np.uint64)
+    e = oracle.estimate(x)
+    assert e == dict(k_hat=4096, u=1024, f1=1024, f2=0, n_samples=1024, stride=4, saturated=1)
+
+
+def test_estimate_all_doubletons():
+    # 512 values twice each: u = 512, f1 = 0, f2 = 512 -> K^ = 512 + 0
+    x = np.repeat(np.arange(512, dtype=np.uint64) * np.uint64(977), 2)
+    e = oracle.estimate(x)
+    assert e == dict(k_hat=512, u=512, f1=0, f2=512, n_samples=1024, stride=1, saturated=0)
+
+
+def test_estimate_f2_zero_blowup():
+    # 999 singletons + one value 25 times: u = 1000, f1 = 999, f2 = 0
+    # K^ = 1000 + floor(998001 / 2) = 1000 + 499000 = 500000
+    x = np.concatenate([np.arange(1, 1000, dtype=np.uint64), np.full(25, 7777, dtype=np.uint64)])
+    e = oracle.estimate(x)
+    assert e == dict(k_hat=500000, u=1000, f1=999, f2=0, n_samples=1024, stride=1, saturated=0)
+
+
+def test_estimate_mixed_spectrum():
+    # 10 values x1, 6 values x2, 1 value x1002 (1024 samples, stride 1):
+    # u = 17, f1 = 10, f2 = 6 -> K^ = 17 + floor(100 / 14) = 17 + 7 = 24
+    x = np.concatenate([np.arange(100, 110), np.repeat(np.arange(200, 206), 2),
+                        np.full(1002, 5)]).astype(np.uint64)
+    e = oracle.estimate(x)
+    assert e == dict(k_hat=24, u=17, f1=10, f2=6, n_samples=1024, stride=1, saturated=0)
+
+
+def test_estimate_small_and_empty():
+    assert oracle.estimate(np.zeros(0, dtype=np.uint64)) == dict(
+        k_hat=0, u=0, f1=0, f2=0, n_samples=0, stride=1, saturated=0)
+    # N = 5 < s: stride 1, every element sampled, never saturated
+    e = oracle.estimate(np.array([1, 2, 3, 4, 5], dtype=np.uint64))
+    assert e == dict(k_hat=5 + 25 // 2, u=5, f1=5, f2=0, n_samples=5, stride=1, saturated=0)
+
+
+@pytest.mark.parametrize("n,stride,last", [
+    (1023, 1, 1022), (1024, 1, 1023), (2047, 1, 1023), (2048, 2, 2046),
+    (3071, 2, 2046), (3072, 3, 3069), (10**6, 976, 976 * 1023),
+])
+def test_sample_positions(n, stride, last):
+    """Samples are x[0], x[stride], ... while i < min(N, 1024*stride).
+
+    Marking exactly those positions with distinct values and everything else with
+    one other value gives u = n_samples; changing any other position changes
+    nothing; changing a sampled position changes u.
+    """
+    x = np.zeros(n, dtype=np.uint64)
+    pos = np.arange(0, last + 1, stride)
+    assert pos.size == min(n, 1024)
+    x[pos] = np.arange(1, pos.size + 1, dtype=np.uint64) * np.uint64(3)  # distinct, nonzero
+    e = oracle.estimate(x)
+    assert e["stride"] == stride and e["n_samples"] == pos.size and e["u"] == pos.size
+    y = x.copy()
+    others = np.setdiff1d(np.arange(n), pos)
+    if others.size:
+        y[others] = np.uint64(999999937)
+        assert oracle.estimate(y) == e
+    z = x.copy()
+    z[pos[-1]] = z[pos[0]]  # one sampled value duplicated -> u drops by one
+    assert oracle.estimate(z)["u"] == pos.size - 1
+
+
+def test_estimate_relabelling_invariance():
+    x = gen.column(100000, 700, dist="zipf", s=1.0, dtype=np.uint64)
+    e = oracle.estimate(x)
+    # any bijection of the values (odd multiplier plus offset mod 2^64)
+    y = x * np.uint64(0xD1B54A32D192ED03) + np.uint64(12345)
+    assert oracle.estimate(y) == e
+
+
+# --------------------------------------------------------------------------
+# Eq. Msize with the paper's worked sizes; Eq. hash closed forms
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", GOLDEN["table_M_worked"]["cases"])
+def test_table_M_worked_values(case):
+    n = 1 << 26  # large enough that the upper clamp bit_ceil(N/4) does not bind
+    M = oracle.table_M(case["k_hat"], n)
+    assert M == case["M"]
+    assert M * GOLDEN["table_M_worked"]["bucket_bytes"] == case["bytes"]
+
+
+def test_table_M_clamps():
+    assert oracle.table_M(1, 10**6) == 8           # 2*1 -> 2, lower clamp 8
+    assert oracle.table_M(3, 10**6) == 8           # 6 -> 8
+    assert oracle.table_M(5, 10**6) == 16          # 10 -> 16
+    assert oracle.table_M(1000, 2048) == 512       # bit_ceil(2000) = 2048 > bit_ceil(512)
+    assert oracle.table_M(1000, 2051) == 512       # integer N/4 = 512
+    assert oracle.table_M(1000, 2052) == 1024      # N/4 = 513 -> bit_ceil = 1024
+
+
+def test_hash_constant_and_inverse():
+    assert int(GOLDEN["hash_multiplier"]["value_hex"], 16) == crafted.PHI
+    assert (crafted.PHI * crafted.PHI_INV) % (1 << 64) == 1
+
+
+def test_hash_closed_forms():
+    # h(1) = top m bits of 0x9E3779B97F4A7C15: 0x9E37 = 1001 1110 0011 0111b
+    assert oracle.hash_bucket(1, 512) == 0b100111100          # 316
+    assert oracle.hash_bucket(1, 4096) == 0b100111100011       # 2531
+    assert oracle.hash_bucket(1, 8) == 0b100
+    # 2^63 * odd = 2^63 (mod 2^64): the top bit only -> M/2
+    for M in (8, 512, 1 << 20):
+        assert oracle.hash_bucket(1 << 63, M) == M // 2
+        assert oracle.hash_bucket(0, M) == 0
+    rng = np.random.default_rng(11)
+    for m in (3, 5, 9, 17, 30):
+        for _ in range(50):
+            b = int(rng.integers(0, 1 << m))
+            assert oracle.hash_bucket(crafted.key_in_bucket(b, m, int(rng.integers(0, 2**62))), 1 << m) == b
+
+
+def test_dictionary_codes_spread():
+    # Codes 0..K-1 under the multiplicative hash (Sec. 4.2): consecutive keys are
+    # spread apart (Fibonacci hashing), so K <= M/2 codes never fill a 4-slot
+    # bucket.  A progression with step M, which x mod M would send to one bucket,
+    # is spread as well: 64 such keys into M = 1024 buckets spill nothing.
+    for K in (200, 1000, 5000):
+        M = 1 << (2 * K - 1).bit_length()
+        assert oracle.spill(np.arange(K, dtype=np.uint64), M) == 0
+    prog = np.arange(0, 64 * 1024, 1024, dtype=np.uint64)  # 64 keys, step M
+    assert oracle.spill(prog, 1024) == 0
+
+
+# --------------------------------------------------------------------------
+# Bucket simulation and guard (Alg. 1 + RLE, Alg. 4)
+# --------------------------------------------------------------------------
+
+def test_spill_first_four_claim():
+    M, m = 8, 3
+    ks = [crafted.key_in_bucket(5, m, 100 + i) for i in range(7)]
+    # first-occurrence order k0..k6, counts 1..7: k4, k5, k6 spill -> 5 + 6 + 7
+    seq = []
+    for i, k in enumerate(ks):
+        seq += [k] * (i + 1)
+    assert oracle.spill(np.array(seq, dtype=np.uint64), M) == 18
+    # later occurrences of early keys interleaved after the spilled ones: no change
+    seq2 = seq + [ks[0], ks[4], ks[1], ks[6]]
+    assert oracle.spill(np.array(seq2, dtype=np.uint64), M) == 18 + 2
+    # four keys per bucket in every bucket: nothing spills
+    full = [crafted.key_in_bucket(b, m, 7 * i) for b in range(8) for i in range(4)]
+    assert oracle.spill(np.array(full * 3, dtype=np.uint64), M) == 0
+
+
+def test_spill_runs_counted_in_elements():
+    M, m = 8, 3
+    ks = [crafted.key_in_bucket(2, m, 50 + i) for i in range(5)]
+    x = np.array(ks[:4] + [ks[4]] * 100 + ks[:4], dtype=np.uint64)
+    assert oracle.spill(x, M) == 100
+
+
+@pytest.mark.parametrize("name", list(crafted.all_cases().keys()))
+def test_crafted_reports(name):
+    x, exp = crafted.all_cases()[name]
+    for dtype in (np.int64, np.uint64):
+        r = oracle.report(x.view(dtype), dtype)
+        for key, val in exp.items():
+            assert r[key] == val, (name, dtype, key, r[key], val)
+
+
+def test_poisson_overflow_rate():
+    """K = 2^20 distinct random keys into M = 2^21 buckets (mean fill 0.5, cap 4):
+    expected spilled keys = M * E[(X - 4)^+] for X ~ Poisson(0.5).  The paper's
+    P(X >= 5) ~ 1.7e-4 is the leading term of that sum.
+    """
+    lam, cap = GOLDEN["poisson_overflow"]["mean_fill"], GOLDEN["poisson_overflow"]["cap"]
+    p5 = math.exp(-lam) * sum(lam ** k / math.factorial(k) for k in range(cap + 1, 40))
+    assert abs(p5 - GOLDEN["poisson_overflow"]["p_overflow"]) < 0.05e-4
+    excess = math.exp(-lam) * sum((k - cap) * lam ** k / math.factorial(k) for k in range(cap + 1, 40))
+    M = 1 << 21
+    x = gen.column(1 << 20, 1 << 20, dtype=np.uint64)  # K >= n: n distinct random values
+    assert np.unique(x).size == x.size
+    sp = oracle.spill(x, M)
+    mean = M * excess
+    assert abs(sp - mean) < 6 * math.sqrt(mean * 1.5), (sp, mean)
+
+
+def test_zipf_sweep_reports_main_path():
+    # Zipf(1.1) with K = 1e4 at N = 2e6: Chao1 underestimates K (Sec. 2.4's
+    # singleton/doubleton signal is weak under skew) but stays on the main path.
+    x = gen.column(2_000_000, 10_000, dist="zipf", s=1.1)
+    r = oracle.report(x)
+    assert r["path"] == "MAIN" and r["k_hat"] < r["k_exact"]
+    assert r["table_M"] == oracle.table_M(r["k_hat"], x.size)
