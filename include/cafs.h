@@ -1,0 +1,176 @@
+/*
+ * cafs.h -- C ABI of the MI355X (gfx950) CAFS hot path.
+ *
+ * CAFS ("A Cache-Aware Frequency Sort for Low-Cardinality Integer Data on
+ * x86-64") sorts a column of N 64-bit integers whose number of distinct values
+ * K is much smaller than N by counting and emitting instead of comparing.  This
+ * library runs every stage of that method on one GPU:
+ *   estimate  Chao1 over 1024 strided samples           (Sec. 4.3, Alg. 2, Eq. chao1)
+ *   dispatch  monotone / N < 2048 / tiny / 2K^ > N / main (Sec. 4.4, Alg. 3, Table dispatcher)
+ *   count     tiny-count or hash-count                    (Sec. 4.4)
+ *   guard     spill guard |spill| > N/2                   (Sec. 4.5, Alg. 4, Alg. 1, Eq. hash, Eq. Msize)
+ *   order     sort of the K distinct (key, count) pairs   (Sec. 4.5, Alg. 4)
+ *   emit      expansion of the pairs into the output      (Sec. 4.5, Alg. 4)
+ *   fallback  LSD radix sort for the high-entropy branches (Table dispatcher; the
+ *             paper's fallback is a comparison sort, any correct sort gives the
+ *             same output because the sorted multiset is unique, Sec. 3.1).
+ *
+ * Conventions for every entry point:
+ *   - Pointers prefixed d_ are device pointers (hipMalloc'd or equivalent) on the
+ *     context's device; h_ pointers are host memory.  The caller owns every
+ *     buffer it passes; the library frees nothing it did not allocate.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls only enqueue work on it and return; no call synchronises the host,
+ *     except cafs_ctx_create.  Outputs (sorted keys, counts, reports) are valid
+ *     once the stream has reached the enqueued work.
+ *   - Errors are returned as cafs_status_t and never thrown.  On any error
+ *     nothing has been enqueued, except CAFS_EHIP, which reports a failed
+ *     launch; cafs_last_error() then holds the HIP error string.
+ *   - Keys are 64-bit.  CAFS_I64 orders them as signed integers, CAFS_U64 as
+ *     unsigned; equality (used by the estimate, the counts and the guard's
+ *     buckets) is on the raw 64-bit pattern.
+ *   - N must be below 2^32.
+ */
+#ifndef CAFS_H
+#define CAFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CAFS_OK = 0,
+    CAFS_EINVAL = -1,       /* bad argument: NULL pointer with n > 0, unknown dtype,
+                               partially overlapping in/out, n >= 2^32, counts
+                               requested without a report */
+    CAFS_EWORKSPACE = -2,   /* ws_bytes < cafs_workspace_bytes(n) or d_ws misaligned */
+    CAFS_EHIP = -3,         /* a HIP call or launch failed; see cafs_last_error() */
+    CAFS_EUNSUPPORTED = -4, /* feature not available on this device */
+    CAFS_ENOMEM = -5        /* host allocation failed */
+} cafs_status_t;
+
+typedef enum { CAFS_I64 = 0, CAFS_U64 = 1 } cafs_dtype_t;
+
+/* Branch chosen by the dispatcher (Alg. 3), in the order it tests them. */
+typedef enum {
+    CAFS_PATH_MONOTONE = 0, /* input already nondecreasing: output = input */
+    CAFS_PATH_SMALL_N = 1,  /* N < 2048: fallback sort without sampling */
+    CAFS_PATH_TINY = 2,     /* K^ <= 8 and u <= 8 and the sampled keys cover the input */
+    CAFS_PATH_HIGH_K = 3,   /* 2 K^ > N: fallback sort */
+    CAFS_PATH_MAIN = 4,     /* hash-count main path; the spill guard did not fire */
+    CAFS_PATH_GUARD = 5     /* main path whose spill exceeded N/2 (Alg. 4) */
+} cafs_path_t;
+
+/* What actually ran on the GPU (the label above follows the paper). */
+typedef enum {
+    CAFS_ENGINE_NONE = 0,  /* copy only (monotone input) */
+    CAFS_ENGINE_TINY = 1,  /* wave-ballot tiny count + emit */
+    CAFS_ENGINE_HASH = 2,  /* LDS/global hash count + order + emit */
+    CAFS_ENGINE_RADIX = 3  /* LSD radix sort of the keys */
+} cafs_engine_t;
+
+/* Chao1 estimate over strided samples (Alg. 2, Eq. chao1):
+ *   stride = max(1, floor(N/1024)); samples x[0], x[stride], ... while the index
+ *   is below min(N, 1024*stride), so n_samples = min(N, 1024);
+ *   u = distinct sampled values, f1 / f2 = values seen once / twice;
+ *   saturated = (u == 1024); k_hat = saturated ? N : u + floor(f1^2 / (2 (f2+1)))
+ *   in unsigned 64-bit arithmetic. */
+typedef struct {
+    uint64_t k_hat, u, f1, f2, n_samples, stride;
+    uint32_t saturated, pad;
+} cafs_estimate_t;
+
+/* Per-call report.  est is zero on the MONOTONE and SMALL_N paths (the
+ * dispatcher returns before sampling).  table_M (Eq. Msize, cap 4 for 64-bit
+ * keys) and spill_elems (elements that the paper's bucket table of Alg. 1 would
+ * send to the spill, counted in elements) are set on MAIN and GUARD only.
+ * k_exact is the exact number of distinct keys.  engine is a cafs_engine_t.
+ * flags: bit 0 = the GPU hash table overflowed and the radix engine sorted the
+ * column instead; bit 1 = the guard needed the first-occurrence pass. */
+typedef struct {
+    cafs_estimate_t est;
+    int32_t path;
+    int32_t tiny_miss; /* 1 if the tiny branch was chosen but an unsampled value exists */
+    uint64_t table_M;
+    uint64_t spill_elems;
+    uint64_t k_exact;
+    uint32_t engine;
+    uint32_t flags;
+} cafs_report_t;
+
+typedef struct cafs_ctx cafs_ctx_t;
+
+/* Creates a context on `device` (queries its compute-unit count; synchronous).
+ * Returns CAFS_EINVAL for a NULL ctx, CAFS_EHIP if the device is unusable. */
+cafs_status_t cafs_ctx_create(cafs_ctx_t** ctx, int device);
+void cafs_ctx_destroy(cafs_ctx_t* ctx);
+
+/* Upper bound on the device workspace of one cafs_sort_i64/u64 call of n keys
+ * (the same for both dtypes); depends on n only.  The workspace must be
+ * 256-byte aligned and is used as scratch: its contents on entry do not matter. */
+size_t cafs_workspace_bytes(uint64_t n, cafs_dtype_t dtype);
+
+/* Chao1 estimate of the distinct-value count of d_keys[0..n) (Alg. 2).
+ * Writes one cafs_estimate_t to device memory d_out.  Uses no workspace.
+ * The estimate ignores signedness.  n = 0 gives the all-zero estimate with
+ * stride 1. */
+cafs_status_t cafs_estimate(cafs_ctx_t* ctx, const void* d_keys, uint64_t n,
+                            cafs_estimate_t* d_out, void* stream);
+
+/* Sorts d_in[0..n) into d_out[0..n) (nondecreasing in the dtype's order) along
+ * the dispatcher of Alg. 3.  d_in == d_out (in place) is allowed; any other
+ * overlap is CAFS_EINVAL.  Both must be 8-byte aligned.
+ *   d_uniq, d_counts  optional (may be NULL), device arrays with room for n
+ *                     entries: the distinct keys in order and their counts
+ *                     (uint64); K = report.k_exact entries are written.  If
+ *                     either is given, d_report must be given too.
+ *   d_report          optional device cafs_report_t.
+ *   d_ws, ws_bytes    device workspace of at least cafs_workspace_bytes(n).
+ * Dispatch happens on the device: the call enqueues a fixed sequence of kernels
+ * whose branches not taken exit at once, so it never waits for the GPU and can
+ * be captured in a HIP graph. */
+cafs_status_t cafs_sort_i64(cafs_ctx_t* ctx, const int64_t* d_in, int64_t* d_out, uint64_t n,
+                            int64_t* d_uniq, uint64_t* d_counts, cafs_report_t* d_report,
+                            void* d_ws, size_t ws_bytes, void* stream);
+cafs_status_t cafs_sort_u64(cafs_ctx_t* ctx, const uint64_t* d_in, uint64_t* d_out, uint64_t n,
+                            uint64_t* d_uniq, uint64_t* d_counts, cafs_report_t* d_report,
+                            void* d_ws, size_t ws_bytes, void* stream);
+
+/* The fallback engine on its own: LSD radix sort with 8-bit digits and decoupled
+ * look-back (digits on which every key agrees are skipped).  It is the GPU
+ * baseline the CAFS path is measured against.  Same buffer rules as above;
+ * uses cafs_workspace_bytes(n) of workspace. */
+cafs_status_t cafs_radix_sort(cafs_ctx_t* ctx, const void* d_in, void* d_out, uint64_t n,
+                              cafs_dtype_t dtype, void* d_ws, size_t ws_bytes, void* stream);
+
+/* One column of a batched call. */
+typedef struct {
+    const void* d_in;
+    void* d_out;
+    uint64_t n;
+    int32_t dtype;          /* cafs_dtype_t */
+    int32_t flags;          /* reserved, must be 0 */
+    void* d_uniq;           /* optional, room for n keys */
+    uint64_t* d_counts;     /* optional, room for n counts */
+    cafs_report_t* d_report;/* optional (required if d_uniq or d_counts is set) */
+} cafs_column_t;
+
+/* Workspace for a batched call over the given column lengths. */
+size_t cafs_batched_workspace_bytes(const uint64_t* h_ns, uint32_t n_cols);
+
+/* Sorts n_cols independent columns; each column's outputs are identical to a
+ * cafs_sort_* call on it.  h_cols is read before the call returns. */
+cafs_status_t cafs_sort_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, uint32_t n_cols,
+                                void* d_ws, size_t ws_bytes, void* stream);
+
+const char* cafs_status_str(cafs_status_t status);
+/* Detail of the last CAFS_EHIP on the calling thread ("" if none). */
+const char* cafs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAFS_H */

@@ -1,0 +1,202 @@
+"""Python binding of the MI355X CAFS library (libcafs.so, C ABI in include/cafs.h).
+
+Argument marshalling only: every step of the sort runs in the HIP kernels.
+PyTorch provides device memory and streams.  The library must have been built
+(``python -m paper_2605_25040_amd.build``); there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcafs.so")
+
+PATHS = ("MONOTONE", "SMALL_N", "TINY", "HIGH_K", "MAIN", "GUARD")
+ENGINES = ("NONE", "TINY", "HASH", "RADIX")
+I64, U64 = 0, 1
+STATUS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "HIP error", -4: "unsupported", -5: "nomem"}
+
+EXPORTS = ("cafs_ctx_create", "cafs_ctx_destroy", "cafs_workspace_bytes", "cafs_estimate",
+           "cafs_sort_i64", "cafs_sort_u64", "cafs_radix_sort", "cafs_batched_workspace_bytes",
+           "cafs_sort_batched", "cafs_status_str", "cafs_last_error")
+
+
+class Estimate(ctypes.Structure):
+    _fields_ = [("k_hat", ctypes.c_uint64), ("u", ctypes.c_uint64), ("f1", ctypes.c_uint64),
+                ("f2", ctypes.c_uint64), ("n_samples", ctypes.c_uint64), ("stride", ctypes.c_uint64),
+                ("saturated", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("est", Estimate), ("path", ctypes.c_int32), ("tiny_miss", ctypes.c_int32),
+                ("table_M", ctypes.c_uint64), ("spill_elems", ctypes.c_uint64), ("k_exact", ctypes.c_uint64),
+                ("engine", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class Column(ctypes.Structure):
+    _fields_ = [("d_in", ctypes.c_void_p), ("d_out", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("dtype", ctypes.c_int32), ("flags", ctypes.c_int32), ("d_uniq", ctypes.c_void_p),
+                ("d_counts", ctypes.c_void_p), ("d_report", ctypes.c_void_p)]
+
+
+class CafsError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    """Load libcafs.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise CafsError("libcafs.so is not built; run `python -m paper_2605_25040_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    p, u64, i32, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32
+    lib.cafs_ctx_create.argtypes = [ctypes.POINTER(p), ctypes.c_int]
+    lib.cafs_ctx_create.restype = i32
+    lib.cafs_ctx_destroy.argtypes = [p]
+    lib.cafs_ctx_destroy.restype = None
+    lib.cafs_workspace_bytes.argtypes = [u64, i32]
+    lib.cafs_workspace_bytes.restype = ctypes.c_size_t
+    lib.cafs_estimate.argtypes = [p, p, u64, p, p]
+    lib.cafs_estimate.restype = i32
+    for name in ("cafs_sort_i64", "cafs_sort_u64"):
+        getattr(lib, name).argtypes = [p, p, p, u64, p, p, p, p, ctypes.c_size_t, p]
+        getattr(lib, name).restype = i32
+    lib.cafs_radix_sort.argtypes = [p, p, p, u64, i32, p, ctypes.c_size_t, p]
+    lib.cafs_radix_sort.restype = i32
+    lib.cafs_batched_workspace_bytes.argtypes = [p, u32]
+    lib.cafs_batched_workspace_bytes.restype = ctypes.c_size_t
+    lib.cafs_sort_batched.argtypes = [p, p, u32, p, ctypes.c_size_t, p]
+    lib.cafs_sort_batched.restype = i32
+    lib.cafs_status_str.argtypes = [i32]
+    lib.cafs_status_str.restype = ctypes.c_char_p
+    lib.cafs_last_error.argtypes = []
+    lib.cafs_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        lib = load()
+        msg = lib.cafs_status_str(rc).decode()
+        detail = lib.cafs_last_error().decode()
+        raise CafsError("cafs error %d (%s) %s" % (rc, msg, detail))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """A device context (compute-unit count) plus a cached workspace."""
+
+    def __init__(self, device=0):
+        if not torch.cuda.is_available():
+            raise CafsError("no GPU visible: the CAFS library runs on the GPU only")
+        self.device = torch.device("cuda", device)
+        self._lib = load()
+        h = ctypes.c_void_p()
+        _check(self._lib.cafs_ctx_create(ctypes.byref(h), device))
+        self._h = h
+        self._ws = None
+
+    def close(self):
+        if self._h:
+            self._lib.cafs_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, n):
+        return int(self._lib.cafs_workspace_bytes(int(n), 0))
+
+    def workspace(self, nbytes):
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def estimate(self, x):
+        """Chao1 estimate of x (int64 tensor) as a dict."""
+        out = torch.zeros(ctypes.sizeof(Estimate), dtype=torch.uint8, device=self.device)
+        _check(self._lib.cafs_estimate(self._h, _ptr(x), x.numel(), _ptr(out), _stream(self.device)))
+        e = Estimate.from_buffer_copy(bytes(out.cpu().numpy()))
+        return {k: int(getattr(e, k)) for k, _ in Estimate._fields_ if k != "pad"}
+
+    def sort(self, x, unsigned=False, out=None, counts=False, report=True, ws=None):
+        """Sort a 1-D int64 tensor on the GPU (uint64 order if ``unsigned``).
+
+        Returns (out, report_tensor, uniq, counts); uniq/counts are None unless
+        ``counts``.  Call ``parse_report`` on the report tensor after a sync.
+        """
+        n = x.numel()
+        if x.dtype != torch.int64 or not x.is_cuda:
+            raise CafsError("sort takes a CUDA int64 tensor")
+        if out is None:
+            out = torch.empty_like(x)
+        rep = torch.zeros(ctypes.sizeof(Report), dtype=torch.uint8, device=self.device) if (report or counts) else None
+        uq = torch.empty_like(x) if counts else None
+        ct = torch.empty_like(x) if counts else None
+        if ws is None:
+            ws = self.workspace(self.workspace_bytes(n))
+        fn = self._lib.cafs_sort_u64 if unsigned else self._lib.cafs_sort_i64
+        _check(fn(self._h, _ptr(x), _ptr(out), n, _ptr(uq), _ptr(ct), _ptr(rep), _ptr(ws), ws.numel(),
+                  _stream(self.device)))
+        return out, rep, uq, ct
+
+    def radix_sort(self, x, unsigned=False, out=None, ws=None):
+        n = x.numel()
+        if out is None:
+            out = torch.empty_like(x)
+        if ws is None:
+            ws = self.workspace(self.workspace_bytes(n))
+        _check(self._lib.cafs_radix_sort(self._h, _ptr(x), _ptr(out), n, U64 if unsigned else I64, _ptr(ws),
+                                         ws.numel(), _stream(self.device)))
+        return out
+
+    def batched_workspace_bytes(self, ns):
+        arr = (ctypes.c_uint64 * len(ns))(*[int(v) for v in ns])
+        return int(self._lib.cafs_batched_workspace_bytes(arr, len(ns)))
+
+    def sort_batched(self, cols, ws=None):
+        """cols: list of dicts with keys in, out, unsigned, uniq, counts, report (tensors or None)."""
+        arr = (Column * len(cols))()
+        for i, cdesc in enumerate(cols):
+            arr[i].d_in = cdesc["in"].data_ptr()
+            arr[i].d_out = cdesc["out"].data_ptr()
+            arr[i].n = cdesc["in"].numel()
+            arr[i].dtype = U64 if cdesc.get("unsigned") else I64
+            arr[i].flags = 0
+            arr[i].d_uniq = cdesc["uniq"].data_ptr() if cdesc.get("uniq") is not None else None
+            arr[i].d_counts = cdesc["counts"].data_ptr() if cdesc.get("counts") is not None else None
+            arr[i].d_report = cdesc["report"].data_ptr() if cdesc.get("report") is not None else None
+        if ws is None:
+            ws = self.workspace(self.batched_workspace_bytes([c["in"].numel() for c in cols]))
+        _check(self._lib.cafs_sort_batched(self._h, arr, len(cols), _ptr(ws), ws.numel(), _stream(self.device)))
+
+
+def parse_report(rep):
+    """Report tensor (device, after a sync) -> dict with the oracle's field names."""
+    r = Report.from_buffer_copy(bytes(rep.cpu().numpy()))
+    d = {k: int(getattr(r.est, k)) for k, _ in Estimate._fields_ if k != "pad"}
+    d.update(path=PATHS[r.path], tiny_miss=int(r.tiny_miss), table_M=int(r.table_M),
+             spill_elems=int(r.spill_elems), k_exact=int(r.k_exact), engine=ENGINES[r.engine],
+             flags=int(r.flags))
+    return d
+
+
+def report_size():
+    return ctypes.sizeof(Report)

@@ -1,0 +1,357 @@
+// C ABI of the CAFS hot path (declared in include/cafs.h).
+//
+// The host side only validates arguments, lays out the caller's workspace and
+// enqueues a fixed sequence of kernels; every decision of the dispatcher is
+// taken on the device (see cafs_dev.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "cafs_dev.h"
+#include "k_count.h"
+#include "k_emit.h"
+#include "k_estimate.h"
+#include "k_guard.h"
+#include "k_radix.h"
+
+struct cafs_ctx {
+    int device;
+    int cus;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+cafs_status_t hip_fail(hipError_t e, const char* where) {
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return CAFS_EHIP;
+}
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+uint64_t bit_ceil_host(uint64_t v) {
+    uint64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+uint32_t log2_host(uint64_t p) {
+    uint32_t m = 0;
+    while ((1ull << m) < p) ++m;
+    return m;
+}
+
+// Workspace of one column of n keys.  Regions are 256-byte aligned.
+struct Layout {
+    size_t ctrl, gkeys, gcnt, claimed, pk, pv, uniq, cnt, off, tmp_k, tmp_v, status, dcount, rle_tile;
+    size_t total;
+    uint32_t cap_log2;
+    uint64_t status_slot;
+    uint64_t m_ws;
+};
+
+Layout make_layout(uint64_t n) {
+    Layout L{};
+    const uint64_t nn = n > 0 ? n : 1;
+    uint32_t lg = log2_host(bit_ceil_host(std::max<uint64_t>(4 * nn, 1ull << cafs::kMinTableLog2)));
+    lg = std::min<uint32_t>(std::max<uint32_t>(lg, cafs::kMinTableLog2), cafs::kMaxTableLog2);
+    L.cap_log2 = lg;
+    const uint64_t cap = 1ull << lg;
+    L.m_ws = std::max<uint64_t>(8, bit_ceil_host(nn / cafs::kBucketCap));
+    const uint64_t radix_max = std::max<uint64_t>(nn, cap);
+    const uint64_t tiles = (radix_max + cafs::kRadixTile - 1) / cafs::kRadixTile;
+    L.status_slot = tiles * 256;
+    const uint64_t rle_tiles = (nn + cafs::kRleTile - 1) / cafs::kRleTile;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    L.ctrl = take(sizeof(cafs::Ctrl));
+    L.gkeys = take(cap * 8);
+    L.gcnt = take(cap * 8);
+    L.claimed = take(cap * 4);
+    L.pk = take(cap * 8);
+    L.pv = take(cap * 8);
+    L.uniq = take(nn * 8);
+    L.cnt = take(nn * 8);
+    // off (n + 1 entries) doubles as the guard's first-occurrence array (n u32)
+    L.off = take((nn + 1) * 8);
+    // the radix scratch doubles as the guard's four per-bucket minima (4 * m_ws u32)
+    L.tmp_k = take(std::max<uint64_t>(radix_max * 8, 16 * L.m_ws));
+    L.tmp_v = take(cap * 8);
+    L.status = take(2 * L.status_slot * 8);
+    L.dcount = take(L.m_ws * 4);
+    L.rle_tile = take(rle_tiles * 8);
+    L.total = o;
+    return L;
+}
+
+template <class T>
+T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
+
+bool overlaps(const void* a, const void* b, uint64_t n) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    const uintptr_t bytes = n * 8;
+    return x != y && x < y + bytes && y < x + bytes;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        int cur = 0;
+        if (hipGetDevice(&cur) == hipSuccess && cur != dev) {
+            prev = cur;
+            (void)hipSetDevice(dev);
+        }
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+uint32_t grid_for(uint64_t work_items, uint64_t per_block, uint32_t cap) {
+    uint64_t g = (work_items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+cafs_status_t launch_radix(const cafs::Args& a, uint64_t n_max, int cus, hipStream_t s) {
+    const uint64_t tiles = (n_max + cafs::kRadixTile - 1) / cafs::kRadixTile;
+    const uint32_t g_hist = grid_for(n_max, 256 * 16, cus * 4);
+    const uint32_t g_pass = grid_for(tiles, 1, cus * 2);
+    cafs::k_radix_hist<<<g_hist, 256, 0, s>>>(a);
+    for (uint32_t p = 0; p < 8; ++p) cafs::k_radix_pass<<<g_pass, cafs::kRadixThreads, 0, s>>>(a, p);
+    cafs::k_radix_copy<<<grid_for(n_max, 256 * 8, cus * 4), 256, 0, s>>>(a);
+    return CAFS_OK;
+}
+
+cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void* out, uint64_t n, cafs_dtype_t dt,
+                     void* uniq, uint64_t* counts, cafs_report_t* report, void* ws) {
+    (void)ctx;
+    cafs::Args a{};
+    a.in = static_cast<const uint64_t*>(in);
+    a.out = static_cast<uint64_t*>(out);
+    a.n = n;
+    a.flip = (dt == CAFS_I64) ? (1ull << 63) : 0ull;
+    a.in_head = (reinterpret_cast<uintptr_t>(in) % 16) ? 1u : 0u;
+    a.out_head = (reinterpret_cast<uintptr_t>(out) % 16) ? 1u : 0u;
+    a.want_report = report != nullptr;
+    a.want_counts = (uniq != nullptr) || (counts != nullptr);
+    a.report = report;
+    a.c = at<cafs::Ctrl>(ws, L.ctrl);
+    a.uniq = uniq ? static_cast<uint64_t*>(uniq) : at<uint64_t>(ws, L.uniq);
+    a.cnt = counts ? counts : at<uint64_t>(ws, L.cnt);
+    a.off = at<uint64_t>(ws, L.off);
+    a.gkeys = at<uint64_t>(ws, L.gkeys);
+    a.gcnt = at<uint64_t>(ws, L.gcnt);
+    a.claimed = at<uint32_t>(ws, L.claimed);
+    a.cap_ws_log2 = L.cap_log2;
+    a.pk = at<uint64_t>(ws, L.pk);
+    a.pv = at<uint64_t>(ws, L.pv);
+    a.tmp_k = at<uint64_t>(ws, L.tmp_k);
+    a.tmp_v = at<uint64_t>(ws, L.tmp_v);
+    a.status = at<uint64_t>(ws, L.status);
+    a.status_slot = L.status_slot;
+    a.dcount = at<uint32_t>(ws, L.dcount);
+    a.bmin = at<uint32_t>(ws, L.tmp_k);
+    a.first_idx = at<uint32_t>(ws, L.off);
+    a.m_ws = L.m_ws;
+    a.rle_tile = at<uint64_t>(ws, L.rle_tile);
+    return a;
+}
+
+cafs_status_t check_buffers(const void* in, const void* out, uint64_t n) {
+    if (n >= (1ull << 32)) return CAFS_EINVAL;
+    if (n > 0 && (!in || !out)) return CAFS_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) % 8) return CAFS_EINVAL;
+    if (overlaps(in, out, n)) return CAFS_EINVAL;
+    return CAFS_OK;
+}
+
+cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, cafs_dtype_t dt, void* uniq,
+                        uint64_t* counts, cafs_report_t* report, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return CAFS_EINVAL;
+    if (dt != CAFS_I64 && dt != CAFS_U64) return CAFS_EINVAL;
+    cafs_status_t st = check_buffers(in, out, n);
+    if (st != CAFS_OK) return st;
+    if ((uniq || counts) && !report) return CAFS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceGuard dg(ctx->device);
+    if (n == 0) {
+        if (report) cafs::k_report_empty<<<1, 64, 0, s>>>(report);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? CAFS_OK : hip_fail(e, "launch");
+    }
+    const Layout L = make_layout(n);
+    if (!ws || ws_bytes < L.total || reinterpret_cast<uintptr_t>(ws) % kAlign) return CAFS_EWORKSPACE;
+    const cafs::Args a = make_args(ctx, L, in, out, n, dt, uniq, counts, report, ws);
+    const int cus = ctx->cus;
+    const uint64_t cap_ws = 1ull << L.cap_log2;
+    (void)hipGetLastError();  // clear any stale error so the check below is ours
+    cafs::k_pre<<<1, 1024, 0, s>>>(a);
+    if (n > cafs::kMonoPrefix) cafs::k_mono_full<<<grid_for(n, 256 * 16, cus * 4), 256, 0, s>>>(a);
+    cafs::k_plan<<<1, 256, 0, s>>>(a);
+    const bool countable = n >= cafs::kSmallN;  // tiny and main need N >= 2048
+    if (countable) {
+        cafs::k_phase2<<<grid_for(std::max<uint64_t>(n / 2, cap_ws), 256 * 8, cus * 4), 256, 0, s>>>(a);
+        cafs::k_hash_count<<<grid_for(n, cafs::kCountThreads * 8, cus), cafs::kCountThreads, 0, s>>>(a);
+        cafs::k_compact_order<<<1, 1024, 0, s>>>(a);
+    }
+    launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s);
+    if (countable) {
+        if (n > cafs::kOrderMax) cafs::k_pair_scan<<<1, 1024, 0, s>>>(a);
+        cafs::k_emit<<<grid_for(n, 2 * cafs::kEmitTilePairs, cus * 8), cafs::kEmitThreads, 0, s>>>(a);
+    }
+    cafs::k_copy_mono<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s>>>(a);
+    const uint32_t g_rle = grid_for(n, cafs::kRleTile, cus * 4);
+    cafs::k_rle_count<<<g_rle, 256, 0, s>>>(a);
+    cafs::k_rle_write<<<g_rle, 256, 0, s>>>(a);
+    cafs::k_rle_counts<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s>>>(a);
+    if (countable) {
+        const uint32_t g = grid_for(std::max<uint64_t>(n / 8, 1), 256 * 8, cus * 4);
+        cafs::k_guard_prep<<<grid_for(L.m_ws, 256 * 8, cus * 4), 256, 0, s>>>(a);
+        cafs::k_guard_bucket<<<g, 256, 0, s>>>(a);
+        cafs::k_guard_mark<<<g, 256, 0, s>>>(a);
+        cafs::k_guard_first<<<grid_for(n, cafs::kGuardChunk, cus * 2), 256, 0, s>>>(a);
+        for (uint32_t r = 0; r < 4; ++r) cafs::k_guard_round<<<g, 256, 0, s>>>(a, r);
+        cafs::k_guard_final<<<g, 256, 0, s>>>(a);
+    }
+    cafs::k_finalize<<<1, 64, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CAFS_OK : hip_fail(e, "launch");
+}
+
+__global__ void k_radix_setup(cafs::Args a) {
+    if (threadIdx.x != 0) return;
+    cafs::Ctrl* c = a.c;
+    for (int d = 0; d < 8; ++d) {
+        c->tile_ctr[d] = 0;
+        for (int b = 0; b < 256; ++b) c->hist[d][b] = 0;
+    }
+    c->hist_done = 0;
+    c->radix_on = 1;
+    cafs::RadixJob& j = c->rj;
+    j.src_k = a.in; j.src_v = nullptr;
+    j.dst_k = a.out; j.dst_v = nullptr;
+    j.tmp_k = a.tmp_k; j.tmp_v = nullptr;
+    j.n = a.n;
+    j.has_vals = 0;
+    j.n_active = 0;
+    j.copy_mode = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+cafs_status_t cafs_ctx_create(cafs_ctx_t** ctx, int device) {
+    if (!ctx) return CAFS_EINVAL;
+    *ctx = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count) return CAFS_EINVAL;
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    cafs_ctx_t* c = new (std::nothrow) cafs_ctx_t;
+    if (!c) return CAFS_ENOMEM;
+    c->device = device;
+    c->cus = cus > 0 ? cus : 1;
+    *ctx = c;
+    return CAFS_OK;
+}
+
+void cafs_ctx_destroy(cafs_ctx_t* ctx) { delete ctx; }
+
+size_t cafs_workspace_bytes(uint64_t n, cafs_dtype_t dtype) {
+    (void)dtype;
+    return make_layout(n).total;
+}
+
+cafs_status_t cafs_estimate(cafs_ctx_t* ctx, const void* d_keys, uint64_t n, cafs_estimate_t* d_out, void* stream) {
+    if (!ctx || !d_out || (n > 0 && !d_keys) || reinterpret_cast<uintptr_t>(d_keys) % 8) return CAFS_EINVAL;
+    if (n >= (1ull << 32)) return CAFS_EINVAL;
+    DeviceGuard dg(ctx->device);
+    (void)hipGetLastError();
+    cafs::k_estimate_only<<<1, 1024, 0, static_cast<hipStream_t>(stream)>>>(static_cast<const uint64_t*>(d_keys), n,
+                                                                            d_out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CAFS_OK : hip_fail(e, "launch");
+}
+
+cafs_status_t cafs_sort_i64(cafs_ctx_t* ctx, const int64_t* d_in, int64_t* d_out, uint64_t n, int64_t* d_uniq,
+                            uint64_t* d_counts, cafs_report_t* d_report, void* d_ws, size_t ws_bytes, void* stream) {
+    return sort_impl(ctx, d_in, d_out, n, CAFS_I64, d_uniq, d_counts, d_report, d_ws, ws_bytes, stream);
+}
+
+cafs_status_t cafs_sort_u64(cafs_ctx_t* ctx, const uint64_t* d_in, uint64_t* d_out, uint64_t n, uint64_t* d_uniq,
+                            uint64_t* d_counts, cafs_report_t* d_report, void* d_ws, size_t ws_bytes, void* stream) {
+    return sort_impl(ctx, d_in, d_out, n, CAFS_U64, d_uniq, d_counts, d_report, d_ws, ws_bytes, stream);
+}
+
+cafs_status_t cafs_radix_sort(cafs_ctx_t* ctx, const void* d_in, void* d_out, uint64_t n, cafs_dtype_t dtype,
+                              void* d_ws, size_t ws_bytes, void* stream) {
+    if (!ctx) return CAFS_EINVAL;
+    if (dtype != CAFS_I64 && dtype != CAFS_U64) return CAFS_EINVAL;
+    cafs_status_t st = check_buffers(d_in, d_out, n);
+    if (st != CAFS_OK) return st;
+    if (n == 0) return CAFS_OK;
+    const Layout L = make_layout(n);
+    if (!d_ws || ws_bytes < L.total || reinterpret_cast<uintptr_t>(d_ws) % kAlign) return CAFS_EWORKSPACE;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const cafs::Args a = make_args(ctx, L, d_in, d_out, n, dtype, nullptr, nullptr, nullptr, d_ws);
+    (void)hipGetLastError();
+    k_radix_setup<<<1, 64, 0, s>>>(a);
+    launch_radix(a, n, ctx->cus, s);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CAFS_OK : hip_fail(e, "launch");
+}
+
+size_t cafs_batched_workspace_bytes(const uint64_t* h_ns, uint32_t n_cols) {
+    size_t m = 0;
+    for (uint32_t i = 0; h_ns && i < n_cols; ++i) m = std::max(m, make_layout(h_ns[i]).total);
+    return m;
+}
+
+cafs_status_t cafs_sort_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, uint32_t n_cols, void* d_ws,
+                                size_t ws_bytes, void* stream) {
+    if (!ctx || (n_cols > 0 && !h_cols)) return CAFS_EINVAL;
+    for (uint32_t i = 0; i < n_cols; ++i) {
+        const cafs_column_t& col = h_cols[i];
+        if (col.flags != 0 || (col.dtype != CAFS_I64 && col.dtype != CAFS_U64)) return CAFS_EINVAL;
+        cafs_status_t st = check_buffers(col.d_in, col.d_out, col.n);
+        if (st != CAFS_OK) return st;
+        if ((col.d_uniq || col.d_counts) && !col.d_report) return CAFS_EINVAL;
+        if (col.n > 0 && ws_bytes < make_layout(col.n).total) return CAFS_EWORKSPACE;
+    }
+    for (uint32_t i = 0; i < n_cols; ++i) {
+        const cafs_column_t& col = h_cols[i];
+        cafs_status_t st = sort_impl(ctx, col.d_in, col.d_out, col.n, (cafs_dtype_t)col.dtype, col.d_uniq,
+                                     col.d_counts, col.d_report, d_ws, ws_bytes, stream);
+        if (st != CAFS_OK) return st;
+    }
+    return CAFS_OK;
+}
+
+const char* cafs_status_str(cafs_status_t status) {
+    switch (status) {
+    case CAFS_OK: return "ok";
+    case CAFS_EINVAL: return "invalid argument";
+    case CAFS_EWORKSPACE: return "workspace too small or misaligned";
+    case CAFS_EHIP: return "HIP error";
+    case CAFS_EUNSUPPORTED: return "unsupported";
+    case CAFS_ENOMEM: return "out of host memory";
+    }
+    return "unknown status";
+}
+
+const char* cafs_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,222 @@
+// Device-side definitions shared by the CAFS kernels for gfx950.
+//
+// Dispatch happens on the device.  Every call enqueues one fixed sequence of
+// kernels; the first kernels write their decisions (path, engine, table sizes,
+// sizes of intermediate arrays) into a Ctrl block in the workspace, and every
+// later kernel reads it and returns at once when its branch is not taken.  The
+// host never waits for the GPU, and the sequence can be captured in a graph.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cafs.h"
+
+namespace cafs {
+
+// ---- constants of the method (CAFS paper) ---------------------------------
+constexpr uint32_t kSamples = 1024;            // s, strided samples (Sec. 4.3)
+constexpr uint32_t kFreqSlotsLog2 = 12;        // FreqSet of 4096 slots (Sec. 4.3)
+constexpr uint64_t kSmallN = 2048;             // Table dispatcher: N < 2048 -> fallback
+constexpr uint64_t kTinyK = 8;                 // Table dispatcher: K^ <= 8 and u <= 8
+constexpr uint64_t kPhi = 0x9E3779B97F4A7C15ull;  // Eq. hash multiplier
+constexpr uint32_t kBucketCap = 4;             // keys per 64-bit bucket (Sec. 4.2)
+
+// ---- GPU design constants (not from the paper) ----------------------------
+constexpr uint64_t kEmpty = ~0ull;             // empty-slot marker of the GPU hash tables;
+                                               // keys equal to it are counted apart
+constexpr uint32_t kMonoPrefix = 1u << 13;     // elements the pre kernel checks for order
+constexpr int kCountThreads = 1024;            // hash-count workgroup
+constexpr uint32_t kLdsSlotsLog2 = 13;         // per-workgroup LDS table: 8192 slots
+constexpr uint32_t kLdsProbe = 32;             // LDS probe limit before the global table
+constexpr uint32_t kGlobalProbe = 4096;        // global probe limit before overflow
+constexpr uint32_t kMinTableLog2 = 12;         // smallest global table (4096 slots)
+constexpr uint32_t kMaxTableLog2 = 22;         // largest global table (4M slots, 64 MiB)
+constexpr uint32_t kOrderMax = 8192;           // K sorted by the single-workgroup order kernel
+constexpr uint32_t kGuardLdsBuckets = 16384;   // guard bucket counts kept in LDS up to this M
+constexpr int kRadixThreads = 256;             // radix workgroup (4 waves)
+constexpr int kRadixItems = 16;                // keys per thread per tile
+constexpr uint32_t kRadixTile = kRadixThreads * kRadixItems;  // 4096 keys per tile
+constexpr uint32_t kRleTile = 4096;            // elements per run-detection tile
+constexpr uint32_t kGuardChunk = 16384;        // elements per first-occurrence chunk
+
+enum Path : int32_t { P_MONOTONE = 0, P_SMALL_N = 1, P_TINY = 2, P_HIGH_K = 3, P_MAIN = 4, P_GUARD = 5 };
+enum Engine : uint32_t { E_NONE = 0, E_TINY = 1, E_HASH = 2, E_RADIX = 3 };
+
+// Look-back status word of the radix passes: two flag bits over a 62-bit value.
+constexpr uint64_t kStatAgg = 1ull << 62;
+constexpr uint64_t kStatInc = 2ull << 62;
+constexpr uint64_t kStatMask = (1ull << 62) - 1;
+
+// One LSD radix job (the fallback sort of the keys, or the sort of the distinct
+// (key, count) pairs when K is too large for the single-workgroup order kernel).
+struct RadixJob {
+    const uint64_t* src_k;
+    const uint64_t* src_v;
+    uint64_t* dst_k;
+    uint64_t* dst_v;
+    uint64_t* tmp_k;
+    uint64_t* tmp_v;
+    uint64_t n;
+    uint32_t has_vals;
+    uint32_t n_active;                // passes whose digit is not constant
+    uint32_t digit[8];                // digit index of each active pass, in order
+    const uint64_t* ps_k[8];          // source of active pass i
+    const uint64_t* ps_v[8];
+    uint64_t* pd_k[8];                // destination of active pass i
+    uint64_t* pd_v[8];
+    uint32_t copy_mode;               // after the passes: 0 nothing, 1 copy src->dst, 2 tmp->dst
+    uint32_t pad;
+};
+
+// Decisions and counters of one call, in device memory (workspace).
+struct Ctrl {
+    // monotone check
+    uint32_t inversion;
+    uint32_t mono_full;               // the full order check is still needed
+    // Chao1 estimate
+    uint64_t k_hat, u, f1, f2, n_samples, stride;
+    uint32_t saturated;
+    uint32_t n_tiny;                  // distinct sampled keys kept for the tiny branch (<= 8)
+    uint64_t tiny_keys[8];            // sorted in the dtype's order
+    // plan
+    int32_t path;
+    uint32_t engine;
+    uint32_t tiny_miss;
+    uint32_t flags;                   // report flags
+    uint64_t table_M;                 // Eq. Msize
+    uint32_t cap_log2;                // GPU global table size (log2 slots)
+    uint32_t cap_limit;               // claimed slots allowed before overflow
+    // tiny count
+    uint64_t tiny_cnt[8];
+    // hash count
+    uint32_t overflow;
+    uint32_t claimed;
+    uint64_t ecount;                  // elements equal to kEmpty
+    // dense (key, count) arrays
+    uint64_t K;
+    uint32_t dense_ready;
+    uint32_t pair_sort;
+    uint32_t radix_on;
+    uint32_t guard_on;
+    // radix
+    RadixJob rj;
+    uint64_t hist[8][256];
+    uint32_t hist_done;
+    uint32_t tile_ctr[8];
+    // run-length pass over a sorted column
+    uint32_t rle_done;
+    uint32_t rle_on;
+    // guard
+    uint64_t n_contested;
+    uint64_t found;
+    uint32_t chunk_ctr;
+    uint32_t guard_done;
+    uint64_t spill;
+};
+
+// Everything a kernel needs to know about the call; passed by value.
+struct Args {
+    const uint64_t* in;
+    uint64_t* out;
+    uint64_t n;
+    uint64_t flip;                    // 1<<63 for int64 (signed order), 0 for uint64
+    uint32_t in_head;                 // 1 if in is 8- but not 16-byte aligned
+    uint32_t out_head;
+    uint32_t want_report;
+    uint32_t want_counts;
+    cafs_report_t* report;
+    Ctrl* c;
+    // dense arrays (capacity n): user arrays when given, else workspace
+    uint64_t* uniq;
+    uint64_t* cnt;
+    uint64_t* off;                    // n + 1 entries
+    // GPU hash table
+    uint64_t* gkeys;
+    uint64_t* gcnt;
+    uint32_t* claimed;
+    uint32_t cap_ws_log2;             // largest table the workspace holds
+    // unsorted pairs for the pair sort
+    uint64_t* pk;
+    uint64_t* pv;
+    // radix scratch
+    uint64_t* tmp_k;
+    uint64_t* tmp_v;
+    uint64_t* status;                 // 2 slots of status_slot words
+    uint64_t status_slot;
+    // guard scratch
+    uint32_t* dcount;                 // m_ws entries
+    uint32_t* bmin;                   // 4 * m_ws entries
+    uint32_t* first_idx;              // n entries
+    uint64_t m_ws;
+    // run-length scratch
+    uint64_t* rle_tile;               // per-tile run counts
+};
+
+// ---- helpers ---------------------------------------------------------------
+
+// Multiplicative hash of Eq. hash: top `bits` bits of x * phi mod 2^64.
+__device__ __forceinline__ uint32_t phi_hash(uint64_t x, uint32_t bits) {
+    return (uint32_t)((x * kPhi) >> (64 - bits));
+}
+
+__device__ __forceinline__ uint64_t bit_ceil64(uint64_t v) {
+    if (v <= 1) return 1;
+    return 1ull << (64 - __clzll(v - 1));
+}
+
+__device__ __forceinline__ uint32_t log2_pow2(uint64_t p) { return 63 - __clzll(p); }
+
+template <class T>
+__device__ __forceinline__ T atomic_load_agent(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void atomic_store_agent(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Sum over the wave (64 lanes).
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Exclusive prefix sum over a workgroup of `nthreads` (multiple of 64) threads.
+// `scratch` holds one entry per wave.  Returns the exclusive prefix; *total gets
+// the sum over the workgroup.  Must be called by every thread.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* scratch, T* total) {
+    const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = (blockDim.x + 63) >> 6;
+    T incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        T t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) scratch[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            T t = scratch[w];
+            scratch[w] = run;
+            run += t;
+        }
+        scratch[nwaves] = run;
+    }
+    __syncthreads();
+    T res = scratch[wave] + incl - v;
+    *total = scratch[nwaves];
+    __syncthreads();
+    return res;
+}
+
+}  // namespace cafs

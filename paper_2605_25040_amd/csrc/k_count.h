@@ -1,0 +1,351 @@
+// Count stage: tiny count, hash count, compaction and order of the distinct keys.
+#pragma once
+#include "cafs_dev.h"
+
+namespace cafs {
+
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+// The column is walked in 16-byte "pairs".  When the base pointer is 8- but not
+// 16-byte aligned (head = 1), pair 0 holds only element 0 and pair p >= 1 holds
+// elements 2p-1 and 2p, which start on a 16-byte boundary.
+__device__ __forceinline__ uint64_t num_pairs(uint64_t n, uint32_t head) { return (n + head + 1) / 2; }
+
+__device__ __forceinline__ void load_pair(const uint64_t* __restrict__ x, uint64_t n, uint32_t head,
+                                          uint64_t p, uint64_t& v0, uint64_t& v1, bool& ok0, bool& ok1) {
+    const int64_t e0 = (int64_t)(2 * p) - (int64_t)head;
+    ok0 = e0 >= 0 && (uint64_t)e0 < n;
+    ok1 = (uint64_t)(e0 + 1) < n;
+    if (ok0 && ok1) {
+        const u64x2 w = *reinterpret_cast<const u64x2*>(x + e0);
+        v0 = w.x;
+        v1 = w.y;
+    } else {
+        v0 = ok0 ? x[e0] : 0;
+        v1 = ok1 ? x[e0 + 1] : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Phase 2: initialise the global table (tiny and hash engines) and run the
+// tiny count (Sec. 4.4): one counter per sampled key, every element compared
+// with every key.  The GPU form of the paper's eight branchless counters is a
+// wave ballot: v_cmp_eq_u64 gives a 64-lane mask per key whose population count
+// is added to a wave-uniform (scalar) counter.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_phase2(Args a) {
+    Ctrl* c = a.c;
+    const uint32_t engine = c->engine;
+    if (engine != E_TINY && engine != E_HASH) return;
+    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t cap = 1ull << c->cap_log2;
+    for (uint64_t i = gtid; i < cap; i += gstride) {
+        a.gkeys[i] = kEmpty;
+        a.gcnt[i] = 0;
+    }
+    if (engine != E_TINY) return;
+    const uint32_t nk = c->n_tiny;
+    uint64_t key[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) key[j] = c->tiny_keys[j];
+    uint64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint64_t P = num_pairs(a.n, a.in_head);
+    // every lane of a wave iterates the same number of times so that ballots see the wave
+    const uint64_t waves_total = gstride / 64;
+    const uint64_t wave_id = gtid / 64;
+    const uint32_t lane = __lane_id();
+    for (uint64_t pb = wave_id * 64; pb < P; pb += waves_total * 64) {
+        const uint64_t p = pb + lane;
+        uint64_t v0 = 0, v1 = 0;
+        bool ok0 = false, ok1 = false;
+        if (p < P) load_pair(a.in, a.n, a.in_head, p, v0, v1, ok0, ok1);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (j < (int)nk) {
+                cnt[j] += __popcll(__ballot(ok0 && v0 == key[j]));
+                cnt[j] += __popcll(__ballot(ok1 && v1 == key[j]));
+            }
+        }
+    }
+    if (lane == 0) {
+        for (uint32_t j = 0; j < nk; ++j)
+            if (cnt[j]) atomicAdd((unsigned long long*)&c->tiny_cnt[j], (unsigned long long)cnt[j]);
+    }
+}
+
+__device__ __noinline__ void set_overflow(Ctrl* c) {
+    if (atomicExch(&c->overflow, 1u) == 0) {
+        atomicExch(&c->radix_on, 1u);
+        atomicExch(&c->guard_on, 1u);
+        atomicOr(&c->flags, 1u);
+    }
+}
+
+// Insert (v, cnt) into the global open-addressing table (linear probing, Eq. hash
+// slot).  A slot is claimed by CAS from kEmpty and never freed, so a key is either
+// in the table or (after an overflow) the whole table is abandoned for the radix
+// engine.  Claimed slots are listed so that compaction reads K entries, not the table.
+__device__ void global_insert(const Args& a, Ctrl* c, uint64_t v, uint64_t cnt) {
+    if (atomic_load_agent(&c->overflow)) return;
+    const uint32_t lg = c->cap_log2;
+    const uint64_t mask = (1ull << lg) - 1;
+    uint64_t h = phi_hash(v, lg);
+    for (uint32_t pr = 0; pr < kGlobalProbe; ++pr) {
+        uint64_t k = atomic_load_agent(&a.gkeys[h]);
+        if (k == kEmpty) {
+            const unsigned long long old =
+                atomicCAS((unsigned long long*)&a.gkeys[h], (unsigned long long)kEmpty, (unsigned long long)v);
+            if (old == kEmpty) {
+                const uint32_t idx = atomicAdd(&c->claimed, 1u);
+                if (idx >= c->cap_limit) { set_overflow(c); return; }
+                a.claimed[idx] = (uint32_t)h;
+                atomicAdd((unsigned long long*)&a.gcnt[h], (unsigned long long)cnt);
+                return;
+            }
+            k = old;
+        }
+        if (k == v) {
+            atomicAdd((unsigned long long*)&a.gcnt[h], (unsigned long long)cnt);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+    set_overflow(c);
+}
+
+// ---------------------------------------------------------------------------
+// Hash count (main path, Sec. 4.4).  The paper's x86 hot loop updates one
+// cache-line bucket per element.  Here each workgroup owns an open-addressing
+// table of 8192 (key, count) slots in LDS; an element hashes to a slot (Eq. hash),
+// probes linearly, claims an empty slot with a 64-bit LDS CAS and adds 1 with an
+// LDS atomic.  Keys that find no LDS slot within the probe limit go straight to
+// the global table.  At the end each workgroup flushes its occupied slots to the
+// global table.  Elements equal to the empty marker are counted in registers.
+//
+// This kernel also resolves the tiny branch: if the tiny counters sum to N the
+// column is tiny and the dense arrays are written here; otherwise the element set
+// has an unsampled value and the main path runs with the same estimate (Sec. 4.4).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
+    Ctrl* c = a.c;
+    const uint32_t engine = c->engine;
+    if (engine == E_TINY) {
+        const uint32_t nk = c->n_tiny;
+        uint64_t tot = 0;
+        for (uint32_t j = 0; j < nk; ++j) tot += c->tiny_cnt[j];
+        if (tot == a.n) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                uint64_t run = 0;
+                for (uint32_t j = 0; j < nk; ++j) {
+                    a.uniq[j] = c->tiny_keys[j];
+                    a.cnt[j] = c->tiny_cnt[j];
+                    a.off[j] = run;
+                    run += c->tiny_cnt[j];
+                }
+                a.off[nk] = run;
+                c->K = nk;
+                c->dense_ready = 1;
+            }
+            return;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            c->tiny_miss = 1;
+            c->path = P_MAIN;
+            c->engine = E_HASH;
+        }
+    } else if (engine != E_HASH) {
+        return;
+    }
+
+    constexpr uint32_t S = 1u << kLdsSlotsLog2;
+    __shared__ uint64_t skeys[S];
+    __shared__ uint32_t scnt[S];
+    for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
+        skeys[i] = kEmpty;
+        scnt[i] = 0;
+    }
+    __syncthreads();
+
+    uint32_t ecnt = 0;
+    const uint64_t P = num_pairs(a.n, a.in_head);
+    constexpr int U = 4;  // pairs per thread per step (loads in flight)
+    const uint64_t step = (uint64_t)gridDim.x * blockDim.x * U;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x * U; base < P; base += step) {
+        uint64_t v[2 * U];
+        bool ok[2 * U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t p = base + (uint64_t)u * blockDim.x + threadIdx.x;
+            v[2 * u] = v[2 * u + 1] = 0;
+            ok[2 * u] = ok[2 * u + 1] = false;
+            if (p < P) load_pair(a.in, a.n, a.in_head, p, v[2 * u], v[2 * u + 1], ok[2 * u], ok[2 * u + 1]);
+        }
+#pragma unroll
+        for (int e = 0; e < 2 * U; ++e) {
+            if (!ok[e]) continue;
+            const uint64_t x = v[e];
+            if (x == kEmpty) { ++ecnt; continue; }
+            uint32_t h = phi_hash(x, kLdsSlotsLog2);
+            bool done = false;
+            for (uint32_t pr = 0; pr < kLdsProbe; ++pr) {
+                const uint64_t k = skeys[h];
+                if (k == x) { atomicAdd(&scnt[h], 1u); done = true; break; }
+                if (k == kEmpty) {
+                    const unsigned long long old = atomicCAS((unsigned long long*)&skeys[h],
+                                                             (unsigned long long)kEmpty, (unsigned long long)x);
+                    if (old == kEmpty || old == x) { atomicAdd(&scnt[h], 1u); done = true; break; }
+                }
+                h = (h + 1) & (S - 1);
+            }
+            if (!done) global_insert(a, c, x, 1);
+        }
+    }
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < S; s += blockDim.x) {
+        const uint32_t cn = scnt[s];
+        if (cn) global_insert(a, c, skeys[s], cn);
+    }
+    const uint32_t wsum = wave_sum_u32(ecnt);
+    if (__lane_id() == 0 && wsum) atomicAdd((unsigned long long*)&c->ecount, (unsigned long long)wsum);
+}
+
+// ---------------------------------------------------------------------------
+// Compaction and order (Alg. 4, steps "collect non-empty bucket slots", "sort
+// pairs by key").  One workgroup.  For K <= 8192 the (key, count) pairs are
+// sorted in LDS by a bitonic network and their counts scanned into run offsets;
+// larger K goes to the radix engine in pair mode.  With the sorted pairs at hand
+// this kernel also checks the spill guard's buckets: if no bucket of the paper's
+// table (M buckets, Eq. hash) receives more than 4 distinct keys, nothing spills
+// (Alg. 1) and the guard is settled here.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_compact_order(Args a) {
+    Ctrl* c = a.c;
+    if (c->engine != E_HASH || c->overflow || c->dense_ready) return;
+    const uint32_t claimed = c->claimed;
+    const uint64_t ecount = c->ecount;
+    const uint32_t K = claimed + (ecount > 0 ? 1u : 0u);
+    const uint64_t flip = a.flip;
+    const uint32_t tid = threadIdx.x;
+    if (K > kOrderMax) {
+        for (uint32_t i = tid; i < claimed; i += blockDim.x) {
+            const uint32_t h = a.claimed[i];
+            a.pk[i] = a.gkeys[h];
+            a.pv[i] = a.gcnt[h];
+        }
+        if (tid == 0) {
+            if (ecount) { a.pk[claimed] = kEmpty; a.pv[claimed] = ecount; }
+            RadixJob& j = c->rj;
+            j.src_k = a.pk; j.src_v = a.pv;
+            j.dst_k = a.uniq; j.dst_v = a.cnt;
+            j.tmp_k = a.tmp_k; j.tmp_v = a.tmp_v;
+            j.n = K;
+            j.has_vals = 1;
+            c->K = K;
+            c->pair_sort = 1;
+            c->radix_on = 1;
+            c->guard_on = 1;
+        }
+        return;
+    }
+    __shared__ uint64_t sk[kOrderMax];
+    __shared__ uint64_t sv[kOrderMax];
+    __shared__ uint64_t scan_tmp[17];
+    uint32_t P = 64;
+    while (P < K) P <<= 1;
+    for (uint32_t i = tid; i < P; i += blockDim.x) {
+        if (i < claimed) {
+            const uint32_t h = a.claimed[i];
+            sk[i] = a.gkeys[h] ^ flip;
+            sv[i] = a.gcnt[h];
+        } else if (i < K) {
+            sk[i] = kEmpty ^ flip;
+            sv[i] = ecount;
+        } else {
+            sk[i] = ~0ull;  // padding sorts last: ties with a real key are broken by count 0
+            sv[i] = 0;
+        }
+    }
+    __syncthreads();
+    // bitonic sort of (key, count) by key ascending; equal keys only occur between a
+    // real key and padding, and the real key (count >= 1) goes first
+    for (uint32_t kk = 2; kk <= P; kk <<= 1) {
+        for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (uint32_t i = tid; i < P; i += blockDim.x) {
+                const uint32_t l = i ^ jj;
+                if (l > i) {
+                    const uint64_t ki = sk[i], kl = sk[l];
+                    const uint64_t vi = sv[i], vl = sv[l];
+                    const bool i_gt = (ki > kl) || (ki == kl && vi < vl);
+                    const bool up = (i & kk) == 0;
+                    if (up == i_gt) {
+                        sk[i] = kl; sk[l] = ki;
+                        sv[i] = vl; sv[l] = vi;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // exclusive scan of the counts -> run offsets; each thread takes a contiguous chunk
+    const uint32_t per = (K + blockDim.x - 1) / blockDim.x;
+    const uint32_t b0 = tid * per < K ? tid * per : K;
+    const uint32_t b1 = b0 + per < K ? b0 + per : K;
+    uint64_t local = 0;
+    for (uint32_t i = b0; i < b1; ++i) local += sv[i];
+    uint64_t total;
+    uint64_t run = block_exclusive_scan<uint64_t>(local, scan_tmp, &total);
+    for (uint32_t i = b0; i < b1; ++i) {
+        a.uniq[i] = sk[i] ^ flip;
+        a.cnt[i] = sv[i];
+        a.off[i] = run;
+        run += sv[i];
+    }
+    if (tid == 0) {
+        a.off[K] = total;
+        c->K = K;
+        c->dense_ready = 1;
+    }
+    // guard check on the paper's M buckets (main path only)
+    if (c->path != P_MAIN) return;
+    const uint64_t M = c->table_M;
+    if (M > kGuardLdsBuckets) {
+        if (tid == 0) c->guard_on = 1;
+        return;
+    }
+    __syncthreads();
+    uint32_t* bc = reinterpret_cast<uint32_t*>(sv);  // reuse: M <= 16384 u32 counters
+    const uint32_t lg = log2_pow2(M);
+    for (uint32_t i = tid; i < M; i += blockDim.x) bc[i] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < K; i += blockDim.x) atomicAdd(&bc[phi_hash(sk[i] ^ flip, lg)], 1u);
+    __syncthreads();
+    uint32_t over = 0;
+    for (uint32_t i = tid; i < M; i += blockDim.x) over |= bc[i] > kBucketCap;
+    if (__any(over) && __lane_id() == 0) c->guard_on = 1;  // a bucket spills: resolve exactly later
+}
+
+// Exclusive scan of the sorted counts after a pair sort (K > 8192).  One workgroup.
+__global__ __launch_bounds__(1024) void k_pair_scan(Args a) {
+    Ctrl* c = a.c;
+    if (!c->pair_sort || c->overflow) return;
+    __shared__ uint64_t scan_tmp[17];
+    const uint64_t K = c->K;
+    const uint64_t per = (K + blockDim.x - 1) / blockDim.x;
+    const uint64_t b0 = threadIdx.x * per < K ? threadIdx.x * per : K;
+    const uint64_t b1 = b0 + per < K ? b0 + per : K;
+    uint64_t local = 0;
+    for (uint64_t i = b0; i < b1; ++i) local += a.cnt[i];
+    uint64_t total;
+    uint64_t run = block_exclusive_scan<uint64_t>(local, scan_tmp, &total);
+    for (uint64_t i = b0; i < b1; ++i) {
+        a.off[i] = run;
+        run += a.cnt[i];
+    }
+    if (threadIdx.x == 0) {
+        a.off[K] = total;
+        c->dense_ready = 1;
+    }
+}
+
+}  // namespace cafs

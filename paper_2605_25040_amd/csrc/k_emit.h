@@ -1,0 +1,202 @@
+// Emit stage (Alg. 4: fill each key count times, in key order) and the run-length
+// pass that recovers (key, count) pairs from an already sorted column.
+#pragma once
+#include "cafs_dev.h"
+#include "k_count.h"
+
+namespace cafs {
+
+constexpr uint32_t kEmitPairsPerThread = 8;
+constexpr uint32_t kEmitThreads = 256;
+constexpr uint64_t kEmitTilePairs = (uint64_t)kEmitPairsPerThread * kEmitThreads;  // 2048 pairs
+constexpr uint32_t kEmitLdsRuns = 2048;
+
+// Largest j in [lo, hi] with off[j] <= e (off is nondecreasing, off[lo] <= e).
+template <typename OffT>
+__device__ __forceinline__ uint64_t run_of(const OffT* off, uint64_t lo, uint64_t hi, uint64_t e) {
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo + 1) / 2;
+        if ((uint64_t)off[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void store_pair(uint64_t* __restrict__ y, uint64_t n, uint32_t head, uint64_t p,
+                                           uint64_t v0, uint64_t v1) {
+    const int64_t e0 = (int64_t)(2 * p) - (int64_t)head;
+    const bool ok0 = e0 >= 0 && (uint64_t)e0 < n;
+    const bool ok1 = (uint64_t)(e0 + 1) < n;
+    if (ok0 && ok1) {
+        u64x2 w;
+        w.x = v0;
+        w.y = v1;
+        __builtin_nontemporal_store(w, reinterpret_cast<u64x2*>(y + e0));
+    } else {
+        if (ok0) y[e0] = v0;
+        if (ok1) y[e0 + 1] = v1;
+    }
+}
+
+// Output tiles of 4096 elements; each tile finds the runs it covers by binary
+// search in the run offsets.  A tile inside one run is a plain fill; otherwise the
+// tile's offsets and keys are staged in LDS and each element searches there.
+__global__ __launch_bounds__(kEmitThreads) void k_emit(Args a) {
+    Ctrl* c = a.c;
+    if (!c->dense_ready || c->overflow) return;
+    const uint64_t n = a.n;
+    const uint64_t K = c->K;
+    const uint32_t head = a.out_head;
+    const uint64_t P = num_pairs(n, head);
+    const uint64_t tiles = (P + kEmitTilePairs - 1) / kEmitTilePairs;
+    __shared__ uint64_t s_j0, s_j1;
+    __shared__ uint64_t s_off[kEmitLdsRuns + 1];
+    __shared__ uint64_t s_key[kEmitLdsRuns];
+    const uint64_t* __restrict__ off = a.off;
+    const uint64_t* __restrict__ uq = a.uniq;
+    for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint64_t p0 = t * kEmitTilePairs;
+        const uint64_t p1 = (p0 + kEmitTilePairs < P) ? p0 + kEmitTilePairs : P;
+        const int64_t e_lo_s = (int64_t)(2 * p0) - (int64_t)head;
+        const uint64_t e_lo = e_lo_s < 0 ? 0 : (uint64_t)e_lo_s;
+        const uint64_t e_hi = (2 * p1 - head < n) ? 2 * p1 - head : n;  // exclusive
+        if (threadIdx.x == 0) {
+            const uint64_t j0 = run_of(off, 0, K - 1, e_lo);
+            s_j0 = j0;
+            s_j1 = run_of(off, j0, K - 1, e_hi - 1);
+        }
+        __syncthreads();
+        const uint64_t j0 = s_j0, j1 = s_j1;
+        if (j0 == j1) {
+            const uint64_t v = uq[j0];
+            for (uint64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) store_pair(a.out, n, head, p, v, v);
+        } else if (j1 - j0 + 1 <= kEmitLdsRuns) {
+            const uint32_t R = (uint32_t)(j1 - j0 + 1);
+            for (uint32_t i = threadIdx.x; i <= R; i += blockDim.x) s_off[i] = off[j0 + i];
+            for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) s_key[i] = uq[j0 + i];
+            __syncthreads();
+            for (uint64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+                const int64_t e0s = (int64_t)(2 * p) - (int64_t)head;
+                const uint64_t e0 = e0s < 0 ? 0 : (uint64_t)e0s;
+                const uint64_t r0 = run_of(s_off, 0, R - 1, e0);
+                const uint64_t r1 = (r0 + 1 < R && s_off[r0 + 1] <= e0 + 1) ? r0 + 1 : r0;
+                store_pair(a.out, n, head, p, s_key[r0], s_key[r1]);
+            }
+        } else {
+            for (uint64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+                const int64_t e0s = (int64_t)(2 * p) - (int64_t)head;
+                const uint64_t e0 = e0s < 0 ? 0 : (uint64_t)e0s;
+                const uint64_t r0 = run_of(off, j0, j1, e0);
+                const uint64_t r1 = (r0 + 1 <= j1 && off[r0 + 1] <= e0 + 1) ? r0 + 1 : r0;
+                store_pair(a.out, n, head, p, uq[r0], uq[r1]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Monotone input: the output is the input.
+__global__ __launch_bounds__(256) void k_copy_mono(Args a) {
+    Ctrl* c = a.c;
+    if (c->path != P_MONOTONE || a.in == a.out) return;
+    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = gtid; i < a.n; i += gstride) a.out[i] = a.in[i];
+}
+
+// Run-length pass over the sorted output, needed when the column was not counted
+// (monotone input, radix engine) but the report, the counts or the guard need
+// the (key, count) pairs.
+__device__ __forceinline__ bool rle_needed(const Args& a, const Ctrl* c) {
+    if (c->dense_ready && !c->overflow) return false;
+    return a.want_report || a.want_counts || (c->path == P_MAIN);
+}
+
+// Pass 1: runs starting in each tile; the last workgroup scans the tile counts.
+__global__ __launch_bounds__(256) void k_rle_count(Args a) {
+    Ctrl* c = a.c;
+    if (!rle_needed(a, c)) return;
+    const uint64_t n = a.n;
+    const uint64_t* __restrict__ y = a.out;
+    const uint64_t tiles = (n + kRleTile - 1) / kRleTile;
+    __shared__ uint32_t s_cnt;
+    __shared__ uint32_t s_last;
+    __shared__ uint64_t scan_tmp[8];
+    for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        const uint64_t b = t * kRleTile;
+        const uint64_t e = (b + kRleTile < n) ? b + kRleTile : n;
+        uint32_t local = 0;
+        for (uint64_t i = b + threadIdx.x; i < e; i += blockDim.x) local += (i == 0) || (y[i] != y[i - 1]);
+        local = wave_sum_u32(local);
+        if (__lane_id() == 0) atomicAdd(&s_cnt, local);
+        __syncthreads();
+        if (threadIdx.x == 0) a.rle_tile[t] = s_cnt;
+        __syncthreads();
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(&c->rle_done, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    // exclusive scan of the tile counts (one workgroup, contiguous chunks per thread)
+    const uint64_t per = (tiles + blockDim.x - 1) / blockDim.x;
+    const uint64_t b0 = threadIdx.x * per < tiles ? threadIdx.x * per : tiles;
+    const uint64_t b1 = b0 + per < tiles ? b0 + per : tiles;
+    uint64_t local = 0;
+    for (uint64_t i = b0; i < b1; ++i) local += atomic_load_agent(&a.rle_tile[i]);
+    uint64_t total;
+    uint64_t run = block_exclusive_scan<uint64_t>(local, scan_tmp, &total);
+    for (uint64_t i = b0; i < b1; ++i) {
+        const uint64_t v = atomic_load_agent(&a.rle_tile[i]);
+        a.rle_tile[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) c->K = total;
+}
+
+// Pass 2: write each run's key and start position (its offset).
+__global__ __launch_bounds__(256) void k_rle_write(Args a) {
+    Ctrl* c = a.c;
+    if (!rle_needed(a, c)) return;
+    const uint64_t n = a.n;
+    const uint64_t* __restrict__ y = a.out;
+    const uint64_t tiles = (n + kRleTile - 1) / kRleTile;
+    constexpr uint32_t per = kRleTile / 256;  // contiguous elements per thread
+    __shared__ uint32_t scan_tmp[8];
+    for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint64_t b = t * kRleTile + (uint64_t)threadIdx.x * per;
+        uint32_t local = 0;
+        for (uint32_t k = 0; k < per; ++k) {
+            const uint64_t i = b + k;
+            if (i < n) local += (i == 0) || (y[i] != y[i - 1]);
+        }
+        uint32_t total;
+        uint32_t ex = block_exclusive_scan<uint32_t>(local, scan_tmp, &total);
+        uint64_t j = a.rle_tile[t] + ex;
+        for (uint32_t k = 0; k < per; ++k) {
+            const uint64_t i = b + k;
+            if (i < n && ((i == 0) || (y[i] != y[i - 1]))) {
+                if (j < n) {  // always true: there are at most n runs
+                    a.uniq[j] = y[i];
+                    a.off[j] = i;
+                }
+                ++j;
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.off[c->K] = n;
+}
+
+// Pass 3: counts from consecutive offsets; marks the pairs ready for the guard.
+__global__ __launch_bounds__(256) void k_rle_counts(Args a) {
+    Ctrl* c = a.c;
+    if (!rle_needed(a, c)) return;
+    const uint64_t K = c->K;
+    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t jj = gtid; jj < K; jj += gstride) a.cnt[jj] = a.off[jj + 1] - a.off[jj];
+}
+
+}  // namespace cafs

@@ -1,0 +1,260 @@
+// Estimate, order check, plan and report kernels.
+#pragma once
+#include "cafs_dev.h"
+
+namespace cafs {
+
+// Chao1 over strided samples (Sec. 4.3, Alg. 2, Eq. chao1), one workgroup.
+//   stride = max(1, floor(N/1024)), samples at 0, stride, ... below min(N, 1024*stride),
+//   i.e. min(N, 1024) samples; a 4096-slot open-addressing FreqSet in LDS counts them;
+//   u, f1, f2 are read from the slot counters; K^ = N when u = 1024, else
+//   u + floor(f1^2 / (2 (f2 + 1))).
+// The FreqSet uses kEmpty as its empty marker; samples equal to kEmpty are counted
+// in a separate LDS counter, which acts as one more slot.  When u <= 8 the distinct
+// sampled keys are returned too, sorted in the dtype's order (tiny branch).
+// Every thread must call it; thread 0's outputs are the results.
+struct Chao1Result {
+    uint64_t k_hat, u, f1, f2, n_samples, stride;
+    uint32_t saturated, n_small;
+    uint64_t small[8];
+};
+
+__device__ void chao1_block(const uint64_t* __restrict__ x, uint64_t n, uint64_t flip,
+                            Chao1Result* res) {
+    __shared__ uint64_t fkeys[1u << kFreqSlotsLog2];
+    __shared__ uint32_t fcnt[1u << kFreqSlotsLog2];
+    __shared__ uint32_t s_e, s_u, s_f1, s_f2, s_ns;
+    __shared__ uint64_t s_small[9];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t slots = 1u << kFreqSlotsLog2;
+    for (uint32_t i = tid; i < slots; i += blockDim.x) {
+        fkeys[i] = kEmpty;
+        fcnt[i] = 0;
+    }
+    if (tid == 0) { s_e = 0; s_u = 0; s_f1 = 0; s_f2 = 0; s_ns = 0; }
+    __syncthreads();
+    const uint64_t stride = n / kSamples > 1 ? n / kSamples : 1;
+    const uint64_t ns = n < kSamples ? n : kSamples;
+    for (uint64_t t = tid; t < ns; t += blockDim.x) {
+        const uint64_t v = x[t * stride];
+        if (v == kEmpty) {
+            atomicAdd(&s_e, 1u);
+            continue;
+        }
+        uint32_t h = phi_hash(v, kFreqSlotsLog2);
+        while (true) {
+            const uint64_t k = fkeys[h];
+            if (k == v) { atomicAdd(&fcnt[h], 1u); break; }
+            if (k == kEmpty) {
+                const unsigned long long old =
+                    atomicCAS((unsigned long long*)&fkeys[h], (unsigned long long)kEmpty,
+                              (unsigned long long)v);
+                if (old == kEmpty || old == v) { atomicAdd(&fcnt[h], 1u); break; }
+            }
+            h = (h + 1) & (slots - 1);
+        }
+    }
+    __syncthreads();
+    uint32_t lu = 0, l1 = 0, l2 = 0;
+    for (uint32_t i = tid; i < slots; i += blockDim.x) {
+        const uint32_t cn = fcnt[i];
+        lu += cn > 0;
+        l1 += cn == 1;
+        l2 += cn == 2;
+    }
+    lu = wave_sum_u32(lu); l1 = wave_sum_u32(l1); l2 = wave_sum_u32(l2);
+    if (__lane_id() == 0) {
+        atomicAdd(&s_u, lu); atomicAdd(&s_f1, l1); atomicAdd(&s_f2, l2);
+    }
+    __syncthreads();
+    uint32_t u = s_u + (s_e > 0);
+    if (u <= kTinyK) {
+        for (uint32_t i = tid; i < slots; i += blockDim.x)
+            if (fcnt[i] > 0) s_small[atomicAdd(&s_ns, 1u)] = fkeys[i];
+        __syncthreads();
+        if (tid == 0 && s_e > 0) s_small[s_ns++] = kEmpty;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const uint64_t f1 = s_f1 + (s_e == 1);
+        const uint64_t f2 = s_f2 + (s_e == 2);
+        res->u = u;
+        res->f1 = f1;
+        res->f2 = f2;
+        res->n_samples = ns;
+        res->stride = stride;
+        res->saturated = (u == kSamples);
+        res->k_hat = res->saturated ? n : u + (f1 * f1) / (2 * (f2 + 1));
+        uint32_t m = (u <= kTinyK) ? s_ns : 0;
+        // insertion sort of at most 8 keys in the dtype's order
+        for (uint32_t i = 0; i < m; ++i) {
+            uint64_t v = s_small[i];
+            uint32_t j = i;
+            while (j > 0 && (s_small[j - 1] ^ flip) > (v ^ flip)) { s_small[j] = s_small[j - 1]; --j; }
+            s_small[j] = v;
+        }
+        res->n_small = m;
+        for (uint32_t i = 0; i < m; ++i) res->small[i] = s_small[i];
+    }
+}
+
+// First kernel of a sort: order check of a prefix and the Chao1 estimate.
+__global__ __launch_bounds__(1024) void k_pre(Args a) {
+    Ctrl* c = a.c;
+    __shared__ uint32_t s_inv;
+    __shared__ Chao1Result s_res;
+    if (threadIdx.x == 0) s_inv = 0;
+    __syncthreads();
+    const uint64_t lim = a.n < kMonoPrefix ? a.n : kMonoPrefix;
+    uint32_t inv = 0;
+    for (uint64_t i = threadIdx.x; i + 1 < lim; i += blockDim.x)
+        inv |= (a.in[i] ^ a.flip) > (a.in[i + 1] ^ a.flip);
+    if (inv) s_inv = 1;
+    chao1_block(a.in, a.n, a.flip, &s_res);  // contains __syncthreads
+    if (threadIdx.x == 0) {
+        c->inversion = s_inv;
+        c->mono_full = (!s_inv && a.n > kMonoPrefix) ? 1u : 0u;
+        c->k_hat = s_res.k_hat; c->u = s_res.u; c->f1 = s_res.f1; c->f2 = s_res.f2;
+        c->n_samples = s_res.n_samples; c->stride = s_res.stride;
+        c->saturated = s_res.saturated;
+        c->n_tiny = s_res.n_small;
+        for (uint32_t i = 0; i < 8; ++i) c->tiny_keys[i] = i < s_res.n_small ? s_res.small[i] : 0;
+    }
+}
+
+// Standalone estimate (cafs_estimate).
+__global__ __launch_bounds__(1024) void k_estimate_only(const uint64_t* x, uint64_t n,
+                                                        cafs_estimate_t* out) {
+    __shared__ Chao1Result s_res;
+    chao1_block(x, n, 0, &s_res);
+    if (threadIdx.x == 0) {
+        cafs_estimate_t e;
+        e.k_hat = s_res.k_hat; e.u = s_res.u; e.f1 = s_res.f1; e.f2 = s_res.f2;
+        e.n_samples = s_res.n_samples; e.stride = s_res.stride;
+        e.saturated = s_res.saturated; e.pad = 0;
+        *out = e;
+    }
+}
+
+// Full order check, only when the prefix was in order (IsMonotone, Alg. 3).  Exits
+// early once any workgroup has found an inversion.
+__global__ __launch_bounds__(256) void k_mono_full(Args a) {
+    Ctrl* c = a.c;
+    if (!c->mono_full) return;
+    const uint64_t n = a.n;
+    const uint64_t chunk = 256 * 16;
+    for (uint64_t base = (uint64_t)blockIdx.x * chunk; base + 1 < n; base += (uint64_t)gridDim.x * chunk) {
+        if (atomic_load_agent(&c->inversion)) return;
+        uint32_t inv = 0;
+        const uint64_t end = (base + chunk < n - 1) ? base + chunk : n - 1;  // pairs (i, i+1), i < end
+        for (uint64_t i = base + threadIdx.x; i < end; i += 256)
+            inv |= (a.in[i] ^ a.flip) > (a.in[i + 1] ^ a.flip);
+        if (__any(inv) && __lane_id() == 0) atomicOr(&c->inversion, 1u);
+    }
+}
+
+// Eq. Msize with cap = 4: M = bit_ceil(8 K^ / 4) clamped to [8, bit_ceil(N / 4)].
+__device__ __forceinline__ uint64_t paper_table_M(uint64_t k_hat, uint64_t n) {
+    uint64_t m = bit_ceil64(8 * k_hat / kBucketCap);
+    const uint64_t hi = bit_ceil64(n / kBucketCap);
+    if (m > hi) m = hi;
+    if (m < 8) m = 8;
+    return m;
+}
+
+// Dispatcher (Alg. 3): picks the path and the engine and resets the counters
+// of the later stages.  One workgroup.
+__global__ __launch_bounds__(256) void k_plan(Args a) {
+    Ctrl* c = a.c;
+    const uint64_t n = a.n;
+    // reset counters (all threads)
+    for (uint32_t i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&c->hist[0][0])[i] = 0;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const bool mono = (n <= 1) || !c->inversion;
+    int32_t path;
+    uint32_t engine;
+    if (mono) { path = P_MONOTONE; engine = E_NONE; }
+    else if (n < kSmallN) { path = P_SMALL_N; engine = E_RADIX; }
+    else if (c->k_hat <= kTinyK && c->u <= kTinyK) { path = P_TINY; engine = E_TINY; }
+    else if (2 * c->k_hat > n) { path = P_HIGH_K; engine = E_RADIX; }
+    else { path = P_MAIN; engine = E_HASH; }
+    c->table_M = 0;
+    c->cap_log2 = kMinTableLog2;
+    if (path == P_TINY || path == P_MAIN) {
+        c->table_M = paper_table_M(c->k_hat, n);
+        uint32_t lg = log2_pow2(bit_ceil64(8 * c->k_hat));
+        if (lg < kMinTableLog2) lg = kMinTableLog2;
+        if (lg > a.cap_ws_log2) {
+            engine = E_RADIX;  // the table the estimate asks for does not fit: sort instead
+            lg = a.cap_ws_log2;
+        }
+        c->cap_log2 = lg;
+    }
+    const uint64_t cap = 1ull << c->cap_log2;
+    c->cap_limit = (uint32_t)(cap - cap / 8);
+    c->path = path;
+    c->engine = engine;
+    c->tiny_miss = 0;
+    c->flags = 0;
+    for (int j = 0; j < 8; ++j) { c->tiny_cnt[j] = 0; c->tile_ctr[j] = 0; }
+    c->overflow = 0;
+    c->claimed = 0;
+    c->ecount = 0;
+    c->K = 0;
+    c->dense_ready = 0;
+    c->pair_sort = 0;
+    c->radix_on = (engine == E_RADIX);
+    c->guard_on = (path == P_MAIN && engine == E_RADIX);
+    c->hist_done = 0;
+    c->rle_done = 0;
+    c->rle_on = 0;
+    c->n_contested = 0;
+    c->found = 0;
+    c->chunk_ctr = 0;
+    c->guard_done = 0;
+    c->spill = 0;
+    RadixJob& j = c->rj;
+    j.src_k = a.in; j.src_v = nullptr;
+    j.dst_k = a.out; j.dst_v = nullptr;
+    j.tmp_k = a.tmp_k; j.tmp_v = nullptr;
+    j.n = n;
+    j.has_vals = 0;
+    j.n_active = 0;
+    j.copy_mode = 0;
+}
+
+// Writes the caller's report.  One thread.
+__global__ void k_finalize(Args a) {
+    if (threadIdx.x != 0 || !a.want_report) return;
+    const Ctrl* c = a.c;
+    cafs_report_t r;
+    const bool sampled = !(c->path == P_MONOTONE || c->path == P_SMALL_N);
+    r.est.k_hat = sampled ? c->k_hat : 0;
+    r.est.u = sampled ? c->u : 0;
+    r.est.f1 = sampled ? c->f1 : 0;
+    r.est.f2 = sampled ? c->f2 : 0;
+    r.est.n_samples = sampled ? c->n_samples : 0;
+    r.est.stride = sampled ? c->stride : 0;
+    r.est.saturated = sampled ? c->saturated : 0;
+    r.est.pad = 0;
+    r.path = c->path;
+    r.tiny_miss = (int32_t)c->tiny_miss;
+    const bool main_path = (c->path == P_MAIN || c->path == P_GUARD);
+    r.table_M = main_path ? c->table_M : 0;
+    r.spill_elems = main_path ? c->spill : 0;
+    r.k_exact = c->K;
+    r.engine = c->engine;
+    r.flags = c->flags;
+    *a.report = r;
+}
+
+// Report of an empty column (n = 0): path MONOTONE, everything else zero.
+__global__ void k_report_empty(cafs_report_t* r) {
+    if (threadIdx.x != 0) return;
+    cafs_report_t z = {};
+    z.path = P_MONOTONE;
+    *r = z;
+}
+
+}  // namespace cafs

@@ -1,0 +1,284 @@
+// LSD radix sort with 8-bit digits (the fallback engine of the dispatcher, and the
+// sort of the distinct (key, count) pairs when K is large).
+//
+// Structure (after Adinets and Merrill's single-pass "onesweep" radix sort):
+//   k_radix_hist   one read of the keys builds the histograms of all eight digits;
+//                  the last workgroup to finish scans them into digit bases and
+//                  plans the passes, skipping digits on which every key agrees.
+//   k_radix_pass   one launch per active digit.  Tiles of 4096 keys are claimed in
+//                  order from an atomic counter; each tile ranks its keys stably
+//                  per wave (8-ballot match), publishes its digit counts, finds
+//                  its global offsets by decoupled look-back over the tiles before
+//                  it, reorders the tile in LDS by digit and writes it out in
+//                  runs.  Claiming tiles in order means a tile only ever waits for
+//                  tiles already held by running workgroups.
+//   k_radix_copy   final copy when the passes end in the scratch buffer.
+// Signed keys (int64) are ordered by flipping bit 63 in the digit extraction.
+#pragma once
+#include "cafs_dev.h"
+
+namespace cafs {
+
+__device__ __forceinline__ uint32_t digit_of(uint64_t key, uint64_t flip, uint32_t d) {
+    return (uint32_t)(((key ^ flip) >> (8 * d)) & 255u);
+}
+
+__global__ __launch_bounds__(256) void k_radix_hist(Args a) {
+    Ctrl* c = a.c;
+    if (!c->radix_on) return;
+    const RadixJob& j = c->rj;
+    const uint64_t n = j.n;
+    const uint64_t* __restrict__ src = j.src_k;
+    const uint64_t flip = a.flip;
+    __shared__ uint32_t lh[8][256];
+    __shared__ uint32_t s_last;
+    for (uint32_t i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&lh[0][0])[i] = 0;
+    // clear the look-back status words of the first pass
+    const uint64_t tiles = (n + kRadixTile - 1) / kRadixTile;
+    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = gtid; i < tiles * 256; i += gstride) a.status[i] = 0;
+    __syncthreads();
+    const uint32_t lane = __lane_id();
+    const uint64_t iters = (n + gstride - 1) / gstride;
+    for (uint64_t it = 0; it < iters; ++it) {
+        const uint64_t i = it * gstride + gtid;
+        const bool ok = i < n;
+        const uint64_t v = ok ? src[i] : 0;
+        const uint64_t act = __ballot(ok);
+        if (act == 0) continue;
+        for (uint32_t d = 0; d < 8; ++d) {
+            const uint32_t dg = digit_of(v, flip, d);
+            const uint32_t first = __shfl(dg, (int)(__ffsll((unsigned long long)act) - 1), 64);
+            const uint64_t same = __ballot(ok && dg == first);
+            if (same == act) {
+                // wave-uniform digit: one atomic for the wave (skewed and low-K data)
+                if (lane == (uint32_t)(__ffsll((unsigned long long)act) - 1))
+                    atomicAdd(&lh[d][dg], (uint32_t)__popcll(act));
+            } else if (ok) {
+                atomicAdd(&lh[d][dg], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < 8 * 256; i += blockDim.x) {
+        const uint32_t h = (&lh[0][0])[i];
+        if (h) atomicAdd((unsigned long long*)&(&c->hist[0][0])[i], (unsigned long long)h);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(&c->hist_done, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    // last workgroup: digit bases (exclusive scans) and the pass plan
+    __shared__ uint32_t s_active[8];
+    if (threadIdx.x < 8) {
+        const uint32_t d = threadIdx.x;
+        uint64_t run = 0;
+        bool constant = false;
+        for (uint32_t b = 0; b < 256; ++b) {
+            const uint64_t h = atomic_load_agent(&c->hist[d][b]);
+            if (h == n) constant = true;
+            c->hist[d][b] = run;
+            run += h;
+        }
+        s_active[d] = (!constant && n > 0) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        RadixJob& jw = c->rj;
+        uint32_t np = 0;
+        for (uint32_t d = 0; d < 8; ++d)
+            if (s_active[d]) jw.digit[np++] = d;
+        jw.n_active = np;
+        const bool inplace = (jw.src_k == jw.dst_k);
+        // ping-pong so that the last pass lands in dst; when sorting in place with an
+        // odd number of passes the first pass must not write dst, so all passes shift
+        // by one and a final copy moves the result from tmp to dst
+        const uint32_t shift = (inplace && (np & 1u)) ? 1u : 0u;
+        const uint64_t* ck = jw.src_k;
+        const uint64_t* cv = jw.src_v;
+        for (uint32_t i = 0; i < np; ++i) {
+            const bool to_dst = ((np - 1 - i + shift) % 2) == 0;
+            jw.ps_k[i] = ck; jw.ps_v[i] = cv;
+            jw.pd_k[i] = to_dst ? jw.dst_k : jw.tmp_k;
+            jw.pd_v[i] = to_dst ? jw.dst_v : jw.tmp_v;
+            ck = jw.pd_k[i]; cv = jw.pd_v[i];
+        }
+        if (np == 0) jw.copy_mode = inplace ? 0u : 1u;
+        else jw.copy_mode = shift ? 2u : 0u;
+    }
+}
+
+// Stable match of equal 8-bit digits across the wave: the lanes (within `act`)
+// whose digit equals this lane's digit.
+__device__ __forceinline__ uint64_t match_digit(uint32_t dg, uint64_t act) {
+    uint64_t peers = act;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (dg >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+__global__ __launch_bounds__(kRadixThreads) void k_radix_pass(Args a, uint32_t pass) {
+    Ctrl* c = a.c;
+    if (!c->radix_on) return;
+    const RadixJob& j = c->rj;
+    if (pass >= j.n_active) return;
+    const uint64_t n = j.n;
+    const uint32_t d = j.digit[pass];
+    const uint64_t flip = a.flip;
+    const bool vals = j.has_vals != 0;
+    const uint64_t* __restrict__ sk = j.ps_k[pass];
+    const uint64_t* __restrict__ sv = j.ps_v[pass];
+    uint64_t* __restrict__ dk = j.pd_k[pass];
+    uint64_t* __restrict__ dv = j.pd_v[pass];
+    const uint64_t tiles = (n + kRadixTile - 1) / kRadixTile;
+    uint64_t* status = a.status + (pass & 1u) * a.status_slot;
+    uint64_t* status_next = a.status + ((pass + 1) & 1u) * a.status_slot;
+    const uint64_t* bases = c->hist[d];
+
+    __shared__ uint64_t lk[kRadixTile];
+    __shared__ uint64_t lv[kRadixTile];
+    __shared__ uint32_t wcnt[kRadixThreads / 64][256];
+    __shared__ uint32_t tcount[256];
+    __shared__ uint32_t toff[256];
+    __shared__ uint64_t gofs[256];
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t scan_tmp[8];
+
+    // clear the status words the next pass will use (the previous pass is done with them)
+    {
+        const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+        if (pass + 1 < j.n_active)
+            for (uint64_t i = gtid; i < tiles * 256; i += gstride) status_next[i] = 0;
+    }
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = __lane_id();
+    const uint32_t wave = tid >> 6;
+    const uint64_t lt_mask = (1ull << lane) - 1;
+
+    while (true) {
+        if (tid == 0) s_tile = atomicAdd(&c->tile_ctr[pass], 1u);
+        for (uint32_t i = tid; i < (kRadixThreads / 64) * 256; i += blockDim.x) (&wcnt[0][0])[i] = 0;
+        __syncthreads();
+        const uint64_t t = s_tile;
+        if (t >= tiles) break;
+        const uint64_t base = t * kRadixTile;
+        // load: wave w owns positions base + w*1024 + i*64 + lane, i = 0..15 (in order)
+        uint64_t key[kRadixItems];
+        uint64_t val[kRadixItems];
+        uint16_t rank[kRadixItems];
+        uint32_t dig[kRadixItems];
+#pragma unroll
+        for (int i = 0; i < kRadixItems; ++i) {
+            const uint64_t pos = base + (uint64_t)wave * (64 * kRadixItems) + (uint64_t)i * 64 + lane;
+            const bool ok = pos < n;
+            key[i] = ok ? sk[pos] : 0;
+            val[i] = (ok && vals) ? sv[pos] : 0;
+            dig[i] = ok ? digit_of(key[i], flip, d) : 256u;
+        }
+        // stable rank within the wave, item by item
+#pragma unroll
+        for (int i = 0; i < kRadixItems; ++i) {
+            const bool ok = dig[i] < 256u;
+            const uint64_t act = __ballot(ok);
+            const uint64_t peers = match_digit(dig[i] & 255u, act);
+            uint32_t before = 0;
+            if (ok) before = wcnt[wave][dig[i]];
+            rank[i] = (uint16_t)(before + __popcll(peers & lt_mask));
+            const bool leader = ok && ((peers & lt_mask) == 0);
+            if (leader) wcnt[wave][dig[i]] = before + (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+        // per digit: tile total and per-wave exclusive prefix
+        {
+            const uint32_t dd = tid;  // 256 threads, one digit each
+            uint32_t run = 0;
+#pragma unroll
+            for (int w = 0; w < kRadixThreads / 64; ++w) {
+                const uint32_t cw = wcnt[w][dd];
+                wcnt[w][dd] = run;
+                run += cw;
+            }
+            tcount[dd] = run;
+            // publish this tile's aggregate, then look back for the exclusive prefix
+            uint64_t* st = status + t * 256 + dd;
+            uint64_t excl = 0;
+            if (t == 0) {
+                atomic_store_agent(st, kStatInc | (uint64_t)run);
+            } else {
+                atomic_store_agent(st, kStatAgg | (uint64_t)run);
+                uint64_t tt = t - 1;
+                while (true) {
+                    const uint64_t* sp = status + tt * 256 + dd;
+                    uint64_t s = atomic_load_agent(sp);
+                    while ((s & (kStatAgg | kStatInc)) == 0) {
+                        __builtin_amdgcn_s_sleep(1);
+                        s = atomic_load_agent(sp);
+                    }
+                    excl += s & kStatMask;
+                    if (s & kStatInc) break;
+                    --tt;
+                }
+                atomic_store_agent(st, kStatInc | (excl + run));
+            }
+            gofs[dd] = bases[dd] + excl;
+        }
+        // tile-local digit offsets
+        {
+            uint32_t total;
+            const uint32_t ex = block_exclusive_scan<uint32_t>(tcount[tid], scan_tmp, &total);
+            toff[tid] = ex;
+            __syncthreads();
+            gofs[tid] -= ex;  // global position = gofs[digit] + local position
+        }
+        __syncthreads();
+        // reorder the tile in LDS by digit (stable)
+#pragma unroll
+        for (int i = 0; i < kRadixItems; ++i) {
+            if (dig[i] < 256u) {
+                const uint32_t q = toff[dig[i]] + wcnt[wave][dig[i]] + rank[i];
+                if (q < kRadixTile) {  // always true when the ranks are consistent
+                    lk[q] = key[i];
+                    if (vals) lv[q] = val[i];
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t cnt = (uint32_t)((n - base) < kRadixTile ? (n - base) : kRadixTile);
+        for (uint32_t q = tid; q < cnt; q += blockDim.x) {
+            const uint64_t k = lk[q];
+            const uint64_t g = gofs[digit_of(k, flip, d)] + q;
+            if (g < n) {  // always true when the look-back prefixes are consistent
+                dk[g] = k;
+                if (vals) dv[g] = lv[q];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_radix_copy(Args a) {
+    Ctrl* c = a.c;
+    if (!c->radix_on) return;
+    const RadixJob& j = c->rj;
+    if (j.copy_mode == 0) return;
+    const uint64_t* sk = j.copy_mode == 1 ? j.src_k : j.tmp_k;
+    const uint64_t* sv = j.copy_mode == 1 ? j.src_v : j.tmp_v;
+    const uint64_t n = j.n;
+    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = gtid; i < n; i += gstride) {
+        j.dst_k[i] = sk[i];
+        if (j.has_vals) j.dst_v[i] = sv[i];
+    }
+}
+
+}  // namespace cafs

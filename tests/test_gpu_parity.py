@@ -1,0 +1,184 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer work, so every comparison is bit-exact: the sorted output, the distinct
+keys and their counts, and every report field (estimate, path, tiny miss, M,
+spill, K).  Inputs are seeded synthetic columns (gen/) and the hand-built
+dispatcher / guard cases (tests/crafted.py).
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from tests import crafted
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_25040_amd as cafs
+    return cafs.Context(0)
+
+
+ORACLE_FIELDS = oracle.REPORT_FIELDS
+
+
+def run_gpu(ctx, x_np, unsigned, counts=True, shift_in=0, shift_out=0, inplace=False):
+    """Sort x_np on the GPU; optional 8-byte misalignment of input/output."""
+    import paper_2605_25040_amd as cafs
+    n = x_np.size
+    xi = x_np.view(np.int64)
+    buf = torch.empty(n + 2, dtype=torch.int64, device="cuda:0")
+    buf[shift_in:shift_in + n].copy_(torch.from_numpy(xi.copy()))
+    x = buf[shift_in:shift_in + n]
+    if inplace:
+        out = x
+    else:
+        obuf = torch.empty(n + 2, dtype=torch.int64, device="cuda:0")
+        out = obuf[shift_out:shift_out + n]
+    out, rep, uq, ct = ctx.sort(x, unsigned=unsigned, out=out, counts=counts)
+    torch.cuda.synchronize()
+    r = cafs.parse_report(rep)
+    y = out.cpu().numpy().view(np.uint64 if unsigned else np.int64)
+    if counts:
+        k = r["k_exact"]
+        u = uq[:k].cpu().numpy().view(np.uint64 if unsigned else np.int64)
+        c = ct[:k].cpu().numpy().view(np.uint64)
+    else:
+        u = c = None
+    return y, r, u, c
+
+
+def check(ctx, x_np, unsigned, label="", **kw):
+    dt = np.uint64 if unsigned else np.int64
+    x = x_np.view(dt)
+    y, r, u, c = run_gpu(ctx, x_np, unsigned, **kw)
+    want = oracle.sort(x, dt)
+    assert np.array_equal(y, want), "%s: sorted output differs" % label
+    ro = oracle.report(x, dt)
+    for f in ORACLE_FIELDS:
+        assert r[f] == ro[f], "%s: report field %s gpu=%r oracle=%r (gpu %r)" % (label, f, r[f], ro[f], r)
+    if u is not None:
+        uo, co = oracle.counts(x, dt)
+        assert np.array_equal(u, uo), "%s: distinct keys differ" % label
+        assert np.array_equal(c, co), "%s: counts differ" % label
+    return r
+
+
+SEEDED = [
+    # n, K, dist, s, palette
+    (3000, 5, "uniform", 1.1, "random"),
+    (5000, 200, "uniform", 1.1, "random"),
+    (131_072 + 123, 200, "uniform", 1.1, "random"),
+    (200_000, 1000, "zipf", 1.0, "random"),
+    (250_000, 3000, "zipf", 1.1, "random"),
+    (300_001, 10_000, "uniform", 1.1, "random"),   # K > 8192: pair sort
+    (100_000, 100_000, "uniform", 1.1, "random"),  # all distinct: HIGH_K
+    (1_000_000, 200, "uniform", 1.1, "random"),    # the plain single-column config
+    (1_000_000, 4, "uniform", 1.1, "random"),      # tiny
+    (1_000_000, 8, "zipf", 1.1, "random"),         # tiny
+    (400_000, 1000, "uniform", 1.1, "codes"),      # dictionary codes 0..K-1
+    (200_000, 64, "runs", 1.1, "random"),
+    (200_000, 300, "grouped", 1.1, "random"),      # sorted by group -> MONOTONE
+    (200_000, 300, "almost_sorted", 1.1, "ap"),
+    (60_000, 30_000, "zipf", 1.1, "random"),       # Chao1 underestimate
+    (2_000_000, 200_000, "zipf", 1.1, "random"),   # underestimate: table overflow -> radix engine
+    (500_000, 150_000, "uniform", 1.1, "random"),
+]
+
+
+@pytest.mark.parametrize("unsigned", [False, True])
+@pytest.mark.parametrize("n,k,dist,s,pal", SEEDED)
+def test_seeded_columns(ctx, n, k, dist, s, pal, unsigned):
+    x = gen.column(n, k, dist=dist, s=s, palette=pal, dtype=np.uint64)
+    check(ctx, x, unsigned, label="%s n=%d k=%d" % (dist, n, k))
+
+
+@pytest.mark.parametrize("name", list(crafted.all_cases().keys()))
+@pytest.mark.parametrize("unsigned", [False, True])
+def test_crafted(ctx, name, unsigned):
+    x, exp = crafted.all_cases()[name]
+    r = check(ctx, x, unsigned, label=name)
+    for key, val in exp.items():
+        assert r[key] == val, (name, key, r[key], val)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 7, 64, 2047, 2048, 2049, 4095, 4097, 8193, 9000])
+@pytest.mark.parametrize("unsigned", [False, True])
+def test_small_and_ragged(ctx, n, unsigned):
+    x = gen.column(n, max(1, n // 3), dtype=np.uint64)
+    check(ctx, x, unsigned, label="n=%d" % n)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2047, 2048, 100_000])
+def test_sorted_inputs(ctx, n):
+    x, _ = crafted.t1_sorted(n)
+    r = check(ctx, x, False, label="sorted n=%d" % n)
+    assert r["path"] == "MONOTONE"
+
+
+def test_extreme_values_every_path(ctx):
+    ext = np.array([0, 1, (1 << 63) - 1, 1 << 63, (1 << 64) - 1, (1 << 64) - 2, 5, 1 << 62],
+                   dtype=np.uint64)
+    rng = np.random.default_rng(10)
+    for n, kk in ((1000, 8), (50_000, 3), (50_000, 8), (80_000, 1000)):
+        pal = np.concatenate([ext, rng.integers(0, 2**63, size=max(0, kk - ext.size), dtype=np.uint64)])[:max(kk, 3)]
+        x = pal[rng.integers(0, pal.size, size=n)]
+        for unsigned in (False, True):
+            check(ctx, x, unsigned, label="extremes n=%d k=%d" % (n, kk))
+
+
+@pytest.mark.parametrize("shift_in,shift_out", [(1, 0), (0, 1), (1, 1)])
+def test_misaligned_buffers(ctx, shift_in, shift_out):
+    for n, k in ((100_001, 50), (100_001, 4), (20_001, 20_001)):
+        x = gen.column(n, k, dtype=np.uint64)
+        check(ctx, x, False, label="misaligned n=%d k=%d" % (n, k), shift_in=shift_in, shift_out=shift_out)
+
+
+def test_in_place(ctx):
+    for n, k, dist in ((300_000, 200, "uniform"), (5000, 5000, "uniform"), (100_000, 4, "uniform"),
+                       (100_000, 300, "grouped")):
+        x = gen.column(n, k, dist=dist, dtype=np.uint64)
+        check(ctx, x, False, label="inplace n=%d k=%d" % (n, k), inplace=True)
+
+
+def test_without_counts_or_report(ctx):
+    x = gen.column(300_000, 700, dist="zipf", s=1.0, dtype=np.uint64)
+    xt = torch.from_numpy(x.view(np.int64).copy()).cuda()
+    out, rep, uq, ct = ctx.sort(xt, report=False)
+    torch.cuda.synchronize()
+    assert rep is None
+    assert np.array_equal(out.cpu().numpy(), oracle.sort(x.view(np.int64)))
+
+
+def test_estimate_api(ctx):
+    for n, k, dist in ((0, 1, "uniform"), (5, 5, "uniform"), (5000, 200, "uniform"),
+                       (1_000_000, 1000, "zipf"), (100_000, 100_000, "uniform")):
+        x = gen.column(n, k, dist=dist, dtype=np.uint64)
+        e = ctx.estimate(torch.from_numpy(x.view(np.int64).copy()).cuda())
+        assert e == oracle.estimate(x), (n, k, dist)
+
+
+@pytest.mark.parametrize("unsigned", [False, True])
+def test_radix_sort_api(ctx, unsigned):
+    for n, k, pal in ((1, 1, "random"), (4095, 4095, "random"), (300_000, 300_000, "random"),
+                      (200_000, 1000, "codes"), (100_003, 3, "random")):
+        x = gen.column(n, k, palette=pal, dtype=np.uint64)
+        xt = torch.from_numpy(x.view(np.int64).copy()).cuda()
+        y = ctx.radix_sort(xt, unsigned=unsigned)
+        torch.cuda.synchronize()
+        dt = np.uint64 if unsigned else np.int64
+        assert np.array_equal(y.cpu().numpy().view(dt), np.sort(x.view(dt)))
+
+
+def test_deterministic_reports(ctx):
+    x = gen.column(500_000, 2000, dist="zipf", s=1.1, dtype=np.uint64)
+    a = run_gpu(ctx, x, False)
+    b = run_gpu(ctx, x, False)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
