@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput of the CAFS hot path on one MI355X.
+
+A step is one cafs_sort_i64 call over the HBM-scale column: N = 2^28 int64 keys,
+K = 1000 distinct random 64-bit values with Zipf(1.0) frequencies (seed
+42 + N + K).  The input is resident in HBM before the timed region; the report
+(estimate, path, K, spill) is produced in every step.  Prints one JSON line.
+
+Beside the CAFS number it times the library's own LSD radix sort (the GPU
+baseline) on the same input, the dominant kernel's achieved HBM bandwidth from
+HIP events recorded around it inside the timed region, and the CPU oracle on a
+bounded prefix of the same column.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+WORKLOADS = {
+    # name: (n, k, dist, s, palette)
+    "hbm_scale_column": (1 << 28, 1000, "zipf", 1.0, "random"),
+    "plain_single_column": (1_000_000, 200, "uniform", 1.1, "random"),
+}
+# algorithmic bytes per key of each single-kernel stage
+STAGE_BYTES_PER_KEY = {"count": 8.0, "emit": 8.0}
+STAGE_KERNEL = {"count": "k_hash_count", "emit": "k_emit"}
+KERNEL_SOURCES = ["paper_2605_25040_amd/csrc/cafs_dev.h", "paper_2605_25040_amd/csrc/k_count.h",
+                  "paper_2605_25040_amd/csrc/k_emit.h"]
+
+
+def sources_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, n):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None when
+    absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except ValueError:
+        return None
+    e = t.get(kernel)
+    if not e or e.get("sources_hash") != sources_hash() or e.get("n") != n:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(x_np, seconds_hint):
+    import numpy as np
+
+    import oracle
+    m = min(x_np.size, 1 << 25)
+    sample = np.ascontiguousarray(x_np[:m])
+    best = None
+    for _ in range(2):  # the paper's protocol: minimum of two runs
+        t0 = time.perf_counter()
+        oracle.sort(sample)
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return {"value": m / best / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d keys of the same column (std::map count + emit, single thread, min of 2 runs, %.2f s each)"
+                      % (m, best)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="hbm_scale_column", choices=sorted(WORKLOADS))
+    ap.add_argument("--radix-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        sys.stderr.write("bench.py runs on one GPU only: this build has no multi-GPU path "
+                         "(a column would shard by an all-gather of the per-GPU (key, count) tables; "
+                         "see the design notes).  Use --gpus 1.\n")
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2605_25040_amd as cafs
+
+    n, k, dist, s, pal = WORKLOADS[args.workload]
+    x_np = gen.column(n, k, dist=dist, s=s, palette=pal, dtype=np.int64)
+    dev = torch.device("cuda", 0)
+    x = torch.from_numpy(x_np).to(dev)
+    ctx = cafs.Context(0)
+    ws = ctx.workspace(ctx.workspace_bytes(n))
+    out = torch.empty_like(x)
+    rep = torch.zeros(cafs.report_size(), dtype=torch.uint8, device=dev)
+    lib, h = ctx._lib, ctx._h
+
+    def step():
+        rc = lib.cafs_sort_i64(h, x.data_ptr(), out.data_ptr(), n, None, None, rep.data_ptr(), ws.data_ptr(),
+                               ws.numel(), torch.cuda.current_stream(dev).cuda_stream)
+        if rc != 0:
+            raise RuntimeError("cafs_sort_i64 failed: %d" % rc)
+
+    # one checked call: report against the oracle's estimate, output ordered, counts sum to N
+    import oracle
+    step()
+    torch.cuda.synchronize()
+    r = cafs.parse_report(rep)
+    est = oracle.estimate(x_np)
+    for f, v in est.items():
+        assert r[f] == v, ("estimate field", f, r[f], v)
+    assert bool((out[1:] >= out[:-1]).all()), "output not ordered"
+    k_true = int(torch.unique(x).numel())
+    assert r["k_exact"] == k_true, (r["k_exact"], k_true)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.enable_timing(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ctx.enable_timing(False)
+    ms = ev0.elapsed_time(ev1) / args.steps
+    stages, calls = ctx.stage_ms()
+    stage_avg = {kk: v / max(calls, 1) for kk, v in stages.items()}
+    value = n / (ms * 1e-3) / 1e9
+
+    # dominant single-kernel stage and its roofline
+    dom = max(STAGE_BYTES_PER_KEY, key=lambda st: stage_avg[st])
+    dom_bytes = STAGE_BYTES_PER_KEY[dom] * n
+    achieved = dom_bytes / (stage_avg[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(STAGE_KERNEL[dom], n)
+    roofline = {"bound": "hbm", "kernel": STAGE_KERNEL[dom], "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic}
+
+    # the GPU radix baseline on the same input
+    for _ in range(2):
+        ctx.radix_sort(x, out=out, ws=ws)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.radix_steps):
+        ctx.radix_sort(x, out=out, ws=ws)
+    ev1.record()
+    torch.cuda.synchronize()
+    radix_ms = ev0.elapsed_time(ev1) / args.radix_steps
+    radix_value = n / (radix_ms * 1e-3) / 1e9
+
+    line = {
+        "metric": "Gkeys/s int64 sort at K<<N (HBM-scale column), % HBM peak, vs GPU radix",
+        "value": round(value, 3),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "k": k, "freq": "%s(%s)" % (dist, s) if dist == "zipf" else dist,
+                   "values": "distinct random 64-bit" if pal == "random" else pal, "seed": "42+N+K",
+                   "path": r["path"], "k_hat": r["k_hat"], "k_exact": r["k_exact"]},
+        "hbm_frac_path": round(16.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "stages_ms": {kk: round(v, 4) for kk, v in stage_avg.items()},
+        "radix_baseline": {"value": round(radix_value, 3), "unit": "Gkeys/s", "ms": round(radix_ms, 4)},
+        "vs_radix": round(value / radix_value, 2),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(x_np, 20)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,6 +108,22 @@ typedef struct cafs_ctx cafs_ctx_t;
 cafs_status_t cafs_ctx_create(cafs_ctx_t** ctx, int device);
 void cafs_ctx_destroy(cafs_ctx_t* ctx);
 
+/* Per-stage timing.  While enabled, every cafs_sort_i64/u64 call on the context
+ * records HIP events on its stream at the stage boundaries:
+ *   0 pre    order check, Chao1 estimate, plan          (Alg. 2, Alg. 3)
+ *   1 init   table initialisation and tiny count         (Sec. 4.4)
+ *   2 count  hash count                                  (Sec. 4.4)
+ *   3 order  compaction, pair sort, fallback radix       (Alg. 4, Table dispatcher)
+ *   4 emit   run expansion                               (Alg. 4)
+ *   5 tail   monotone copy, run-length pass, guard, report (Alg. 4)
+ * cafs_ctx_stage_ms waits for the recorded events, writes into h_ms[0..n_stages)
+ * the summed milliseconds of each stage over every call recorded since the last
+ * read, stores the number of calls in *h_calls, and forgets them.  Enabling
+ * adds one event record per stage boundary to each call. */
+#define CAFS_N_STAGES 6
+cafs_status_t cafs_ctx_enable_timing(cafs_ctx_t* ctx, int enable);
+cafs_status_t cafs_ctx_stage_ms(cafs_ctx_t* ctx, float* h_ms, int n_stages, int* h_calls);
+
 /* Upper bound on the device workspace of one cafs_sort_i64/u64 call of n keys
  * (the same for both dtypes); depends on n only.  The workspace must be
  * 256-byte aligned and is used as scratch: its contents on entry do not matter. */

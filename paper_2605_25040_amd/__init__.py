@@ -17,7 +17,10 @@ ENGINES = ("NONE", "TINY", "HASH", "RADIX")
 I64, U64 = 0, 1
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "HIP error", -4: "unsupported", -5: "nomem"}
 
-EXPORTS = ("cafs_ctx_create", "cafs_ctx_destroy", "cafs_workspace_bytes", "cafs_estimate",
+STAGES = ("pre", "init", "count", "order", "emit", "tail")
+
+EXPORTS = ("cafs_ctx_create", "cafs_ctx_destroy", "cafs_ctx_enable_timing", "cafs_ctx_stage_ms",
+           "cafs_workspace_bytes", "cafs_estimate",
            "cafs_sort_i64", "cafs_sort_u64", "cafs_radix_sort", "cafs_batched_workspace_bytes",
            "cafs_sort_batched", "cafs_status_str", "cafs_last_error")
 
@@ -60,6 +63,10 @@ def load():
     lib.cafs_ctx_create.restype = i32
     lib.cafs_ctx_destroy.argtypes = [p]
     lib.cafs_ctx_destroy.restype = None
+    lib.cafs_ctx_enable_timing.argtypes = [p, ctypes.c_int]
+    lib.cafs_ctx_enable_timing.restype = i32
+    lib.cafs_ctx_stage_ms.argtypes = [p, ctypes.POINTER(ctypes.c_float), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.cafs_ctx_stage_ms.restype = i32
     lib.cafs_workspace_bytes.argtypes = [u64, i32]
     lib.cafs_workspace_bytes.restype = ctypes.c_size_t
     lib.cafs_estimate.argtypes = [p, p, u64, p, p]
@@ -120,6 +127,16 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def enable_timing(self, on=True):
+        _check(self._lib.cafs_ctx_enable_timing(self._h, 1 if on else 0))
+
+    def stage_ms(self):
+        """Summed per-stage milliseconds of the calls recorded since the last read."""
+        arr = (ctypes.c_float * len(STAGES))()
+        calls = ctypes.c_int()
+        _check(self._lib.cafs_ctx_stage_ms(self._h, arr, len(STAGES), ctypes.byref(calls)))
+        return {k: float(v) for k, v in zip(STAGES, arr)}, int(calls.value)
 
     def workspace_bytes(self, n):
         return int(self._lib.cafs_workspace_bytes(int(n), 0))

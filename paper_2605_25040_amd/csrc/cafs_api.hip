@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "cafs_dev.h"
 #include "k_count.h"
@@ -20,6 +21,9 @@
 struct cafs_ctx {
     int device;
     int cus;
+    bool timing;
+    std::vector<hipEvent_t> pool;                 // free events
+    std::vector<std::vector<hipEvent_t>> calls;   // CAFS_N_STAGES + 1 events per recorded call
 };
 
 namespace {
@@ -49,7 +53,7 @@ uint32_t log2_host(uint64_t p) {
 
 // Workspace of one column of n keys.  Regions are 256-byte aligned.
 struct Layout {
-    size_t ctrl, gkeys, gcnt, claimed, pk, pv, uniq, cnt, off, tmp_k, tmp_v, status, dcount, rle_tile;
+    size_t ctrl, gkeys, gcnt, claimed, pk, pv, uniq, cnt, off, tmp_k, tmp_v, status, dcount, clist, rle_tile;
     size_t total;
     uint32_t cap_log2;
     uint64_t status_slot;
@@ -85,6 +89,7 @@ Layout make_layout(uint64_t n) {
     L.tmp_v = take(cap * 8);
     L.status = take(2 * L.status_slot * 8);
     L.dcount = take(L.m_ws * 4);
+    L.clist = take(nn * 4);
     L.rle_tile = take(rle_tiles * 8);
     L.total = o;
     return L;
@@ -160,6 +165,7 @@ cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void*
     a.dcount = at<uint32_t>(ws, L.dcount);
     a.bmin = at<uint32_t>(ws, L.tmp_k);
     a.first_idx = at<uint32_t>(ws, L.off);
+    a.clist = at<uint32_t>(ws, L.clist);
     a.m_ws = L.m_ws;
     a.rle_tile = at<uint64_t>(ws, L.rle_tile);
     return a;
@@ -191,37 +197,61 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     if (!ws || ws_bytes < L.total || reinterpret_cast<uintptr_t>(ws) % kAlign) return CAFS_EWORKSPACE;
     const cafs::Args a = make_args(ctx, L, in, out, n, dt, uniq, counts, report, ws);
     const int cus = ctx->cus;
+    std::vector<hipEvent_t> evs;
+    if (ctx->timing) {
+        for (int i = 0; i <= CAFS_N_STAGES; ++i) {
+            hipEvent_t e;
+            if (!ctx->pool.empty()) {
+                e = ctx->pool.back();
+                ctx->pool.pop_back();
+            } else if (hipEventCreate(&e) != hipSuccess) {
+                return hip_fail(hipGetLastError(), "hipEventCreate");
+            }
+            evs.push_back(e);
+        }
+    }
+    auto mark = [&](int i) {
+        if (!evs.empty()) (void)hipEventRecord(evs[i], s);
+    };
     const uint64_t cap_ws = 1ull << L.cap_log2;
     (void)hipGetLastError();  // clear any stale error so the check below is ours
+    mark(0);
     cafs::k_pre<<<1, 1024, 0, s>>>(a);
     if (n > cafs::kMonoPrefix) cafs::k_mono_full<<<grid_for(n, 256 * 16, cus * 4), 256, 0, s>>>(a);
     cafs::k_plan<<<1, 256, 0, s>>>(a);
+    mark(1);
     const bool countable = n >= cafs::kSmallN;  // tiny and main need N >= 2048
-    if (countable) {
+    if (countable)
         cafs::k_phase2<<<grid_for(std::max<uint64_t>(n / 2, cap_ws), 256 * 8, cus * 4), 256, 0, s>>>(a);
+    mark(2);
+    if (countable)
         cafs::k_hash_count<<<grid_for(n, cafs::kCountThreads * 8, cus), cafs::kCountThreads, 0, s>>>(a);
-        cafs::k_compact_order<<<1, 1024, 0, s>>>(a);
-    }
+    mark(3);
+    if (countable) cafs::k_compact_order<<<1, 1024, 0, s>>>(a);
     launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s);
-    if (countable) {
-        if (n > cafs::kOrderMax) cafs::k_pair_scan<<<1, 1024, 0, s>>>(a);
+    if (countable && n > cafs::kOrderMax) cafs::k_pair_scan<<<1, 1024, 0, s>>>(a);
+    mark(4);
+    if (countable)
         cafs::k_emit<<<grid_for(n, 2 * cafs::kEmitTilePairs, cus * 8), cafs::kEmitThreads, 0, s>>>(a);
-    }
+    mark(5);
     cafs::k_copy_mono<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s>>>(a);
     const uint32_t g_rle = grid_for(n, cafs::kRleTile, cus * 4);
     cafs::k_rle_count<<<g_rle, 256, 0, s>>>(a);
     cafs::k_rle_write<<<g_rle, 256, 0, s>>>(a);
     cafs::k_rle_counts<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s>>>(a);
     if (countable) {
-        const uint32_t g = grid_for(std::max<uint64_t>(n / 8, 1), 256 * 8, cus * 4);
+        const uint32_t g = grid_for(n, 256 * 64, cus * 2);
         cafs::k_guard_prep<<<grid_for(L.m_ws, 256 * 8, cus * 4), 256, 0, s>>>(a);
         cafs::k_guard_bucket<<<g, 256, 0, s>>>(a);
         cafs::k_guard_mark<<<g, 256, 0, s>>>(a);
-        cafs::k_guard_first<<<grid_for(n, cafs::kGuardChunk, cus * 2), 256, 0, s>>>(a);
+        cafs::k_guard_first<<<grid_for(n, cafs::kGuardChunk, cus), 256, 0, s>>>(a);
+        cafs::k_guard_resolve<<<1, 1024, 0, s>>>(a);
         for (uint32_t r = 0; r < 4; ++r) cafs::k_guard_round<<<g, 256, 0, s>>>(a, r);
         cafs::k_guard_final<<<g, 256, 0, s>>>(a);
     }
     cafs::k_finalize<<<1, 64, 0, s>>>(a);
+    mark(6);
+    if (!evs.empty()) ctx->calls.push_back(evs);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? CAFS_OK : hip_fail(e, "launch");
 }
@@ -263,11 +293,45 @@ cafs_status_t cafs_ctx_create(cafs_ctx_t** ctx, int device) {
     if (!c) return CAFS_ENOMEM;
     c->device = device;
     c->cus = cus > 0 ? cus : 1;
+    c->timing = false;
     *ctx = c;
     return CAFS_OK;
 }
 
-void cafs_ctx_destroy(cafs_ctx_t* ctx) { delete ctx; }
+void cafs_ctx_destroy(cafs_ctx_t* ctx) {
+    if (!ctx) return;
+    for (auto& call : ctx->calls)
+        for (hipEvent_t e : call) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+cafs_status_t cafs_ctx_enable_timing(cafs_ctx_t* ctx, int enable) {
+    if (!ctx) return CAFS_EINVAL;
+    ctx->timing = enable != 0;
+    return CAFS_OK;
+}
+
+cafs_status_t cafs_ctx_stage_ms(cafs_ctx_t* ctx, float* h_ms, int n_stages, int* h_calls) {
+    if (!ctx || (n_stages > 0 && !h_ms) || n_stages < 0 || n_stages > CAFS_N_STAGES) return CAFS_EINVAL;
+    DeviceGuard dg(ctx->device);
+    for (int i = 0; i < n_stages; ++i) h_ms[i] = 0.f;
+    cafs_status_t st = CAFS_OK;
+    for (auto& call : ctx->calls) {
+        hipError_t e = hipEventSynchronize(call.back());
+        if (e != hipSuccess && st == CAFS_OK) st = hip_fail(e, "hipEventSynchronize");
+        for (int i = 0; i < n_stages && st == CAFS_OK; ++i) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, call[i], call[i + 1]);
+            if (e != hipSuccess) st = hip_fail(e, "hipEventElapsedTime");
+            h_ms[i] += ms;
+        }
+        for (hipEvent_t ev : call) ctx->pool.push_back(ev);
+    }
+    if (h_calls) *h_calls = (int)ctx->calls.size();
+    ctx->calls.clear();
+    return st;
+}
 
 size_t cafs_workspace_bytes(uint64_t n, cafs_dtype_t dtype) {
     (void)dtype;

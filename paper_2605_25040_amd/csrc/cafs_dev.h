@@ -38,7 +38,8 @@ constexpr int kRadixThreads = 256;             // radix workgroup (4 waves)
 constexpr int kRadixItems = 16;                // keys per thread per tile
 constexpr uint32_t kRadixTile = kRadixThreads * kRadixItems;  // 4096 keys per tile
 constexpr uint32_t kRleTile = 4096;            // elements per run-detection tile
-constexpr uint32_t kGuardChunk = 16384;        // elements per first-occurrence chunk
+constexpr uint32_t kGuardChunk = 4096;         // elements per first-occurrence chunk
+constexpr uint32_t kGuardLdsKeys = 2048;       // contested keys resolved in LDS
 
 enum Path : int32_t { P_MONOTONE = 0, P_SMALL_N = 1, P_TINY = 2, P_HIGH_K = 3, P_MAIN = 4, P_GUARD = 5 };
 enum Engine : uint32_t { E_NONE = 0, E_TINY = 1, E_HASH = 2, E_RADIX = 3 };
@@ -108,6 +109,8 @@ struct Ctrl {
     uint32_t rle_done;
     uint32_t rle_on;
     // guard
+    uint32_t guard_general;           // bucket counts must be built from the dense pairs
+    uint32_t guard_rounds;            // too many contested keys for one workgroup
     uint64_t n_contested;
     uint64_t found;
     uint32_t chunk_ctr;
@@ -148,6 +151,7 @@ struct Args {
     uint32_t* dcount;                 // m_ws entries
     uint32_t* bmin;                   // 4 * m_ws entries
     uint32_t* first_idx;              // n entries
+    uint32_t* clist;                  // n entries: indices of contested keys
     uint64_t m_ws;
     // run-length scratch
     uint64_t* rle_tile;               // per-tile run counts
@@ -158,6 +162,15 @@ struct Args {
 // Multiplicative hash of Eq. hash: top `bits` bits of x * phi mod 2^64.
 __device__ __forceinline__ uint32_t phi_hash(uint64_t x, uint32_t bits) {
     return (uint32_t)((x * kPhi) >> (64 - bits));
+}
+
+// The same hash on 32-bit halves, for bits <= 32: only the high word of the
+// low 64 bits of the product is needed, which takes three 32-bit multiplies.
+__device__ __forceinline__ uint32_t phi_hash32(uint64_t x, uint32_t bits) {
+    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    const uint32_t plo = (uint32_t)kPhi, phi = (uint32_t)(kPhi >> 32);
+    const uint32_t top = __umulhi(lo, plo) + lo * phi + hi * plo;
+    return top >> (32 - bits);
 }
 
 __device__ __forceinline__ uint64_t bit_ceil64(uint64_t v) {

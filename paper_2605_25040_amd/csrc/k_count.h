@@ -78,6 +78,7 @@ __device__ __noinline__ void set_overflow(Ctrl* c) {
     if (atomicExch(&c->overflow, 1u) == 0) {
         atomicExch(&c->radix_on, 1u);
         atomicExch(&c->guard_on, 1u);
+        atomicExch(&c->guard_general, 1u);
         atomicOr(&c->flags, 1u);
     }
 }
@@ -86,7 +87,7 @@ __device__ __noinline__ void set_overflow(Ctrl* c) {
 // slot).  A slot is claimed by CAS from kEmpty and never freed, so a key is either
 // in the table or (after an overflow) the whole table is abandoned for the radix
 // engine.  Claimed slots are listed so that compaction reads K entries, not the table.
-__device__ void global_insert(const Args& a, Ctrl* c, uint64_t v, uint64_t cnt) {
+__device__ __forceinline__ void global_insert(const Args& a, Ctrl* c, uint64_t v, uint64_t cnt) {
     if (atomic_load_agent(&c->overflow)) return;
     const uint32_t lg = c->cap_log2;
     const uint64_t mask = (1ull << lg) - 1;
@@ -117,16 +118,35 @@ __device__ void global_insert(const Args& a, Ctrl* c, uint64_t v, uint64_t cnt) 
 // ---------------------------------------------------------------------------
 // Hash count (main path, Sec. 4.4).  The paper's x86 hot loop updates one
 // cache-line bucket per element.  Here each workgroup owns an open-addressing
-// table of 8192 (key, count) slots in LDS; an element hashes to a slot (Eq. hash),
-// probes linearly, claims an empty slot with a 64-bit LDS CAS and adds 1 with an
-// LDS atomic.  Keys that find no LDS slot within the probe limit go straight to
-// the global table.  At the end each workgroup flushes its occupied slots to the
-// global table.  Elements equal to the empty marker are counted in registers.
+// table of 8192 (key, count) slots in LDS; an element hashes to a slot (Eq. hash)
+// and, when the slot already holds it (the common case once the table is warm),
+// adds 1 with an LDS atomic.  That fast path is straight-line code for the eight
+// keys a thread holds, while the loads of its next eight keys are in flight.
+// Keys that miss their home slot take the slow path: linear probing, claiming an
+// empty slot with a 64-bit LDS CAS, and after kLdsProbe slots the global table.
+// At the end each workgroup flushes its occupied slots to the global table.
+// Elements equal to the empty marker are counted in registers.
 //
 // This kernel also resolves the tiny branch: if the tiny counters sum to N the
 // column is tiny and the dense arrays are written here; otherwise the element set
 // has an unsampled value and the main path runs with the same estimate (Sec. 4.4).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void lds_insert_slow(const Args& a, Ctrl* c, uint64_t* skeys, uint32_t* scnt, uint64_t x) {
+    constexpr uint32_t S = 1u << kLdsSlotsLog2;
+    uint32_t h = phi_hash32(x, kLdsSlotsLog2);
+    for (uint32_t pr = 0; pr < kLdsProbe; ++pr) {
+        const uint64_t k = skeys[h];
+        if (k == x) { atomicAdd(&scnt[h], 1u); return; }
+        if (k == kEmpty) {
+            const unsigned long long old =
+                atomicCAS((unsigned long long*)&skeys[h], (unsigned long long)kEmpty, (unsigned long long)x);
+            if (old == kEmpty || old == x) { atomicAdd(&scnt[h], 1u); return; }
+        }
+        h = (h + 1) & (S - 1);
+    }
+    global_insert(a, c, x, 1);
+}
+
 __global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
     Ctrl* c = a.c;
     const uint32_t engine = c->engine;
@@ -168,38 +188,65 @@ __global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
     __syncthreads();
 
     uint32_t ecnt = 0;
-    const uint64_t P = num_pairs(a.n, a.in_head);
-    constexpr int U = 4;  // pairs per thread per step (loads in flight)
-    const uint64_t step = (uint64_t)gridDim.x * blockDim.x * U;
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x * U; base < P; base += step) {
-        uint64_t v[2 * U];
-        bool ok[2 * U];
+    const uint32_t head = a.in_head;
+    const uint64_t P = num_pairs(a.n, head);
+    const uint64_t Pf = (a.n + head) / 2;  // pairs [head, Pf) hold two in-range elements
+    constexpr int U = 4;                   // pairs per thread per step
+    const uint64_t span = (uint64_t)blockDim.x * U;
+    const uint64_t step = (uint64_t)gridDim.x * span;
+    uint64_t base = (uint64_t)blockIdx.x * span;
+    uint64_t v[2 * U];
+    uint32_t okm = 0;  // bit e: element e of the batch is in range
+    auto load = [&](uint64_t b) {
+        if (b >= head && b + span <= Pf) {
+            // interior batch: every pair is two aligned in-range elements
+            const u64x2* src = reinterpret_cast<const u64x2*>(a.in + 2 * (b + threadIdx.x) - head);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t p = base + (uint64_t)u * blockDim.x + threadIdx.x;
-            v[2 * u] = v[2 * u + 1] = 0;
-            ok[2 * u] = ok[2 * u + 1] = false;
-            if (p < P) load_pair(a.in, a.n, a.in_head, p, v[2 * u], v[2 * u + 1], ok[2 * u], ok[2 * u + 1]);
+            for (int u = 0; u < U; ++u) {
+                const u64x2 w = src[(uint64_t)u * blockDim.x];
+                v[2 * u] = w.x;
+                v[2 * u + 1] = w.y;
+            }
+            okm = (1u << (2 * U)) - 1;
+        } else {
+            okm = 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t p = b + (uint64_t)u * blockDim.x + threadIdx.x;
+                bool o0 = false, o1 = false;
+                v[2 * u] = v[2 * u + 1] = 0;
+                if (p < P) load_pair(a.in, a.n, head, p, v[2 * u], v[2 * u + 1], o0, o1);
+                okm |= (o0 ? 1u : 0u) << (2 * u);
+                okm |= (o1 ? 1u : 0u) << (2 * u + 1);
+            }
         }
+    };
+    if (base < P) load(base);
+    while (base < P) {
+        uint64_t x[2 * U];
+#pragma unroll
+        for (int e = 0; e < 2 * U; ++e) x[e] = v[e];
+        const uint32_t xok = okm;
+        const uint64_t next = base + step;
+        if (next < P) load(next);  // next batch in flight while this one is counted
+        uint32_t pend = 0;
 #pragma unroll
         for (int e = 0; e < 2 * U; ++e) {
-            if (!ok[e]) continue;
-            const uint64_t x = v[e];
-            if (x == kEmpty) { ++ecnt; continue; }
-            uint32_t h = phi_hash(x, kLdsSlotsLog2);
-            bool done = false;
-            for (uint32_t pr = 0; pr < kLdsProbe; ++pr) {
-                const uint64_t k = skeys[h];
-                if (k == x) { atomicAdd(&scnt[h], 1u); done = true; break; }
-                if (k == kEmpty) {
-                    const unsigned long long old = atomicCAS((unsigned long long*)&skeys[h],
-                                                             (unsigned long long)kEmpty, (unsigned long long)x);
-                    if (old == kEmpty || old == x) { atomicAdd(&scnt[h], 1u); done = true; break; }
-                }
-                h = (h + 1) & (S - 1);
-            }
-            if (!done) global_insert(a, c, x, 1);
+            const bool in = (xok >> e) & 1u;
+            const bool is_empty_key = x[e] == kEmpty;
+            ecnt += (in && is_empty_key) ? 1u : 0u;
+            const bool want = in && !is_empty_key;
+            const uint32_t h = phi_hash32(x[e], kLdsSlotsLog2);
+            const bool hit = want && (skeys[h] == x[e]);
+            atomicAdd(&scnt[h], hit ? 1u : 0u);  // branch-free: a miss adds 0
+            pend |= (want && !hit) ? (1u << e) : 0u;
         }
+        if (pend) {
+#pragma unroll 1
+            for (int e = 0; e < 2 * U; ++e)
+                if (pend & (1u << e)) lds_insert_slow(a, c, skeys, scnt, x[e]);
+        }
+        base = next;
     }
     __syncthreads();
     for (uint32_t s = threadIdx.x; s < S; s += blockDim.x) {
@@ -244,7 +291,8 @@ __global__ __launch_bounds__(1024) void k_compact_order(Args a) {
             c->K = K;
             c->pair_sort = 1;
             c->radix_on = 1;
-            c->guard_on = 1;
+            c->guard_on = (c->path == P_MAIN);
+            c->guard_general = c->guard_on;
         }
         return;
     }
@@ -306,23 +354,43 @@ __global__ __launch_bounds__(1024) void k_compact_order(Args a) {
         c->K = K;
         c->dense_ready = 1;
     }
-    // guard check on the paper's M buckets (main path only)
+    // guard check on the paper's M buckets (main path only): count the distinct keys
+    // of each bucket in LDS and list the keys of buckets holding more than four
     if (c->path != P_MAIN) return;
     const uint64_t M = c->table_M;
     if (M > kGuardLdsBuckets) {
-        if (tid == 0) c->guard_on = 1;
+        if (tid == 0) { c->guard_on = 1; c->guard_general = 1; }
         return;
     }
+    __shared__ uint32_t s_nc;
     __syncthreads();
     uint32_t* bc = reinterpret_cast<uint32_t*>(sv);  // reuse: M <= 16384 u32 counters
     const uint32_t lg = log2_pow2(M);
     for (uint32_t i = tid; i < M; i += blockDim.x) bc[i] = 0;
+    if (tid == 0) s_nc = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < K; i += blockDim.x) atomicAdd(&bc[phi_hash(sk[i] ^ flip, lg)], 1u);
+    for (uint32_t i = tid; i < K; i += blockDim.x) atomicAdd(&bc[phi_hash32(sk[i] ^ flip, lg)], 1u);
     __syncthreads();
     uint32_t over = 0;
-    for (uint32_t i = tid; i < M; i += blockDim.x) over |= bc[i] > kBucketCap;
-    if (__any(over) && __lane_id() == 0) c->guard_on = 1;  // a bucket spills: resolve exactly later
+    for (uint32_t i = tid; i < K; i += blockDim.x) over += bc[phi_hash32(sk[i] ^ flip, lg)] > kBucketCap;
+    over = wave_sum_u32(over);
+    if (__lane_id() == 0 && over) atomicAdd(&s_nc, over);
+    __syncthreads();
+    const uint32_t nc = s_nc;
+    if (nc > kGuardLdsKeys) {
+        // too many for the one-workgroup resolution: the general kernels recount
+        if (tid == 0) { c->guard_on = 1; c->guard_general = 1; }
+        return;
+    }
+    __syncthreads();
+    if (tid == 0) s_nc = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < K; i += blockDim.x)
+        if (bc[phi_hash32(sk[i] ^ flip, lg)] > kBucketCap) a.clist[atomicAdd(&s_nc, 1u)] = i;
+    if (tid == 0) {
+        c->n_contested = nc;
+        c->guard_on = nc > 0;
+    }
 }
 
 // Exclusive scan of the sorted counts after a pair sort (K > 8192).  One workgroup.

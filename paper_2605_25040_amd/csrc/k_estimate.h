@@ -206,6 +206,8 @@ __global__ __launch_bounds__(256) void k_plan(Args a) {
     c->pair_sort = 0;
     c->radix_on = (engine == E_RADIX);
     c->guard_on = (path == P_MAIN && engine == E_RADIX);
+    c->guard_general = c->guard_on;
+    c->guard_rounds = 0;
     c->hist_done = 0;
     c->rle_done = 0;
     c->rle_on = 0;

@@ -10,14 +10,19 @@
 // The guard of Alg. 4 fires when |spill| > N/2 (tested as 2 |spill| > N).
 //
 // The GPU computes it in these steps, all skipped when no bucket is over-full:
-//   k_guard_prep    clear bucket counters and the four per-bucket minima
-//   k_guard_bucket  distinct keys per bucket
-//   k_guard_mark    count the keys of over-full ("contested") buckets
+//   (the order kernel counts the buckets in LDS and lists the keys of over-full,
+//    "contested", buckets when K <= 8192, M <= 16384 and at most 2048 are contested;
+//    otherwise the three general kernels below do it from the dense pairs)
+//   k_guard_prep    clear bucket counters and the four per-bucket minima (general)
+//   k_guard_bucket  distinct keys per bucket (general)
+//   k_guard_mark    list the contested keys (general); reset their first occurrences
 //   k_guard_first   first occurrence of each contested key: one pass over the
 //                   input in increasing chunks that stops once every contested
 //                   key has been seen (later chunks cannot hold a first occurrence)
-//   k_guard_round   r = 0..3: the r-th smallest first occurrence of each bucket
-//   k_guard_final   sum the counts of keys later than the 4th, decide the path
+//   k_guard_resolve at most 2048 contested keys: rank them by first occurrence
+//                   within their bucket in LDS and sum the spilled counts
+//   k_guard_round   otherwise, r = 0..3: the r-th smallest first occurrence per bucket
+//   k_guard_final   and the sum of the counts of keys later than the 4th
 #pragma once
 #include "cafs_dev.h"
 
@@ -29,9 +34,15 @@ __device__ __forceinline__ bool guard_active(const Ctrl* c) {
     return c->guard_on && c->path == P_MAIN;
 }
 
+// The bucket counting kernels run only when the order kernel could not count the
+// buckets itself (pairs from the radix engine or the pair sort, or M too large).
+__device__ __forceinline__ bool guard_general(const Ctrl* c) {
+    return c->guard_on && c->guard_general && c->path == P_MAIN;
+}
+
 __global__ __launch_bounds__(256) void k_guard_prep(Args a) {
     const Ctrl* c = a.c;
-    if (!guard_active(c)) return;
+    if (!guard_general(c)) return;
     const uint64_t M = c->table_M;
     const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
@@ -43,7 +54,7 @@ __global__ __launch_bounds__(256) void k_guard_prep(Args a) {
 
 __global__ __launch_bounds__(256) void k_guard_bucket(Args a) {
     const Ctrl* c = a.c;
-    if (!guard_active(c)) return;
+    if (!guard_general(c)) return;
     const uint64_t K = c->K;
     const uint32_t lg = log2_pow2(c->table_M);
     const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -51,20 +62,25 @@ __global__ __launch_bounds__(256) void k_guard_bucket(Args a) {
     for (uint64_t j = gtid; j < K; j += gstride) atomicAdd(&a.dcount[phi_hash(a.uniq[j], lg)], 1u);
 }
 
+// Lists the contested keys (general mode) and resets their first-occurrence
+// minima.  The minima share memory with the run offsets, so this runs after emit.
 __global__ __launch_bounds__(256) void k_guard_mark(Args a) {
     Ctrl* c = a.c;
     if (!guard_active(c)) return;
-    const uint64_t K = c->K;
-    const uint32_t lg = log2_pow2(c->table_M);
     const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
-    uint32_t local = 0;
-    for (uint64_t j = gtid; j < K; j += gstride) {
-        a.first_idx[j] = kNoIndex;
-        local += a.dcount[phi_hash(a.uniq[j], lg)] > kBucketCap;
+    if (c->guard_general) {
+        const uint64_t K = c->K;
+        const uint32_t lg = log2_pow2(c->table_M);
+        for (uint64_t j = gtid; j < K; j += gstride)
+            if (a.dcount[phi_hash(a.uniq[j], lg)] > kBucketCap) {
+                a.first_idx[j] = kNoIndex;
+                a.clist[atomicAdd((unsigned long long*)&c->n_contested, 1ull)] = (uint32_t)j;
+            }
+    } else {
+        const uint64_t nc = c->n_contested;
+        for (uint64_t li = gtid; li < nc; li += gstride) a.first_idx[a.clist[li]] = kNoIndex;
     }
-    local = wave_sum_u32(local);
-    if (__lane_id() == 0 && local) atomicAdd((unsigned long long*)&c->n_contested, (unsigned long long)local);
 }
 
 // Position of key v in the sorted distinct keys (it is present).
@@ -78,17 +94,58 @@ __device__ __forceinline__ uint64_t find_key(const uint64_t* uq, uint64_t K, uin
     return lo;
 }
 
+// First occurrence of every contested key.  Chunks of the input are claimed in
+// increasing order; a workgroup stops claiming once every contested key has been
+// seen, because a chunk claimed later cannot hold the first occurrence of a key
+// already seen in an earlier chunk, and every claimed chunk is finished.  With at
+// most kGuardLdsKeys contested keys each workgroup keeps them in an LDS hash table
+// with per-key minima that it merges into the global minima after each chunk;
+// otherwise each element of a contested bucket is located by binary search.
 __global__ __launch_bounds__(256) void k_guard_first(Args a) {
     Ctrl* c = a.c;
-    if (!guard_active(c)) return;
+    if (c->path != P_MAIN || !c->guard_on) return;
     const uint64_t nc = c->n_contested;
     if (nc == 0) return;
     const uint64_t n = a.n;
     const uint64_t K = c->K;
-    const uint32_t lg = log2_pow2(c->table_M);
+    const uint64_t M = c->table_M;
+    const uint32_t lg = log2_pow2(M);
+    const uint64_t flip = a.flip;
     const uint64_t chunks = (n + kGuardChunk - 1) / kGuardChunk;
-    __shared__ uint32_t s_chunk;
-    __shared__ uint32_t s_stop;
+    constexpr uint32_t TS = 2 * kGuardLdsKeys;  // LDS table slots
+    __shared__ uint64_t tkey[TS];
+    __shared__ uint16_t tidx[TS];
+    __shared__ uint32_t lmin[kGuardLdsKeys];
+    __shared__ uint32_t lsent[kGuardLdsKeys];
+    __shared__ uint32_t bflag[kGuardLdsBuckets / 32];  // contested-bucket bitmap when M is small
+    __shared__ uint32_t s_chunk, s_stop;
+    const bool small = nc <= kGuardLdsKeys;
+    const bool bits = small && M <= kGuardLdsBuckets;  // bitmap built with the LDS table
+    if (small) {
+        for (uint32_t i = threadIdx.x; i < TS; i += blockDim.x) tkey[i] = kEmpty;
+        for (uint32_t i = threadIdx.x; i < nc; i += blockDim.x) { lmin[i] = kNoIndex; lsent[i] = kNoIndex; }
+        if (bits)
+            for (uint32_t i = threadIdx.x; i < kGuardLdsBuckets / 32; i += blockDim.x) bflag[i] = 0;
+        __syncthreads();
+        for (uint32_t li = threadIdx.x; li < nc; li += blockDim.x) {
+            const uint64_t key = a.uniq[a.clist[li]];
+            if (bits) {
+                const uint32_t b = phi_hash32(key, lg);
+                atomicOr(&bflag[b >> 5], 1u << (b & 31));
+            }
+            // keys are distinct, so claiming the first empty slot never races with an equal key
+            uint32_t h = phi_hash32(key, 12);
+            while (true) {
+                const unsigned long long old =
+                    atomicCAS((unsigned long long*)&tkey[h], (unsigned long long)kEmpty, (unsigned long long)key);
+                if (old == kEmpty) { tidx[h] = (uint16_t)li; break; }
+                h = (h + 1) & (TS - 1);
+            }
+        }
+        __syncthreads();
+    }
+    // Every key of a contested bucket is contested.  The LDS table cannot hold a key
+    // equal to its empty marker; such a key takes the binary-search path.
     while (true) {
         if (threadIdx.x == 0) {
             s_stop = atomic_load_agent(&c->found) >= nc;
@@ -99,25 +156,109 @@ __global__ __launch_bounds__(256) void k_guard_first(Args a) {
         const bool stop = s_stop || ch >= chunks;
         __syncthreads();
         if (stop) break;
-        const uint64_t b = ch * kGuardChunk;
-        const uint64_t e = (b + kGuardChunk < n) ? b + kGuardChunk : n;
+        const uint64_t b0 = ch * kGuardChunk;
+        const uint64_t e0 = (b0 + kGuardChunk < n) ? b0 + kGuardChunk : n;
         uint32_t newly = 0;
-        for (uint64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+        for (uint64_t i = b0 + threadIdx.x; i < e0; i += blockDim.x) {
             const uint64_t v = a.in[i];
-            if (a.dcount[phi_hash(v, lg)] > kBucketCap) {
-                const uint64_t jj = find_key(a.uniq, K, v, a.flip);
+            const uint32_t b = phi_hash32(v, lg);
+            const bool cont = bits ? ((bflag[b >> 5] >> (b & 31)) & 1u) : (a.dcount[b] > kBucketCap);
+            if (!cont) continue;
+            if (small && v != kEmpty) {
+                uint32_t h = phi_hash32(v, 12);
+                while (true) {
+                    const uint64_t tk = tkey[h];
+                    if (tk == v) { atomicMin(&lmin[tidx[h]], (uint32_t)i); break; }
+                    if (tk == kEmpty) break;  // unreachable: contested keys are all in the table
+                    h = (h + 1) & (TS - 1);
+                }
+            } else if (bits || a.dcount[b] > kBucketCap) {
+                const uint64_t jj = find_key(a.uniq, K, v, flip);
                 const uint32_t old = atomicMin(&a.first_idx[jj], (uint32_t)i);
                 newly += (old == kNoIndex);
             }
         }
+        if (small) {
+            __syncthreads();
+            for (uint32_t li = threadIdx.x; li < nc; li += blockDim.x) {
+                const uint32_t m = lmin[li];
+                if (m < lsent[li]) {
+                    lsent[li] = m;
+                    const uint32_t old = atomicMin(&a.first_idx[a.clist[li]], m);
+                    newly += (old == kNoIndex);
+                }
+            }
+        }
         newly = wave_sum_u32(newly);
         if (__lane_id() == 0 && newly) atomicAdd((unsigned long long*)&c->found, (unsigned long long)newly);
+        __syncthreads();
+    }
+}
+
+// Rank of each contested key within its bucket by first occurrence, for at most
+// kGuardLdsKeys contested keys: sort (bucket, first occurrence) in LDS; position p
+// is the 5th or later key of its bucket exactly when position p - 4 holds the same
+// bucket.  The spill is the sum of those keys' counts.  One workgroup.
+__global__ __launch_bounds__(1024) void k_guard_resolve(Args a) {
+    Ctrl* c = a.c;
+    if (c->path != P_MAIN || !c->guard_on) return;
+    const uint64_t nc = c->n_contested;
+    if (nc == 0) return;
+    if (nc > kGuardLdsKeys) {
+        if (threadIdx.x == 0) c->guard_rounds = 1;
+        return;
+    }
+    __shared__ uint64_t sk[kGuardLdsKeys];
+    __shared__ uint64_t sv[kGuardLdsKeys];
+    __shared__ unsigned long long s_spill;
+    const uint32_t lg = log2_pow2(c->table_M);
+    uint32_t P = 64;
+    while (P < nc) P <<= 1;
+    for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+        if (i < nc) {
+            const uint32_t j = a.clist[i];
+            sk[i] = ((uint64_t)phi_hash32(a.uniq[j], lg) << 32) | a.first_idx[j];
+            sv[i] = a.cnt[j];
+        } else {
+            sk[i] = ~0ull;
+            sv[i] = 0;
+        }
+    }
+    if (threadIdx.x == 0) s_spill = 0;
+    __syncthreads();
+    // keys are distinct (distinct first occurrences), padding sorts last
+    for (uint32_t kk = 2; kk <= P; kk <<= 1) {
+        for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+                const uint32_t l = i ^ jj;
+                if (l > i) {
+                    const uint64_t ki = sk[i], kl = sk[l];
+                    const bool up = (i & kk) == 0;
+                    if (up == (ki > kl)) {
+                        sk[i] = kl; sk[l] = ki;
+                        const uint64_t t = sv[i]; sv[i] = sv[l]; sv[l] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    unsigned long long local = 0;
+    for (uint32_t p = threadIdx.x; p < nc; p += blockDim.x)
+        if (p >= 4 && (sk[p - 4] >> 32) == (sk[p] >> 32)) local += sv[p];
+    local = wave_sum_u64(local);
+    if (__lane_id() == 0 && local) atomicAdd(&s_spill, local);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        c->spill = s_spill;
+        c->flags |= 2u;
+        if (2 * s_spill > a.n) c->path = P_GUARD;
     }
 }
 
 __global__ __launch_bounds__(256) void k_guard_round(Args a, uint32_t r) {
     const Ctrl* c = a.c;
-    if (!guard_active(c) || c->n_contested == 0) return;
+    if (!guard_active(c) || !c->guard_rounds) return;
     const uint64_t K = c->K;
     const uint32_t lg = log2_pow2(c->table_M);
     const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -132,18 +273,16 @@ __global__ __launch_bounds__(256) void k_guard_round(Args a, uint32_t r) {
 
 __global__ __launch_bounds__(256) void k_guard_final(Args a) {
     Ctrl* c = a.c;
-    if (!guard_active(c)) return;
+    if (!guard_active(c) || !c->guard_rounds) return;
     __shared__ uint32_t s_last;
     const uint64_t K = c->K;
     const uint32_t lg = log2_pow2(c->table_M);
     const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
     uint64_t local = 0;
-    if (c->n_contested) {
-        for (uint64_t j = gtid; j < K; j += gstride) {
-            const uint32_t b = phi_hash(a.uniq[j], lg);
-            if (a.dcount[b] > kBucketCap && a.first_idx[j] > a.bmin[3 * a.m_ws + b]) local += a.cnt[j];
-        }
+    for (uint64_t j = gtid; j < K; j += gstride) {
+        const uint32_t b = phi_hash(a.uniq[j], lg);
+        if (a.dcount[b] > kBucketCap && a.first_idx[j] > a.bmin[3 * a.m_ws + b]) local += a.cnt[j];
     }
     local = wave_sum_u64(local);
     if (__lane_id() == 0 && local) atomicAdd((unsigned long long*)&c->spill, (unsigned long long)local);
