@@ -110,12 +110,16 @@ void cafs_ctx_destroy(cafs_ctx_t* ctx);
 
 /* Per-stage timing.  While enabled, every cafs_sort_i64/u64 call on the context
  * records HIP events on its stream at the stage boundaries:
- *   0 pre    order check, Chao1 estimate, plan          (Alg. 2, Alg. 3)
- *   1 init   table initialisation and tiny count         (Sec. 4.4)
- *   2 count  hash count                                  (Sec. 4.4)
- *   3 order  compaction, pair sort, fallback radix       (Alg. 4, Table dispatcher)
- *   4 emit   run expansion                               (Alg. 4)
- *   5 tail   monotone copy, run-length pass, guard, report (Alg. 4)
+ *   0 pre    order check, Chao1 estimate, dispatch        (Alg. 2, Alg. 3)
+ *   1 init   table initialisation and tiny count           (Sec. 4.4)
+ *   2 count  hash count                                    (Sec. 4.4)
+ *   3 order  compaction and order of at most 8192 pairs    (Alg. 4)
+ *   4 emit   run expansion on the caller's stream          (Alg. 4)
+ *   5 tail   the rest until the report is written: the radix engine, the
+ *            larger pair sort and its emit, the monotone copy, the run-length
+ *            pass and the guard run on a side stream of the context, forked
+ *            after stage 3, and count here as far as they outlast the emit.
+ * Calls on one context share its side stream.
  * cafs_ctx_stage_ms waits for the recorded events, writes into h_ms[0..n_stages)
  * the summed milliseconds of each stage over every call recorded since the last
  * read, stores the number of calls in *h_calls, and forgets them.  Enabling

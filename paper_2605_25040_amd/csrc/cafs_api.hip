@@ -21,6 +21,8 @@
 struct cafs_ctx {
     int device;
     int cus;
+    hipStream_t side;       // default-priority stream for the branches that overlap the emit
+    hipEvent_t fork, join;  // side stream starts after the order kernel; the report waits for it
     bool timing;
     std::vector<hipEvent_t> pool;                 // free events
     std::vector<std::vector<hipEvent_t>> calls;   // CAFS_N_STAGES + 1 events per recorded call
@@ -53,7 +55,8 @@ uint32_t log2_host(uint64_t p) {
 
 // Workspace of one column of n keys.  Regions are 256-byte aligned.
 struct Layout {
-    size_t ctrl, gkeys, gcnt, claimed, pk, pv, uniq, cnt, off, tmp_k, tmp_v, status, dcount, clist, rle_tile;
+    size_t ctrl, gkeys, gcnt, claimed, pk, pv, uniq, cnt, off, tmp_k, tmp_v, status, dcount, bfound, clist, first,
+        rle_tile;
     size_t total;
     uint32_t cap_log2;
     uint64_t status_slot;
@@ -82,14 +85,15 @@ Layout make_layout(uint64_t n) {
     L.pv = take(cap * 8);
     L.uniq = take(nn * 8);
     L.cnt = take(nn * 8);
-    // off (n + 1 entries) doubles as the guard's first-occurrence array (n u32)
     L.off = take((nn + 1) * 8);
     // the radix scratch doubles as the guard's four per-bucket minima (4 * m_ws u32)
     L.tmp_k = take(std::max<uint64_t>(radix_max * 8, 16 * L.m_ws));
     L.tmp_v = take(cap * 8);
     L.status = take(2 * L.status_slot * 8);
     L.dcount = take(L.m_ws * 4);
+    L.bfound = take(L.m_ws * 4);
     L.clist = take(nn * 4);
+    L.first = take(nn * 4);
     L.rle_tile = take(rle_tiles * 8);
     L.total = o;
     return L;
@@ -164,8 +168,9 @@ cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void*
     a.status_slot = L.status_slot;
     a.dcount = at<uint32_t>(ws, L.dcount);
     a.bmin = at<uint32_t>(ws, L.tmp_k);
-    a.first_idx = at<uint32_t>(ws, L.off);
+    a.first_idx = at<uint32_t>(ws, L.first);
     a.clist = at<uint32_t>(ws, L.clist);
+    a.bfound = at<uint32_t>(ws, L.bfound);
     a.m_ws = L.m_ws;
     a.rle_tile = at<uint64_t>(ws, L.rle_tile);
     return a;
@@ -218,7 +223,6 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     mark(0);
     cafs::k_pre<<<1, 1024, 0, s>>>(a);
     if (n > cafs::kMonoPrefix) cafs::k_mono_full<<<grid_for(n, 256 * 16, cus * 4), 256, 0, s>>>(a);
-    cafs::k_plan<<<1, 256, 0, s>>>(a);
     mark(1);
     const bool countable = n >= cafs::kSmallN;  // tiny and main need N >= 2048
     if (countable)
@@ -228,27 +232,44 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
         cafs::k_hash_count<<<grid_for(n, cafs::kCountThreads * 8, cus), cafs::kCountThreads, 0, s>>>(a);
     mark(3);
     if (countable) cafs::k_compact_order<<<1, 1024, 0, s>>>(a);
-    launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s);
-    if (countable && n > cafs::kOrderMax) cafs::k_pair_scan<<<1, 1024, 0, s>>>(a);
     mark(4);
-    if (countable)
-        cafs::k_emit<<<grid_for(n, 2 * cafs::kEmitTilePairs, cus * 8), cafs::kEmitThreads, 0, s>>>(a);
+    // Fork: the branches that are idle on the common path (radix engine and pair
+    // sort with their own emit, monotone copy, run-length pass, guard resolution)
+    // run on the side stream and overlap the emit on the caller's stream.
+    // In place, the guard's first-occurrence pass reads the input that the emit
+    // overwrites, so then the emit waits for the side stream.
+    hipStream_t s2 = ctx->side;
+    const bool inplace = (in == out);
+    (void)hipEventRecord(ctx->fork, s);
+    (void)hipStreamWaitEvent(s2, ctx->fork, 0);
+    // four workgroups per CU saturate the write bandwidth and leave CU slots free
+    // for the side stream
+    const uint32_t g_emit = grid_for(n, 2 * cafs::kEmitTilePairs, cus * 4);
+    if (countable && !inplace) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 0u);
     mark(5);
-    cafs::k_copy_mono<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s>>>(a);
+    launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2);
+    if (countable && n > cafs::kOrderMax) {
+        cafs::k_pair_scan<<<1, 1024, 0, s2>>>(a);
+        cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s2>>>(a, 1u);
+    }
+    cafs::k_copy_mono<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s2>>>(a);
     const uint32_t g_rle = grid_for(n, cafs::kRleTile, cus * 4);
-    cafs::k_rle_count<<<g_rle, 256, 0, s>>>(a);
-    cafs::k_rle_write<<<g_rle, 256, 0, s>>>(a);
-    cafs::k_rle_counts<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s>>>(a);
+    cafs::k_rle_count<<<g_rle, 256, 0, s2>>>(a);
+    cafs::k_rle_write<<<g_rle, 256, 0, s2>>>(a);
+    cafs::k_rle_counts<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s2>>>(a);
     if (countable) {
         const uint32_t g = grid_for(n, 256 * 64, cus * 2);
-        cafs::k_guard_prep<<<grid_for(L.m_ws, 256 * 8, cus * 4), 256, 0, s>>>(a);
-        cafs::k_guard_bucket<<<g, 256, 0, s>>>(a);
-        cafs::k_guard_mark<<<g, 256, 0, s>>>(a);
-        cafs::k_guard_first<<<grid_for(n, cafs::kGuardChunk, cus), 256, 0, s>>>(a);
-        cafs::k_guard_resolve<<<1, 1024, 0, s>>>(a);
-        for (uint32_t r = 0; r < 4; ++r) cafs::k_guard_round<<<g, 256, 0, s>>>(a, r);
-        cafs::k_guard_final<<<g, 256, 0, s>>>(a);
+        cafs::k_guard_prep<<<grid_for(L.m_ws, 256 * 8, cus * 4), 256, 0, s2>>>(a);
+        cafs::k_guard_bucket<<<g, 256, 0, s2>>>(a);
+        cafs::k_guard_mark<<<g, 256, 0, s2>>>(a);
+        cafs::k_guard_first<<<grid_for(n, cafs::kGuardChunk, cus), 256, 0, s2>>>(a);
+        cafs::k_guard_resolve<<<1, 1024, 0, s2>>>(a);
+        for (uint32_t r = 0; r < 4; ++r) cafs::k_guard_round<<<g, 256, 0, s2>>>(a, r);
+        cafs::k_guard_final<<<g, 256, 0, s2>>>(a);
     }
+    (void)hipEventRecord(ctx->join, s2);
+    (void)hipStreamWaitEvent(s, ctx->join, 0);
+    if (countable && inplace) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 0u);
     cafs::k_finalize<<<1, 64, 0, s>>>(a);
     mark(6);
     if (!evs.empty()) ctx->calls.push_back(evs);
@@ -294,6 +315,16 @@ cafs_status_t cafs_ctx_create(cafs_ctx_t** ctx, int device) {
     c->device = device;
     c->cus = cus > 0 ? cus : 1;
     c->timing = false;
+    {
+        DeviceGuard dg(device);
+        e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail(e, "side stream");
+        }
+    }
     *ctx = c;
     return CAFS_OK;
 }
@@ -303,6 +334,12 @@ void cafs_ctx_destroy(cafs_ctx_t* ctx) {
     for (auto& call : ctx->calls)
         for (hipEvent_t e : call) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    {
+        DeviceGuard dg(ctx->device);
+        (void)hipEventDestroy(ctx->fork);
+        (void)hipEventDestroy(ctx->join);
+        (void)hipStreamDestroy(ctx->side);
+    }
     delete ctx;
 }
 

@@ -27,8 +27,9 @@ constexpr uint64_t kEmpty = ~0ull;             // empty-slot marker of the GPU h
                                                // keys equal to it are counted apart
 constexpr uint32_t kMonoPrefix = 1u << 13;     // elements the pre kernel checks for order
 constexpr int kCountThreads = 1024;            // hash-count workgroup
-constexpr uint32_t kLdsSlotsLog2 = 13;         // per-workgroup LDS table: 8192 slots
-constexpr uint32_t kLdsProbe = 32;             // LDS probe limit before the global table
+constexpr uint32_t kLdsBuckets = 3072;         // per-workgroup LDS table: 3072 buckets of 4 keys
+constexpr uint32_t kLdsBucketSlots = 4;        // (12288 slots, 144 KiB with 32-bit counts)
+constexpr uint32_t kLdsProbeBuckets = 8;       // buckets probed before the global table
 constexpr uint32_t kGlobalProbe = 4096;        // global probe limit before overflow
 constexpr uint32_t kMinTableLog2 = 12;         // smallest global table (4096 slots)
 constexpr uint32_t kMaxTableLog2 = 22;         // largest global table (4M slots, 64 MiB)
@@ -75,6 +76,7 @@ struct Ctrl {
     // monotone check
     uint32_t inversion;
     uint32_t mono_full;               // the full order check is still needed
+    uint32_t mono_done;               // workgroups of the full order check that finished
     // Chao1 estimate
     uint64_t k_hat, u, f1, f2, n_samples, stride;
     uint32_t saturated;
@@ -96,6 +98,7 @@ struct Ctrl {
     uint64_t ecount;                  // elements equal to kEmpty
     // dense (key, count) arrays
     uint64_t K;
+    uint32_t emit_main;               // dense arrays from the tiny or single-workgroup order path
     uint32_t dense_ready;
     uint32_t pair_sort;
     uint32_t radix_on;
@@ -112,6 +115,8 @@ struct Ctrl {
     uint32_t guard_general;           // bucket counts must be built from the dense pairs
     uint32_t guard_rounds;            // too many contested keys for one workgroup
     uint64_t n_contested;
+    uint64_t n_cbuckets;              // buckets holding more than four distinct keys
+    uint64_t buckets_done;            // of those, buckets whose first four keys are known
     uint64_t found;
     uint32_t chunk_ctr;
     uint32_t guard_done;
@@ -152,6 +157,7 @@ struct Args {
     uint32_t* bmin;                   // 4 * m_ws entries
     uint32_t* first_idx;              // n entries
     uint32_t* clist;                  // n entries: indices of contested keys
+    uint32_t* bfound;                 // m_ws entries: contested keys seen per bucket
     uint64_t m_ws;
     // run-length scratch
     uint64_t* rle_tile;               // per-tile run counts

@@ -49,23 +49,44 @@ __global__ __launch_bounds__(256) void k_phase2(Args a) {
     uint64_t key[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) key[j] = c->tiny_keys[j];
-    uint64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const uint64_t P = num_pairs(a.n, a.in_head);
-    // every lane of a wave iterates the same number of times so that ballots see the wave
+    uint32_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // per wave, fits: a wave sees < 2^32 elements
+    const uint32_t head = a.in_head;
+    const uint64_t P = num_pairs(a.n, head);
+    const uint64_t Pf = (a.n + head) / 2;
+    constexpr int U = 8;  // pairs in flight per lane
+    // every lane of a wave runs the same iterations so that each ballot sees the whole wave
     const uint64_t waves_total = gstride / 64;
     const uint64_t wave_id = gtid / 64;
     const uint32_t lane = __lane_id();
-    for (uint64_t pb = wave_id * 64; pb < P; pb += waves_total * 64) {
-        const uint64_t p = pb + lane;
-        uint64_t v0 = 0, v1 = 0;
-        bool ok0 = false, ok1 = false;
-        if (p < P) load_pair(a.in, a.n, a.in_head, p, v0, v1, ok0, ok1);
+    for (uint64_t pb = wave_id * 64 * U; pb < P; pb += waves_total * 64 * U) {
+        uint64_t v[2 * U];
+        uint32_t okm = 0;
+        if (pb >= head && pb + 64 * U <= Pf) {
+            const u64x2* src = reinterpret_cast<const u64x2*>(a.in + 2 * (pb + lane) - head);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (j < (int)nk) {
-                cnt[j] += __popcll(__ballot(ok0 && v0 == key[j]));
-                cnt[j] += __popcll(__ballot(ok1 && v1 == key[j]));
+            for (int u = 0; u < U; ++u) {
+                const u64x2 w = src[u * 64];
+                v[2 * u] = w.x;
+                v[2 * u + 1] = w.y;
             }
+            okm = (1u << (2 * U)) - 1;
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t p = pb + (uint64_t)u * 64 + lane;
+                bool o0 = false, o1 = false;
+                v[2 * u] = v[2 * u + 1] = 0;
+                if (p < P) load_pair(a.in, a.n, head, p, v[2 * u], v[2 * u + 1], o0, o1);
+                okm |= (o0 ? 1u : 0u) << (2 * u);
+                okm |= (o1 ? 1u : 0u) << (2 * u + 1);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 2 * U; ++e) {
+            const bool in = (okm >> e) & 1u;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (j < (int)nk) cnt[j] += (uint32_t)__popcll(__ballot(in && v[e] == key[j]));
         }
     }
     if (lane == 0) {
@@ -116,35 +137,56 @@ __device__ __forceinline__ void global_insert(const Args& a, Ctrl* c, uint64_t v
 }
 
 // ---------------------------------------------------------------------------
-// Hash count (main path, Sec. 4.4).  The paper's x86 hot loop updates one
-// cache-line bucket per element.  Here each workgroup owns an open-addressing
-// table of 8192 (key, count) slots in LDS; an element hashes to a slot (Eq. hash)
-// and, when the slot already holds it (the common case once the table is warm),
-// adds 1 with an LDS atomic.  That fast path is straight-line code for the eight
-// keys a thread holds, while the loads of its next eight keys are in flight.
-// Keys that miss their home slot take the slow path: linear probing, claiming an
-// empty slot with a 64-bit LDS CAS, and after kLdsProbe slots the global table.
-// At the end each workgroup flushes its occupied slots to the global table.
-// Elements equal to the empty marker are counted in registers.
+// Hash count (main path, Sec. 4.4).  The paper's hot loop updates a bucket of four
+// 64-bit keys on one cache line (Sec. 4.2, Alg. 1).  Here each workgroup owns a
+// table of 3072 such buckets in LDS (12288 keys with 32-bit counters).  An element
+// hashes to a bucket (Eq. hash, reduced to 3072 by a multiply), reads its four keys
+// with two 16-byte LDS loads and compares them with the element, the GPU analogue
+// of the paper's cmpeq + movemask + tzcnt; on a match it adds 1 to that slot's
+// counter with an LDS atomic.  Within a bucket occupied slots form a prefix and a
+// key is stored in the first bucket, in probe order, that had room for it, so a
+// lookup can stop at the first bucket with a free slot.  The fast path covers the
+// home bucket and, when that one is full, the next bucket, as straight-line code
+// for the eight keys a thread holds while the loads of its next eight keys are in
+// flight.  Other keys take the slow path: claim the first free slot of the first
+// bucket with room by a 64-bit LDS CAS, and after kLdsProbeBuckets full buckets go
+// to the global table.  At the end each workgroup flushes its occupied slots to
+// the global table.  Elements equal to the empty marker are counted in registers.
 //
 // This kernel also resolves the tiny branch: if the tiny counters sum to N the
 // column is tiny and the dense arrays are written here; otherwise the element set
 // has an unsampled value and the main path runs with the same estimate (Sec. 4.4).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lds_bucket(uint64_t x) {
+    return (uint32_t)(((uint64_t)phi_hash32(x, 32) * kLdsBuckets) >> 32);
+}
+
 __device__ __forceinline__ void lds_insert_slow(const Args& a, Ctrl* c, uint64_t* skeys, uint32_t* scnt, uint64_t x) {
-    constexpr uint32_t S = 1u << kLdsSlotsLog2;
-    uint32_t h = phi_hash32(x, kLdsSlotsLog2);
-    for (uint32_t pr = 0; pr < kLdsProbe; ++pr) {
-        const uint64_t k = skeys[h];
-        if (k == x) { atomicAdd(&scnt[h], 1u); return; }
-        if (k == kEmpty) {
-            const unsigned long long old =
-                atomicCAS((unsigned long long*)&skeys[h], (unsigned long long)kEmpty, (unsigned long long)x);
-            if (old == kEmpty || old == x) { atomicAdd(&scnt[h], 1u); return; }
+    uint32_t b = lds_bucket(x);
+    for (uint32_t pr = 0; pr < kLdsProbeBuckets; ++pr) {
+        const uint32_t base = b * kLdsBucketSlots;
+        for (uint32_t s = 0; s < kLdsBucketSlots; ++s) {
+            const uint64_t k = skeys[base + s];
+            if (k == x) { atomicAdd(&scnt[s * kLdsBuckets + b], 1u); return; }
+            if (k == kEmpty) {
+                const unsigned long long old = atomicCAS((unsigned long long*)&skeys[base + s],
+                                                         (unsigned long long)kEmpty, (unsigned long long)x);
+                if (old == kEmpty || old == x) { atomicAdd(&scnt[s * kLdsBuckets + b], 1u); return; }
+                // another key took the slot: the next slot may be free
+            }
         }
-        h = (h + 1) & (S - 1);
+        b = (b + 1 == kLdsBuckets) ? 0 : b + 1;
     }
     global_insert(a, c, x, 1);
+}
+
+// Slot of x among the four keys of a bucket, or -1; `full` tells whether the last
+// slot is taken (then x may sit in a later bucket).
+__device__ __forceinline__ int match4(const uint64_t* skeys, uint32_t b, uint64_t x, bool& full) {
+    const u64x2 lo = *reinterpret_cast<const u64x2*>(skeys + b * kLdsBucketSlots);
+    const u64x2 hi = *reinterpret_cast<const u64x2*>(skeys + b * kLdsBucketSlots + 2);
+    full = hi.y != kEmpty;
+    return lo.x == x ? 0 : lo.y == x ? 1 : hi.x == x ? 2 : hi.y == x ? 3 : -1;
 }
 
 __global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
@@ -166,6 +208,7 @@ __global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
                 a.off[nk] = run;
                 c->K = nk;
                 c->dense_ready = 1;
+                c->emit_main = 1;
             }
             return;
         }
@@ -178,8 +221,8 @@ __global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
         return;
     }
 
-    constexpr uint32_t S = 1u << kLdsSlotsLog2;
-    __shared__ uint64_t skeys[S];
+    constexpr uint32_t S = kLdsBuckets * kLdsBucketSlots;
+    __shared__ __attribute__((aligned(16))) uint64_t skeys[S];
     __shared__ uint32_t scnt[S];
     for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
         skeys[i] = kEmpty;
@@ -236,9 +279,17 @@ __global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
             const bool is_empty_key = x[e] == kEmpty;
             ecnt += (in && is_empty_key) ? 1u : 0u;
             const bool want = in && !is_empty_key;
-            const uint32_t h = phi_hash32(x[e], kLdsSlotsLog2);
-            const bool hit = want && (skeys[h] == x[e]);
-            atomicAdd(&scnt[h], hit ? 1u : 0u);  // branch-free: a miss adds 0
+            uint32_t b = lds_bucket(x[e]);
+            bool full;
+            int m = match4(skeys, b, x[e], full);
+            if (m < 0 && full) {  // home bucket full without x: x may be in the next one
+                b = (b + 1 == kLdsBuckets) ? 0 : b + 1;
+                m = match4(skeys, b, x[e], full);
+            }
+            const bool hit = want && m >= 0;
+            // counters are slot-major (slot s of bucket b at s * 3072 + b) so that the
+            // first slots of many buckets spread over the LDS banks; a miss adds 0
+            atomicAdd(&scnt[(m < 0 ? 0 : m) * kLdsBuckets + b], hit ? 1u : 0u);
             pend |= (want && !hit) ? (1u << e) : 0u;
         }
         if (pend) {
@@ -249,9 +300,9 @@ __global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
         base = next;
     }
     __syncthreads();
-    for (uint32_t s = threadIdx.x; s < S; s += blockDim.x) {
-        const uint32_t cn = scnt[s];
-        if (cn) global_insert(a, c, skeys[s], cn);
+    for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
+        const uint32_t cn = scnt[i];  // slot i / 3072 of bucket i % 3072; never 0 once claimed
+        if (cn) global_insert(a, c, skeys[(i % kLdsBuckets) * kLdsBucketSlots + i / kLdsBuckets], cn);
     }
     const uint32_t wsum = wave_sum_u32(ecnt);
     if (__lane_id() == 0 && wsum) atomicAdd((unsigned long long*)&c->ecount, (unsigned long long)wsum);
@@ -353,6 +404,7 @@ __global__ __launch_bounds__(1024) void k_compact_order(Args a) {
         a.off[K] = total;
         c->K = K;
         c->dense_ready = 1;
+        c->emit_main = 1;
     }
     // guard check on the paper's M buckets (main path only): count the distinct keys
     // of each bucket in LDS and list the keys of buckets holding more than four
@@ -371,10 +423,16 @@ __global__ __launch_bounds__(1024) void k_compact_order(Args a) {
     __syncthreads();
     for (uint32_t i = tid; i < K; i += blockDim.x) atomicAdd(&bc[phi_hash32(sk[i] ^ flip, lg)], 1u);
     __syncthreads();
-    uint32_t over = 0;
+    __shared__ uint32_t s_nb;
+    if (tid == 0) s_nb = 0;
+    __syncthreads();
+    uint32_t over = 0, over_b = 0;
     for (uint32_t i = tid; i < K; i += blockDim.x) over += bc[phi_hash32(sk[i] ^ flip, lg)] > kBucketCap;
+    for (uint32_t i = tid; i < M; i += blockDim.x) over_b += bc[i] > kBucketCap;
     over = wave_sum_u32(over);
+    over_b = wave_sum_u32(over_b);
     if (__lane_id() == 0 && over) atomicAdd(&s_nc, over);
+    if (__lane_id() == 0 && over_b) atomicAdd(&s_nb, over_b);
     __syncthreads();
     const uint32_t nc = s_nc;
     if (nc > kGuardLdsKeys) {
@@ -389,6 +447,7 @@ __global__ __launch_bounds__(1024) void k_compact_order(Args a) {
         if (bc[phi_hash32(sk[i] ^ flip, lg)] > kBucketCap) a.clist[atomicAdd(&s_nc, 1u)] = i;
     if (tid == 0) {
         c->n_contested = nc;
+        c->n_cbuckets = s_nb;
         c->guard_on = nc > 0;
     }
 }

@@ -9,7 +9,7 @@ namespace cafs {
 constexpr uint32_t kEmitPairsPerThread = 8;
 constexpr uint32_t kEmitThreads = 256;
 constexpr uint64_t kEmitTilePairs = (uint64_t)kEmitPairsPerThread * kEmitThreads;  // 2048 pairs
-constexpr uint32_t kEmitLdsRuns = 2048;
+constexpr uint32_t kEmitLdsRuns = 512;  // small LDS footprint leaves room for the side stream
 
 // Largest j in [lo, hi] with off[j] <= e (off is nondecreasing, off[lo] <= e).
 template <typename OffT>
@@ -40,9 +40,12 @@ __device__ __forceinline__ void store_pair(uint64_t* __restrict__ y, uint64_t n,
 // Output tiles of 4096 elements; each tile finds the runs it covers by binary
 // search in the run offsets.  A tile inside one run is a plain fill; otherwise the
 // tile's offsets and keys are staged in LDS and each element searches there.
-__global__ __launch_bounds__(kEmitThreads) void k_emit(Args a) {
+// `after_pair_sort` selects the instance: one runs on the caller's stream right
+// after the single-workgroup order kernel (or the tiny branch), the other on the
+// side stream after the pair sort; exactly one of them has work.
+__global__ __launch_bounds__(kEmitThreads) void k_emit(Args a, uint32_t after_pair_sort) {
     Ctrl* c = a.c;
-    if (!c->dense_ready || c->overflow) return;
+    if (after_pair_sort ? !(c->pair_sort && c->dense_ready && !c->overflow) : !c->emit_main) return;
     const uint64_t n = a.n;
     const uint64_t K = c->K;
     const uint32_t head = a.out_head;

@@ -98,61 +98,6 @@ __device__ void chao1_block(const uint64_t* __restrict__ x, uint64_t n, uint64_t
     }
 }
 
-// First kernel of a sort: order check of a prefix and the Chao1 estimate.
-__global__ __launch_bounds__(1024) void k_pre(Args a) {
-    Ctrl* c = a.c;
-    __shared__ uint32_t s_inv;
-    __shared__ Chao1Result s_res;
-    if (threadIdx.x == 0) s_inv = 0;
-    __syncthreads();
-    const uint64_t lim = a.n < kMonoPrefix ? a.n : kMonoPrefix;
-    uint32_t inv = 0;
-    for (uint64_t i = threadIdx.x; i + 1 < lim; i += blockDim.x)
-        inv |= (a.in[i] ^ a.flip) > (a.in[i + 1] ^ a.flip);
-    if (inv) s_inv = 1;
-    chao1_block(a.in, a.n, a.flip, &s_res);  // contains __syncthreads
-    if (threadIdx.x == 0) {
-        c->inversion = s_inv;
-        c->mono_full = (!s_inv && a.n > kMonoPrefix) ? 1u : 0u;
-        c->k_hat = s_res.k_hat; c->u = s_res.u; c->f1 = s_res.f1; c->f2 = s_res.f2;
-        c->n_samples = s_res.n_samples; c->stride = s_res.stride;
-        c->saturated = s_res.saturated;
-        c->n_tiny = s_res.n_small;
-        for (uint32_t i = 0; i < 8; ++i) c->tiny_keys[i] = i < s_res.n_small ? s_res.small[i] : 0;
-    }
-}
-
-// Standalone estimate (cafs_estimate).
-__global__ __launch_bounds__(1024) void k_estimate_only(const uint64_t* x, uint64_t n,
-                                                        cafs_estimate_t* out) {
-    __shared__ Chao1Result s_res;
-    chao1_block(x, n, 0, &s_res);
-    if (threadIdx.x == 0) {
-        cafs_estimate_t e;
-        e.k_hat = s_res.k_hat; e.u = s_res.u; e.f1 = s_res.f1; e.f2 = s_res.f2;
-        e.n_samples = s_res.n_samples; e.stride = s_res.stride;
-        e.saturated = s_res.saturated; e.pad = 0;
-        *out = e;
-    }
-}
-
-// Full order check, only when the prefix was in order (IsMonotone, Alg. 3).  Exits
-// early once any workgroup has found an inversion.
-__global__ __launch_bounds__(256) void k_mono_full(Args a) {
-    Ctrl* c = a.c;
-    if (!c->mono_full) return;
-    const uint64_t n = a.n;
-    const uint64_t chunk = 256 * 16;
-    for (uint64_t base = (uint64_t)blockIdx.x * chunk; base + 1 < n; base += (uint64_t)gridDim.x * chunk) {
-        if (atomic_load_agent(&c->inversion)) return;
-        uint32_t inv = 0;
-        const uint64_t end = (base + chunk < n - 1) ? base + chunk : n - 1;  // pairs (i, i+1), i < end
-        for (uint64_t i = base + threadIdx.x; i < end; i += 256)
-            inv |= (a.in[i] ^ a.flip) > (a.in[i + 1] ^ a.flip);
-        if (__any(inv) && __lane_id() == 0) atomicOr(&c->inversion, 1u);
-    }
-}
-
 // Eq. Msize with cap = 4: M = bit_ceil(8 K^ / 4) clamped to [8, bit_ceil(N / 4)].
 __device__ __forceinline__ uint64_t paper_table_M(uint64_t k_hat, uint64_t n) {
     uint64_t m = bit_ceil64(8 * k_hat / kBucketCap);
@@ -163,13 +108,13 @@ __device__ __forceinline__ uint64_t paper_table_M(uint64_t k_hat, uint64_t n) {
 }
 
 // Dispatcher (Alg. 3): picks the path and the engine and resets the counters
-// of the later stages.  One workgroup.
-__global__ __launch_bounds__(256) void k_plan(Args a) {
+// of the later stages.  Called by every thread of one workgroup once the order
+// check is settled: by the pre kernel when its prefix already shows an inversion
+// (or covers the column), else by the last workgroup of the full order check.
+__device__ void plan_block(const Args& a) {
     Ctrl* c = a.c;
     const uint64_t n = a.n;
-    // reset counters (all threads)
     for (uint32_t i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&c->hist[0][0])[i] = 0;
-    __syncthreads();
     if (threadIdx.x != 0) return;
     const bool mono = (n <= 1) || !c->inversion;
     int32_t path;
@@ -202,6 +147,7 @@ __global__ __launch_bounds__(256) void k_plan(Args a) {
     c->claimed = 0;
     c->ecount = 0;
     c->K = 0;
+    c->emit_main = 0;
     c->dense_ready = 0;
     c->pair_sort = 0;
     c->radix_on = (engine == E_RADIX);
@@ -212,6 +158,8 @@ __global__ __launch_bounds__(256) void k_plan(Args a) {
     c->rle_done = 0;
     c->rle_on = 0;
     c->n_contested = 0;
+    c->n_cbuckets = 0;
+    c->buckets_done = 0;
     c->found = 0;
     c->chunk_ctr = 0;
     c->guard_done = 0;
@@ -224,6 +172,80 @@ __global__ __launch_bounds__(256) void k_plan(Args a) {
     j.has_vals = 0;
     j.n_active = 0;
     j.copy_mode = 0;
+}
+
+// First kernel of a sort: order check of a prefix and the Chao1 estimate.
+__global__ __launch_bounds__(1024) void k_pre(Args a) {
+    Ctrl* c = a.c;
+    __shared__ uint32_t s_inv;
+    __shared__ Chao1Result s_res;
+    if (threadIdx.x == 0) s_inv = 0;
+    __syncthreads();
+    const uint64_t lim = a.n < kMonoPrefix ? a.n : kMonoPrefix;
+    uint32_t inv = 0;
+    for (uint64_t i = threadIdx.x; i + 1 < lim; i += blockDim.x)
+        inv |= (a.in[i] ^ a.flip) > (a.in[i + 1] ^ a.flip);
+    if (inv) s_inv = 1;
+    chao1_block(a.in, a.n, a.flip, &s_res);  // contains __syncthreads
+    const bool settled = s_inv || a.n <= kMonoPrefix;
+    if (threadIdx.x == 0) {
+        c->inversion = s_inv;
+        c->mono_full = settled ? 0u : 1u;
+        c->mono_done = 0;
+        c->k_hat = s_res.k_hat; c->u = s_res.u; c->f1 = s_res.f1; c->f2 = s_res.f2;
+        c->n_samples = s_res.n_samples; c->stride = s_res.stride;
+        c->saturated = s_res.saturated;
+        c->n_tiny = s_res.n_small;
+        for (uint32_t i = 0; i < 8; ++i) c->tiny_keys[i] = i < s_res.n_small ? s_res.small[i] : 0;
+    }
+    if (settled) {
+        __syncthreads();
+        plan_block(a);
+    }
+}
+
+// Standalone estimate (cafs_estimate).
+__global__ __launch_bounds__(1024) void k_estimate_only(const uint64_t* x, uint64_t n,
+                                                        cafs_estimate_t* out) {
+    __shared__ Chao1Result s_res;
+    chao1_block(x, n, 0, &s_res);
+    if (threadIdx.x == 0) {
+        cafs_estimate_t e;
+        e.k_hat = s_res.k_hat; e.u = s_res.u; e.f1 = s_res.f1; e.f2 = s_res.f2;
+        e.n_samples = s_res.n_samples; e.stride = s_res.stride;
+        e.saturated = s_res.saturated; e.pad = 0;
+        *out = e;
+    }
+}
+
+// Full order check, only when the prefix was in order (IsMonotone, Alg. 3).  Exits
+// early once any workgroup has found an inversion.
+__global__ __launch_bounds__(256) void k_mono_full(Args a) {
+    Ctrl* c = a.c;
+    if (!c->mono_full) return;
+    const uint64_t n = a.n;
+    const uint64_t chunk = 256 * 16;
+    __shared__ uint32_t s_stop, s_last;
+    for (uint64_t base = (uint64_t)blockIdx.x * chunk; base + 1 < n; base += (uint64_t)gridDim.x * chunk) {
+        if (threadIdx.x == 0) s_stop = atomic_load_agent(&c->inversion);
+        __syncthreads();
+        if (s_stop) break;
+        uint32_t inv = 0;
+        const uint64_t end = (base + chunk < n - 1) ? base + chunk : n - 1;  // pairs (i, i+1), i < end
+        for (uint64_t i = base + threadIdx.x; i < end; i += 256)
+            inv |= (a.in[i] ^ a.flip) > (a.in[i + 1] ^ a.flip);
+        if (__any(inv) && __lane_id() == 0) atomicOr(&c->inversion, 1u);
+        __syncthreads();
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(&c->mono_done, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (threadIdx.x == 0) c->inversion = atomic_load_agent(&c->inversion);
+    __syncthreads();
+    plan_block(a);
 }
 
 // Writes the caller's report.  One thread.

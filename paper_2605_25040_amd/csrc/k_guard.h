@@ -69,6 +69,14 @@ __global__ __launch_bounds__(256) void k_guard_mark(Args a) {
     if (!guard_active(c)) return;
     const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t M = c->table_M;
+    uint32_t nb = 0;
+    for (uint64_t b = gtid; b < M; b += gstride) {
+        a.bfound[b] = 0;
+        if (c->guard_general) nb += a.dcount[b] > kBucketCap;
+    }
+    nb = wave_sum_u32(nb);
+    if (__lane_id() == 0 && nb) atomicAdd((unsigned long long*)&c->n_cbuckets, (unsigned long long)nb);
     if (c->guard_general) {
         const uint64_t K = c->K;
         const uint32_t lg = log2_pow2(c->table_M);
@@ -94,10 +102,12 @@ __device__ __forceinline__ uint64_t find_key(const uint64_t* uq, uint64_t K, uin
     return lo;
 }
 
-// First occurrence of every contested key.  Chunks of the input are claimed in
-// increasing order; a workgroup stops claiming once every contested key has been
-// seen, because a chunk claimed later cannot hold the first occurrence of a key
-// already seen in an earlier chunk, and every claimed chunk is finished.  With at
+// First occurrences of the contested keys.  Chunks of the input are claimed in
+// increasing order and every claimed chunk is finished, so the minima found so far
+// are exact for every key seen in a claimed chunk.  A workgroup stops claiming
+// once every contested bucket has seen four of its keys: a key first seen in a
+// later chunk occurs after those four and cannot be among the bucket's first four,
+// so its first occurrence (left at the maximum) does not change the spill.  With at
 // most kGuardLdsKeys contested keys each workgroup keeps them in an LDS hash table
 // with per-key minima that it merges into the global minima after each chunk;
 // otherwise each element of a contested bucket is located by binary search.
@@ -148,7 +158,7 @@ __global__ __launch_bounds__(256) void k_guard_first(Args a) {
     // equal to its empty marker; such a key takes the binary-search path.
     while (true) {
         if (threadIdx.x == 0) {
-            s_stop = atomic_load_agent(&c->found) >= nc;
+            s_stop = atomic_load_agent(&c->buckets_done) >= c->n_cbuckets;
             s_chunk = s_stop ? 0 : atomicAdd(&c->chunk_ctr, 1u);
         }
         __syncthreads();
@@ -175,7 +185,7 @@ __global__ __launch_bounds__(256) void k_guard_first(Args a) {
             } else if (bits || a.dcount[b] > kBucketCap) {
                 const uint64_t jj = find_key(a.uniq, K, v, flip);
                 const uint32_t old = atomicMin(&a.first_idx[jj], (uint32_t)i);
-                newly += (old == kNoIndex);
+                if (old == kNoIndex && atomicAdd(&a.bfound[b], 1u) == kBucketCap - 1) ++newly;
             }
         }
         if (small) {
@@ -184,13 +194,16 @@ __global__ __launch_bounds__(256) void k_guard_first(Args a) {
                 const uint32_t m = lmin[li];
                 if (m < lsent[li]) {
                     lsent[li] = m;
-                    const uint32_t old = atomicMin(&a.first_idx[a.clist[li]], m);
-                    newly += (old == kNoIndex);
+                    const uint32_t j = a.clist[li];
+                    const uint32_t old = atomicMin(&a.first_idx[j], m);
+                    if (old == kNoIndex && atomicAdd(&a.bfound[phi_hash32(a.uniq[j], lg)], 1u) == kBucketCap - 1)
+                        ++newly;
                 }
             }
         }
-        newly = wave_sum_u32(newly);
-        if (__lane_id() == 0 && newly) atomicAdd((unsigned long long*)&c->found, (unsigned long long)newly);
+        newly = wave_sum_u32(newly);  // buckets that now know four keys
+        if (__lane_id() == 0 && newly)
+            atomicAdd((unsigned long long*)&c->buckets_done, (unsigned long long)newly);
         __syncthreads();
     }
 }
