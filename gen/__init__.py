@@ -91,3 +91,27 @@ def zipf_cdf(k, s):
     cdf = np.empty(int(k), dtype=np.float64)
     _load().gen_zipf_cdf(cdf.ctypes.data, int(k), float(s))
     return cdf
+
+
+def batch_spec(n_cols, seed=7, n_lo=1e3, n_hi=1e7, k_cap=1e5, total=None):
+    """Column shapes of the batched workload.
+
+    N log-uniform in [n_lo, n_hi]; K log-uniform in [2, min(N/2, k_cap)]; each
+    column uniform or Zipf(1.1) frequencies by a fair coin; one seed per column
+    (42 + N + K + 2^40 * column).  With ``total`` every N is scaled so that the
+    sum is about ``total`` (floor n_lo) and K is re-clipped to N/2.
+    Returns a list of dicts (n, k, dist, s, seed).
+    """
+    import math
+    rng = np.random.default_rng(seed)
+    ns = np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), size=n_cols))
+    if total is not None:
+        ns = np.maximum(n_lo, ns * (float(total) / ns.sum()))
+    ns = ns.astype(np.int64)
+    out = []
+    for i, n in enumerate(ns):
+        khi = max(2.0, min(n / 2.0, k_cap))
+        k = int(math.exp(rng.uniform(math.log(2.0), math.log(khi)))) if khi > 2 else 2
+        dist = "zipf" if rng.random() < 0.5 else "uniform"
+        out.append(dict(n=int(n), k=max(2, k), dist=dist, s=1.1, seed=default_seed(n, k, column=i)))
+    return out

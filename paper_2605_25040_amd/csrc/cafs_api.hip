@@ -23,6 +23,10 @@ struct cafs_ctx {
     int cus;
     hipStream_t side;       // default-priority stream for the branches that overlap the emit
     hipEvent_t fork, join;  // side stream starts after the order kernel; the report waits for it
+    void* staging;          // pinned host buffer for the block tables of batched calls
+    size_t staging_bytes;
+    hipEvent_t staged;      // the last upload from `staging` has been consumed
+    bool staged_pending;
     bool timing;
     std::vector<hipEvent_t> pool;                 // free events
     std::vector<std::vector<hipEvent_t>> calls;   // CAFS_N_STAGES + 1 events per recorded call
@@ -55,8 +59,7 @@ uint32_t log2_host(uint64_t p) {
 
 // Workspace of one column of n keys.  Regions are 256-byte aligned.
 struct Layout {
-    size_t ctrl, gkeys, gcnt, claimed, pk, pv, uniq, cnt, off, tmp_k, tmp_v, status, dcount, bfound, clist, first,
-        rle_tile;
+    size_t ctrl, gkeys, gcnt, claimed, uniq, cnt, off, tmp_k, status, dcount, bfound, bmin, clist, first, rle_tile;
     size_t total;
     uint32_t cap_log2;
     uint64_t status_slot;
@@ -66,7 +69,9 @@ struct Layout {
 Layout make_layout(uint64_t n) {
     Layout L{};
     const uint64_t nn = n > 0 ? n : 1;
-    uint32_t lg = log2_host(bit_ceil_host(std::max<uint64_t>(4 * nn, 1ull << cafs::kMinTableLog2)));
+    // the global table never needs more than bit_ceil(n) slots (K <= n); the device
+    // picks a smaller one from the estimate
+    uint32_t lg = log2_host(bit_ceil_host(std::max<uint64_t>(nn, 1ull << cafs::kMinTableLog2)));
     lg = std::min<uint32_t>(std::max<uint32_t>(lg, cafs::kMinTableLog2), cafs::kMaxTableLog2);
     L.cap_log2 = lg;
     const uint64_t cap = 1ull << lg;
@@ -81,17 +86,14 @@ Layout make_layout(uint64_t n) {
     L.gkeys = take(cap * 8);
     L.gcnt = take(cap * 8);
     L.claimed = take(cap * 4);
-    L.pk = take(cap * 8);
-    L.pv = take(cap * 8);
     L.uniq = take(nn * 8);
     L.cnt = take(nn * 8);
     L.off = take((nn + 1) * 8);
-    // the radix scratch doubles as the guard's four per-bucket minima (4 * m_ws u32)
-    L.tmp_k = take(std::max<uint64_t>(radix_max * 8, 16 * L.m_ws));
-    L.tmp_v = take(cap * 8);
+    L.tmp_k = take(nn * 8);
     L.status = take(2 * L.status_slot * 8);
     L.dcount = take(L.m_ws * 4);
     L.bfound = take(L.m_ws * 4);
+    L.bmin = take(L.m_ws * 16);
     L.clist = take(nn * 4);
     L.first = take(nn * 4);
     L.rle_tile = take(rle_tiles * 8);
@@ -160,14 +162,11 @@ cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void*
     a.gcnt = at<uint64_t>(ws, L.gcnt);
     a.claimed = at<uint32_t>(ws, L.claimed);
     a.cap_ws_log2 = L.cap_log2;
-    a.pk = at<uint64_t>(ws, L.pk);
-    a.pv = at<uint64_t>(ws, L.pv);
     a.tmp_k = at<uint64_t>(ws, L.tmp_k);
-    a.tmp_v = at<uint64_t>(ws, L.tmp_v);
     a.status = at<uint64_t>(ws, L.status);
     a.status_slot = L.status_slot;
     a.dcount = at<uint32_t>(ws, L.dcount);
-    a.bmin = at<uint32_t>(ws, L.tmp_k);
+    a.bmin = at<uint32_t>(ws, L.bmin);
     a.first_idx = at<uint32_t>(ws, L.first);
     a.clist = at<uint32_t>(ws, L.clist);
     a.bfound = at<uint32_t>(ws, L.bfound);
@@ -248,10 +247,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     if (countable && !inplace) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 0u);
     mark(5);
     launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2);
-    if (countable && n > cafs::kOrderMax) {
-        cafs::k_pair_scan<<<1, 1024, 0, s2>>>(a);
-        cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s2>>>(a, 1u);
-    }
+    if (countable && n > cafs::kOrderMax) cafs::k_pair_scan<<<1, 1024, 0, s2>>>(a);
     cafs::k_copy_mono<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s2>>>(a);
     const uint32_t g_rle = grid_for(n, cafs::kRleTile, cus * 4);
     cafs::k_rle_count<<<g_rle, 256, 0, s2>>>(a);
@@ -266,6 +262,9 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
         cafs::k_guard_resolve<<<1, 1024, 0, s2>>>(a);
         for (uint32_t r = 0; r < 4; ++r) cafs::k_guard_round<<<g, 256, 0, s2>>>(a, r);
         cafs::k_guard_final<<<g, 256, 0, s2>>>(a);
+        // outputs written after the guard: it reads the input, which an in-place sort overwrites
+        cafs::k_copy_deferred<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s2>>>(a);
+        if (n > cafs::kOrderMax) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s2>>>(a, 1u);
     }
     (void)hipEventRecord(ctx->join, s2);
     (void)hipStreamWaitEvent(s, ctx->join, 0);
@@ -315,11 +314,15 @@ cafs_status_t cafs_ctx_create(cafs_ctx_t** ctx, int device) {
     c->device = device;
     c->cus = cus > 0 ? cus : 1;
     c->timing = false;
+    c->staging = nullptr;
+    c->staging_bytes = 0;
+    c->staged_pending = false;
     {
         DeviceGuard dg(device);
         e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->staged, hipEventDisableTiming);
         if (e != hipSuccess) {
             delete c;
             return hip_fail(e, "side stream");
@@ -338,6 +341,9 @@ void cafs_ctx_destroy(cafs_ctx_t* ctx) {
         DeviceGuard dg(ctx->device);
         (void)hipEventDestroy(ctx->fork);
         (void)hipEventDestroy(ctx->join);
+        if (ctx->staged_pending) (void)hipEventSynchronize(ctx->staged);
+        (void)hipEventDestroy(ctx->staged);
+        if (ctx->staging) (void)hipHostFree(ctx->staging);
         (void)hipStreamDestroy(ctx->side);
     }
     delete ctx;
@@ -415,30 +421,162 @@ cafs_status_t cafs_radix_sort(cafs_ctx_t* ctx, const void* d_in, void* d_out, ui
     return e == hipSuccess ? CAFS_OK : hip_fail(e, "launch");
 }
 
+// ---- batched calls ----------------------------------------------------------
+// Workspace of a batched call: a header (per-column call arguments and three
+// block tables) followed by one single-column workspace per column.  Every
+// kernel is launched once for the whole batch; each block works on one column.
+
+namespace {
+
+struct BatchPlan {
+    std::vector<size_t> col_off;   // workspace offset of each column
+    std::vector<uint32_t> bp, bh;  // blocks per column: general kernels, hash count
+    uint32_t total_p = 0, total_h = 0;
+    size_t off_args = 0, off_m1 = 0, off_mp = 0, off_mh = 0, header = 0, total = 0;
+};
+
+constexpr uint64_t kBatchElemsPerBlock = 1ull << 16;       // general kernels
+constexpr uint64_t kBatchElemsPerHashBlock = 1ull << 18;   // hash count (1024 threads)
+constexpr uint32_t kBatchMaxBlocks = 64;                    // per column and kernel
+
+uint32_t blocks_for(uint64_t n, uint64_t per) {
+    uint64_t b = (n + per - 1) / per;
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(b, 1), kBatchMaxBlocks);
+}
+
+BatchPlan plan_batch(const uint64_t* ns, uint32_t n_cols) {
+    BatchPlan P;
+    P.bp.resize(n_cols);
+    P.bh.resize(n_cols);
+    for (uint32_t i = 0; i < n_cols; ++i) {
+        P.bp[i] = blocks_for(ns[i], kBatchElemsPerBlock);
+        P.bh[i] = blocks_for(ns[i], kBatchElemsPerHashBlock);
+        P.total_p += P.bp[i];
+        P.total_h += P.bh[i];
+    }
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    P.off_args = take(sizeof(cafs::Args) * (size_t)n_cols);
+    // a block table: col[total], first[n_cols], count[n_cols]
+    P.off_m1 = take(4ull * (n_cols + 2ull * n_cols));
+    P.off_mp = take(4ull * (P.total_p + 2ull * n_cols));
+    P.off_mh = take(4ull * (P.total_h + 2ull * n_cols));
+    P.header = o;
+    P.col_off.resize(n_cols);
+    for (uint32_t i = 0; i < n_cols; ++i) P.col_off[i] = take(make_layout(ns[i]).total);
+    P.total = o;
+    return P;
+}
+
+void fill_table(uint32_t* dst, uint32_t n_cols, const std::vector<uint32_t>* per_col, uint32_t total) {
+    uint32_t* col = dst;
+    uint32_t* first = dst + total;
+    uint32_t* count = first + n_cols;
+    uint32_t b = 0;
+    for (uint32_t c = 0; c < n_cols; ++c) {
+        const uint32_t k = per_col ? (*per_col)[c] : 1u;
+        first[c] = b;
+        count[c] = k;
+        for (uint32_t j = 0; j < k; ++j) col[b++] = c;
+    }
+}
+
+cafs::BatchGrid grid_at(void* ws, const BatchPlan& P, size_t off, uint32_t total, uint32_t n_cols) {
+    cafs::BatchGrid g;
+    g.args = at<cafs::Args>(ws, P.off_args);
+    g.col = at<uint32_t>(ws, off);
+    g.first = g.col + total;
+    g.count = g.first + n_cols;
+    return g;
+}
+
+}  // namespace
+
 size_t cafs_batched_workspace_bytes(const uint64_t* h_ns, uint32_t n_cols) {
-    size_t m = 0;
-    for (uint32_t i = 0; h_ns && i < n_cols; ++i) m = std::max(m, make_layout(h_ns[i]).total);
-    return m;
+    if (n_cols > 0 && !h_ns) return 0;
+    return plan_batch(h_ns, n_cols).total;
 }
 
 cafs_status_t cafs_sort_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, uint32_t n_cols, void* d_ws,
                                 size_t ws_bytes, void* stream) {
     if (!ctx || (n_cols > 0 && !h_cols)) return CAFS_EINVAL;
+    if (n_cols == 0) return CAFS_OK;
+    std::vector<uint64_t> ns(n_cols);
     for (uint32_t i = 0; i < n_cols; ++i) {
         const cafs_column_t& col = h_cols[i];
         if (col.flags != 0 || (col.dtype != CAFS_I64 && col.dtype != CAFS_U64)) return CAFS_EINVAL;
         cafs_status_t st = check_buffers(col.d_in, col.d_out, col.n);
         if (st != CAFS_OK) return st;
         if ((col.d_uniq || col.d_counts) && !col.d_report) return CAFS_EINVAL;
-        if (col.n > 0 && ws_bytes < make_layout(col.n).total) return CAFS_EWORKSPACE;
+        ns[i] = col.n;
     }
+    const BatchPlan P = plan_batch(ns.data(), n_cols);
+    if (!d_ws || ws_bytes < P.total || reinterpret_cast<uintptr_t>(d_ws) % kAlign) return CAFS_EWORKSPACE;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // host image of the header, staged in pinned memory and uploaded asynchronously
+    if (ctx->staged_pending) {
+        hipError_t e = hipEventSynchronize(ctx->staged);  // the previous upload has been read
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        ctx->staged_pending = false;
+    }
+    if (ctx->staging_bytes < P.header) {
+        if (ctx->staging) (void)hipHostFree(ctx->staging);
+        ctx->staging = nullptr;
+        ctx->staging_bytes = 0;
+        hipError_t e = hipHostMalloc(&ctx->staging, P.header, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+        ctx->staging_bytes = P.header;
+    }
+    char* h = static_cast<char*>(ctx->staging);
+    cafs::Args* args = reinterpret_cast<cafs::Args*>(h + P.off_args);
     for (uint32_t i = 0; i < n_cols; ++i) {
         const cafs_column_t& col = h_cols[i];
-        cafs_status_t st = sort_impl(ctx, col.d_in, col.d_out, col.n, (cafs_dtype_t)col.dtype, col.d_uniq,
-                                     col.d_counts, col.d_report, d_ws, ws_bytes, stream);
-        if (st != CAFS_OK) return st;
+        void* cws = static_cast<char*>(d_ws) + P.col_off[i];
+        args[i] = make_args(ctx, make_layout(col.n), col.d_in, col.d_out, col.n, (cafs_dtype_t)col.dtype,
+                            col.d_uniq, col.d_counts, col.d_report, cws);
     }
-    return CAFS_OK;
+    fill_table(reinterpret_cast<uint32_t*>(h + P.off_m1), n_cols, nullptr, n_cols);
+    fill_table(reinterpret_cast<uint32_t*>(h + P.off_mp), n_cols, &P.bp, P.total_p);
+    fill_table(reinterpret_cast<uint32_t*>(h + P.off_mh), n_cols, &P.bh, P.total_h);
+    (void)hipGetLastError();
+    hipError_t e = hipMemcpyAsync(d_ws, ctx->staging, P.header, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipEventRecord(ctx->staged, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    ctx->staged_pending = true;
+
+    const cafs::BatchGrid g1 = grid_at(d_ws, P, P.off_m1, n_cols, n_cols);
+    const cafs::BatchGrid gp = grid_at(d_ws, P, P.off_mp, P.total_p, n_cols);
+    const cafs::BatchGrid gh = grid_at(d_ws, P, P.off_mh, P.total_h, n_cols);
+    const uint32_t C = n_cols, TP = P.total_p, TH = P.total_h;
+    cafs::kb_pre<<<C, 1024, 0, s>>>(g1);
+    cafs::kb_mono_full<<<TP, 256, 0, s>>>(gp);
+    cafs::kb_phase2<<<TP, 256, 0, s>>>(gp);
+    cafs::kb_hash_count<<<TH, cafs::kCountThreads, 0, s>>>(gh);
+    cafs::kb_compact_order<<<C, 1024, 0, s>>>(g1);
+    cafs::kb_radix_hist<<<TP, 256, 0, s>>>(gp);
+    for (uint32_t p = 0; p < 8; ++p) cafs::kb_radix_pass<<<TP, cafs::kRadixThreads, 0, s>>>(gp, p);
+    cafs::kb_radix_copy<<<TP, 256, 0, s>>>(gp);
+    cafs::kb_pair_scan<<<C, 1024, 0, s>>>(g1);
+    cafs::kb_copy_mono<<<TP, 256, 0, s>>>(gp);
+    cafs::kb_rle_count<<<TP, 256, 0, s>>>(gp);
+    cafs::kb_rle_write<<<TP, 256, 0, s>>>(gp);
+    cafs::kb_rle_counts<<<TP, 256, 0, s>>>(gp);
+    cafs::kb_guard_prep<<<TP, 256, 0, s>>>(gp);
+    cafs::kb_guard_bucket<<<TP, 256, 0, s>>>(gp);
+    cafs::kb_guard_mark<<<TP, 256, 0, s>>>(gp);
+    cafs::kb_guard_first<<<TP, 256, 0, s>>>(gp);
+    cafs::kb_guard_resolve<<<C, 1024, 0, s>>>(g1);
+    for (uint32_t r = 0; r < 4; ++r) cafs::kb_guard_round<<<TP, 256, 0, s>>>(gp, r);
+    cafs::kb_guard_final<<<TP, 256, 0, s>>>(gp);
+    // outputs written after the guard: it reads the input, which an in-place sort overwrites
+    cafs::kb_copy_deferred<<<TP, 256, 0, s>>>(gp);
+    cafs::kb_emit<<<TP, cafs::kEmitThreads, 0, s>>>(gp, 1u);
+    cafs::kb_emit<<<TP, cafs::kEmitThreads, 0, s>>>(gp, 0u);
+    cafs::kb_finalize<<<C, 64, 0, s>>>(g1);
+    e = hipGetLastError();
+    return e == hipSuccess ? CAFS_OK : hip_fail(e, "launch");
 }
 
 const char* cafs_status_str(cafs_status_t status) {

@@ -96,6 +96,11 @@ struct Ctrl {
     uint32_t overflow;
     uint32_t claimed;
     uint64_t ecount;                  // elements equal to kEmpty
+    // where the sorted column is when the radix engine ran (the output, or scratch
+    // when sorting in place on the main path, copied out after the guard)
+    uint64_t* sorted;
+    uint32_t deferred_copy;
+    uint32_t pad0;
     // dense (key, count) arrays
     uint64_t K;
     uint32_t emit_main;               // dense arrays from the tiny or single-workgroup order path
@@ -144,12 +149,8 @@ struct Args {
     uint64_t* gcnt;
     uint32_t* claimed;
     uint32_t cap_ws_log2;             // largest table the workspace holds
-    // unsorted pairs for the pair sort
-    uint64_t* pk;
-    uint64_t* pv;
-    // radix scratch
+    // radix scratch (n keys; the pair sort uses the dead hash table instead)
     uint64_t* tmp_k;
-    uint64_t* tmp_v;
     uint64_t* status;                 // 2 slots of status_slot words
     uint64_t status_slot;
     // guard scratch
@@ -162,6 +163,33 @@ struct Args {
     // run-length scratch
     uint64_t* rle_tile;               // per-tile run counts
 };
+
+// Block table of a batched launch: block b works on column col[b] as block
+// b - first[col[b]] of count[col[b]] blocks given to that column.
+struct BatchGrid {
+    const Args* args;
+    const uint32_t* col;
+    const uint32_t* first;
+    const uint32_t* count;
+};
+
+// Every kernel body is a device function of (call arguments, block id, block
+// count); this emits the single-column kernel k_NAME over the launch grid and
+// the batched kernel kb_NAME over a block table.
+#define CAFS_KERNELS0(NAME, T)                                                         \
+    __global__ __launch_bounds__(T) void k_##NAME(Args a) { NAME##_body(a, blockIdx.x, gridDim.x); } \
+    __global__ __launch_bounds__(T) void kb_##NAME(BatchGrid g) {                     \
+        const uint32_t col = g.col[blockIdx.x];                                        \
+        NAME##_body(g.args[col], blockIdx.x - g.first[col], g.count[col]);             \
+    }
+#define CAFS_KERNELS1(NAME, T, XT, XN)                                                 \
+    __global__ __launch_bounds__(T) void k_##NAME(Args a, XT XN) {                     \
+        NAME##_body(a, XN, blockIdx.x, gridDim.x);                                     \
+    }                                                                                  \
+    __global__ __launch_bounds__(T) void kb_##NAME(BatchGrid g, XT XN) {              \
+        const uint32_t col = g.col[blockIdx.x];                                        \
+        NAME##_body(g.args[col], XN, blockIdx.x - g.first[col], g.count[col]);         \
+    }
 
 // ---- helpers ---------------------------------------------------------------
 

@@ -33,12 +33,12 @@ __device__ __forceinline__ void load_pair(const uint64_t* __restrict__ x, uint64
 // wave ballot: v_cmp_eq_u64 gives a 64-lane mask per key whose population count
 // is added to a wave-uniform (scalar) counter.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_phase2(Args a) {
+__device__ __forceinline__ void phase2_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     const uint32_t engine = c->engine;
     if (engine != E_TINY && engine != E_HASH) return;
-    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     const uint64_t cap = 1ull << c->cap_log2;
     for (uint64_t i = gtid; i < cap; i += gstride) {
         a.gkeys[i] = kEmpty;
@@ -94,9 +94,16 @@ __global__ __launch_bounds__(256) void k_phase2(Args a) {
             if (cnt[j]) atomicAdd((unsigned long long*)&c->tiny_cnt[j], (unsigned long long)cnt[j]);
     }
 }
+CAFS_KERNELS0(phase2, 256)
 
-__device__ __noinline__ void set_overflow(Ctrl* c) {
+__device__ __noinline__ void set_overflow(const Args& a, Ctrl* c) {
     if (atomicExch(&c->overflow, 1u) == 0) {
+        if (a.in == a.out) {  // see the dispatcher: keep the input for the guard
+            c->rj.dst_k = a.tmp_k;
+            c->rj.tmp_k = a.uniq;
+            c->sorted = a.tmp_k;
+            c->deferred_copy = 1;
+        }
         atomicExch(&c->radix_on, 1u);
         atomicExch(&c->guard_on, 1u);
         atomicExch(&c->guard_general, 1u);
@@ -120,7 +127,7 @@ __device__ __forceinline__ void global_insert(const Args& a, Ctrl* c, uint64_t v
                 atomicCAS((unsigned long long*)&a.gkeys[h], (unsigned long long)kEmpty, (unsigned long long)v);
             if (old == kEmpty) {
                 const uint32_t idx = atomicAdd(&c->claimed, 1u);
-                if (idx >= c->cap_limit) { set_overflow(c); return; }
+                if (idx >= c->cap_limit) { set_overflow(a, c); return; }
                 a.claimed[idx] = (uint32_t)h;
                 atomicAdd((unsigned long long*)&a.gcnt[h], (unsigned long long)cnt);
                 return;
@@ -133,7 +140,7 @@ __device__ __forceinline__ void global_insert(const Args& a, Ctrl* c, uint64_t v
         }
         h = (h + 1) & mask;
     }
-    set_overflow(c);
+    set_overflow(a, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -189,7 +196,7 @@ __device__ __forceinline__ int match4(const uint64_t* skeys, uint32_t b, uint64_
     return lo.x == x ? 0 : lo.y == x ? 1 : hi.x == x ? 2 : hi.y == x ? 3 : -1;
 }
 
-__global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
+__device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     const uint32_t engine = c->engine;
     if (engine == E_TINY) {
@@ -197,7 +204,7 @@ __global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
         uint64_t tot = 0;
         for (uint32_t j = 0; j < nk; ++j) tot += c->tiny_cnt[j];
         if (tot == a.n) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (bid == 0 && threadIdx.x == 0) {
                 uint64_t run = 0;
                 for (uint32_t j = 0; j < nk; ++j) {
                     a.uniq[j] = c->tiny_keys[j];
@@ -212,7 +219,7 @@ __global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
             }
             return;
         }
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (bid == 0 && threadIdx.x == 0) {
             c->tiny_miss = 1;
             c->path = P_MAIN;
             c->engine = E_HASH;
@@ -236,8 +243,8 @@ __global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
     const uint64_t Pf = (a.n + head) / 2;  // pairs [head, Pf) hold two in-range elements
     constexpr int U = 4;                   // pairs per thread per step
     const uint64_t span = (uint64_t)blockDim.x * U;
-    const uint64_t step = (uint64_t)gridDim.x * span;
-    uint64_t base = (uint64_t)blockIdx.x * span;
+    const uint64_t step = (uint64_t)nblk * span;
+    uint64_t base = (uint64_t)bid * span;
     uint64_t v[2 * U];
     uint32_t okm = 0;  // bit e: element e of the batch is in range
     auto load = [&](uint64_t b) {
@@ -307,6 +314,7 @@ __global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
     const uint32_t wsum = wave_sum_u32(ecnt);
     if (__lane_id() == 0 && wsum) atomicAdd((unsigned long long*)&c->ecount, (unsigned long long)wsum);
 }
+CAFS_KERNELS0(hash_count, kCountThreads)
 
 // ---------------------------------------------------------------------------
 // Compaction and order (Alg. 4, steps "collect non-empty bucket slots", "sort
@@ -317,7 +325,7 @@ __global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
 // table (M buckets, Eq. hash) receives more than 4 distinct keys, nothing spills
 // (Alg. 1) and the guard is settled here.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_compact_order(Args a) {
+__device__ __forceinline__ void compact_order_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (c->engine != E_HASH || c->overflow || c->dense_ready) return;
     const uint32_t claimed = c->claimed;
@@ -326,17 +334,20 @@ __global__ __launch_bounds__(1024) void k_compact_order(Args a) {
     const uint64_t flip = a.flip;
     const uint32_t tid = threadIdx.x;
     if (K > kOrderMax) {
+        // gather the pairs into the dense arrays and sort them there, in place, with
+        // the radix engine; the hash table is dead after the gather and serves as
+        // the radix scratch (K <= table size)
         for (uint32_t i = tid; i < claimed; i += blockDim.x) {
             const uint32_t h = a.claimed[i];
-            a.pk[i] = a.gkeys[h];
-            a.pv[i] = a.gcnt[h];
+            a.uniq[i] = a.gkeys[h];
+            a.cnt[i] = a.gcnt[h];
         }
         if (tid == 0) {
-            if (ecount) { a.pk[claimed] = kEmpty; a.pv[claimed] = ecount; }
+            if (ecount) { a.uniq[claimed] = kEmpty; a.cnt[claimed] = ecount; }
             RadixJob& j = c->rj;
-            j.src_k = a.pk; j.src_v = a.pv;
+            j.src_k = a.uniq; j.src_v = a.cnt;
             j.dst_k = a.uniq; j.dst_v = a.cnt;
-            j.tmp_k = a.tmp_k; j.tmp_v = a.tmp_v;
+            j.tmp_k = a.gkeys; j.tmp_v = a.gcnt;
             j.n = K;
             j.has_vals = 1;
             c->K = K;
@@ -451,9 +462,10 @@ __global__ __launch_bounds__(1024) void k_compact_order(Args a) {
         c->guard_on = nc > 0;
     }
 }
+CAFS_KERNELS0(compact_order, 1024)
 
 // Exclusive scan of the sorted counts after a pair sort (K > 8192).  One workgroup.
-__global__ __launch_bounds__(1024) void k_pair_scan(Args a) {
+__device__ __forceinline__ void pair_scan_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!c->pair_sort || c->overflow) return;
     __shared__ uint64_t scan_tmp[17];
@@ -474,5 +486,6 @@ __global__ __launch_bounds__(1024) void k_pair_scan(Args a) {
         c->dense_ready = 1;
     }
 }
+CAFS_KERNELS0(pair_scan, 1024)
 
 }  // namespace cafs

@@ -43,7 +43,7 @@ __device__ __forceinline__ void store_pair(uint64_t* __restrict__ y, uint64_t n,
 // `after_pair_sort` selects the instance: one runs on the caller's stream right
 // after the single-workgroup order kernel (or the tiny branch), the other on the
 // side stream after the pair sort; exactly one of them has work.
-__global__ __launch_bounds__(kEmitThreads) void k_emit(Args a, uint32_t after_pair_sort) {
+__device__ __forceinline__ void emit_body(const Args& a, uint32_t after_pair_sort, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (after_pair_sort ? !(c->pair_sort && c->dense_ready && !c->overflow) : !c->emit_main) return;
     const uint64_t n = a.n;
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Args a, uint32_t after_pa
     __shared__ uint64_t s_key[kEmitLdsRuns];
     const uint64_t* __restrict__ off = a.off;
     const uint64_t* __restrict__ uq = a.uniq;
-    for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    for (uint64_t t = bid; t < tiles; t += nblk) {
         const uint64_t p0 = t * kEmitTilePairs;
         const uint64_t p1 = (p0 + kEmitTilePairs < P) ? p0 + kEmitTilePairs : P;
         const int64_t e_lo_s = (int64_t)(2 * p0) - (int64_t)head;
@@ -96,15 +96,17 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(Args a, uint32_t after_pa
         __syncthreads();
     }
 }
+CAFS_KERNELS1(emit, kEmitThreads, uint32_t, after_pair_sort)
 
 // Monotone input: the output is the input.
-__global__ __launch_bounds__(256) void k_copy_mono(Args a) {
+__device__ __forceinline__ void copy_mono_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (c->path != P_MONOTONE || a.in == a.out) return;
-    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     for (uint64_t i = gtid; i < a.n; i += gstride) a.out[i] = a.in[i];
 }
+CAFS_KERNELS0(copy_mono, 256)
 
 // Run-length pass over the sorted output, needed when the column was not counted
 // (monotone input, radix engine) but the report, the counts or the guard need
@@ -115,16 +117,16 @@ __device__ __forceinline__ bool rle_needed(const Args& a, const Ctrl* c) {
 }
 
 // Pass 1: runs starting in each tile; the last workgroup scans the tile counts.
-__global__ __launch_bounds__(256) void k_rle_count(Args a) {
+__device__ __forceinline__ void rle_count_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!rle_needed(a, c)) return;
     const uint64_t n = a.n;
-    const uint64_t* __restrict__ y = a.out;
+    const uint64_t* __restrict__ y = c->sorted;
     const uint64_t tiles = (n + kRleTile - 1) / kRleTile;
     __shared__ uint32_t s_cnt;
     __shared__ uint32_t s_last;
     __shared__ uint64_t scan_tmp[8];
-    for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    for (uint64_t t = bid; t < tiles; t += nblk) {
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
         const uint64_t b = t * kRleTile;
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(256) void k_rle_count(Args a) {
     }
     __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(&c->rle_done, 1u) == gridDim.x - 1);
+    if (threadIdx.x == 0) s_last = (atomicAdd(&c->rle_done, 1u) == nblk - 1);
     __syncthreads();
     if (!s_last) return;
     __threadfence();
@@ -158,17 +160,18 @@ __global__ __launch_bounds__(256) void k_rle_count(Args a) {
     }
     if (threadIdx.x == 0) c->K = total;
 }
+CAFS_KERNELS0(rle_count, 256)
 
 // Pass 2: write each run's key and start position (its offset).
-__global__ __launch_bounds__(256) void k_rle_write(Args a) {
+__device__ __forceinline__ void rle_write_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!rle_needed(a, c)) return;
     const uint64_t n = a.n;
-    const uint64_t* __restrict__ y = a.out;
+    const uint64_t* __restrict__ y = c->sorted;
     const uint64_t tiles = (n + kRleTile - 1) / kRleTile;
     constexpr uint32_t per = kRleTile / 256;  // contiguous elements per thread
     __shared__ uint32_t scan_tmp[8];
-    for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    for (uint64_t t = bid; t < tiles; t += nblk) {
         const uint64_t b = t * kRleTile + (uint64_t)threadIdx.x * per;
         uint32_t local = 0;
         for (uint32_t k = 0; k < per; ++k) {
@@ -189,17 +192,31 @@ __global__ __launch_bounds__(256) void k_rle_write(Args a) {
             }
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.off[c->K] = n;
+    if (bid == 0 && threadIdx.x == 0) a.off[c->K] = n;
 }
+CAFS_KERNELS0(rle_write, 256)
 
 // Pass 3: counts from consecutive offsets; marks the pairs ready for the guard.
-__global__ __launch_bounds__(256) void k_rle_counts(Args a) {
+__device__ __forceinline__ void rle_counts_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!rle_needed(a, c)) return;
     const uint64_t K = c->K;
-    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     for (uint64_t jj = gtid; jj < K; jj += gstride) a.cnt[jj] = a.off[jj + 1] - a.off[jj];
 }
+CAFS_KERNELS0(rle_counts, 256)
+
+// In-place main-path sort by the radix engine: the sorted column waited in
+// scratch until the guard had read the input.
+__device__ __forceinline__ void copy_deferred_body(const Args& a, uint32_t bid, uint32_t nblk) {
+    const Ctrl* c = a.c;
+    if (!c->deferred_copy) return;
+    const uint64_t* src = c->sorted;
+    const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)nblk * blockDim.x;
+    for (uint64_t i = gtid; i < a.n; i += gstride) a.out[i] = src[i];
+}
+CAFS_KERNELS0(copy_deferred, 256)
 
 }  // namespace cafs

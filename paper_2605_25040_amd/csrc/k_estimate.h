@@ -172,10 +172,20 @@ __device__ void plan_block(const Args& a) {
     j.has_vals = 0;
     j.n_active = 0;
     j.copy_mode = 0;
+    c->sorted = a.out;
+    c->deferred_copy = 0;
+    if (path == P_MAIN && engine == E_RADIX && a.in == a.out) {
+        // in place on the main path: the guard still reads the input after the sort,
+        // so sort into scratch (ping-pong with the dense key array, written later)
+        j.dst_k = a.tmp_k;
+        j.tmp_k = a.uniq;
+        c->sorted = a.tmp_k;
+        c->deferred_copy = 1;
+    }
 }
 
 // First kernel of a sort: order check of a prefix and the Chao1 estimate.
-__global__ __launch_bounds__(1024) void k_pre(Args a) {
+__device__ __forceinline__ void pre_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     __shared__ uint32_t s_inv;
     __shared__ Chao1Result s_res;
@@ -203,6 +213,7 @@ __global__ __launch_bounds__(1024) void k_pre(Args a) {
         plan_block(a);
     }
 }
+CAFS_KERNELS0(pre, 1024)
 
 // Standalone estimate (cafs_estimate).
 __global__ __launch_bounds__(1024) void k_estimate_only(const uint64_t* x, uint64_t n,
@@ -220,13 +231,13 @@ __global__ __launch_bounds__(1024) void k_estimate_only(const uint64_t* x, uint6
 
 // Full order check, only when the prefix was in order (IsMonotone, Alg. 3).  Exits
 // early once any workgroup has found an inversion.
-__global__ __launch_bounds__(256) void k_mono_full(Args a) {
+__device__ __forceinline__ void mono_full_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!c->mono_full) return;
     const uint64_t n = a.n;
     const uint64_t chunk = 256 * 16;
     __shared__ uint32_t s_stop, s_last;
-    for (uint64_t base = (uint64_t)blockIdx.x * chunk; base + 1 < n; base += (uint64_t)gridDim.x * chunk) {
+    for (uint64_t base = (uint64_t)bid * chunk; base + 1 < n; base += (uint64_t)nblk * chunk) {
         if (threadIdx.x == 0) s_stop = atomic_load_agent(&c->inversion);
         __syncthreads();
         if (s_stop) break;
@@ -239,7 +250,7 @@ __global__ __launch_bounds__(256) void k_mono_full(Args a) {
     }
     __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(&c->mono_done, 1u) == gridDim.x - 1);
+    if (threadIdx.x == 0) s_last = (atomicAdd(&c->mono_done, 1u) == nblk - 1);
     __syncthreads();
     if (!s_last) return;
     __threadfence();
@@ -247,9 +258,10 @@ __global__ __launch_bounds__(256) void k_mono_full(Args a) {
     __syncthreads();
     plan_block(a);
 }
+CAFS_KERNELS0(mono_full, 256)
 
 // Writes the caller's report.  One thread.
-__global__ void k_finalize(Args a) {
+__device__ __forceinline__ void finalize_body(const Args& a, uint32_t bid, uint32_t nblk) {
     if (threadIdx.x != 0 || !a.want_report) return;
     const Ctrl* c = a.c;
     cafs_report_t r;
@@ -272,6 +284,7 @@ __global__ void k_finalize(Args a) {
     r.flags = c->flags;
     *a.report = r;
 }
+CAFS_KERNELS0(finalize, 64)
 
 // Report of an empty column (n = 0): path MONOTONE, everything else zero.
 __global__ void k_report_empty(cafs_report_t* r) {

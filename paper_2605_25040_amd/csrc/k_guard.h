@@ -40,35 +40,37 @@ __device__ __forceinline__ bool guard_general(const Ctrl* c) {
     return c->guard_on && c->guard_general && c->path == P_MAIN;
 }
 
-__global__ __launch_bounds__(256) void k_guard_prep(Args a) {
+__device__ __forceinline__ void guard_prep_body(const Args& a, uint32_t bid, uint32_t nblk) {
     const Ctrl* c = a.c;
     if (!guard_general(c)) return;
     const uint64_t M = c->table_M;
-    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     for (uint64_t i = gtid; i < M; i += gstride) {
         a.dcount[i] = 0;
         for (int r = 0; r < 4; ++r) a.bmin[r * a.m_ws + i] = kNoIndex;
     }
 }
+CAFS_KERNELS0(guard_prep, 256)
 
-__global__ __launch_bounds__(256) void k_guard_bucket(Args a) {
+__device__ __forceinline__ void guard_bucket_body(const Args& a, uint32_t bid, uint32_t nblk) {
     const Ctrl* c = a.c;
     if (!guard_general(c)) return;
     const uint64_t K = c->K;
     const uint32_t lg = log2_pow2(c->table_M);
-    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     for (uint64_t j = gtid; j < K; j += gstride) atomicAdd(&a.dcount[phi_hash(a.uniq[j], lg)], 1u);
 }
+CAFS_KERNELS0(guard_bucket, 256)
 
 // Lists the contested keys (general mode) and resets their first-occurrence
 // minima.  The minima share memory with the run offsets, so this runs after emit.
-__global__ __launch_bounds__(256) void k_guard_mark(Args a) {
+__device__ __forceinline__ void guard_mark_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!guard_active(c)) return;
-    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     const uint64_t M = c->table_M;
     uint32_t nb = 0;
     for (uint64_t b = gtid; b < M; b += gstride) {
@@ -90,6 +92,7 @@ __global__ __launch_bounds__(256) void k_guard_mark(Args a) {
         for (uint64_t li = gtid; li < nc; li += gstride) a.first_idx[a.clist[li]] = kNoIndex;
     }
 }
+CAFS_KERNELS0(guard_mark, 256)
 
 // Position of key v in the sorted distinct keys (it is present).
 __device__ __forceinline__ uint64_t find_key(const uint64_t* uq, uint64_t K, uint64_t v, uint64_t flip) {
@@ -111,7 +114,7 @@ __device__ __forceinline__ uint64_t find_key(const uint64_t* uq, uint64_t K, uin
 // most kGuardLdsKeys contested keys each workgroup keeps them in an LDS hash table
 // with per-key minima that it merges into the global minima after each chunk;
 // otherwise each element of a contested bucket is located by binary search.
-__global__ __launch_bounds__(256) void k_guard_first(Args a) {
+__device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (c->path != P_MAIN || !c->guard_on) return;
     const uint64_t nc = c->n_contested;
@@ -207,12 +210,13 @@ __global__ __launch_bounds__(256) void k_guard_first(Args a) {
         __syncthreads();
     }
 }
+CAFS_KERNELS0(guard_first, 256)
 
 // Rank of each contested key within its bucket by first occurrence, for at most
 // kGuardLdsKeys contested keys: sort (bucket, first occurrence) in LDS; position p
 // is the 5th or later key of its bucket exactly when position p - 4 holds the same
 // bucket.  The spill is the sum of those keys' counts.  One workgroup.
-__global__ __launch_bounds__(1024) void k_guard_resolve(Args a) {
+__device__ __forceinline__ void guard_resolve_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (c->path != P_MAIN || !c->guard_on) return;
     const uint64_t nc = c->n_contested;
@@ -268,14 +272,15 @@ __global__ __launch_bounds__(1024) void k_guard_resolve(Args a) {
         if (2 * s_spill > a.n) c->path = P_GUARD;
     }
 }
+CAFS_KERNELS0(guard_resolve, 1024)
 
-__global__ __launch_bounds__(256) void k_guard_round(Args a, uint32_t r) {
+__device__ __forceinline__ void guard_round_body(const Args& a, uint32_t r, uint32_t bid, uint32_t nblk) {
     const Ctrl* c = a.c;
     if (!guard_active(c) || !c->guard_rounds) return;
     const uint64_t K = c->K;
     const uint32_t lg = log2_pow2(c->table_M);
-    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     for (uint64_t j = gtid; j < K; j += gstride) {
         const uint32_t b = phi_hash(a.uniq[j], lg);
         if (a.dcount[b] <= kBucketCap) continue;
@@ -283,15 +288,16 @@ __global__ __launch_bounds__(256) void k_guard_round(Args a, uint32_t r) {
         if (r == 0 || f > a.bmin[(r - 1) * a.m_ws + b]) atomicMin(&a.bmin[r * a.m_ws + b], f);
     }
 }
+CAFS_KERNELS1(guard_round, 256, uint32_t, r)
 
-__global__ __launch_bounds__(256) void k_guard_final(Args a) {
+__device__ __forceinline__ void guard_final_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!guard_active(c) || !c->guard_rounds) return;
     __shared__ uint32_t s_last;
     const uint64_t K = c->K;
     const uint32_t lg = log2_pow2(c->table_M);
-    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     uint64_t local = 0;
     for (uint64_t j = gtid; j < K; j += gstride) {
         const uint32_t b = phi_hash(a.uniq[j], lg);
@@ -301,7 +307,7 @@ __global__ __launch_bounds__(256) void k_guard_final(Args a) {
     if (__lane_id() == 0 && local) atomicAdd((unsigned long long*)&c->spill, (unsigned long long)local);
     __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(&c->guard_done, 1u) == gridDim.x - 1);
+    if (threadIdx.x == 0) s_last = (atomicAdd(&c->guard_done, 1u) == nblk - 1);
     __syncthreads();
     if (!s_last || threadIdx.x != 0) return;
     __threadfence();
@@ -309,5 +315,6 @@ __global__ __launch_bounds__(256) void k_guard_final(Args a) {
     if (c->n_contested) c->flags |= 2u;
     if (2 * spill > a.n) c->path = P_GUARD;
 }
+CAFS_KERNELS0(guard_final, 256)
 
 }  // namespace cafs

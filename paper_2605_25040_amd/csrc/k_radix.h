@@ -23,7 +23,7 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t key, uint64_t flip, uint32
     return (uint32_t)(((key ^ flip) >> (8 * d)) & 255u);
 }
 
-__global__ __launch_bounds__(256) void k_radix_hist(Args a) {
+__device__ __forceinline__ void radix_hist_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!c->radix_on) return;
     const RadixJob& j = c->rj;
@@ -35,8 +35,8 @@ __global__ __launch_bounds__(256) void k_radix_hist(Args a) {
     for (uint32_t i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&lh[0][0])[i] = 0;
     // clear the look-back status words of the first pass
     const uint64_t tiles = (n + kRadixTile - 1) / kRadixTile;
-    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     for (uint64_t i = gtid; i < tiles * 256; i += gstride) a.status[i] = 0;
     __syncthreads();
     const uint32_t lane = __lane_id();
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_radix_hist(Args a) {
     }
     __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(&c->hist_done, 1u) == gridDim.x - 1);
+    if (threadIdx.x == 0) s_last = (atomicAdd(&c->hist_done, 1u) == nblk - 1);
     __syncthreads();
     if (!s_last) return;
     __threadfence();
@@ -110,6 +110,7 @@ __global__ __launch_bounds__(256) void k_radix_hist(Args a) {
         else jw.copy_mode = shift ? 2u : 0u;
     }
 }
+CAFS_KERNELS0(radix_hist, 256)
 
 // Stable match of equal 8-bit digits across the wave: the lanes (within `act`)
 // whose digit equals this lane's digit.
@@ -124,7 +125,7 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t dg, uint64_t act) {
     return peers;
 }
 
-__global__ __launch_bounds__(kRadixThreads) void k_radix_pass(Args a, uint32_t pass) {
+__device__ __forceinline__ void radix_pass_body(const Args& a, uint32_t pass, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!c->radix_on) return;
     const RadixJob& j = c->rj;
@@ -153,8 +154,8 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_pass(Args a, uint32_t p
 
     // clear the status words the next pass will use (the previous pass is done with them)
     {
-        const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+        const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
+        const uint64_t gstride = (uint64_t)nblk * blockDim.x;
         if (pass + 1 < j.n_active)
             for (uint64_t i = gtid; i < tiles * 256; i += gstride) status_next[i] = 0;
     }
@@ -264,8 +265,9 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_pass(Args a, uint32_t p
         __syncthreads();
     }
 }
+CAFS_KERNELS1(radix_pass, kRadixThreads, uint32_t, pass)
 
-__global__ __launch_bounds__(256) void k_radix_copy(Args a) {
+__device__ __forceinline__ void radix_copy_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!c->radix_on) return;
     const RadixJob& j = c->rj;
@@ -273,12 +275,13 @@ __global__ __launch_bounds__(256) void k_radix_copy(Args a) {
     const uint64_t* sk = j.copy_mode == 1 ? j.src_k : j.tmp_k;
     const uint64_t* sv = j.copy_mode == 1 ? j.src_v : j.tmp_v;
     const uint64_t n = j.n;
-    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     for (uint64_t i = gtid; i < n; i += gstride) {
         j.dst_k[i] = sk[i];
         if (j.has_vals) j.dst_v[i] = sv[i];
     }
 }
+CAFS_KERNELS0(radix_copy, 256)
 
 }  // namespace cafs

@@ -67,3 +67,15 @@ def test_report_layout_matches_header():
     # cafs_estimate_t: 6 u64 + 2 u32 = 56 bytes; cafs_report_t: 56 + 2*i32 + 3*u64 + 2*u32 = 96
     assert ctypes.sizeof(cafs.Estimate) == 56
     assert cafs.report_size() == 96
+
+
+def test_batched_workspace_is_sum_of_columns(lib):
+    import ctypes as ct
+    ns = [0, 1, 5000, 10**6, 3 * 10**6]
+    arr = (ct.c_uint64 * len(ns))(*ns)
+    lib.cafs_batched_workspace_bytes.argtypes = [ct.c_void_p, ct.c_uint32]
+    lib.cafs_batched_workspace_bytes.restype = ct.c_size_t
+    total = lib.cafs_batched_workspace_bytes(arr, len(ns))
+    per = sum(lib.cafs_workspace_bytes(n, 0) for n in ns)
+    assert total >= per and total % 256 == 0
+    assert total - per < 1 << 20  # the header (arguments and block tables) is small

@@ -1,0 +1,110 @@
+"""Batched sorting (one launch sequence for many columns) against the oracle and
+against the single-column call on the same column: bit-identical outputs,
+counts and reports."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from tests import crafted
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_25040_amd as cafs
+    return cafs.Context(0)
+
+
+def make_cols(arrays, unsigned_flags, counts_flags, report_flags, inplace_flags=None, shift_flags=None):
+    import paper_2605_25040_amd as cafs
+    cols = []
+    for i, x in enumerate(arrays):
+        n = x.size
+        sh = shift_flags[i] if shift_flags else 0
+        buf = torch.empty(n + 1, dtype=torch.int64, device="cuda:0")
+        if n:
+            buf[sh:sh + n].copy_(torch.from_numpy(x.view(np.int64).copy()))
+        xin = buf[sh:sh + n]
+        out = xin if (inplace_flags and inplace_flags[i]) else torch.empty(n, dtype=torch.int64, device="cuda:0")
+        want_counts = counts_flags[i]
+        cols.append(dict(
+            **{"in": xin}, out=out, unsigned=unsigned_flags[i],
+            uniq=torch.empty(max(n, 1), dtype=torch.int64, device="cuda:0") if want_counts else None,
+            counts=torch.empty(max(n, 1), dtype=torch.int64, device="cuda:0") if want_counts else None,
+            report=torch.zeros(cafs.report_size(), dtype=torch.uint8, device="cuda:0")
+            if (report_flags[i] or want_counts) else None,
+            src=x))
+    return cols
+
+
+def check_cols(cols, label):
+    import paper_2605_25040_amd as cafs
+    torch.cuda.synchronize()
+    for i, c in enumerate(cols):
+        dt = np.uint64 if c["unsigned"] else np.int64
+        x = c["src"].view(dt)
+        y = c["out"].cpu().numpy().view(dt)
+        assert np.array_equal(y, oracle.sort(x, dt)), "%s col %d output" % (label, i)
+        if c["report"] is not None:
+            r = cafs.parse_report(c["report"])
+            ro = oracle.report(x, dt)
+            for f in oracle.REPORT_FIELDS:
+                assert r[f] == ro[f], "%s col %d field %s gpu=%r oracle=%r" % (label, i, f, r[f], ro[f])
+            if c["uniq"] is not None:
+                k = r["k_exact"]
+                uo, co = oracle.counts(x, dt)
+                assert np.array_equal(c["uniq"][:k].cpu().numpy().view(dt), uo), (label, i)
+                assert np.array_equal(c["counts"][:k].cpu().numpy().view(np.uint64), co), (label, i)
+
+
+def test_batch_mixed_shapes(ctx):
+    spec = gen.batch_spec(160, seed=3, n_lo=10, n_hi=3e5, k_cap=3e4)
+    arrays = [gen.column(c["n"], c["k"], dist=c["dist"], s=c["s"], seed=c["seed"], dtype=np.uint64) for c in spec]
+    arrays += [np.zeros(0, dtype=np.uint64), np.array([5], dtype=np.uint64),
+               crafted.t1_sorted(50_000)[0]]
+    m = len(arrays)
+    rng = np.random.default_rng(5)
+    cols = make_cols(arrays, unsigned_flags=list(rng.random(m) < 0.3), counts_flags=list(rng.random(m) < 0.5),
+                     report_flags=list(rng.random(m) < 0.8), inplace_flags=list(rng.random(m) < 0.2),
+                     shift_flags=[int(v) for v in rng.integers(0, 2, size=m)])
+    ctx.sort_batched(cols)
+    check_cols(cols, "mixed")
+
+
+def test_batch_crafted_cases(ctx):
+    cases = crafted.all_cases()
+    arrays = [x for x, _ in cases.values()]
+    m = len(arrays)
+    cols = make_cols(arrays, [False] * m, [True] * m, [True] * m)
+    ctx.sort_batched(cols)
+    check_cols(cols, "crafted")
+    import paper_2605_25040_amd as cafs
+    for (name, (_, exp)), c in zip(cases.items(), cols):
+        r = cafs.parse_report(c["report"])
+        for k, v in exp.items():
+            assert r[k] == v, (name, k, r[k], v)
+
+
+def test_batch_equals_single_calls(ctx):
+    """Alone and in the mix: each column's output and report are bit-identical."""
+    import paper_2605_25040_amd as cafs
+    spec = gen.batch_spec(600, seed=11, n_lo=1e3, n_hi=1e7, total=1 << 23)
+    arrays = [gen.column(c["n"], c["k"], dist=c["dist"], s=c["s"], seed=c["seed"], dtype=np.uint64) for c in spec]
+    m = len(arrays)
+    cols = make_cols(arrays, [False] * m, [False] * m, [True] * m)
+    ctx.sort_batched(cols)
+    torch.cuda.synchronize()
+    for i in range(0, m, 7):
+        c = cols[i]
+        out, rep, _, _ = ctx.sort(c["in"].clone())
+        torch.cuda.synchronize()
+        assert torch.equal(out, c["out"]), i
+        assert cafs.parse_report(rep) == cafs.parse_report(c["report"]), i
+    # oracle on a sample of columns
+    sub = [cols[i] for i in range(0, m, 29)]
+    check_cols(sub, "sample")

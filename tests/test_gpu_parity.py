@@ -142,9 +142,15 @@ def test_misaligned_buffers(ctx, shift_in, shift_out):
 
 def test_in_place(ctx):
     for n, k, dist in ((300_000, 200, "uniform"), (5000, 5000, "uniform"), (100_000, 4, "uniform"),
-                       (100_000, 300, "grouped")):
+                       (100_000, 300, "grouped"),
+                       (300_001, 10_000, "uniform"),      # pair sort, guard with contested buckets
+                       (2_000_000, 200_000, "zipf"),      # table overflow: radix engine on the main path
+                       (60_000, 30_000, "zipf")):
         x = gen.column(n, k, dist=dist, dtype=np.uint64)
         check(ctx, x, False, label="inplace n=%d k=%d" % (n, k), inplace=True)
+    for name in ("t7_even_fire", "t8_big_last", "t9_tiny_miss_guard"):
+        x, _ = crafted.all_cases()[name]
+        check(ctx, x, False, label="inplace " + name, inplace=True)
 
 
 def test_without_counts_or_report(ctx):
