@@ -17,6 +17,11 @@ DISTS = {"uniform": 0, "zipf": 1, "grouped": 2, "runs": 3, "almost_sorted": 4}
 PALETTES = {"random": 0, "codes": 1, "ap": 2}
 
 
+_DEV_SRC = os.path.join(_HERE, "cafs_load.hip")
+_DEV_LIB = os.path.join(_HERE, "libcafs_load.so")
+_PKG_DIR = os.path.join(os.path.dirname(_HERE), "paper_2605_25040_amd")
+
+
 def build(force=False):
     if force or not os.path.exists(_LIB_PATH) or \
             os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
@@ -25,6 +30,93 @@ def build(force=False):
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def build_device(force=False):
+    """Device generator and serving load driver (needs the built libcafs.so)."""
+    if force or not os.path.exists(_DEV_LIB) or \
+            os.path.getmtime(_DEV_LIB) < os.path.getmtime(_DEV_SRC):
+        tmp = _DEV_LIB + ".tmp"
+        subprocess.check_call(["/opt/rocm/bin/hipcc", "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
+                               "-shared", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                               "-o", tmp, _DEV_SRC, "-L" + _PKG_DIR, "-lcafs",
+                               "-Wl,-rpath,$ORIGIN/../paper_2605_25040_amd"],
+                              stderr=subprocess.DEVNULL)
+        os.replace(tmp, _DEV_LIB)
+    return _DEV_LIB
+
+
+_dev = None
+
+
+def _load_dev():
+    global _dev
+    if _dev is None:
+        if not os.path.exists(_DEV_LIB):
+            build_device()
+        lib = ctypes.CDLL(_DEV_LIB)
+        u64, p = ctypes.c_uint64, ctypes.c_void_p
+        lib.gen_column_dev.argtypes = [p, u64, u64, ctypes.c_int, ctypes.c_double, ctypes.c_int, u64, p]
+        lib.gen_column_dev.restype = ctypes.c_int
+        lib.serve_replay.argtypes = [ctypes.c_int, p, p, p, p, u64, ctypes.c_double, u64, ctypes.c_uint32,
+                                     ctypes.c_uint32, p, p, p, p, p]
+        lib.serve_replay.restype = ctypes.c_int
+        _dev = lib
+    return _dev
+
+
+def column_device(out, k, dist="uniform", s=1.1, palette="random", seed=None, stream=None):
+    """Fill a CUDA int64 tensor on the device (uniform: identical to ``column``;
+    zipf: continuous power-law ranks, see cafs_load.hip)."""
+    n = out.numel()
+    if seed is None:
+        seed = default_seed(n, k)
+    d = {"uniform": 0, "zipf": 1}[dist]
+    rc = _load_dev().gen_column_dev(ctypes.c_void_p(out.data_ptr()), n, int(k), d, float(s), PALETTES[palette],
+                                    int(seed) & (2**64 - 1), ctypes.c_void_p(stream) if stream else None)
+    if rc != 0:
+        raise RuntimeError("gen_column_dev failed: %d" % rc)
+    return out
+
+
+def serving_trace(rate, seconds, seed=99, n_lo=1e3, n_hi=3e7, k_cap=1e6):
+    """Poisson arrivals at ``rate`` per second for ``seconds``; N log-uniform in
+    [n_lo, n_hi]; K log-uniform in [2, min(N, k_cap)]; per-request seeds."""
+    import math
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=int(rate * seconds * 1.2) + 16)
+    t = np.cumsum(gaps)
+    t = t[t < seconds]
+    m = t.size
+    n = np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), size=m)).astype(np.uint64)
+    khi = np.maximum(2.0, np.minimum(n.astype(np.float64), k_cap))
+    k = np.exp(rng.uniform(0.0, 1.0, size=m) * np.log(khi / 2.0) + math.log(2.0)).astype(np.uint64)
+    k = np.maximum(k, 2)
+    seeds = np.array([default_seed(int(a), int(b), column=i) for i, (a, b) in enumerate(zip(n, k))],
+                     dtype=np.uint64)
+    return t.astype(np.float64), n, k, seeds
+
+
+def serve_replay(arrival, n, k, seeds, zipf_s=1.1, budget=64 << 30, n_streams=4, max_batch=1024, device=0):
+    """Replay a trace through a CAFS server in real time (C++ driver)."""
+    m = arrival.size
+    arrival = np.ascontiguousarray(arrival, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.uint64)
+    k = np.ascontiguousarray(k, dtype=np.uint64)
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
+    t_admit = np.zeros(m)
+    t_done = np.zeros(m)
+    path = np.zeros(m, dtype=np.int32)
+    kex = np.zeros(m, dtype=np.uint64)
+    stats = np.zeros(10)
+    rc = _load_dev().serve_replay(device, arrival.ctypes.data, n.ctypes.data, k.ctypes.data, seeds.ctypes.data, m,
+                                  float(zipf_s), int(budget), int(n_streams), int(max_batch), t_admit.ctypes.data,
+                                  t_done.ctypes.data, path.ctypes.data, kex.ctypes.data, stats.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("serve_replay failed: %d" % rc)
+    keys = ["wall_s", "keys", "batches", "launched", "refused", "max_busy_streams", "arena_high_water",
+            "arena_used", "queued", "max_waiting"]
+    return dict(t_admit=t_admit, t_done=t_done, path=path, k_exact=kex, stats=dict(zip(keys, stats.tolist())))
 
 
 _lib = None

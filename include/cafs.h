@@ -49,7 +49,8 @@ typedef enum {
     CAFS_EWORKSPACE = -2,   /* ws_bytes < cafs_workspace_bytes(n) or d_ws misaligned */
     CAFS_EHIP = -3,         /* a HIP call or launch failed; see cafs_last_error() */
     CAFS_EUNSUPPORTED = -4, /* feature not available on this device */
-    CAFS_ENOMEM = -5        /* host allocation failed */
+    CAFS_ENOMEM = -5,       /* host allocation failed */
+    CAFS_EBUSY = -6         /* server: the request does not fit the memory budget now */
 } cafs_status_t;
 
 typedef enum { CAFS_I64 = 0, CAFS_U64 = 1 } cafs_dtype_t;
@@ -182,9 +183,58 @@ typedef struct {
 size_t cafs_batched_workspace_bytes(const uint64_t* h_ns, uint32_t n_cols);
 
 /* Sorts n_cols independent columns; each column's outputs are identical to a
- * cafs_sort_* call on it.  h_cols is read before the call returns. */
+ * cafs_sort_* call on it.  Every kernel is launched once for the whole batch
+ * (each block works on one column), so the launch count does not grow with
+ * n_cols.  h_cols is read before the call returns.  The call may be captured in
+ * a HIP graph; a captured call keeps a small pinned host buffer until the
+ * context is destroyed.  A call on a stream that is not capturing waits on the
+ * host until the previous batched call of the context has read its staged
+ * header (an early, small copy). */
 cafs_status_t cafs_sort_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, uint32_t n_cols,
                                 void* d_ws, size_t ws_bytes, void* stream);
+
+/* Block sizing of batched launches: each column gets ceil(n / elems_per_block)
+ * blocks (at most 64) in the general kernels and ceil(n / elems_per_hash_block)
+ * in the hash count.  Affects speed only.  Defaults 65536 and 262144; the
+ * autotuner (cafs_autotune_batched) picks them by timing. */
+cafs_status_t cafs_ctx_set_batch_tuning(cafs_ctx_t* ctx, uint64_t elems_per_block, uint64_t elems_per_hash_block);
+
+/* Autotuner of the batched block sizing: times the batch (synchronously, three
+ * runs per candidate, candidates 2^15..2^18 and 2^17..2^20 elements per block)
+ * and keeps the fastest in the context.  The batch is sorted several times, so
+ * in-place columns are timed as already sorted after the first run. */
+cafs_status_t cafs_autotune_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, uint32_t n_cols, void* d_ws,
+                                    size_t ws_bytes, void* stream, double* h_best_ms);
+
+/* ---- Serving: continuous batching under an HBM budget ------------------------
+ * A server owns one device arena of hbm_budget bytes (allocated at create) and
+ * n_streams streams.  A request first reserves arena memory for its workspace
+ * (and, when all three pointers are given, for its input, output and report):
+ * that is admission, refused with CAFS_EBUSY while the budget is used up.  Once
+ * its input is ready on `ready_stream` it is submitted.  cafs_server_poll
+ * launches queued requests as batches (at most max_batch columns each, in
+ * submission order) on streams whose previous batch has finished, and returns the
+ * tickets of finished requests, whose outputs and reports are then valid.
+ * Requests submitted while batches run go into the next batch on another stream,
+ * so their work overlaps on the GPU.  Each request's results are identical to a
+ * cafs_sort_* call on it.  A server is used from one host thread; the context's
+ * batch tuning applies.  Memory goes back to the arena with cafs_server_release. */
+typedef struct cafs_server cafs_server_t;
+cafs_status_t cafs_server_create(cafs_ctx_t* ctx, size_t hbm_budget, uint32_t n_streams, uint32_t max_batch,
+                                 cafs_server_t** out);
+void cafs_server_destroy(cafs_server_t* sv);  /* waits for running batches */
+cafs_status_t cafs_server_reserve(cafs_server_t* sv, uint64_t n, int32_t dtype, uint64_t* h_ticket,
+                                  void** h_d_in, void** h_d_out, cafs_report_t** h_d_report);
+/* col = NULL sorts the reserved buffers; otherwise col (same n and dtype) names
+ * the caller's buffers and only the workspace comes from the arena. */
+cafs_status_t cafs_server_submit(cafs_server_t* sv, uint64_t ticket, const cafs_column_t* col, void* ready_stream);
+cafs_status_t cafs_server_poll(cafs_server_t* sv, uint64_t* h_tickets, uint32_t cap, uint32_t* h_n);
+/* Returns the memory of a finished (or never submitted) request to the arena. */
+cafs_status_t cafs_server_release(cafs_server_t* sv, uint64_t ticket);
+/* h_stats[0..n): batches launched, requests launched, reservations refused,
+ * most batches running at once, arena high-water bytes, arena bytes in use,
+ * requests queued. */
+cafs_status_t cafs_server_stats(cafs_server_t* sv, uint64_t* h_stats, uint32_t n);
 
 const char* cafs_status_str(cafs_status_t status);
 /* Detail of the last CAFS_EHIP on the calling thread ("" if none). */

@@ -15,14 +15,19 @@ LIB_PATH = os.path.join(_HERE, "libcafs.so")
 PATHS = ("MONOTONE", "SMALL_N", "TINY", "HIGH_K", "MAIN", "GUARD")
 ENGINES = ("NONE", "TINY", "HASH", "RADIX")
 I64, U64 = 0, 1
-STATUS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "HIP error", -4: "unsupported", -5: "nomem"}
+STATUS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "HIP error", -4: "unsupported", -5: "nomem",
+          -6: "busy"}
 
 STAGES = ("pre", "init", "count", "order", "emit", "tail")
 
 EXPORTS = ("cafs_ctx_create", "cafs_ctx_destroy", "cafs_ctx_enable_timing", "cafs_ctx_stage_ms",
            "cafs_workspace_bytes", "cafs_estimate",
            "cafs_sort_i64", "cafs_sort_u64", "cafs_radix_sort", "cafs_batched_workspace_bytes",
-           "cafs_sort_batched", "cafs_status_str", "cafs_last_error")
+           "cafs_sort_batched", "cafs_ctx_set_batch_tuning", "cafs_autotune_batched",
+           "cafs_server_create", "cafs_server_destroy", "cafs_server_reserve", "cafs_server_submit",
+           "cafs_server_poll", "cafs_server_release", "cafs_server_stats",
+           "cafs_status_str", "cafs_last_error")
+EBUSY = -6
 
 
 class Estimate(ctypes.Structure):
@@ -80,6 +85,25 @@ def load():
     lib.cafs_batched_workspace_bytes.restype = ctypes.c_size_t
     lib.cafs_sort_batched.argtypes = [p, p, u32, p, ctypes.c_size_t, p]
     lib.cafs_sort_batched.restype = i32
+    lib.cafs_ctx_set_batch_tuning.argtypes = [p, u64, u64]
+    lib.cafs_ctx_set_batch_tuning.restype = i32
+    lib.cafs_autotune_batched.argtypes = [p, p, u32, p, ctypes.c_size_t, p, ctypes.POINTER(ctypes.c_double)]
+    lib.cafs_autotune_batched.restype = i32
+    lib.cafs_server_create.argtypes = [p, ctypes.c_size_t, u32, u32, ctypes.POINTER(p)]
+    lib.cafs_server_create.restype = i32
+    lib.cafs_server_destroy.argtypes = [p]
+    lib.cafs_server_destroy.restype = None
+    lib.cafs_server_reserve.argtypes = [p, u64, i32, ctypes.POINTER(u64), ctypes.POINTER(p), ctypes.POINTER(p),
+                                        ctypes.POINTER(p)]
+    lib.cafs_server_reserve.restype = i32
+    lib.cafs_server_submit.argtypes = [p, u64, p, p]
+    lib.cafs_server_submit.restype = i32
+    lib.cafs_server_poll.argtypes = [p, ctypes.POINTER(u64), u32, ctypes.POINTER(u32)]
+    lib.cafs_server_poll.restype = i32
+    lib.cafs_server_release.argtypes = [p, u64]
+    lib.cafs_server_release.restype = i32
+    lib.cafs_server_stats.argtypes = [p, ctypes.POINTER(u64), u32]
+    lib.cafs_server_stats.restype = i32
     lib.cafs_status_str.argtypes = [i32]
     lib.cafs_status_str.restype = ctypes.c_char_p
     lib.cafs_last_error.argtypes = []
@@ -188,8 +212,7 @@ class Context:
         arr = (ctypes.c_uint64 * len(ns))(*[int(v) for v in ns])
         return int(self._lib.cafs_batched_workspace_bytes(arr, len(ns)))
 
-    def sort_batched(self, cols, ws=None):
-        """cols: list of dicts with keys in, out, unsigned, uniq, counts, report (tensors or None)."""
+    def _columns(self, cols):
         arr = (Column * len(cols))()
         for i, cdesc in enumerate(cols):
             arr[i].d_in = cdesc["in"].data_ptr()
@@ -200,9 +223,73 @@ class Context:
             arr[i].d_uniq = cdesc["uniq"].data_ptr() if cdesc.get("uniq") is not None else None
             arr[i].d_counts = cdesc["counts"].data_ptr() if cdesc.get("counts") is not None else None
             arr[i].d_report = cdesc["report"].data_ptr() if cdesc.get("report") is not None else None
+        return arr
+
+    def sort_batched(self, cols, ws=None):
+        """cols: list of dicts with keys in, out, unsigned, uniq, counts, report (tensors or None)."""
+        arr = self._columns(cols)
         if ws is None:
             ws = self.workspace(self.batched_workspace_bytes([c["in"].numel() for c in cols]))
         _check(self._lib.cafs_sort_batched(self._h, arr, len(cols), _ptr(ws), ws.numel(), _stream(self.device)))
+
+    def set_batch_tuning(self, elems_per_block, elems_per_hash_block):
+        _check(self._lib.cafs_ctx_set_batch_tuning(self._h, int(elems_per_block), int(elems_per_hash_block)))
+
+    def autotune_batched(self, cols, ws=None):
+        arr = self._columns(cols)
+        if ws is None:
+            ws = self.workspace(self.batched_workspace_bytes([c["in"].numel() for c in cols]))
+        best = ctypes.c_double()
+        _check(self._lib.cafs_autotune_batched(self._h, arr, len(cols), _ptr(ws), ws.numel(), _stream(self.device),
+                                               ctypes.byref(best)))
+        return best.value
+
+
+class Server:
+    """Continuous-batching server over one context (see include/cafs.h)."""
+
+    STATS = ("batches", "launched", "refused", "max_busy_streams", "arena_high_water", "arena_used", "queued")
+
+    def __init__(self, ctx, hbm_budget, n_streams=4, max_batch=1024):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        h = ctypes.c_void_p()
+        _check(self._lib.cafs_server_create(ctx._h, int(hbm_budget), int(n_streams), int(max_batch), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            self._lib.cafs_server_destroy(self._h)
+            self._h = None
+
+    def reserve(self, n, unsigned=False, buffers=False):
+        """Returns (ticket, d_in, d_out, d_report) or None when the budget is full."""
+        t = ctypes.c_uint64()
+        pi, po, pr = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        args = (ctypes.byref(pi), ctypes.byref(po), ctypes.byref(pr)) if buffers else (None, None, None)
+        rc = self._lib.cafs_server_reserve(self._h, int(n), U64 if unsigned else I64, ctypes.byref(t), *args)
+        if rc == EBUSY:
+            return None
+        _check(rc)
+        return int(t.value), pi.value, po.value, pr.value
+
+    def submit(self, ticket, col=None):
+        arr = self.ctx._columns([col]) if col is not None else None
+        _check(self._lib.cafs_server_submit(self._h, int(ticket), arr, _stream(self.ctx.device)))
+
+    def poll(self, cap=4096):
+        buf = (ctypes.c_uint64 * cap)()
+        k = ctypes.c_uint32()
+        _check(self._lib.cafs_server_poll(self._h, buf, cap, ctypes.byref(k)))
+        return [int(buf[i]) for i in range(k.value)]
+
+    def release(self, ticket):
+        _check(self._lib.cafs_server_release(self._h, int(ticket)))
+
+    def stats(self):
+        arr = (ctypes.c_uint64 * len(self.STATS))()
+        _check(self._lib.cafs_server_stats(self._h, arr, len(self.STATS)))
+        return {k: int(v) for k, v in zip(self.STATS, arr)}
 
 
 def parse_report(rep):

@@ -6,6 +6,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <deque>
+#include <map>
+#include <unordered_map>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -27,6 +31,9 @@ struct cafs_ctx {
     size_t staging_bytes;
     hipEvent_t staged;      // the last upload from `staging` has been consumed
     bool staged_pending;
+    std::vector<void*> captured_staging;  // staging buffers referenced by captured graphs
+    uint64_t batch_per_block;       // batched launch: elements per block of the general kernels
+    uint64_t batch_per_hash_block;  // and of the hash count
     bool timing;
     std::vector<hipEvent_t> pool;                 // free events
     std::vector<std::vector<hipEvent_t>> calls;   // CAFS_N_STAGES + 1 events per recorded call
@@ -317,6 +324,8 @@ cafs_status_t cafs_ctx_create(cafs_ctx_t** ctx, int device) {
     c->staging = nullptr;
     c->staging_bytes = 0;
     c->staged_pending = false;
+    c->batch_per_block = 1ull << 16;
+    c->batch_per_hash_block = 1ull << 18;
     {
         DeviceGuard dg(device);
         e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
@@ -344,6 +353,7 @@ void cafs_ctx_destroy(cafs_ctx_t* ctx) {
         if (ctx->staged_pending) (void)hipEventSynchronize(ctx->staged);
         (void)hipEventDestroy(ctx->staged);
         if (ctx->staging) (void)hipHostFree(ctx->staging);
+        for (void* p : ctx->captured_staging) (void)hipHostFree(p);
         (void)hipStreamDestroy(ctx->side);
     }
     delete ctx;
@@ -422,50 +432,51 @@ cafs_status_t cafs_radix_sort(cafs_ctx_t* ctx, const void* d_in, void* d_out, ui
 }
 
 // ---- batched calls ----------------------------------------------------------
-// Workspace of a batched call: a header (per-column call arguments and three
-// block tables) followed by one single-column workspace per column.  Every
-// kernel is launched once for the whole batch; each block works on one column.
+// A batched call launches every kernel once for the whole batch; each block works
+// on one column through a block table.  The device header of a batch holds the
+// per-column call arguments and three block tables (one block per column; the
+// general kernels; the hash count); it is built on the host in pinned memory and
+// uploaded with one asynchronous copy.  Each column has its own single-column
+// workspace.
 
 namespace {
 
-struct BatchPlan {
-    std::vector<size_t> col_off;   // workspace offset of each column
+constexpr uint32_t kBatchMaxBlocks = 64;  // per column and kernel
+
+struct BatchShape {
     std::vector<uint32_t> bp, bh;  // blocks per column: general kernels, hash count
     uint32_t total_p = 0, total_h = 0;
-    size_t off_args = 0, off_m1 = 0, off_mp = 0, off_mh = 0, header = 0, total = 0;
+    size_t off_args = 0, off_m1 = 0, off_mp = 0, off_mh = 0, header = 0;
 };
-
-constexpr uint64_t kBatchElemsPerBlock = 1ull << 16;       // general kernels
-constexpr uint64_t kBatchElemsPerHashBlock = 1ull << 18;   // hash count (1024 threads)
-constexpr uint32_t kBatchMaxBlocks = 64;                    // per column and kernel
 
 uint32_t blocks_for(uint64_t n, uint64_t per) {
     uint64_t b = (n + per - 1) / per;
     return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(b, 1), kBatchMaxBlocks);
 }
 
-BatchPlan plan_batch(const uint64_t* ns, uint32_t n_cols) {
-    BatchPlan P;
+// Header layout; its size is bounded by header_bound(n_cols) whatever the tuning.
+BatchShape shape_batch(const uint64_t* ns, uint32_t n_cols, uint64_t per_block, uint64_t per_hash_block) {
+    BatchShape P;
     P.bp.resize(n_cols);
     P.bh.resize(n_cols);
     for (uint32_t i = 0; i < n_cols; ++i) {
-        P.bp[i] = blocks_for(ns[i], kBatchElemsPerBlock);
-        P.bh[i] = blocks_for(ns[i], kBatchElemsPerHashBlock);
+        P.bp[i] = blocks_for(ns[i], per_block);
+        P.bh[i] = blocks_for(ns[i], per_hash_block);
         P.total_p += P.bp[i];
         P.total_h += P.bh[i];
     }
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
     P.off_args = take(sizeof(cafs::Args) * (size_t)n_cols);
-    // a block table: col[total], first[n_cols], count[n_cols]
-    P.off_m1 = take(4ull * (n_cols + 2ull * n_cols));
+    P.off_m1 = take(4ull * (n_cols + 2ull * n_cols));   // col[total], first[n_cols], count[n_cols]
     P.off_mp = take(4ull * (P.total_p + 2ull * n_cols));
     P.off_mh = take(4ull * (P.total_h + 2ull * n_cols));
     P.header = o;
-    P.col_off.resize(n_cols);
-    for (uint32_t i = 0; i < n_cols; ++i) P.col_off[i] = take(make_layout(ns[i]).total);
-    P.total = o;
     return P;
+}
+
+size_t header_bound(uint32_t n_cols) {
+    return align_up(sizeof(cafs::Args) * (size_t)n_cols) + 3 * align_up(4ull * (kBatchMaxBlocks + 2ull) * n_cols);
 }
 
 void fill_table(uint32_t* dst, uint32_t n_cols, const std::vector<uint32_t>* per_col, uint32_t total) {
@@ -481,74 +492,49 @@ void fill_table(uint32_t* dst, uint32_t n_cols, const std::vector<uint32_t>* per
     }
 }
 
-cafs::BatchGrid grid_at(void* ws, const BatchPlan& P, size_t off, uint32_t total, uint32_t n_cols) {
+cafs::BatchGrid grid_at(void* hdr, const BatchShape& P, size_t off, uint32_t total, uint32_t n_cols) {
     cafs::BatchGrid g;
-    g.args = at<cafs::Args>(ws, P.off_args);
-    g.col = at<uint32_t>(ws, off);
+    g.args = at<cafs::Args>(hdr, P.off_args);
+    g.col = at<uint32_t>(hdr, off);
     g.first = g.col + total;
     g.count = g.first + n_cols;
     return g;
 }
 
-}  // namespace
-
-size_t cafs_batched_workspace_bytes(const uint64_t* h_ns, uint32_t n_cols) {
-    if (n_cols > 0 && !h_ns) return 0;
-    return plan_batch(h_ns, n_cols).total;
-}
-
-cafs_status_t cafs_sort_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, uint32_t n_cols, void* d_ws,
-                                size_t ws_bytes, void* stream) {
-    if (!ctx || (n_cols > 0 && !h_cols)) return CAFS_EINVAL;
-    if (n_cols == 0) return CAFS_OK;
-    std::vector<uint64_t> ns(n_cols);
+cafs_status_t check_columns(const cafs_column_t* cols, uint32_t n_cols, std::vector<uint64_t>& ns) {
+    ns.resize(n_cols);
     for (uint32_t i = 0; i < n_cols; ++i) {
-        const cafs_column_t& col = h_cols[i];
+        const cafs_column_t& col = cols[i];
         if (col.flags != 0 || (col.dtype != CAFS_I64 && col.dtype != CAFS_U64)) return CAFS_EINVAL;
         cafs_status_t st = check_buffers(col.d_in, col.d_out, col.n);
         if (st != CAFS_OK) return st;
         if ((col.d_uniq || col.d_counts) && !col.d_report) return CAFS_EINVAL;
         ns[i] = col.n;
     }
-    const BatchPlan P = plan_batch(ns.data(), n_cols);
-    if (!d_ws || ws_bytes < P.total || reinterpret_cast<uintptr_t>(d_ws) % kAlign) return CAFS_EWORKSPACE;
-    DeviceGuard dg(ctx->device);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    // host image of the header, staged in pinned memory and uploaded asynchronously
-    if (ctx->staged_pending) {
-        hipError_t e = hipEventSynchronize(ctx->staged);  // the previous upload has been read
-        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-        ctx->staged_pending = false;
-    }
-    if (ctx->staging_bytes < P.header) {
-        if (ctx->staging) (void)hipHostFree(ctx->staging);
-        ctx->staging = nullptr;
-        ctx->staging_bytes = 0;
-        hipError_t e = hipHostMalloc(&ctx->staging, P.header, hipHostMallocDefault);
-        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
-        ctx->staging_bytes = P.header;
-    }
-    char* h = static_cast<char*>(ctx->staging);
+    return CAFS_OK;
+}
+
+// Enqueues one batch.  col_ws[i] is column i's workspace (make_layout(n_i).total
+// bytes, 256-byte aligned); hdr_dev receives the header, staged through hdr_host
+// (pinned, at least P.header bytes, not reused before this upload has run).
+cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uint32_t n_cols, void* const* col_ws,
+                           const BatchShape& P, void* hdr_dev, void* hdr_host, hipStream_t s) {
+    char* h = static_cast<char*>(hdr_host);
     cafs::Args* args = reinterpret_cast<cafs::Args*>(h + P.off_args);
     for (uint32_t i = 0; i < n_cols; ++i) {
-        const cafs_column_t& col = h_cols[i];
-        void* cws = static_cast<char*>(d_ws) + P.col_off[i];
+        const cafs_column_t& col = cols[i];
         args[i] = make_args(ctx, make_layout(col.n), col.d_in, col.d_out, col.n, (cafs_dtype_t)col.dtype,
-                            col.d_uniq, col.d_counts, col.d_report, cws);
+                            col.d_uniq, col.d_counts, col.d_report, col_ws[i]);
     }
     fill_table(reinterpret_cast<uint32_t*>(h + P.off_m1), n_cols, nullptr, n_cols);
     fill_table(reinterpret_cast<uint32_t*>(h + P.off_mp), n_cols, &P.bp, P.total_p);
     fill_table(reinterpret_cast<uint32_t*>(h + P.off_mh), n_cols, &P.bh, P.total_h);
     (void)hipGetLastError();
-    hipError_t e = hipMemcpyAsync(d_ws, ctx->staging, P.header, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(hdr_dev, hdr_host, P.header, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-    e = hipEventRecord(ctx->staged, s);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    ctx->staged_pending = true;
-
-    const cafs::BatchGrid g1 = grid_at(d_ws, P, P.off_m1, n_cols, n_cols);
-    const cafs::BatchGrid gp = grid_at(d_ws, P, P.off_mp, P.total_p, n_cols);
-    const cafs::BatchGrid gh = grid_at(d_ws, P, P.off_mh, P.total_h, n_cols);
+    const cafs::BatchGrid g1 = grid_at(hdr_dev, P, P.off_m1, n_cols, n_cols);
+    const cafs::BatchGrid gp = grid_at(hdr_dev, P, P.off_mp, P.total_p, n_cols);
+    const cafs::BatchGrid gh = grid_at(hdr_dev, P, P.off_mh, P.total_h, n_cols);
     const uint32_t C = n_cols, TP = P.total_p, TH = P.total_h;
     cafs::kb_pre<<<C, 1024, 0, s>>>(g1);
     cafs::kb_mono_full<<<TP, 256, 0, s>>>(gp);
@@ -579,6 +565,384 @@ cafs_status_t cafs_sort_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, ui
     return e == hipSuccess ? CAFS_OK : hip_fail(e, "launch");
 }
 
+// Column workspaces of a contiguous batched workspace: header bound, then columns.
+size_t batch_ws_layout(const uint64_t* ns, uint32_t n_cols, std::vector<size_t>* offs) {
+    size_t o = align_up(header_bound(n_cols));
+    if (offs) offs->resize(n_cols);
+    for (uint32_t i = 0; i < n_cols; ++i) {
+        if (offs) (*offs)[i] = o;
+        o = align_up(o + make_layout(ns[i]).total);
+    }
+    return o;
+}
+
+}  // namespace
+
+size_t cafs_batched_workspace_bytes(const uint64_t* h_ns, uint32_t n_cols) {
+    if (n_cols > 0 && !h_ns) return 0;
+    return batch_ws_layout(h_ns, n_cols, nullptr);
+}
+
+cafs_status_t cafs_ctx_set_batch_tuning(cafs_ctx_t* ctx, uint64_t elems_per_block, uint64_t elems_per_hash_block) {
+    if (!ctx || elems_per_block == 0 || elems_per_hash_block == 0) return CAFS_EINVAL;
+    ctx->batch_per_block = elems_per_block;
+    ctx->batch_per_hash_block = elems_per_hash_block;
+    return CAFS_OK;
+}
+
+cafs_status_t cafs_sort_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, uint32_t n_cols, void* d_ws,
+                                size_t ws_bytes, void* stream) {
+    if (!ctx || (n_cols > 0 && !h_cols)) return CAFS_EINVAL;
+    if (n_cols == 0) return CAFS_OK;
+    std::vector<uint64_t> ns;
+    cafs_status_t st = check_columns(h_cols, n_cols, ns);
+    if (st != CAFS_OK) return st;
+    std::vector<size_t> offs;
+    const size_t need = batch_ws_layout(ns.data(), n_cols, &offs);
+    if (!d_ws || ws_bytes < need || reinterpret_cast<uintptr_t>(d_ws) % kAlign) return CAFS_EWORKSPACE;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const BatchShape P = shape_batch(ns.data(), n_cols, ctx->batch_per_block, ctx->batch_per_hash_block);
+    std::vector<void*> col_ws(n_cols);
+    for (uint32_t i = 0; i < n_cols; ++i) col_ws[i] = static_cast<char*>(d_ws) + offs[i];
+    // Staging: a capture records the copy from the staging buffer into the graph, so a
+    // captured call gets a buffer of its own that lives as long as the context.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    (void)hipStreamIsCapturing(s, &cap);
+    void* host = nullptr;
+    if (cap != hipStreamCaptureStatusNone) {
+        hipError_t e = hipHostMalloc(&host, P.header, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+        ctx->captured_staging.push_back(host);
+    } else {
+        if (ctx->staged_pending) {
+            hipError_t e = hipEventSynchronize(ctx->staged);  // the previous upload has been read
+            if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+            ctx->staged_pending = false;
+        }
+        if (ctx->staging_bytes < P.header) {
+            if (ctx->staging) (void)hipHostFree(ctx->staging);
+        for (void* p : ctx->captured_staging) (void)hipHostFree(p);
+            ctx->staging = nullptr;
+            ctx->staging_bytes = 0;
+            hipError_t e = hipHostMalloc(&ctx->staging, P.header, hipHostMallocDefault);
+            if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+            ctx->staging_bytes = P.header;
+        }
+        host = ctx->staging;
+    }
+    st = launch_batch(ctx, h_cols, n_cols, col_ws.data(), P, d_ws, host, s);
+    if (st != CAFS_OK) return st;
+    if (cap == hipStreamCaptureStatusNone) {
+        hipError_t e = hipEventRecord(ctx->staged, s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        ctx->staged_pending = true;
+    }
+    return CAFS_OK;
+}
+
+cafs_status_t cafs_autotune_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, uint32_t n_cols, void* d_ws,
+                                    size_t ws_bytes, void* stream, double* h_best_ms) {
+    if (!ctx || n_cols == 0 || !h_cols) return CAFS_EINVAL;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventCreate");
+    const uint64_t per[] = {1ull << 15, 1ull << 16, 1ull << 17, 1ull << 18};
+    const uint64_t per_h[] = {1ull << 17, 1ull << 18, 1ull << 19, 1ull << 20};
+    double best = 1e30;
+    uint64_t bp = ctx->batch_per_block, bh = ctx->batch_per_hash_block;
+    cafs_status_t st = CAFS_OK;
+    for (uint64_t p : per) {
+        for (uint64_t q : per_h) {
+            ctx->batch_per_block = p;
+            ctx->batch_per_hash_block = q;
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < 3 && st == CAFS_OK; ++rep) {
+                (void)hipEventRecord(e0, s);
+                st = cafs_sort_batched(ctx, h_cols, n_cols, d_ws, ws_bytes, stream);
+                (void)hipEventRecord(e1, s);
+                hipError_t e = hipEventSynchronize(e1);
+                if (e != hipSuccess) st = hip_fail(e, "hipEventSynchronize");
+                float ms = 0.f;
+                if (st == CAFS_OK && rep > 0 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+                    ms_min = std::min(ms_min, ms);
+            }
+            if (st != CAFS_OK) break;
+            if (ms_min < best) { best = ms_min; bp = p; bh = q; }
+        }
+        if (st != CAFS_OK) break;
+    }
+    ctx->batch_per_block = bp;
+    ctx->batch_per_hash_block = bh;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (h_best_ms) *h_best_ms = best;
+    return st;
+}
+
+// ---- serving -------------------------------------------------------------------
+// Continuous batching: requests reserve memory in one device arena of the HBM
+// budget (admission), are submitted once their input is ready, and every call to
+// cafs_server_poll launches the queued requests as batches on the free streams
+// and collects the batches that finished.  Requests arriving while other batches
+// run join the next batch on another stream, so their work overlaps on the GPU.
+
+struct cafs_server {
+    cafs_ctx_t* ctx;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    std::map<size_t, size_t> free_blocks;  // offset -> size, coalesced
+    size_t used = 0, high_water = 0;
+    struct Req {
+        uint64_t n = 0;
+        int32_t dtype = 0;
+        size_t off = 0, bytes = 0;
+        cafs_column_t col{};
+        void* ws = nullptr;
+        hipEvent_t ready = nullptr;
+        int state = 0;  // 0 reserved, 1 queued, 2 running, 3 finished
+    };
+    std::unordered_map<uint64_t, Req> reqs;
+    std::deque<uint64_t> queue;
+    std::deque<uint64_t> finished;
+    struct Slot {
+        hipStream_t s = nullptr;
+        hipEvent_t done = nullptr;
+        void* hdr_dev = nullptr;
+        void* hdr_host = nullptr;
+        std::vector<uint64_t> tickets;
+        bool busy = false;
+    };
+    std::vector<Slot> slots;
+    std::vector<hipEvent_t> events;
+    uint32_t max_batch = 0;
+    uint64_t next_ticket = 1;
+    uint64_t n_batches = 0, n_launched = 0, n_refused = 0, max_busy = 0;
+};
+
+namespace {
+
+bool arena_alloc(cafs_server* sv, size_t bytes, size_t* off) {
+    for (auto it = sv->free_blocks.begin(); it != sv->free_blocks.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t at2 = it->first + bytes;
+            sv->free_blocks.erase(it);
+            if (rest) sv->free_blocks[at2] = rest;
+            sv->used += bytes;
+            sv->high_water = std::max(sv->high_water, sv->used);
+            return true;
+        }
+    }
+    return false;
+}
+
+void arena_free(cafs_server* sv, size_t off, size_t bytes) {
+    sv->used -= bytes;
+    auto it = sv->free_blocks.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != sv->free_blocks.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        sv->free_blocks.erase(nx);
+    }
+    if (it != sv->free_blocks.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            sv->free_blocks.erase(it);
+        }
+    }
+}
+
+}  // namespace
+
+cafs_status_t cafs_server_create(cafs_ctx_t* ctx, size_t hbm_budget, uint32_t n_streams, uint32_t max_batch,
+                                 cafs_server_t** out) {
+    if (!ctx || !out || n_streams == 0 || max_batch == 0 || hbm_budget < (1u << 20)) return CAFS_EINVAL;
+    *out = nullptr;
+    DeviceGuard dg(ctx->device);
+    cafs_server_t* sv = new (std::nothrow) cafs_server_t;
+    if (!sv) return CAFS_ENOMEM;
+    sv->ctx = ctx;
+    sv->max_batch = max_batch;
+    sv->arena_bytes = hbm_budget / kAlign * kAlign;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&sv->arena), sv->arena_bytes);
+    if (e != hipSuccess) {
+        delete sv;
+        return hip_fail(e, "hipMalloc arena");
+    }
+    sv->free_blocks[0] = sv->arena_bytes;
+    sv->slots.resize(n_streams);
+    const size_t hb = header_bound(max_batch);
+    for (auto& sl : sv->slots) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMalloc(&sl.hdr_dev, hb);
+        if (e == hipSuccess) e = hipHostMalloc(&sl.hdr_host, hb, hipHostMallocDefault);
+    }
+    *out = sv;
+    if (e != hipSuccess) {
+        cafs_status_t st = hip_fail(e, "server streams");
+        cafs_server_destroy(sv);
+        *out = nullptr;
+        return st;
+    }
+    return CAFS_OK;
+}
+
+void cafs_server_destroy(cafs_server_t* sv) {
+    if (!sv) return;
+    DeviceGuard dg(sv->ctx->device);
+    for (auto& sl : sv->slots) {
+        if (sl.s) (void)hipStreamSynchronize(sl.s);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.hdr_dev) (void)hipFree(sl.hdr_dev);
+        if (sl.hdr_host) (void)hipHostFree(sl.hdr_host);
+        if (sl.s) (void)hipStreamDestroy(sl.s);
+    }
+    for (auto& kv : sv->reqs)
+        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+    for (hipEvent_t e : sv->events) (void)hipEventDestroy(e);
+    if (sv->arena) (void)hipFree(sv->arena);
+    delete sv;
+}
+
+cafs_status_t cafs_server_reserve(cafs_server_t* sv, uint64_t n, int32_t dtype, uint64_t* h_ticket, void** h_d_in,
+                                  void** h_d_out, cafs_report_t** h_d_report) {
+    if (!sv || !h_ticket || n >= (1ull << 32) || (dtype != CAFS_I64 && dtype != CAFS_U64)) return CAFS_EINVAL;
+    const bool bufs = h_d_in && h_d_out && h_d_report;
+    const size_t data = bufs ? 2 * align_up(n * 8) + align_up(sizeof(cafs_report_t)) : 0;
+    const size_t bytes = data + align_up(make_layout(n).total);
+    size_t off = 0;
+    if (!arena_alloc(sv, bytes, &off)) {
+        ++sv->n_refused;
+        return CAFS_EBUSY;
+    }
+    cafs_server::Req r;
+    r.n = n;
+    r.dtype = dtype;
+    r.off = off;
+    r.bytes = bytes;
+    char* base = sv->arena + off;
+    r.col.n = n;
+    r.col.dtype = dtype;
+    if (bufs) {
+        r.col.d_in = base;
+        r.col.d_out = base + align_up(n * 8);
+        r.col.d_report = reinterpret_cast<cafs_report_t*>(base + 2 * align_up(n * 8));
+        *h_d_in = const_cast<void*>(r.col.d_in);
+        *h_d_out = r.col.d_out;
+        *h_d_report = r.col.d_report;
+    }
+    r.ws = base + data;
+    const uint64_t t = sv->next_ticket++;
+    sv->reqs[t] = r;
+    *h_ticket = t;
+    return CAFS_OK;
+}
+
+cafs_status_t cafs_server_submit(cafs_server_t* sv, uint64_t ticket, const cafs_column_t* col, void* ready_stream) {
+    if (!sv) return CAFS_EINVAL;
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end() || it->second.state != 0) return CAFS_EINVAL;
+    cafs_server::Req& r = it->second;
+    if (col) {
+        if (col->n != r.n || col->dtype != r.dtype || col->flags != 0) return CAFS_EINVAL;
+        cafs_status_t st = check_buffers(col->d_in, col->d_out, col->n);
+        if (st != CAFS_OK) return st;
+        if ((col->d_uniq || col->d_counts) && !col->d_report) return CAFS_EINVAL;
+        r.col = *col;
+    } else if (r.n > 0 && !r.col.d_in) {
+        return CAFS_EINVAL;
+    }
+    DeviceGuard dg(sv->ctx->device);
+    if (!sv->events.empty()) {
+        r.ready = sv->events.back();
+        sv->events.pop_back();
+    } else {
+        hipError_t e = hipEventCreateWithFlags(&r.ready, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    hipError_t e = hipEventRecord(r.ready, static_cast<hipStream_t>(ready_stream));
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    r.state = 1;
+    sv->queue.push_back(ticket);
+    return CAFS_OK;
+}
+
+cafs_status_t cafs_server_poll(cafs_server_t* sv, uint64_t* h_tickets, uint32_t cap, uint32_t* h_n) {
+    if (!sv || !h_n || (cap > 0 && !h_tickets)) return CAFS_EINVAL;
+    DeviceGuard dg(sv->ctx->device);
+    uint64_t busy = 0;
+    for (auto& sl : sv->slots) {
+        if (!sl.busy) continue;
+        const hipError_t q = hipEventQuery(sl.done);
+        if (q == hipErrorNotReady) { ++busy; continue; }
+        if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
+        for (uint64_t t : sl.tickets) {
+            sv->reqs[t].state = 3;
+            sv->finished.push_back(t);
+        }
+        sl.tickets.clear();
+        sl.busy = false;
+    }
+    for (auto& sl : sv->slots) {
+        if (sl.busy || sv->queue.empty()) continue;
+        const uint32_t m = (uint32_t)std::min<size_t>(sv->queue.size(), sv->max_batch);
+        std::vector<cafs_column_t> cols(m);
+        std::vector<void*> ws(m);
+        std::vector<uint64_t> ns(m);
+        sl.tickets.assign(sv->queue.begin(), sv->queue.begin() + m);
+        sv->queue.erase(sv->queue.begin(), sv->queue.begin() + m);
+        for (uint32_t i = 0; i < m; ++i) {
+            cafs_server::Req& r = sv->reqs[sl.tickets[i]];
+            hipError_t e = hipStreamWaitEvent(sl.s, r.ready, 0);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+            cols[i] = r.col;
+            ws[i] = r.ws;
+            ns[i] = r.n;
+            r.state = 2;
+        }
+        const BatchShape P = shape_batch(ns.data(), m, sv->ctx->batch_per_block, sv->ctx->batch_per_hash_block);
+        cafs_status_t st = launch_batch(sv->ctx, cols.data(), m, ws.data(), P, sl.hdr_dev, sl.hdr_host, sl.s);
+        if (st != CAFS_OK) return st;
+        hipError_t e = hipEventRecord(sl.done, sl.s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        sl.busy = true;
+        ++busy;
+        ++sv->n_batches;
+        sv->n_launched += m;
+    }
+    sv->max_busy = std::max(sv->max_busy, busy);
+    uint32_t k = 0;
+    while (k < cap && !sv->finished.empty()) {
+        h_tickets[k++] = sv->finished.front();
+        sv->finished.pop_front();
+    }
+    *h_n = k;
+    return CAFS_OK;
+}
+
+cafs_status_t cafs_server_release(cafs_server_t* sv, uint64_t ticket) {
+    if (!sv) return CAFS_EINVAL;
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end() || (it->second.state != 3 && it->second.state != 0)) return CAFS_EINVAL;
+    arena_free(sv, it->second.off, it->second.bytes);
+    if (it->second.ready) sv->events.push_back(it->second.ready);
+    sv->reqs.erase(it);
+    return CAFS_OK;
+}
+
+cafs_status_t cafs_server_stats(cafs_server_t* sv, uint64_t* h_stats, uint32_t n) {
+    if (!sv || (n > 0 && !h_stats)) return CAFS_EINVAL;
+    const uint64_t v[] = {sv->n_batches, sv->n_launched, sv->n_refused, sv->max_busy, sv->high_water, sv->used,
+                          (uint64_t)sv->queue.size()};
+    for (uint32_t i = 0; i < n && i < sizeof(v) / sizeof(v[0]); ++i) h_stats[i] = v[i];
+    return CAFS_OK;
+}
+
 const char* cafs_status_str(cafs_status_t status) {
     switch (status) {
     case CAFS_OK: return "ok";
@@ -587,6 +951,7 @@ const char* cafs_status_str(cafs_status_t status) {
     case CAFS_EHIP: return "HIP error";
     case CAFS_EUNSUPPORTED: return "unsupported";
     case CAFS_ENOMEM: return "out of host memory";
+    case CAFS_EBUSY: return "not enough room in the server's memory budget now";
     }
     return "unknown status";
 }

@@ -1,0 +1,102 @@
+"""Serving: continuous batching under a memory budget.  Each request's result is
+the same alone and in the mix (bit-identical outputs and reports), and matches
+the oracle; the real-time load driver completes a short Poisson trace."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_25040_amd as cafs
+    return cafs.Context(0)
+
+
+def test_alone_equals_in_the_mix(ctx):
+    import paper_2605_25040_amd as cafs
+    rng = np.random.default_rng(21)
+    sv = cafs.Server(ctx, hbm_budget=512 << 20, n_streams=3, max_batch=16)
+    reqs = []
+    for i in range(60):
+        n = int(np.exp(rng.uniform(np.log(1e3), np.log(3e5))))
+        k = int(np.exp(rng.uniform(np.log(2), np.log(max(3, min(n, 1e5))))))
+        x = gen.column(n, k, dist="zipf" if i % 2 else "uniform", s=1.1, seed=gen.default_seed(n, k, column=i))
+        xt = torch.from_numpy(x).cuda()
+        col = {"in": xt, "out": torch.empty_like(xt), "unsigned": bool(i % 5 == 0),
+               "report": torch.zeros(cafs.report_size(), dtype=torch.uint8, device="cuda:0"),
+               "uniq": None, "counts": None}
+        reqs.append((x, col))
+    done, waiting, live = {}, list(range(len(reqs))), {}
+    refused = 0
+    while len(done) < len(reqs):
+        # admit a few requests per round so that batches overlap and mix
+        for _ in range(5):
+            if not waiting:
+                break
+            i = waiting[0]
+            r = sv.reserve(reqs[i][0].size, unsigned=reqs[i][1]["unsigned"])
+            if r is None:
+                refused += 1
+                break
+            waiting.pop(0)
+            live[r[0]] = i
+            sv.submit(r[0], reqs[i][1])
+        for t in sv.poll():
+            done[live.pop(t)] = True
+            sv.release(t)
+    stats = sv.stats()
+    torch.cuda.synchronize()
+    assert stats["launched"] == len(reqs) and stats["batches"] >= 2
+    for i, (x, col) in enumerate(reqs):
+        dt = np.uint64 if col["unsigned"] else np.int64
+        alone, rep, _, _ = ctx.sort(col["in"], unsigned=col["unsigned"])
+        torch.cuda.synchronize()
+        assert torch.equal(alone, col["out"]), i
+        assert cafs.parse_report(rep) == cafs.parse_report(col["report"]), i
+        if i % 6 == 0:
+            xv = x.view(dt)
+            assert np.array_equal(col["out"].cpu().numpy().view(dt), oracle.sort(xv, dt)), i
+            ro = oracle.report(xv, dt)
+            r = cafs.parse_report(col["report"])
+            assert all(r[f] == ro[f] for f in oracle.REPORT_FIELDS), (i, r, ro)
+    sv.close()
+
+
+def test_budget_admission(ctx):
+    import paper_2605_25040_amd as cafs
+    sv = cafs.Server(ctx, hbm_budget=64 << 20, n_streams=2, max_batch=8)
+    tickets = []
+    while True:
+        r = sv.reserve(200_000, buffers=True)
+        if r is None:
+            break
+        tickets.append(r[0])
+        assert len(tickets) < 100
+    assert tickets and sv.stats()["refused"] == 1
+    sv.release(tickets.pop())
+    assert sv.reserve(200_000, buffers=True) is not None  # memory came back
+    sv.close()
+
+
+def test_device_generator_matches_host_uniform(ctx):
+    x = gen.column(100_003, 777, dtype=np.int64)
+    d = torch.empty(100_003, dtype=torch.int64, device="cuda:0")
+    gen.column_device(d, 777)
+    torch.cuda.synchronize()
+    assert np.array_equal(d.cpu().numpy(), x)
+
+
+def test_replay_short_trace(ctx):
+    arrival, n, k, seeds = gen.serving_trace(rate=2000, seconds=0.5, n_hi=2e6, k_cap=1e5)
+    res = gen.serve_replay(arrival, n, k, seeds, budget=8 << 30, n_streams=4, max_batch=256)
+    assert res["stats"]["launched"] == arrival.size
+    assert np.all(res["t_done"] >= arrival)
+    assert np.all(res["k_exact"] >= 1) and np.all(res["k_exact"] <= n)
+    assert set(np.unique(res["path"]).tolist()) <= {1, 2, 3, 4, 5}
