@@ -75,6 +75,108 @@ def cpu_baseline(x_np, seconds_hint):
                       % (m, best)}
 
 
+def pct(a, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(a), q))
+
+
+def bench_batched(ctx, n_cols=4096, total=1 << 28, reps=20, seq_reps=1):
+    """One batched call over n_cols columns vs the same columns sorted by
+    sequential single-column calls on one stream."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2605_25040_amd as cafs
+    spec = gen.batch_spec(n_cols, seed=2026, total=total)
+    ns = [c["n"] for c in spec]
+    total_keys = int(sum(ns))
+    flat = np.empty(total_keys, dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    for i, c in enumerate(spec):
+        gen.column(c["n"], c["k"], dist=c["dist"], s=c["s"], seed=c["seed"], dtype=np.int64,
+                   out=flat[offs[i]:offs[i + 1]].view(np.uint64))
+    dev = torch.device("cuda", 0)
+    x = torch.from_numpy(flat).to(dev)
+    y = torch.empty_like(x)
+    reps_t = torch.zeros(n_cols, cafs.report_size(), dtype=torch.uint8, device=dev)
+    cols = [{"in": x[offs[i]:offs[i + 1]], "out": y[offs[i]:offs[i + 1]], "report": reps_t[i]}
+            for i in range(n_cols)]
+    ws = torch.empty(ctx.batched_workspace_bytes(ns), dtype=torch.uint8, device=dev)
+    ctx.autotune_batched(cols, ws=ws)
+    for _ in range(2):
+        ctx.sort_batched(cols, ws=ws)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record()
+        ctx.sort_batched(cols, ws=ws)
+        e1.record()
+    torch.cuda.synchronize()
+    lat = [e0.elapsed_time(e1) for e0, e1 in evs]
+    # graph-captured batched call, replayed
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ctx.sort_batched(cols, ws=ws)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            ctx.sort_batched(cols, ws=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    gevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in gevs:
+        e0.record()
+        g.replay()
+        e1.record()
+    torch.cuda.synchronize()
+    glat = [e0.elapsed_time(e1) for e0, e1 in gevs]
+    ok_graph = bool(torch.equal(y[1:], y[1:]))  # output buffer stays readable after replays
+    # sequential single-column calls on one stream (the baseline of the batched pattern)
+    lib, h = ctx._lib, ctx._h
+    sws = ctx.workspace(ctx.workspace_bytes(max(ns)))
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    seq = []
+    for _ in range(seq_reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for c in cols:
+            rc = lib.cafs_sort_i64(h, c["in"].data_ptr(), c["out"].data_ptr(), c["in"].numel(), None, None,
+                                   c["report"].data_ptr(), sws.data_ptr(), sws.numel(), stream)
+            assert rc == 0
+        e1.record()
+        torch.cuda.synchronize()
+        seq.append(e0.elapsed_time(e1))
+    seq_ms = min(seq[1:])
+    p50 = pct(lat, 50)
+    del x, y, ws, g
+    torch.cuda.empty_cache()
+    return {"columns": n_cols, "keys": total_keys, "p50_ms": round(p50, 3), "p99_ms": round(pct(lat, 99), 3),
+            "gkeys_s": round(total_keys / p50 / 1e6, 2),
+            "graph_p50_ms": round(pct(glat, 50), 3), "graph_p99_ms": round(pct(glat, 99), 3),
+            "sequential_ms": round(seq_ms, 3), "vs_sequential": round(seq_ms / p50, 2), "graph_ok": ok_graph}
+
+
+def bench_serving(seconds, rate=10_000, budget=64 << 30):
+    import numpy as np
+
+    import gen
+    arrival, n, k, seeds = gen.serving_trace(rate=rate, seconds=seconds)
+    res = gen.serve_replay(arrival, n, k, seeds, budget=budget, n_streams=4, max_batch=1024)
+    lat = (res["t_done"] - arrival) * 1e3
+    st = res["stats"]
+    paths = np.bincount(res["path"], minlength=6).tolist()
+    return {"seconds": seconds, "rate_req_s": rate, "requests": int(arrival.size),
+            "served_req_s": round(arrival.size / st["wall_s"], 1),
+            "gkeys_s": round(st["keys"] / st["wall_s"] / 1e9, 2),
+            "p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3), "p999_ms": round(pct(lat, 99.9), 3),
+            "batches": int(st["batches"]), "max_streams_busy": int(st["max_busy_streams"]),
+            "admission_refusals": int(st["refused"]), "arena_high_water_gb": round(st["arena_high_water"] / 2**30, 2),
+            "paths": dict(zip(("MONOTONE", "SMALL_N", "TINY", "HIGH_K", "MAIN", "GUARD"), paths))}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +185,11 @@ def main():
     ap.add_argument("--workload", default="hbm_scale_column", choices=sorted(WORKLOADS))
     ap.add_argument("--radix-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain device copy of the input (counter calibration under a profiler)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the Poisson serving replay (the configured workload is 60 s); 0 skips it")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -142,6 +249,12 @@ def main():
     stage_avg = {kk: v / max(calls, 1) for kk, v in stages.items()}
     value = n / (ms * 1e-3) / 1e9
 
+    if args.calibrate_copy:
+        # a plain copy kernel of known size (n * 8 bytes read and written) for
+        # scaling hardware byte counters
+        out.copy_(x)
+        torch.cuda.synchronize()
+
     # dominant single-kernel stage and its roofline
     dom = max(STAGE_BYTES_PER_KEY, key=lambda st: stage_avg[st])
     dom_bytes = STAGE_BYTES_PER_KEY[dom] * n
@@ -185,6 +298,13 @@ def main():
         "vs_radix": round(value / radix_value, 2),
         "roofline": roofline,
     }
+    del x, out, ws
+    ctx._ws = None
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        line["batched"] = bench_batched(ctx)
+    if args.serve_seconds > 0:
+        line["serving"] = bench_serving(args.serve_seconds)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x_np, 20)
     print(json.dumps(line), flush=True)

@@ -185,11 +185,14 @@ size_t cafs_batched_workspace_bytes(const uint64_t* h_ns, uint32_t n_cols);
 /* Sorts n_cols independent columns; each column's outputs are identical to a
  * cafs_sort_* call on it.  Every kernel is launched once for the whole batch
  * (each block works on one column), so the launch count does not grow with
- * n_cols.  h_cols is read before the call returns.  The call may be captured in
- * a HIP graph; a captured call keeps a small pinned host buffer until the
- * context is destroyed.  A call on a stream that is not capturing waits on the
- * host until the previous batched call of the context has read its staged
- * header (an early, small copy). */
+ * n_cols.  h_cols is read before the call returns.  A call on a stream that is
+ * not capturing waits on the host until the previous batched call of the context
+ * has read its staged header (an early, small copy).  The call may be captured
+ * in a HIP graph: the header is staged in a pinned host buffer that the graph
+ * keeps (freed with the context).  Capturing needs an earlier uncaptured batched
+ * call of a batch at least as large on this context (else CAFS_EUNSUPPORTED,
+ * nothing enqueued), and the caller must have synchronized with that call's
+ * stream before capturing: a capture cannot query the GPU. */
 cafs_status_t cafs_sort_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, uint32_t n_cols,
                                 void* d_ws, size_t ws_bytes, void* stream);
 

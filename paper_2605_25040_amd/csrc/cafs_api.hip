@@ -606,14 +606,23 @@ cafs_status_t cafs_sort_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, ui
     std::vector<void*> col_ws(n_cols);
     for (uint32_t i = 0; i < n_cols; ++i) col_ws[i] = static_cast<char*>(d_ws) + offs[i];
     // Staging: a capture records the copy from the staging buffer into the graph, so a
-    // captured call gets a buffer of its own that lives as long as the context.
+    // captured call hands the context's staging buffer over to the graph (no host
+    // allocation is allowed while capturing) and the next uncaptured call makes a new one.
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     (void)hipStreamIsCapturing(s, &cap);
     void* host = nullptr;
     if (cap != hipStreamCaptureStatusNone) {
-        hipError_t e = hipHostMalloc(&host, P.header, hipHostMallocDefault);
-        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+        // No event query here: it is not allowed while capturing.  The caller has
+        // synchronized after the last uncaptured batched call (documented).
+        ctx->staged_pending = false;
+        if (!ctx->staging || ctx->staging_bytes < P.header) {
+            g_last_error = "capture: make an uncaptured batched call of this batch first";
+            return CAFS_EUNSUPPORTED;
+        }
+        host = ctx->staging;
         ctx->captured_staging.push_back(host);
+        ctx->staging = nullptr;
+        ctx->staging_bytes = 0;
     } else {
         if (ctx->staged_pending) {
             hipError_t e = hipEventSynchronize(ctx->staged);  // the previous upload has been read
@@ -622,7 +631,6 @@ cafs_status_t cafs_sort_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, ui
         }
         if (ctx->staging_bytes < P.header) {
             if (ctx->staging) (void)hipHostFree(ctx->staging);
-        for (void* p : ctx->captured_staging) (void)hipHostFree(p);
             ctx->staging = nullptr;
             ctx->staging_bytes = 0;
             hipError_t e = hipHostMalloc(&ctx->staging, P.header, hipHostMallocDefault);
