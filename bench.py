@@ -250,9 +250,9 @@ def main():
     value = n / (ms * 1e-3) / 1e9
 
     if args.calibrate_copy:
-        # a plain copy kernel of known size (n * 8 bytes read and written) for
-        # scaling hardware byte counters
-        out.copy_(x)
+        # a plain copy kernel of known size (n * 8 bytes read and written, 16-byte
+        # accesses like the sort's kernels) for scaling hardware byte counters
+        gen.copy_device(out, x, torch.cuda.current_stream(dev).cuda_stream)
         torch.cuda.synchronize()
 
     # dominant single-kernel stage and its roofline

@@ -58,6 +58,8 @@ def _load_dev():
         u64, p = ctypes.c_uint64, ctypes.c_void_p
         lib.gen_column_dev.argtypes = [p, u64, u64, ctypes.c_int, ctypes.c_double, ctypes.c_int, u64, p]
         lib.gen_column_dev.restype = ctypes.c_int
+        lib.copy_dev.argtypes = [p, p, u64, p]
+        lib.copy_dev.restype = ctypes.c_int
         lib.serve_replay.argtypes = [ctypes.c_int, p, p, p, p, u64, ctypes.c_double, u64, ctypes.c_uint32,
                                      ctypes.c_uint32, p, p, p, p, p]
         lib.serve_replay.restype = ctypes.c_int
@@ -77,6 +79,18 @@ def column_device(out, k, dist="uniform", s=1.1, palette="random", seed=None, st
     if rc != 0:
         raise RuntimeError("gen_column_dev failed: %d" % rc)
     return out
+
+
+def copy_device(dst, src, stream=None):
+    """Plain device copy (16-byte loads, 16-byte nontemporal stores) of src into dst."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst too small")
+    rc = _load_dev().copy_dev(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                              ctypes.c_void_p(stream) if stream else None)
+    if rc != 0:
+        raise RuntimeError("copy_dev failed: %d" % rc)
+    return dst
 
 
 def serving_trace(rate, seconds, seed=99, n_lo=1e3, n_hi=3e7, k_cap=1e6):

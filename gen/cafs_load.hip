@@ -27,6 +27,7 @@
 namespace {
 
 constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
 __host__ __device__ inline uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -65,6 +66,14 @@ __global__ void gen_kernel(uint64_t* out, uint64_t n, uint64_t K, int dist, doub
     }
 }
 
+// Plain copy with 16-byte loads and 16-byte nontemporal stores (the access shape of
+// the sort's streaming kernels); a kernel of known traffic for scaling hardware
+// byte counters.
+__global__ void copy_kernel(const u64x2* __restrict__ src, u64x2* __restrict__ dst, uint64_t n2) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n2; i += (uint64_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(src[i], &dst[i]);
+}
+
 double now_s() {
     using clk = std::chrono::steady_clock;
     static const clk::time_point t0 = clk::now();
@@ -82,6 +91,17 @@ int gen_column_dev(void* d_out, uint64_t n, uint64_t K, int dist, double s, int 
     const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 4096);
     gen_kernel<<<(unsigned)blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(static_cast<uint64_t*>(d_out), n, K,
                                                                                dist, s, palette, seed);
+    return (int)hipGetLastError();
+}
+
+// Copies bytes (a multiple of 16; both pointers 16-byte aligned) on `stream`.
+int copy_dev(void* d_dst, const void* d_src, uint64_t bytes, void* stream) {
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(d_dst) % 16 || reinterpret_cast<uintptr_t>(d_src) % 16) return -1;
+    const uint64_t n2 = bytes / 16;
+    if (n2 == 0) return 0;
+    const uint64_t blocks = std::min<uint64_t>((n2 + 255) / 256, 8192);
+    copy_kernel<<<(unsigned)blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(
+        static_cast<const u64x2*>(d_src), static_cast<u64x2*>(d_dst), n2);
     return (int)hipGetLastError();
 }
 

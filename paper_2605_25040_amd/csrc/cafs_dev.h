@@ -27,13 +27,17 @@ constexpr uint64_t kEmpty = ~0ull;             // empty-slot marker of the GPU h
                                                // keys equal to it are counted apart
 constexpr uint32_t kMonoPrefix = 1u << 13;     // elements the pre kernel checks for order
 constexpr int kCountThreads = 1024;            // hash-count workgroup
-constexpr uint32_t kLdsBuckets = 3072;         // per-workgroup LDS table: 3072 buckets of 4 keys
-constexpr uint32_t kLdsBucketSlots = 4;        // (12288 slots, 144 KiB with 32-bit counts)
-constexpr uint32_t kLdsProbeBuckets = 8;       // buckets probed before the global table
+constexpr uint32_t kLdsBuckets = 3392;         // per-workgroup LDS table: 3392 buckets of 4 keys
+constexpr uint32_t kLdsBucketSlots = 4;        // (13568 slots, 159 KiB with 32-bit counts)
+constexpr uint32_t kLdsWindow = 2;             // buckets probed before an element is deferred
+constexpr uint32_t kLdsProbeBuckets = 8;       // buckets probed in the deferred pass before the global table
+constexpr uint32_t kMaxCountBlocks = 1024;     // workgroups of one hash count
 constexpr uint32_t kGlobalProbe = 4096;        // global probe limit before overflow
 constexpr uint32_t kMinTableLog2 = 12;         // smallest global table (4096 slots)
 constexpr uint32_t kMaxTableLog2 = 22;         // largest global table (4M slots, 64 MiB)
-constexpr uint32_t kOrderMax = 8192;           // K sorted by the single-workgroup order kernel
+constexpr uint32_t kRankMax = 32768;           // K ordered by ranking (larger K: pair radix sort)
+constexpr uint32_t kRankKeysPerBlock = 64;     // keys ranked by one workgroup (16 threads each)
+constexpr uint32_t kRankTile = 8192;           // keys staged in LDS at a time while ranking
 constexpr uint32_t kGuardLdsBuckets = 16384;   // guard bucket counts kept in LDS up to this M
 constexpr int kRadixThreads = 256;             // radix workgroup (4 waves)
 constexpr int kRadixItems = 16;                // keys per thread per tile
@@ -103,7 +107,7 @@ struct Ctrl {
     uint32_t pad0;
     // dense (key, count) arrays
     uint64_t K;
-    uint32_t emit_main;               // dense arrays from the tiny or single-workgroup order path
+    uint32_t emit_main;               // dense arrays from the tiny branch or the rank order
     uint32_t dense_ready;
     uint32_t pair_sort;
     uint32_t radix_on;
@@ -149,8 +153,10 @@ struct Args {
     uint64_t* gcnt;
     uint32_t* claimed;
     uint32_t cap_ws_log2;             // largest table the workspace holds
-    // radix scratch (n keys; the pair sort uses the dead hash table instead)
+    // radix scratch (n keys; the pair sort uses the dead hash table instead); during
+    // the hash count it holds the deferred elements, one region per workgroup
     uint64_t* tmp_k;
+    uint32_t* dfr_cnt;                // kMaxCountBlocks entries: deferred elements per workgroup
     uint64_t* status;                 // 2 slots of status_slot words
     uint64_t status_slot;
     // guard scratch
@@ -192,6 +198,29 @@ struct BatchGrid {
     }
 
 // ---- helpers ---------------------------------------------------------------
+
+// Pointers reach the kernels inside structs, so the compiler sees them as generic
+// (flat) pointers.  Flat accesses also count against the LDS wait counter, which
+// makes every LDS wait in a loop wait for the loads in flight too; the hot loops
+// access memory through these global-address-space views instead.
+#define CAFS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ CAFS_GLOBAL T* gp(T* p) { return (CAFS_GLOBAL T*)p; }
+template <class T>
+__device__ __forceinline__ T g_add(T* p, T v) {
+    return __hip_atomic_fetch_add(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Returns the value found (== expected when the exchange happened).
+template <class T>
+__device__ __forceinline__ T g_cas(T* p, T expected, T desired) {
+    __hip_atomic_compare_exchange_strong(gp(p), &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return expected;
+}
+template <class T>
+__device__ __forceinline__ T g_load(const T* p) {
+    return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Multiplicative hash of Eq. hash: top `bits` bits of x * phi mod 2^64.
 __device__ __forceinline__ uint32_t phi_hash(uint64_t x, uint32_t bits) {

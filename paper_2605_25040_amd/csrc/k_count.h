@@ -96,12 +96,14 @@ __device__ __forceinline__ void phase2_body(const Args& a, uint32_t bid, uint32_
 }
 CAFS_KERNELS0(phase2, 256)
 
-__device__ __noinline__ void set_overflow(const Args& a, Ctrl* c) {
+// Switch to the radix engine after the global table overflowed.  In place, the
+// radix engine then sorts into scratch so that the guard can still read the input.
+__device__ __noinline__ void set_overflow(Ctrl* c, uint32_t inplace, uint64_t* tmp_k, uint64_t* uniq) {
     if (atomicExch(&c->overflow, 1u) == 0) {
-        if (a.in == a.out) {  // see the dispatcher: keep the input for the guard
-            c->rj.dst_k = a.tmp_k;
-            c->rj.tmp_k = a.uniq;
-            c->sorted = a.tmp_k;
+        if (inplace) {
+            c->rj.dst_k = tmp_k;
+            c->rj.tmp_k = uniq;
+            c->sorted = tmp_k;
             c->deferred_copy = 1;
         }
         atomicExch(&c->radix_on, 1u);
@@ -111,56 +113,84 @@ __device__ __noinline__ void set_overflow(const Args& a, Ctrl* c) {
     }
 }
 
+// The global (key, count) table of one column.
+struct GTable {
+    Ctrl* c;
+    uint64_t* keys;
+    unsigned long long* cnt;
+    uint32_t* claimed;
+    uint64_t* tmp_k;
+    uint64_t* uniq;
+    uint32_t inplace;
+};
+
+__device__ __forceinline__ GTable gtable(const Args& a) {
+    GTable t;
+    t.c = a.c;
+    t.keys = a.gkeys;
+    t.cnt = reinterpret_cast<unsigned long long*>(a.gcnt);
+    t.claimed = a.claimed;
+    t.tmp_k = a.tmp_k;
+    t.uniq = a.uniq;
+    t.inplace = a.in == a.out;
+    return t;
+}
+
 // Insert (v, cnt) into the global open-addressing table (linear probing, Eq. hash
 // slot).  A slot is claimed by CAS from kEmpty and never freed, so a key is either
 // in the table or (after an overflow) the whole table is abandoned for the radix
 // engine.  Claimed slots are listed so that compaction reads K entries, not the table.
-__device__ __forceinline__ void global_insert(const Args& a, Ctrl* c, uint64_t v, uint64_t cnt) {
-    if (atomic_load_agent(&c->overflow)) return;
+__device__ __forceinline__ void global_insert(const GTable& t, uint64_t v, uint64_t cnt) {
+    Ctrl* c = t.c;
+    if (g_load(&c->overflow)) return;
     const uint32_t lg = c->cap_log2;
     const uint64_t mask = (1ull << lg) - 1;
     uint64_t h = phi_hash(v, lg);
     for (uint32_t pr = 0; pr < kGlobalProbe; ++pr) {
-        uint64_t k = atomic_load_agent(&a.gkeys[h]);
+        uint64_t k = g_load(&t.keys[h]);
         if (k == kEmpty) {
-            const unsigned long long old =
-                atomicCAS((unsigned long long*)&a.gkeys[h], (unsigned long long)kEmpty, (unsigned long long)v);
-            if (old == kEmpty) {
-                const uint32_t idx = atomicAdd(&c->claimed, 1u);
-                if (idx >= c->cap_limit) { set_overflow(a, c); return; }
-                a.claimed[idx] = (uint32_t)h;
-                atomicAdd((unsigned long long*)&a.gcnt[h], (unsigned long long)cnt);
+            k = g_cas(&t.keys[h], kEmpty, v);
+            if (k == kEmpty) {
+                const uint32_t idx = g_add(&c->claimed, 1u);
+                if (idx >= c->cap_limit) {
+                    set_overflow(c, t.inplace, t.tmp_k, t.uniq);
+                    return;
+                }
+                gp(t.claimed)[idx] = (uint32_t)h;
+                g_add(&t.cnt[h], (unsigned long long)cnt);
                 return;
             }
-            k = old;
         }
         if (k == v) {
-            atomicAdd((unsigned long long*)&a.gcnt[h], (unsigned long long)cnt);
+            g_add(&t.cnt[h], (unsigned long long)cnt);
             return;
         }
         h = (h + 1) & mask;
     }
-    set_overflow(a, c);
+    set_overflow(c, t.inplace, t.tmp_k, t.uniq);
 }
 
 // ---------------------------------------------------------------------------
 // Hash count (main path, Sec. 4.4).  The paper's hot loop updates a bucket of four
 // 64-bit keys on one cache line (Sec. 4.2, Alg. 1).  Here each workgroup owns a
-// table of 3072 such buckets in LDS (12288 keys with 32-bit counters).  An element
-// hashes to a bucket (Eq. hash, reduced to 3072 by a multiply), reads its four keys
+// table of 3392 such buckets in LDS (13568 keys with 32-bit counters).  An element
+// hashes to a bucket (Eq. hash, reduced to 3392 by a multiply), reads its four keys
 // with two 16-byte LDS loads and compares them with the element, the GPU analogue
 // of the paper's cmpeq + movemask + tzcnt; on a match it adds 1 to that slot's
 // counter with an LDS atomic.  Within a bucket occupied slots form a prefix and a
 // key is stored in the first bucket, in probe order, that had room for it, so a
-// lookup can stop at the first bucket with a free slot.  The fast path covers the
-// home bucket and, when that one is full, the next bucket, as straight-line code
-// for the eight keys a thread holds while the loads of its next eight keys are in
-// flight.  Other keys take the slow path: claim the first free slot of the first
-// bucket with room by a 64-bit LDS CAS, and after kLdsProbeBuckets full buckets go
-// to the global table.  At the end each workgroup flushes its occupied slots to
-// the global table.  Elements equal to the empty marker are counted in registers.
+// lookup can stop at the first bucket with a free slot.  Lookups cover the home
+// bucket and, when that one is full, the next one (the window), as straight-line
+// code for the eight keys a thread holds while the loads of its next eight keys
+// are in flight.  A key absent from a window with room is inserted by a 64-bit
+// LDS CAS on the first free slot.  An element whose window is full is deferred:
+// the wave appends it to its workgroup's region of a scratch array, and a second
+// pass counts the deferred elements with a fresh table.  Deferring keeps the
+// rare long probes out of the wave-wide lockstep of the hot loop.  At the end
+// each workgroup flushes its occupied slots to the global table (Eq. hash slot,
+// linear probing).  Elements equal to the empty marker are counted in registers.
 //
-// This kernel also resolves the tiny branch: if the tiny counters sum to N the
+// The first pass also resolves the tiny branch: if the tiny counters sum to N the
 // column is tiny and the dense arrays are written here; otherwise the element set
 // has an unsampled value and the main path runs with the same estimate (Sec. 4.4).
 // ---------------------------------------------------------------------------
@@ -168,23 +198,30 @@ __device__ __forceinline__ uint32_t lds_bucket(uint64_t x) {
     return (uint32_t)(((uint64_t)phi_hash32(x, 32) * kLdsBuckets) >> 32);
 }
 
-__device__ __forceinline__ void lds_insert_slow(const Args& a, Ctrl* c, uint64_t* skeys, uint32_t* scnt, uint64_t x) {
+__device__ __forceinline__ uint32_t next_bucket(uint32_t b) { return (b + 1 == kLdsBuckets) ? 0 : b + 1; }
+
+// Find or claim a slot for x within `window` buckets from its home bucket and add
+// `add` to its counter.  Returns false when those buckets are full without x.
+__device__ __forceinline__ bool lds_insert(uint64_t* skeys, uint32_t* scnt, uint64_t x, uint32_t add,
+                                           uint32_t window) {
     uint32_t b = lds_bucket(x);
-    for (uint32_t pr = 0; pr < kLdsProbeBuckets; ++pr) {
+    for (uint32_t pr = 0; pr < window; ++pr) {
         const uint32_t base = b * kLdsBucketSlots;
         for (uint32_t s = 0; s < kLdsBucketSlots; ++s) {
-            const uint64_t k = skeys[base + s];
-            if (k == x) { atomicAdd(&scnt[s * kLdsBuckets + b], 1u); return; }
+            uint64_t k = __hip_atomic_load(&skeys[base + s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (k == kEmpty) {
-                const unsigned long long old = atomicCAS((unsigned long long*)&skeys[base + s],
-                                                         (unsigned long long)kEmpty, (unsigned long long)x);
-                if (old == kEmpty || old == x) { atomicAdd(&scnt[s * kLdsBuckets + b], 1u); return; }
-                // another key took the slot: the next slot may be free
+                k = atomicCAS((unsigned long long*)&skeys[base + s], (unsigned long long)kEmpty,
+                              (unsigned long long)x);
+                if (k == kEmpty) k = x;  // claimed; otherwise k is the key that took the slot
+            }
+            if (k == x) {
+                atomicAdd(&scnt[s * kLdsBuckets + b], add);
+                return true;
             }
         }
-        b = (b + 1 == kLdsBuckets) ? 0 : b + 1;
+        b = next_bucket(b);
     }
-    global_insert(a, c, x, 1);
+    return false;
 }
 
 // Slot of x among the four keys of a bucket, or -1; `full` tells whether the last
@@ -194,6 +231,47 @@ __device__ __forceinline__ int match4(const uint64_t* skeys, uint32_t b, uint64_
     const u64x2 hi = *reinterpret_cast<const u64x2*>(skeys + b * kLdsBucketSlots + 2);
     full = hi.y != kEmpty;
     return lo.x == x ? 0 : lo.y == x ? 1 : hi.x == x ? 2 : hi.y == x ? 3 : -1;
+}
+
+template <int NE>
+__device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, uint32_t* __restrict__ scnt,
+                                                const uint64_t (&x)[NE], uint32_t want_m) {
+    uint32_t ins = 0, dfr = 0;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const bool want = (want_m >> e) & 1u;
+        uint32_t b = lds_bucket(x[e]);
+        bool full;
+        int m = match4(skeys, b, x[e], full);
+        if (m < 0 && full) {
+            b = next_bucket(b);
+            m = match4(skeys, b, x[e], full);
+        }
+        const bool hit = want && m >= 0;
+        atomicAdd(&scnt[(m < 0 ? 0 : m) * kLdsBuckets + b], hit ? 1u : 0u);
+        const bool miss = want && !hit;
+        ins |= (miss && !full) ? (1u << e) : 0u;
+        dfr |= (miss && full) ? (1u << e) : 0u;
+    }
+    if (ins) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            if (((ins >> e) & 1u) && !lds_insert(skeys, scnt, x[e], 1u, kLdsWindow)) dfr |= 1u << e;
+    }
+    return dfr;
+}
+
+// Each workgroup of the first pass reads one contiguous range of ceil(P / nblk)
+// pairs; its region of the deferred-element scratch (tmp_k) holds that many pairs,
+// so it never fills up (tmp_k has room for n + 2 + 2 * kMaxCountBlocks keys).
+__device__ __forceinline__ uint64_t pairs_per_block(uint64_t P, uint32_t nblk) { return (P + nblk - 1) / nblk; }
+
+__device__ __forceinline__ void flush_table(const GTable& t, const uint64_t* skeys, const uint32_t* scnt) {
+    constexpr uint32_t S = kLdsBuckets * kLdsBucketSlots;
+    for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
+        const uint32_t cn = scnt[i];  // slot i / kLdsBuckets of bucket i % kLdsBuckets; never 0 once claimed
+        if (cn) global_insert(t, skeys[(i % kLdsBuckets) * kLdsBucketSlots + i / kLdsBuckets], cn);
+    }
 }
 
 __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uint32_t nblk) {
@@ -231,109 +309,192 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
     constexpr uint32_t S = kLdsBuckets * kLdsBucketSlots;
     __shared__ __attribute__((aligned(16))) uint64_t skeys[S];
     __shared__ uint32_t scnt[S];
+    __shared__ uint32_t s_ndef;
     for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
         skeys[i] = kEmpty;
         scnt[i] = 0;
     }
+    if (threadIdx.x == 0) s_ndef = 0;
     __syncthreads();
 
+    const GTable t = gtable(a);
+    const uint64_t n = a.n;
+    const CAFS_GLOBAL uint64_t* in = gp(a.in);
+    const uint32_t lane = __lane_id();
     uint32_t ecnt = 0;
     const uint32_t head = a.in_head;
-    const uint64_t P = num_pairs(a.n, head);
-    const uint64_t Pf = (a.n + head) / 2;  // pairs [head, Pf) hold two in-range elements
-    constexpr int U = 4;                   // pairs per thread per step
+    const uint64_t P = num_pairs(n, head);
+    const uint64_t Pf = (n + head) / 2;  // pairs [head, Pf) hold two in-range elements
+    const uint64_t PP = pairs_per_block(P, nblk);
+    const uint64_t p_end = (uint64_t)(bid + 1) * PP < P ? (uint64_t)(bid + 1) * PP : P;
+    const uint64_t p_full = p_end < Pf ? p_end : Pf;
+    CAFS_GLOBAL uint64_t* region = gp(a.tmp_k) + (uint64_t)bid * 2 * PP;
+    constexpr int U = 4;                 // pairs per thread per step
+    constexpr int NE = 2 * U;
     const uint64_t span = (uint64_t)blockDim.x * U;
-    const uint64_t step = (uint64_t)nblk * span;
-    uint64_t base = (uint64_t)bid * span;
-    uint64_t v[2 * U];
+    uint64_t base = (uint64_t)bid * PP;
+    uint64_t v[NE];
     uint32_t okm = 0;  // bit e: element e of the batch is in range
     auto load = [&](uint64_t b) {
-        if (b >= head && b + span <= Pf) {
+        if (b >= head && b + span <= p_full) {
             // interior batch: every pair is two aligned in-range elements
-            const u64x2* src = reinterpret_cast<const u64x2*>(a.in + 2 * (b + threadIdx.x) - head);
+            const CAFS_GLOBAL u64x2* src = reinterpret_cast<const CAFS_GLOBAL u64x2*>(in + 2 * (b + threadIdx.x) - head);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const u64x2 w = src[(uint64_t)u * blockDim.x];
                 v[2 * u] = w.x;
                 v[2 * u + 1] = w.y;
             }
-            okm = (1u << (2 * U)) - 1;
+            okm = (1u << NE) - 1;
         } else {
             okm = 0;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint64_t p = b + (uint64_t)u * blockDim.x + threadIdx.x;
-                bool o0 = false, o1 = false;
-                v[2 * u] = v[2 * u + 1] = 0;
-                if (p < P) load_pair(a.in, a.n, head, p, v[2 * u], v[2 * u + 1], o0, o1);
+                const int64_t e0 = (int64_t)(2 * p) - (int64_t)head;
+                const bool o0 = p < p_end && e0 >= 0 && (uint64_t)e0 < n;
+                const bool o1 = p < p_end && (uint64_t)(e0 + 1) < n;
+                v[2 * u] = o0 ? in[e0] : 0;
+                v[2 * u + 1] = o1 ? in[e0 + 1] : 0;
                 okm |= (o0 ? 1u : 0u) << (2 * u);
                 okm |= (o1 ? 1u : 0u) << (2 * u + 1);
             }
         }
     };
-    if (base < P) load(base);
-    while (base < P) {
-        uint64_t x[2 * U];
+    if (base < p_end) load(base);
+    while (base < p_end) {  // uniform over the workgroup
+        uint64_t x[NE];
 #pragma unroll
-        for (int e = 0; e < 2 * U; ++e) x[e] = v[e];
-        const uint32_t xok = okm;
-        const uint64_t next = base + step;
-        if (next < P) load(next);  // next batch in flight while this one is counted
-        uint32_t pend = 0;
+        for (int e = 0; e < NE; ++e) x[e] = v[e];
+        uint32_t want = okm;
+        const uint64_t next = base + span;
+        if (next < p_end) load(next);  // next batch in flight while this one is counted
 #pragma unroll
-        for (int e = 0; e < 2 * U; ++e) {
-            const bool in = (xok >> e) & 1u;
-            const bool is_empty_key = x[e] == kEmpty;
-            ecnt += (in && is_empty_key) ? 1u : 0u;
-            const bool want = in && !is_empty_key;
-            uint32_t b = lds_bucket(x[e]);
-            bool full;
-            int m = match4(skeys, b, x[e], full);
-            if (m < 0 && full) {  // home bucket full without x: x may be in the next one
-                b = (b + 1 == kLdsBuckets) ? 0 : b + 1;
-                m = match4(skeys, b, x[e], full);
-            }
-            const bool hit = want && m >= 0;
-            // counters are slot-major (slot s of bucket b at s * 3072 + b) so that the
-            // first slots of many buckets spread over the LDS banks; a miss adds 0
-            atomicAdd(&scnt[(m < 0 ? 0 : m) * kLdsBuckets + b], hit ? 1u : 0u);
-            pend |= (want && !hit) ? (1u << e) : 0u;
+        for (int e = 0; e < NE; ++e) {
+            const bool is_empty_key = ((want >> e) & 1u) && x[e] == kEmpty;
+            ecnt += is_empty_key ? 1u : 0u;
+            want &= is_empty_key ? ~(1u << e) : ~0u;
         }
-        if (pend) {
-#pragma unroll 1
-            for (int e = 0; e < 2 * U; ++e)
-                if (pend & (1u << e)) lds_insert_slow(a, c, skeys, scnt, x[e]);
+        const uint32_t dfr = count_batch<NE>(skeys, scnt, x, want);
+        if (__ballot(dfr != 0)) {
+            // append the deferred elements: one LDS reservation per wave, then each
+            // element's place from the ballot of its batch position
+            uint64_t bal[NE];
+            uint32_t tot = 0;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                bal[e] = __ballot((dfr >> e) & 1u);
+                tot += (uint32_t)__popcll(bal[e]);
+            }
+            uint32_t at0 = 0;
+            if (lane == 0) at0 = atomicAdd(&s_ndef, tot);
+            uint32_t run = __shfl(at0, 0, 64);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(bal[e] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal[e], 0u));
+                if ((dfr >> e) & 1u) region[run + below] = x[e];
+                run += (uint32_t)__popcll(bal[e]);
+            }
         }
         base = next;
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
-        const uint32_t cn = scnt[i];  // slot i / 3072 of bucket i % 3072; never 0 once claimed
-        if (cn) global_insert(a, c, skeys[(i % kLdsBuckets) * kLdsBucketSlots + i / kLdsBuckets], cn);
-    }
+    if (threadIdx.x == 0) gp(a.dfr_cnt)[bid] = s_ndef;
+    flush_table(t, skeys, scnt);
     const uint32_t wsum = wave_sum_u32(ecnt);
-    if (__lane_id() == 0 && wsum) atomicAdd((unsigned long long*)&c->ecount, (unsigned long long)wsum);
+    if (lane == 0 && wsum) g_add(&c->ecount, (uint64_t)wsum);
 }
 CAFS_KERNELS0(hash_count, kCountThreads)
 
+// Second pass of the hash count: each workgroup counts the elements it deferred,
+// with a fresh LDS table (the keys that found no room in the first table are few)
+// and a longer probe; what still finds no room goes to the global table.  Launched
+// over the same grid as the first pass.
+__device__ __forceinline__ void defer_count_body(const Args& a, uint32_t bid, uint32_t nblk) {
+    Ctrl* c = a.c;
+    if (c->engine != E_HASH || c->dense_ready || g_load(&c->overflow)) return;
+    const uint32_t d = gp(a.dfr_cnt)[bid];
+    if (d == 0) return;
+    constexpr uint32_t S = kLdsBuckets * kLdsBucketSlots;
+    __shared__ __attribute__((aligned(16))) uint64_t skeys[S];
+    __shared__ uint32_t scnt[S];
+    for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
+        skeys[i] = kEmpty;
+        scnt[i] = 0;
+    }
+    __syncthreads();
+    const GTable t = gtable(a);
+    const CAFS_GLOBAL uint64_t* region = gp(a.tmp_k) + (uint64_t)bid * 2 * pairs_per_block(num_pairs(a.n, a.in_head), nblk);
+    for (uint32_t i0 = 0; i0 < d; i0 += blockDim.x) {  // one element per thread: this pass is short
+        const uint32_t i = i0 + threadIdx.x;
+        const uint64_t x[1] = {i < d ? region[i] : 0};
+        if (count_batch<1>(skeys, scnt, x, i < d ? 1u : 0u) && !lds_insert(skeys, scnt, x[0], 1u, kLdsProbeBuckets))
+            global_insert(t, x[0], 1);
+    }
+    __syncthreads();
+    flush_table(t, skeys, scnt);
+}
+CAFS_KERNELS0(defer_count, kCountThreads)
+
 // ---------------------------------------------------------------------------
-// Compaction and order (Alg. 4, steps "collect non-empty bucket slots", "sort
-// pairs by key").  One workgroup.  For K <= 8192 the (key, count) pairs are
-// sorted in LDS by a bitonic network and their counts scanned into run offsets;
-// larger K goes to the radix engine in pair mode.  With the sorted pairs at hand
-// this kernel also checks the spill guard's buckets: if no bucket of the paper's
-// table (M buckets, Eq. hash) receives more than 4 distinct keys, nothing spills
-// (Alg. 1) and the guard is settled here.
+// Order of the distinct keys (Alg. 4, steps "collect non-empty bucket slots" and
+// "sort pairs by key").  For K <= kRankMax each key's place is its rank, the number
+// of distinct keys below it (keys are distinct, so ranks are a permutation).  Every
+// workgroup ranks 64 keys, 16 threads per key, against all K keys staged through
+// LDS, and writes (key, count) to its place in the dense arrays: K^2 compares spread
+// over the whole GPU instead of a sorting network in one workgroup.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t table_key(const Args& a, uint32_t idx, uint32_t claimed) {
+    return idx < claimed ? gp(a.gkeys)[gp(a.claimed)[idx]] : kEmpty;
+}
+
+__device__ __forceinline__ void rank_body(const Args& a, uint32_t bid, uint32_t nblk) {
+    Ctrl* c = a.c;
+    if (c->engine != E_HASH || c->overflow || c->dense_ready) return;
+    const uint32_t claimed = c->claimed;
+    const uint64_t ecount = c->ecount;
+    const uint32_t K = claimed + (ecount > 0 ? 1u : 0u);
+    if (K > kRankMax || (uint64_t)bid * kRankKeysPerBlock >= K) return;
+    const uint64_t flip = a.flip;
+    __shared__ uint64_t sk[kRankTile];
+    const uint32_t part = threadIdx.x % 16;
+    for (uint32_t i0 = bid * kRankKeysPerBlock; i0 < K; i0 += nblk * kRankKeysPerBlock) {  // uniform
+        const uint32_t i = i0 + threadIdx.x / 16;
+        const bool have = i < K;
+        const uint64_t ki = (have ? table_key(a, i, claimed) : 0) ^ flip;
+        uint32_t r = 0;
+        for (uint32_t j0 = 0; j0 < K; j0 += kRankTile) {
+            const uint32_t jn = K - j0 < kRankTile ? K - j0 : kRankTile;
+            __syncthreads();
+            for (uint32_t j = threadIdx.x; j < jn; j += blockDim.x) sk[j] = table_key(a, j0 + j, claimed) ^ flip;
+            __syncthreads();
+            for (uint32_t j = part; j < jn; j += 16) r += sk[j] < ki ? 1u : 0u;
+        }
+        r += __shfl_xor(r, 8, 16);
+        r += __shfl_xor(r, 4, 16);
+        r += __shfl_xor(r, 2, 16);
+        r += __shfl_xor(r, 1, 16);
+        if (have && part == 0) {
+            gp(a.uniq)[r] = ki ^ flip;
+            gp(a.cnt)[r] = i < claimed ? gp(a.gcnt)[gp(a.claimed)[i]] : ecount;
+        }
+    }
+}
+CAFS_KERNELS0(rank, 1024)
+
+// Run offsets of the ranked pairs and the spill guard's bucket check (one
+// workgroup).  Larger K is gathered for the radix engine in pair mode.  If no
+// bucket of the paper's table (M buckets, Eq. hash) receives more than four
+// distinct keys, nothing spills (Alg. 1) and the guard is settled here.
 __device__ __forceinline__ void compact_order_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (c->engine != E_HASH || c->overflow || c->dense_ready) return;
     const uint32_t claimed = c->claimed;
     const uint64_t ecount = c->ecount;
     const uint32_t K = claimed + (ecount > 0 ? 1u : 0u);
-    const uint64_t flip = a.flip;
     const uint32_t tid = threadIdx.x;
-    if (K > kOrderMax) {
+    if (K > kRankMax) {
         // gather the pairs into the dense arrays and sort them there, in place, with
         // the radix engine; the hash table is dead after the gather and serves as
         // the radix scratch (K <= table size)
@@ -358,58 +519,19 @@ __device__ __forceinline__ void compact_order_body(const Args& a, uint32_t bid, 
         }
         return;
     }
-    __shared__ uint64_t sk[kOrderMax];
-    __shared__ uint64_t sv[kOrderMax];
-    __shared__ uint64_t scan_tmp[17];
-    uint32_t P = 64;
-    while (P < K) P <<= 1;
-    for (uint32_t i = tid; i < P; i += blockDim.x) {
-        if (i < claimed) {
-            const uint32_t h = a.claimed[i];
-            sk[i] = a.gkeys[h] ^ flip;
-            sv[i] = a.gcnt[h];
-        } else if (i < K) {
-            sk[i] = kEmpty ^ flip;
-            sv[i] = ecount;
-        } else {
-            sk[i] = ~0ull;  // padding sorts last: ties with a real key are broken by count 0
-            sv[i] = 0;
-        }
-    }
-    __syncthreads();
-    // bitonic sort of (key, count) by key ascending; equal keys only occur between a
-    // real key and padding, and the real key (count >= 1) goes first
-    for (uint32_t kk = 2; kk <= P; kk <<= 1) {
-        for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
-            for (uint32_t i = tid; i < P; i += blockDim.x) {
-                const uint32_t l = i ^ jj;
-                if (l > i) {
-                    const uint64_t ki = sk[i], kl = sk[l];
-                    const uint64_t vi = sv[i], vl = sv[l];
-                    const bool i_gt = (ki > kl) || (ki == kl && vi < vl);
-                    const bool up = (i & kk) == 0;
-                    if (up == i_gt) {
-                        sk[i] = kl; sk[l] = ki;
-                        sv[i] = vl; sv[l] = vi;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
     // exclusive scan of the counts -> run offsets; each thread takes a contiguous chunk
+    __shared__ uint64_t scan_tmp[17];
+    const CAFS_GLOBAL uint64_t* cnt = gp(a.cnt);
     const uint32_t per = (K + blockDim.x - 1) / blockDim.x;
     const uint32_t b0 = tid * per < K ? tid * per : K;
     const uint32_t b1 = b0 + per < K ? b0 + per : K;
     uint64_t local = 0;
-    for (uint32_t i = b0; i < b1; ++i) local += sv[i];
+    for (uint32_t i = b0; i < b1; ++i) local += cnt[i];
     uint64_t total;
     uint64_t run = block_exclusive_scan<uint64_t>(local, scan_tmp, &total);
     for (uint32_t i = b0; i < b1; ++i) {
-        a.uniq[i] = sk[i] ^ flip;
-        a.cnt[i] = sv[i];
-        a.off[i] = run;
-        run += sv[i];
+        gp(a.off)[i] = run;
+        run += cnt[i];
     }
     if (tid == 0) {
         a.off[K] = total;
@@ -425,20 +547,17 @@ __device__ __forceinline__ void compact_order_body(const Args& a, uint32_t bid, 
         if (tid == 0) { c->guard_on = 1; c->guard_general = 1; }
         return;
     }
-    __shared__ uint32_t s_nc;
-    __syncthreads();
-    uint32_t* bc = reinterpret_cast<uint32_t*>(sv);  // reuse: M <= 16384 u32 counters
+    const CAFS_GLOBAL uint64_t* uq = gp(a.uniq);
+    __shared__ uint32_t bc[kGuardLdsBuckets];
+    __shared__ uint32_t s_nc, s_nb;
     const uint32_t lg = log2_pow2(M);
     for (uint32_t i = tid; i < M; i += blockDim.x) bc[i] = 0;
-    if (tid == 0) s_nc = 0;
+    if (tid == 0) { s_nc = 0; s_nb = 0; }
     __syncthreads();
-    for (uint32_t i = tid; i < K; i += blockDim.x) atomicAdd(&bc[phi_hash32(sk[i] ^ flip, lg)], 1u);
-    __syncthreads();
-    __shared__ uint32_t s_nb;
-    if (tid == 0) s_nb = 0;
+    for (uint32_t i = tid; i < K; i += blockDim.x) atomicAdd(&bc[phi_hash32(uq[i], lg)], 1u);
     __syncthreads();
     uint32_t over = 0, over_b = 0;
-    for (uint32_t i = tid; i < K; i += blockDim.x) over += bc[phi_hash32(sk[i] ^ flip, lg)] > kBucketCap;
+    for (uint32_t i = tid; i < K; i += blockDim.x) over += bc[phi_hash32(uq[i], lg)] > kBucketCap;
     for (uint32_t i = tid; i < M; i += blockDim.x) over_b += bc[i] > kBucketCap;
     over = wave_sum_u32(over);
     over_b = wave_sum_u32(over_b);
@@ -455,7 +574,7 @@ __device__ __forceinline__ void compact_order_body(const Args& a, uint32_t bid, 
     if (tid == 0) s_nc = 0;
     __syncthreads();
     for (uint32_t i = tid; i < K; i += blockDim.x)
-        if (bc[phi_hash32(sk[i] ^ flip, lg)] > kBucketCap) a.clist[atomicAdd(&s_nc, 1u)] = i;
+        if (bc[phi_hash32(uq[i], lg)] > kBucketCap) a.clist[atomicAdd(&s_nc, 1u)] = i;
     if (tid == 0) {
         c->n_contested = nc;
         c->n_cbuckets = s_nb;

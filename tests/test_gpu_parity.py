@@ -89,6 +89,11 @@ SEEDED = [
     (60_000, 30_000, "zipf", 1.1, "random"),       # Chao1 underestimate
     (2_000_000, 200_000, "zipf", 1.1, "random"),   # underestimate: table overflow -> radix engine
     (500_000, 150_000, "uniform", 1.1, "random"),
+    # every workgroup sees most keys: full LDS windows, deferred second pass
+    (1 << 24, 12_000, "uniform", 1.1, "random"),
+    (1 << 23, 10_000, "zipf", 1.1, "random"),
+    (1 << 23, 20_000, "uniform", 1.1, "random"),     # beyond the LDS table: deferred pass overflows to global
+    (3_000_001, 100_000, "uniform", 1.1, "random"),  # deferral regions fill up
 ]
 
 
@@ -188,3 +193,20 @@ def test_deterministic_reports(ctx):
     b = run_gpu(ctx, x, False)
     assert np.array_equal(a[0], b[0]) and a[1] == b[1]
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+
+
+@pytest.mark.parametrize("k", [8191, 8192, 8193, 32767, 32768, 32769])
+@pytest.mark.parametrize("with_marker", [False, True])
+def test_order_boundaries(ctx, k, with_marker):
+    """K at the edges of the rank order (K <= 32768) and the pair radix sort above,
+    with and without the empty-slot marker value among the keys."""
+    rng = np.random.default_rng(k)
+    pal = np.unique(rng.integers(0, 2**64 - 2, size=k + 64, dtype=np.uint64))[:k]
+    if with_marker:
+        pal[0] = np.uint64(2**64 - 1)
+    n = 40 * k
+    x = np.concatenate([pal, pal[rng.integers(0, k, size=n - k)]])
+    rng.shuffle(x)
+    for unsigned in (False, True):
+        r = check(ctx, x, unsigned, label="order k=%d marker=%s" % (k, with_marker))
+        assert r["k_exact"] == k
