@@ -173,7 +173,7 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
         const uint64_t e0 = (b0 + kGuardChunk < n) ? b0 + kGuardChunk : n;
         uint32_t newly = 0;
         for (uint64_t i = b0 + threadIdx.x; i < e0; i += blockDim.x) {
-            const uint64_t v = a.in[i];
+            const uint64_t v = gp(a.in)[i];
             const uint32_t b = phi_hash32(v, lg);
             const bool cont = bits ? ((bflag[b >> 5] >> (b & 31)) & 1u) : (a.dcount[b] > kBucketCap);
             if (!cont) continue;

@@ -28,7 +28,7 @@ __device__ __forceinline__ void radix_hist_body(const Args& a, uint32_t bid, uin
     if (!c->radix_on) return;
     const RadixJob& j = c->rj;
     const uint64_t n = j.n;
-    const uint64_t* __restrict__ src = j.src_k;
+    const CAFS_GLOBAL uint64_t* __restrict__ src = gp(j.src_k);
     const uint64_t flip = a.flip;
     __shared__ uint32_t lh[8][256];
     __shared__ uint32_t s_last;
@@ -40,11 +40,19 @@ __device__ __forceinline__ void radix_hist_body(const Args& a, uint32_t bid, uin
     for (uint64_t i = gtid; i < tiles * 256; i += gstride) a.status[i] = 0;
     __syncthreads();
     const uint32_t lane = __lane_id();
-    const uint64_t iters = (n + gstride - 1) / gstride;
+    constexpr int U = 4;  // loads in flight per thread
+    const uint64_t iters = (n + gstride * U - 1) / (gstride * U);
     for (uint64_t it = 0; it < iters; ++it) {
-        const uint64_t i = it * gstride + gtid;
-        const bool ok = i < n;
-        const uint64_t v = ok ? src[i] : 0;
+        uint64_t vv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = (it * U + u) * gstride + gtid;
+            vv[u] = i < n ? src[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+        const uint64_t v = vv[u];
+        const bool ok = (it * U + u) * gstride + gtid < n;
         const uint64_t act = __ballot(ok);
         if (act == 0) continue;
         for (uint32_t d = 0; d < 8; ++d) {
@@ -58,6 +66,7 @@ __device__ __forceinline__ void radix_hist_body(const Args& a, uint32_t bid, uin
             } else if (ok) {
                 atomicAdd(&lh[d][dg], 1u);
             }
+        }
         }
     }
     __syncthreads();
@@ -134,13 +143,13 @@ __device__ __forceinline__ void radix_pass_body(const Args& a, uint32_t pass, ui
     const uint32_t d = j.digit[pass];
     const uint64_t flip = a.flip;
     const bool vals = j.has_vals != 0;
-    const uint64_t* __restrict__ sk = j.ps_k[pass];
-    const uint64_t* __restrict__ sv = j.ps_v[pass];
-    uint64_t* __restrict__ dk = j.pd_k[pass];
-    uint64_t* __restrict__ dv = j.pd_v[pass];
+    const CAFS_GLOBAL uint64_t* __restrict__ sk = gp(j.ps_k[pass]);
+    const CAFS_GLOBAL uint64_t* __restrict__ sv = gp(j.ps_v[pass]);
+    CAFS_GLOBAL uint64_t* __restrict__ dk = gp(j.pd_k[pass]);
+    CAFS_GLOBAL uint64_t* __restrict__ dv = gp(j.pd_v[pass]);
     const uint64_t tiles = (n + kRadixTile - 1) / kRadixTile;
     uint64_t* status = a.status + (pass & 1u) * a.status_slot;
-    uint64_t* status_next = a.status + ((pass + 1) & 1u) * a.status_slot;
+    CAFS_GLOBAL uint64_t* status_next = gp(a.status) + ((pass + 1) & 1u) * a.status_slot;
     const uint64_t* bases = c->hist[d];
 
     __shared__ uint64_t lk[kRadixTile];
@@ -210,25 +219,25 @@ __device__ __forceinline__ void radix_pass_body(const Args& a, uint32_t pass, ui
             }
             tcount[dd] = run;
             // publish this tile's aggregate, then look back for the exclusive prefix
-            uint64_t* st = status + t * 256 + dd;
+            CAFS_GLOBAL uint64_t* st = gp(status) + t * 256 + dd;
             uint64_t excl = 0;
             if (t == 0) {
-                atomic_store_agent(st, kStatInc | (uint64_t)run);
+                __hip_atomic_store(st, kStatInc | (uint64_t)run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                atomic_store_agent(st, kStatAgg | (uint64_t)run);
+                __hip_atomic_store(st, kStatAgg | (uint64_t)run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 uint64_t tt = t - 1;
                 while (true) {
                     const uint64_t* sp = status + tt * 256 + dd;
-                    uint64_t s = atomic_load_agent(sp);
+                    uint64_t s = g_load(sp);
                     while ((s & (kStatAgg | kStatInc)) == 0) {
                         __builtin_amdgcn_s_sleep(1);
-                        s = atomic_load_agent(sp);
+                        s = g_load(sp);
                     }
                     excl += s & kStatMask;
                     if (s & kStatInc) break;
                     --tt;
                 }
-                atomic_store_agent(st, kStatInc | (excl + run));
+                __hip_atomic_store(st, kStatInc | (excl + run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             gofs[dd] = bases[dd] + excl;
         }
@@ -272,14 +281,17 @@ __device__ __forceinline__ void radix_copy_body(const Args& a, uint32_t bid, uin
     if (!c->radix_on) return;
     const RadixJob& j = c->rj;
     if (j.copy_mode == 0) return;
-    const uint64_t* sk = j.copy_mode == 1 ? j.src_k : j.tmp_k;
-    const uint64_t* sv = j.copy_mode == 1 ? j.src_v : j.tmp_v;
+    const CAFS_GLOBAL uint64_t* sk = gp(j.copy_mode == 1 ? j.src_k : j.tmp_k);
+    const CAFS_GLOBAL uint64_t* sv = gp(j.copy_mode == 1 ? j.src_v : j.tmp_v);
+    CAFS_GLOBAL uint64_t* dk = gp(j.dst_k);
+    CAFS_GLOBAL uint64_t* dv = gp(j.dst_v);
+    const bool vals = j.has_vals != 0;
     const uint64_t n = j.n;
     const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
     const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     for (uint64_t i = gtid; i < n; i += gstride) {
-        j.dst_k[i] = sk[i];
-        if (j.has_vals) j.dst_v[i] = sv[i];
+        dk[i] = sk[i];
+        if (vals) dv[i] = sv[i];
     }
 }
 CAFS_KERNELS0(radix_copy, 256)
