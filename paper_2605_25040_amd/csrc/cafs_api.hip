@@ -139,12 +139,19 @@ uint32_t grid_for(uint64_t work_items, uint64_t per_block, uint32_t cap) {
     return (uint32_t)g;
 }
 
-cafs_status_t launch_radix(const cafs::Args& a, uint64_t n_max, int cus, hipStream_t s) {
+// The radix engine: digit histograms, up to eight passes (keys only, or key-value
+// pairs when `pairs` may be needed), and the final copy.  Passes of constant
+// digits and the variant without work return at once.
+cafs_status_t launch_radix(const cafs::Args& a, uint64_t n_max, int cus, hipStream_t s, bool pairs) {
     const uint64_t tiles = (n_max + cafs::kRadixTile - 1) / cafs::kRadixTile;
     const uint32_t g_hist = grid_for(n_max, 256 * 16, cus * 4);
-    const uint32_t g_pass = grid_for(tiles, 1, cus * 2);
     cafs::k_radix_hist<<<g_hist, 256, 0, s>>>(a);
-    for (uint32_t p = 0; p < 8; ++p) cafs::k_radix_pass<<<g_pass, cafs::kRadixThreads, 0, s>>>(a, p);
+    // resident workgroups per CU: three keys-only (LDS, registers), two key-value
+    const uint32_t g_keys = grid_for(tiles, 1, cus * 3), g_kv = grid_for(tiles, 1, cus * 2);
+    for (uint32_t p = 0; p < 8; ++p) {
+        cafs::k_radix_pass<<<g_keys, cafs::kRadixThreads, 0, s>>>(a, p);
+        if (pairs) cafs::k_radix_pass_kv<<<g_kv, cafs::kRadixThreads, 0, s>>>(a, p);
+    }
     cafs::k_radix_copy<<<grid_for(n_max, 256 * 8, cus * 4), 256, 0, s>>>(a);
     return CAFS_OK;
 }
@@ -234,7 +241,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     mark(1);
     const bool countable = n >= cafs::kSmallN;  // tiny and main need N >= 2048
     if (countable)
-        cafs::k_phase2<<<grid_for(std::max<uint64_t>(n / 2, cap_ws), 256 * 8, cus * 4), 256, 0, s>>>(a);
+        cafs::k_phase2<<<grid_for(std::max<uint64_t>(n / 2, cap_ws), 256 * 8, cus * 2), 256, 0, s>>>(a);
     mark(2);
     if (countable) {
         // one workgroup per CU (the LDS table takes the CU); both passes use the same grid
@@ -263,7 +270,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     const uint32_t g_emit = grid_for(n, 2 * cafs::kEmitTilePairs, cus * 4);
     if (countable && !inplace) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 0u);
     mark(5);
-    launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2);
+    launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2, countable && n > cafs::kRankMax);
     if (countable && n > cafs::kRankMax) cafs::k_pair_scan<<<1, 1024, 0, s2>>>(a);
     cafs::k_copy_mono<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s2>>>(a);
     const uint32_t g_rle = grid_for(n, cafs::kRleTile, cus * 4);
@@ -436,7 +443,7 @@ cafs_status_t cafs_radix_sort(cafs_ctx_t* ctx, const void* d_in, void* d_out, ui
     const cafs::Args a = make_args(ctx, L, d_in, d_out, n, dtype, nullptr, nullptr, nullptr, d_ws);
     (void)hipGetLastError();
     k_radix_setup<<<1, 64, 0, s>>>(a);
-    launch_radix(a, n, ctx->cus, s);
+    launch_radix(a, n, ctx->cus, s, false);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? CAFS_OK : hip_fail(e, "launch");
 }
@@ -554,7 +561,10 @@ cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uin
     cafs::kb_rank<<<TP, 1024, 0, s>>>(gp);
     cafs::kb_compact_order<<<C, 1024, 0, s>>>(g1);
     cafs::kb_radix_hist<<<TP, 256, 0, s>>>(gp);
-    for (uint32_t p = 0; p < 8; ++p) cafs::kb_radix_pass<<<TP, cafs::kRadixThreads, 0, s>>>(gp, p);
+    for (uint32_t p = 0; p < 8; ++p) {
+        cafs::kb_radix_pass<<<TP, cafs::kRadixThreads, 0, s>>>(gp, p);
+        cafs::kb_radix_pass_kv<<<TP, cafs::kRadixThreads, 0, s>>>(gp, p);
+    }
     cafs::kb_radix_copy<<<TP, 256, 0, s>>>(gp);
     cafs::kb_pair_scan<<<C, 1024, 0, s>>>(g1);
     cafs::kb_copy_mono<<<TP, 256, 0, s>>>(gp);

@@ -121,7 +121,7 @@ __device__ __forceinline__ void rle_count_body(const Args& a, uint32_t bid, uint
     Ctrl* c = a.c;
     if (!rle_needed(a, c)) return;
     const uint64_t n = a.n;
-    const uint64_t* __restrict__ y = c->sorted;
+    const CAFS_GLOBAL uint64_t* __restrict__ y = gp(c->sorted);
     const uint64_t tiles = (n + kRleTile - 1) / kRleTile;
     __shared__ uint32_t s_cnt;
     __shared__ uint32_t s_last;
@@ -162,35 +162,58 @@ __device__ __forceinline__ void rle_count_body(const Args& a, uint32_t bid, uint
 }
 CAFS_KERNELS0(rle_count, 256)
 
-// Pass 2: write each run's key and start position (its offset).
+// Pass 2: write each run's key and start position (its offset).  A tile is staged
+// in LDS with coalesced loads; each thread flags the run starts among 16
+// consecutive elements, a block scan places them, and the tile's runs are written
+// back with coalesced stores (their places in the output are consecutive).
 __device__ __forceinline__ void rle_write_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!rle_needed(a, c)) return;
     const uint64_t n = a.n;
-    const uint64_t* __restrict__ y = c->sorted;
+    const CAFS_GLOBAL uint64_t* __restrict__ y = gp(c->sorted);
+    CAFS_GLOBAL uint64_t* __restrict__ uq = gp(a.uniq);
+    CAFS_GLOBAL uint64_t* __restrict__ off = gp(a.off);
     const uint64_t tiles = (n + kRleTile - 1) / kRleTile;
     constexpr uint32_t per = kRleTile / 256;  // contiguous elements per thread
+    __shared__ uint64_t sy[kRleTile + 1];     // sy[i + 1] = y[b + i]; sy[0] = y[b - 1]
+    __shared__ uint16_t spos[kRleTile];       // tile-relative start of each run
     __shared__ uint32_t scan_tmp[8];
     for (uint64_t t = bid; t < tiles; t += nblk) {
-        const uint64_t b = t * kRleTile + (uint64_t)threadIdx.x * per;
-        uint32_t local = 0;
+        const uint64_t b = t * kRleTile;
+        const uint32_t cnt = (uint32_t)(n - b < kRleTile ? n - b : kRleTile);
+        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) sy[i + 1] = y[b + i];
+        if (threadIdx.x == 0) sy[0] = b > 0 ? y[b - 1] : ~y[0];  // element 0 always starts a run
+        __syncthreads();
+        const uint32_t l0 = threadIdx.x * per;
+        uint32_t flags = 0;
+#pragma unroll
         for (uint32_t k = 0; k < per; ++k) {
-            const uint64_t i = b + k;
-            if (i < n) local += (i == 0) || (y[i] != y[i - 1]);
+            const uint32_t i = l0 + k;
+            flags |= (i < cnt && sy[i + 1] != sy[i]) ? (1u << k) : 0u;
         }
         uint32_t total;
-        uint32_t ex = block_exclusive_scan<uint32_t>(local, scan_tmp, &total);
-        uint64_t j = a.rle_tile[t] + ex;
+        const uint32_t ex = block_exclusive_scan<uint32_t>((uint32_t)__popc(flags), scan_tmp, &total);
+        // the staged keys are read before the barrier and the runs written after it
+        uint64_t keys[per];
+#pragma unroll
+        for (uint32_t k = 0; k < per; ++k) keys[k] = sy[l0 + k + 1];
+        __syncthreads();
+        uint32_t j = ex;
+#pragma unroll
         for (uint32_t k = 0; k < per; ++k) {
-            const uint64_t i = b + k;
-            if (i < n && ((i == 0) || (y[i] != y[i - 1]))) {
-                if (j < n) {  // always true: there are at most n runs
-                    a.uniq[j] = y[i];
-                    a.off[j] = i;
-                }
+            if ((flags >> k) & 1u) {
+                sy[j] = keys[k];
+                spos[j] = (uint16_t)(l0 + k);
                 ++j;
             }
         }
+        __syncthreads();
+        const uint64_t j0 = a.rle_tile[t];
+        for (uint32_t r = threadIdx.x; r < total; r += blockDim.x) {
+            uq[j0 + r] = sy[r];
+            off[j0 + r] = b + spos[r];
+        }
+        __syncthreads();
     }
     if (bid == 0 && threadIdx.x == 0) a.off[c->K] = n;
 }

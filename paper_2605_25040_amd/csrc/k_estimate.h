@@ -12,15 +12,22 @@ namespace cafs {
 // The FreqSet uses kEmpty as its empty marker; samples equal to kEmpty are counted
 // in a separate LDS counter, which acts as one more slot.  When u <= 8 the distinct
 // sampled keys are returned too, sorted in the dtype's order (tiny branch).
-// Every thread must call it; thread 0's outputs are the results.
+// Every thread must call it, passing the sample it loaded (chao1_sample) so that
+// the load's latency overlaps other work; thread 0's outputs are the results.
 struct Chao1Result {
     uint64_t k_hat, u, f1, f2, n_samples, stride;
     uint32_t saturated, n_small;
     uint64_t small[8];
 };
 
-__device__ void chao1_block(const uint64_t* __restrict__ x, uint64_t n, uint64_t flip,
-                            Chao1Result* res) {
+// Sample threadIdx.x of the column (0 when there is none): element tid * stride.
+__device__ __forceinline__ uint64_t chao1_sample(const uint64_t* x, uint64_t n) {
+    const uint64_t stride = n / kSamples > 1 ? n / kSamples : 1;
+    const uint64_t ns = n < kSamples ? n : kSamples;
+    return threadIdx.x < ns ? gp(x)[threadIdx.x * stride] : 0;
+}
+
+__device__ void chao1_block(uint64_t v_mine, uint64_t n, uint64_t flip, Chao1Result* res) {
     __shared__ uint64_t fkeys[1u << kFreqSlotsLog2];
     __shared__ uint32_t fcnt[1u << kFreqSlotsLog2];
     __shared__ uint32_t s_e, s_u, s_f1, s_f2, s_ns;
@@ -35,23 +42,24 @@ __device__ void chao1_block(const uint64_t* __restrict__ x, uint64_t n, uint64_t
     __syncthreads();
     const uint64_t stride = n / kSamples > 1 ? n / kSamples : 1;
     const uint64_t ns = n < kSamples ? n : kSamples;
-    for (uint64_t t = tid; t < ns; t += blockDim.x) {
-        const uint64_t v = x[t * stride];
+    // one sample per thread (blockDim.x >= kSamples)
+    if (tid < ns) {
+        const uint64_t v = v_mine;
         if (v == kEmpty) {
             atomicAdd(&s_e, 1u);
-            continue;
-        }
-        uint32_t h = phi_hash(v, kFreqSlotsLog2);
-        while (true) {
-            const uint64_t k = fkeys[h];
-            if (k == v) { atomicAdd(&fcnt[h], 1u); break; }
-            if (k == kEmpty) {
-                const unsigned long long old =
-                    atomicCAS((unsigned long long*)&fkeys[h], (unsigned long long)kEmpty,
-                              (unsigned long long)v);
-                if (old == kEmpty || old == v) { atomicAdd(&fcnt[h], 1u); break; }
+        } else {
+            uint32_t h = phi_hash(v, kFreqSlotsLog2);
+            while (true) {
+                const uint64_t k = fkeys[h];
+                if (k == v) { atomicAdd(&fcnt[h], 1u); break; }
+                if (k == kEmpty) {
+                    const unsigned long long old =
+                        atomicCAS((unsigned long long*)&fkeys[h], (unsigned long long)kEmpty,
+                                  (unsigned long long)v);
+                    if (old == kEmpty || old == v) { atomicAdd(&fcnt[h], 1u); break; }
+                }
+                h = (h + 1) & (slots - 1);
             }
-            h = (h + 1) & (slots - 1);
         }
     }
     __syncthreads();
@@ -189,14 +197,28 @@ __device__ __forceinline__ void pre_body(const Args& a, uint32_t bid, uint32_t n
     Ctrl* c = a.c;
     __shared__ uint32_t s_inv;
     __shared__ Chao1Result s_res;
+    // the sample and the order-check prefix are loaded together, so that their
+    // latencies overlap
+    const uint64_t v_sample = chao1_sample(a.in, a.n);
     if (threadIdx.x == 0) s_inv = 0;
     __syncthreads();
     const uint64_t lim = a.n < kMonoPrefix ? a.n : kMonoPrefix;
+    const CAFS_GLOBAL uint64_t* in = gp(a.in);
     uint32_t inv = 0;
-    for (uint64_t i = threadIdx.x; i + 1 < lim; i += blockDim.x)
-        inv |= (a.in[i] ^ a.flip) > (a.in[i + 1] ^ a.flip);
+    constexpr uint32_t kPer = kMonoPrefix / 1024;  // elements per thread (blockDim.x = 1024)
+    uint64_t pv[kPer + 1];
+#pragma unroll
+    for (uint32_t k = 0; k <= kPer; ++k) {
+        const uint64_t i = (uint64_t)threadIdx.x * kPer + k;
+        pv[k] = i < lim ? in[i] ^ a.flip : 0;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint64_t i = (uint64_t)threadIdx.x * kPer + k;
+        inv |= (i + 1 < lim && pv[k] > pv[k + 1]) ? 1u : 0u;
+    }
     if (inv) s_inv = 1;
-    chao1_block(a.in, a.n, a.flip, &s_res);  // contains __syncthreads
+    chao1_block(v_sample, a.n, a.flip, &s_res);  // contains __syncthreads
     const bool settled = s_inv || a.n <= kMonoPrefix;
     if (threadIdx.x == 0) {
         c->inversion = s_inv;
@@ -219,7 +241,7 @@ CAFS_KERNELS0(pre, 1024)
 __global__ __launch_bounds__(1024) void k_estimate_only(const uint64_t* x, uint64_t n,
                                                         cafs_estimate_t* out) {
     __shared__ Chao1Result s_res;
-    chao1_block(x, n, 0, &s_res);
+    chao1_block(chao1_sample(x, n), n, 0, &s_res);
     if (threadIdx.x == 0) {
         cafs_estimate_t e;
         e.k_hat = s_res.k_hat; e.u = s_res.u; e.f1 = s_res.f1; e.f2 = s_res.f2;

@@ -134,15 +134,19 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t dg, uint64_t act) {
     return peers;
 }
 
-__device__ __forceinline__ void radix_pass_body(const Args& a, uint32_t pass, uint32_t bid, uint32_t nblk) {
+// One LSD pass over tiles of kRadixTile keys (with their values when VALS): stable
+// ranks within the tile by wave matching, tile offsets by decoupled look-back, a
+// reorder through LDS and a scatter of digit runs.  Keys-only and key-value passes
+// are separate kernels so that the keys-only one keeps fewer registers and less LDS.
+template <bool VALS>
+__device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!c->radix_on) return;
     const RadixJob& j = c->rj;
-    if (pass >= j.n_active) return;
+    if ((j.has_vals != 0) != VALS || pass >= j.n_active) return;
     const uint64_t n = j.n;
     const uint32_t d = j.digit[pass];
     const uint64_t flip = a.flip;
-    const bool vals = j.has_vals != 0;
     const CAFS_GLOBAL uint64_t* __restrict__ sk = gp(j.ps_k[pass]);
     const CAFS_GLOBAL uint64_t* __restrict__ sv = gp(j.ps_v[pass]);
     CAFS_GLOBAL uint64_t* __restrict__ dk = gp(j.pd_k[pass]);
@@ -153,9 +157,8 @@ __device__ __forceinline__ void radix_pass_body(const Args& a, uint32_t pass, ui
     const uint64_t* bases = c->hist[d];
 
     __shared__ uint64_t lk[kRadixTile];
-    __shared__ uint64_t lv[kRadixTile];
+    __shared__ uint64_t lv[VALS ? kRadixTile : 1];
     __shared__ uint32_t wcnt[kRadixThreads / 64][256];
-    __shared__ uint32_t tcount[256];
     __shared__ uint32_t toff[256];
     __shared__ uint64_t gofs[256];
     __shared__ uint32_t s_tile;
@@ -183,41 +186,42 @@ __device__ __forceinline__ void radix_pass_body(const Args& a, uint32_t pass, ui
         const uint64_t base = t * kRadixTile;
         // load: wave w owns positions base + w*1024 + i*64 + lane, i = 0..15 (in order)
         uint64_t key[kRadixItems];
-        uint64_t val[kRadixItems];
-        uint16_t rank[kRadixItems];
-        uint32_t dig[kRadixItems];
+        uint64_t val[VALS ? kRadixItems : 1];
+        uint32_t rank2[kRadixItems / 2];  // two 16-bit ranks per register
+        uint32_t okm = 0;  // bit i: item i is in range (digits are recomputed from the keys)
 #pragma unroll
         for (int i = 0; i < kRadixItems; ++i) {
             const uint64_t pos = base + (uint64_t)wave * (64 * kRadixItems) + (uint64_t)i * 64 + lane;
             const bool ok = pos < n;
             key[i] = ok ? sk[pos] : 0;
-            val[i] = (ok && vals) ? sv[pos] : 0;
-            dig[i] = ok ? digit_of(key[i], flip, d) : 256u;
+            if constexpr (VALS) val[i] = ok ? sv[pos] : 0;
+            okm |= (ok ? 1u : 0u) << i;
         }
         // stable rank within the wave, item by item
 #pragma unroll
         for (int i = 0; i < kRadixItems; ++i) {
-            const bool ok = dig[i] < 256u;
+            const bool ok = (okm >> i) & 1u;
+            const uint32_t dg = digit_of(key[i], flip, d);
             const uint64_t act = __ballot(ok);
-            const uint64_t peers = match_digit(dig[i] & 255u, act);
+            const uint64_t peers = match_digit(dg, act);
             uint32_t before = 0;
-            if (ok) before = wcnt[wave][dig[i]];
-            rank[i] = (uint16_t)(before + __popcll(peers & lt_mask));
+            if (ok) before = wcnt[wave][dg];
+            const uint32_t rk = before + (uint32_t)__popcll(peers & lt_mask);
+            if (i & 1) rank2[i >> 1] |= rk << 16; else rank2[i >> 1] = rk;
             const bool leader = ok && ((peers & lt_mask) == 0);
-            if (leader) wcnt[wave][dig[i]] = before + (uint32_t)__popcll(peers);
+            if (leader) wcnt[wave][dg] = before + (uint32_t)__popcll(peers);
         }
         __syncthreads();
         // per digit: tile total and per-wave exclusive prefix
+        uint32_t run = 0;  // this thread's digit: count in the tile
         {
             const uint32_t dd = tid;  // 256 threads, one digit each
-            uint32_t run = 0;
 #pragma unroll
             for (int w = 0; w < kRadixThreads / 64; ++w) {
                 const uint32_t cw = wcnt[w][dd];
                 wcnt[w][dd] = run;
                 run += cw;
             }
-            tcount[dd] = run;
             // publish this tile's aggregate, then look back for the exclusive prefix
             CAFS_GLOBAL uint64_t* st = gp(status) + t * 256 + dd;
             uint64_t excl = 0;
@@ -244,7 +248,7 @@ __device__ __forceinline__ void radix_pass_body(const Args& a, uint32_t pass, ui
         // tile-local digit offsets
         {
             uint32_t total;
-            const uint32_t ex = block_exclusive_scan<uint32_t>(tcount[tid], scan_tmp, &total);
+            const uint32_t ex = block_exclusive_scan<uint32_t>(run, scan_tmp, &total);
             toff[tid] = ex;
             __syncthreads();
             gofs[tid] -= ex;  // global position = gofs[digit] + local position
@@ -253,11 +257,12 @@ __device__ __forceinline__ void radix_pass_body(const Args& a, uint32_t pass, ui
         // reorder the tile in LDS by digit (stable)
 #pragma unroll
         for (int i = 0; i < kRadixItems; ++i) {
-            if (dig[i] < 256u) {
-                const uint32_t q = toff[dig[i]] + wcnt[wave][dig[i]] + rank[i];
+            if ((okm >> i) & 1u) {
+                const uint32_t dg = digit_of(key[i], flip, d);
+                const uint32_t q = toff[dg] + wcnt[wave][dg] + ((rank2[i >> 1] >> (16 * (i & 1))) & 0xFFFFu);
                 if (q < kRadixTile) {  // always true when the ranks are consistent
                     lk[q] = key[i];
-                    if (vals) lv[q] = val[i];
+                    if constexpr (VALS) lv[q] = val[i];
                 }
             }
         }
@@ -268,13 +273,20 @@ __device__ __forceinline__ void radix_pass_body(const Args& a, uint32_t pass, ui
             const uint64_t g = gofs[digit_of(k, flip, d)] + q;
             if (g < n) {  // always true when the look-back prefixes are consistent
                 dk[g] = k;
-                if (vals) dv[g] = lv[q];
+                if constexpr (VALS) dv[g] = lv[q];
             }
         }
         __syncthreads();
     }
 }
+__device__ __forceinline__ void radix_pass_body(const Args& a, uint32_t pass, uint32_t bid, uint32_t nblk) {
+    radix_pass_impl<false>(a, pass, bid, nblk);
+}
+__device__ __forceinline__ void radix_pass_kv_body(const Args& a, uint32_t pass, uint32_t bid, uint32_t nblk) {
+    radix_pass_impl<true>(a, pass, bid, nblk);
+}
 CAFS_KERNELS1(radix_pass, kRadixThreads, uint32_t, pass)
+CAFS_KERNELS1(radix_pass_kv, kRadixThreads, uint32_t, pass)
 
 __device__ __forceinline__ void radix_copy_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
