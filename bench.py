@@ -31,7 +31,7 @@ WORKLOADS = {
 STAGE_BYTES_PER_KEY = {"count": 8.0, "emit": 8.0}
 STAGE_KERNEL = {"count": "k_hash_count", "emit": "k_emit"}
 KERNEL_SOURCES = ["paper_2605_25040_amd/csrc/cafs_dev.h", "paper_2605_25040_amd/csrc/k_count.h",
-                  "paper_2605_25040_amd/csrc/k_emit.h"]
+                  "paper_2605_25040_amd/csrc/k_emit.h", "paper_2605_25040_amd/csrc/cafs_api.hip"]
 
 
 def sources_hash():

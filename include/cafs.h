@@ -111,11 +111,13 @@ void cafs_ctx_destroy(cafs_ctx_t* ctx);
 
 /* Per-stage timing.  While enabled, every cafs_sort_i64/u64 call on the context
  * records HIP events on its stream at the stage boundaries:
- *   0 pre    order check, Chao1 estimate, dispatch        (Alg. 2, Alg. 3)
- *   1 init   table initialisation and tiny count           (Sec. 4.4)
- *   2 count  hash count                                    (Sec. 4.4)
- *   3 order  compaction and order of at most 8192 pairs    (Alg. 4)
- *   4 emit   run expansion on the caller's stream          (Alg. 4)
+ *   0 pre    order check, Chao1 estimate, dispatch, table
+ *            initialisation and tiny count                 (Alg. 2, Alg. 3, Sec. 4.4)
+ *   1 count  hash count, first pass (one kernel)           (Sec. 4.4)
+ *   2 defer  hash count of the deferred elements           (Sec. 4.4)
+ *   3 order  ranking of up to 32768 distinct keys and the
+ *            run offsets, or the gather for a pair sort   (Alg. 4)
+ *   4 emit   run expansion on the caller's stream (one kernel) (Alg. 4)
  *   5 tail   the rest until the report is written: the radix engine, the
  *            larger pair sort and its emit, the monotone copy, the run-length
  *            pass and the guard run on a side stream of the context, forked

@@ -238,17 +238,15 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     mark(0);
     cafs::k_pre<<<1, 1024, 0, s>>>(a);
     if (n > cafs::kMonoPrefix) cafs::k_mono_full<<<grid_for(n, 256 * 16, cus * 4), 256, 0, s>>>(a);
-    mark(1);
     const bool countable = n >= cafs::kSmallN;  // tiny and main need N >= 2048
     if (countable)
         cafs::k_phase2<<<grid_for(std::max<uint64_t>(n / 2, cap_ws), 256 * 8, cus * 2), 256, 0, s>>>(a);
+    mark(1);
+    // one workgroup per CU (the LDS table takes the CU); both count passes use the same grid
+    const uint32_t g_count = grid_for(n, cafs::kCountThreads * 8, std::min<uint32_t>(cus, cafs::kMaxCountBlocks));
+    if (countable) cafs::k_hash_count<<<g_count, cafs::kCountThreads, 0, s>>>(a);
     mark(2);
-    if (countable) {
-        // one workgroup per CU (the LDS table takes the CU); both passes use the same grid
-        const uint32_t g_count = grid_for(n, cafs::kCountThreads * 8, std::min<uint32_t>(cus, cafs::kMaxCountBlocks));
-        cafs::k_hash_count<<<g_count, cafs::kCountThreads, 0, s>>>(a);
-        cafs::k_defer_count<<<g_count, cafs::kCountThreads, 0, s>>>(a);
-    }
+    if (countable) cafs::k_defer_count<<<g_count, cafs::kCountThreads, 0, s>>>(a);
     mark(3);
     if (countable) {
         const uint64_t k_max = std::min<uint64_t>(n, cafs::kRankMax);
