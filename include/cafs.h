@@ -113,21 +113,20 @@ void cafs_ctx_destroy(cafs_ctx_t* ctx);
  * records HIP events on its stream at the stage boundaries:
  *   0 pre    order check, Chao1 estimate, dispatch, table
  *            initialisation and tiny count                 (Alg. 2, Alg. 3, Sec. 4.4)
- *   1 count  hash count, first pass (one kernel)           (Sec. 4.4)
- *   2 defer  hash count of the deferred elements           (Sec. 4.4)
- *   3 order  ranking of up to 32768 distinct keys and the
- *            run offsets, or the gather for a pair sort   (Alg. 4)
- *   4 emit   run expansion on the caller's stream (one kernel) (Alg. 4)
- *   5 tail   the rest until the report is written: the radix engine, the
+ *   1 count  hash count, with its pass over deferred elements (one kernel) (Sec. 4.4)
+ *   2 order  ranking of up to 32768 distinct keys, run offsets and the guard's
+ *            bucket check, or the gather for a pair sort   (Alg. 4)
+ *   3 emit   run expansion on the caller's stream (one kernel) (Alg. 4)
+ *   4 tail   the rest until the report is written: the radix engine, the
  *            larger pair sort and its emit, the monotone copy, the run-length
  *            pass and the guard run on a side stream of the context, forked
- *            after stage 3, and count here as far as they outlast the emit.
+ *            after stage 2, and count here as far as they outlast the emit.
  * Calls on one context share its side stream.
  * cafs_ctx_stage_ms waits for the recorded events, writes into h_ms[0..n_stages)
  * the summed milliseconds of each stage over every call recorded since the last
  * read, stores the number of calls in *h_calls, and forgets them.  Enabling
  * adds one event record per stage boundary to each call. */
-#define CAFS_N_STAGES 6
+#define CAFS_N_STAGES 5
 cafs_status_t cafs_ctx_enable_timing(cafs_ctx_t* ctx, int enable);
 cafs_status_t cafs_ctx_stage_ms(cafs_ctx_t* ctx, float* h_ms, int n_stages, int* h_calls);
 

@@ -18,7 +18,7 @@ I64, U64 = 0, 1
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "HIP error", -4: "unsupported", -5: "nomem",
           -6: "busy"}
 
-STAGES = ("pre", "count", "defer", "order", "emit", "tail")
+STAGES = ("pre", "count", "order", "emit", "tail")
 
 EXPORTS = ("cafs_ctx_create", "cafs_ctx_destroy", "cafs_ctx_enable_timing", "cafs_ctx_stage_ms",
            "cafs_workspace_bytes", "cafs_estimate",

@@ -66,7 +66,7 @@ uint32_t log2_host(uint64_t p) {
 
 // Workspace of one column of n keys.  Regions are 256-byte aligned.
 struct Layout {
-    size_t ctrl, gkeys, gcnt, claimed, uniq, cnt, off, tmp_k, dfr_cnt, status, dcount, bfound, bmin, clist, first, rle_tile;
+    size_t ctrl, gkeys, gcnt, claimed, uniq, cnt, off, tmp_k, status, dcount, bfound, bmin, clist, first, rle_tile;
     size_t total;
     uint32_t cap_log2;
     uint64_t status_slot;
@@ -97,7 +97,6 @@ Layout make_layout(uint64_t n) {
     L.cnt = take(nn * 8);
     L.off = take((nn + 1) * 8);
     L.tmp_k = take((nn + 2 + 2 * cafs::kMaxCountBlocks) * 8);  // also the hash count's deferral regions
-    L.dfr_cnt = take(cafs::kMaxCountBlocks * 4);
     L.status = take(2 * L.status_slot * 8);
     L.dcount = take(L.m_ws * 4);
     L.bfound = take(L.m_ws * 4);
@@ -178,7 +177,6 @@ cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void*
     a.claimed = at<uint32_t>(ws, L.claimed);
     a.cap_ws_log2 = L.cap_log2;
     a.tmp_k = at<uint64_t>(ws, L.tmp_k);
-    a.dfr_cnt = at<uint32_t>(ws, L.dfr_cnt);
     a.status = at<uint64_t>(ws, L.status);
     a.status_slot = L.status_slot;
     a.dcount = at<uint32_t>(ws, L.dcount);
@@ -242,18 +240,16 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     if (countable)
         cafs::k_phase2<<<grid_for(std::max<uint64_t>(n / 2, cap_ws), 256 * 8, cus * 2), 256, 0, s>>>(a);
     mark(1);
-    // one workgroup per CU (the LDS table takes the CU); both count passes use the same grid
+    // one workgroup per CU (the LDS table takes the CU)
     const uint32_t g_count = grid_for(n, cafs::kCountThreads * 8, std::min<uint32_t>(cus, cafs::kMaxCountBlocks));
     if (countable) cafs::k_hash_count<<<g_count, cafs::kCountThreads, 0, s>>>(a);
     mark(2);
-    if (countable) cafs::k_defer_count<<<g_count, cafs::kCountThreads, 0, s>>>(a);
-    mark(3);
     if (countable) {
         const uint64_t k_max = std::min<uint64_t>(n, cafs::kRankMax);
         cafs::k_rank<<<grid_for(k_max, cafs::kRankKeysPerBlock, 1u << 16), 1024, 0, s>>>(a);
         cafs::k_compact_order<<<1, 1024, 0, s>>>(a);
     }
-    mark(4);
+    mark(3);
     // Fork: the branches that are idle on the common path (radix engine and pair
     // sort with their own emit, monotone copy, run-length pass, guard resolution)
     // run on the side stream and overlap the emit on the caller's stream.
@@ -267,7 +263,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     // for the side stream
     const uint32_t g_emit = grid_for(n, 2 * cafs::kEmitTilePairs, cus * 4);
     if (countable && !inplace) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 0u);
-    mark(5);
+    mark(4);
     launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2, countable && n > cafs::kRankMax);
     if (countable && n > cafs::kRankMax) cafs::k_pair_scan<<<1, 1024, 0, s2>>>(a);
     cafs::k_copy_mono<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s2>>>(a);
@@ -292,7 +288,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     (void)hipStreamWaitEvent(s, ctx->join, 0);
     if (countable && inplace) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 0u);
     cafs::k_finalize<<<1, 64, 0, s>>>(a);
-    mark(6);
+    mark(5);
     if (!evs.empty()) ctx->calls.push_back(evs);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? CAFS_OK : hip_fail(e, "launch");
@@ -555,7 +551,6 @@ cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uin
     cafs::kb_mono_full<<<TP, 256, 0, s>>>(gp);
     cafs::kb_phase2<<<TP, 256, 0, s>>>(gp);
     cafs::kb_hash_count<<<TH, cafs::kCountThreads, 0, s>>>(gh);
-    cafs::kb_defer_count<<<TH, cafs::kCountThreads, 0, s>>>(gh);
     cafs::kb_rank<<<TP, 1024, 0, s>>>(gp);
     cafs::kb_compact_order<<<C, 1024, 0, s>>>(g1);
     cafs::kb_radix_hist<<<TP, 256, 0, s>>>(gp);

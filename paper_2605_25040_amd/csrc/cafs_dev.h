@@ -156,7 +156,6 @@ struct Args {
     // radix scratch (n keys; the pair sort uses the dead hash table instead); during
     // the hash count it holds the deferred elements, one region per workgroup
     uint64_t* tmp_k;
-    uint32_t* dfr_cnt;                // kMaxCountBlocks entries: deferred elements per workgroup
     uint64_t* status;                 // 2 slots of status_slot words
     uint64_t status_slot;
     // guard scratch

@@ -233,9 +233,13 @@ __device__ __forceinline__ int match4(const uint64_t* skeys, uint32_t b, uint64_
     return lo.x == x ? 0 : lo.y == x ? 1 : hi.x == x ? 2 : hi.y == x ? 3 : -1;
 }
 
+// Counts the elements of x selected by `want` in the LDS table, one after the
+// other (the loads of the next batch are in flight meanwhile); returns the mask of
+// those whose window was full (not counted).
 template <int NE>
 __device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, uint32_t* __restrict__ scnt,
-                                                const uint64_t (&x)[NE], uint32_t want_m) {
+                                                uint32_t* __restrict__ sink, const uint64_t (&x)[NE],
+                                                uint32_t want_m) {
     uint32_t ins = 0, dfr = 0;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
@@ -243,12 +247,16 @@ __device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, ui
         uint32_t b = lds_bucket(x[e]);
         bool full;
         int m = match4(skeys, b, x[e], full);
-        if (m < 0 && full) {
+        if (m < 0 && full) {  // home bucket full without x: x may be in the next one
             b = next_bucket(b);
             m = match4(skeys, b, x[e], full);
         }
         const bool hit = want && m >= 0;
-        atomicAdd(&scnt[(m < 0 ? 0 : m) * kLdsBuckets + b], hit ? 1u : 0u);
+        // counters are slot-major (slot s of bucket b at s * kLdsBuckets + b) so that
+        // the first slots of many buckets spread over the LDS banks; lanes without a
+        // hit add to their own sink word, off the counters (equal addresses in one
+        // instruction serialise)
+        atomicAdd(hit ? &scnt[m * kLdsBuckets + b] : &sink[__lane_id()], 1u);
         const bool miss = want && !hit;
         ins |= (miss && !full) ? (1u << e) : 0u;
         dfr |= (miss && full) ? (1u << e) : 0u;
@@ -310,6 +318,7 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
     __shared__ __attribute__((aligned(16))) uint64_t skeys[S];
     __shared__ uint32_t scnt[S];
     __shared__ uint32_t s_ndef;
+    __shared__ uint32_t s_sink[64];  // target of the atomics of lanes without a hit
     for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
         skeys[i] = kEmpty;
         scnt[i] = 0;
@@ -375,7 +384,7 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
             ecnt += is_empty_key ? 1u : 0u;
             want &= is_empty_key ? ~(1u << e) : ~0u;
         }
-        const uint32_t dfr = count_batch<NE>(skeys, scnt, x, want);
+        const uint32_t dfr = count_batch<NE>(skeys, scnt, s_sink, x, want);
         if (__ballot(dfr != 0)) {
             // append the deferred elements: one LDS reservation per wave, then each
             // element's place from the ballot of its batch position
@@ -400,42 +409,31 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
         base = next;
     }
     __syncthreads();
-    if (threadIdx.x == 0) gp(a.dfr_cnt)[bid] = s_ndef;
     flush_table(t, skeys, scnt);
     const uint32_t wsum = wave_sum_u32(ecnt);
     if (lane == 0 && wsum) g_add(&c->ecount, (uint64_t)wsum);
-}
-CAFS_KERNELS0(hash_count, kCountThreads)
-
-// Second pass of the hash count: each workgroup counts the elements it deferred,
-// with a fresh LDS table (the keys that found no room in the first table are few)
-// and a longer probe; what still finds no room goes to the global table.  Launched
-// over the same grid as the first pass.
-__device__ __forceinline__ void defer_count_body(const Args& a, uint32_t bid, uint32_t nblk) {
-    Ctrl* c = a.c;
-    if (c->engine != E_HASH || c->dense_ready || g_load(&c->overflow)) return;
-    const uint32_t d = gp(a.dfr_cnt)[bid];
+    // Second pass over this workgroup's deferred elements, with the table cleared
+    // (the keys that found no room are few) and a longer probe; what still finds no
+    // room goes to the global table.
+    const uint32_t d = s_ndef;  // uniform: read after the barrier
     if (d == 0) return;
-    constexpr uint32_t S = kLdsBuckets * kLdsBucketSlots;
-    __shared__ __attribute__((aligned(16))) uint64_t skeys[S];
-    __shared__ uint32_t scnt[S];
+    __syncthreads();  // (the workgroup reads back only its own region)
     for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
         skeys[i] = kEmpty;
         scnt[i] = 0;
     }
     __syncthreads();
-    const GTable t = gtable(a);
-    const CAFS_GLOBAL uint64_t* region = gp(a.tmp_k) + (uint64_t)bid * 2 * pairs_per_block(num_pairs(a.n, a.in_head), nblk);
     for (uint32_t i0 = 0; i0 < d; i0 += blockDim.x) {  // one element per thread: this pass is short
         const uint32_t i = i0 + threadIdx.x;
-        const uint64_t x[1] = {i < d ? region[i] : 0};
-        if (count_batch<1>(skeys, scnt, x, i < d ? 1u : 0u) && !lds_insert(skeys, scnt, x[0], 1u, kLdsProbeBuckets))
-            global_insert(t, x[0], 1);
+        const uint64_t x1[1] = {i < d ? region[i] : 0};
+        if (count_batch<1>(skeys, scnt, s_sink, x1, i < d ? 1u : 0u) &&
+            !lds_insert(skeys, scnt, x1[0], 1u, kLdsProbeBuckets))
+            global_insert(t, x1[0], 1);
     }
     __syncthreads();
     flush_table(t, skeys, scnt);
 }
-CAFS_KERNELS0(defer_count, kCountThreads)
+CAFS_KERNELS0(hash_count, kCountThreads)
 
 // ---------------------------------------------------------------------------
 // Order of the distinct keys (Alg. 4, steps "collect non-empty bucket slots" and
@@ -447,6 +445,99 @@ CAFS_KERNELS0(defer_count, kCountThreads)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t table_key(const Args& a, uint32_t idx, uint32_t claimed) {
     return idx < claimed ? gp(a.gkeys)[gp(a.claimed)[idx]] : kEmpty;
+}
+
+// Gather of the (key, count) pairs for the radix engine in pair mode (K > kRankMax):
+// the dense arrays are sorted in place, with the dead hash table as scratch
+// (K <= table size).  One workgroup.
+__device__ __forceinline__ void gather_pairs(const Args& a, Ctrl* c, uint32_t claimed, uint64_t ecount, uint32_t K) {
+    for (uint32_t i = threadIdx.x; i < claimed; i += blockDim.x) {
+        const uint32_t h = a.claimed[i];
+        a.uniq[i] = a.gkeys[h];
+        a.cnt[i] = a.gcnt[h];
+    }
+    if (threadIdx.x == 0) {
+        if (ecount) { a.uniq[claimed] = kEmpty; a.cnt[claimed] = ecount; }
+        RadixJob& j = c->rj;
+        j.src_k = a.uniq; j.src_v = a.cnt;
+        j.dst_k = a.uniq; j.dst_v = a.cnt;
+        j.tmp_k = a.gkeys; j.tmp_v = a.gcnt;
+        j.n = K;
+        j.has_vals = 1;
+        c->K = K;
+        c->pair_sort = 1;
+        c->radix_on = 1;
+        c->guard_on = (c->path == P_MAIN);
+        c->guard_general = c->guard_on;
+    }
+}
+
+// Run offsets of the ranked pairs and the spill guard's bucket check (one
+// workgroup).  If no bucket of the paper's table (M buckets, Eq. hash)
+// receives more than four distinct keys, nothing spills (Alg. 1) and the guard is
+// settled here.  `bc` holds kGuardLdsBuckets 32-bit words of LDS.
+__device__ __forceinline__ void offsets_and_guard_check(const Args& a, Ctrl* c, uint32_t K, uint32_t* bc) {
+    const uint32_t tid = threadIdx.x;
+    // exclusive scan of the counts -> run offsets; each thread takes a contiguous chunk
+    __shared__ uint64_t scan_tmp[17];
+    const CAFS_GLOBAL uint64_t* cnt = gp(a.cnt);
+    const uint32_t per = (K + blockDim.x - 1) / blockDim.x;
+    const uint32_t b0 = tid * per < K ? tid * per : K;
+    const uint32_t b1 = b0 + per < K ? b0 + per : K;
+    uint64_t local = 0;
+    for (uint32_t i = b0; i < b1; ++i) local += cnt[i];
+    uint64_t total;
+    uint64_t run = block_exclusive_scan<uint64_t>(local, scan_tmp, &total);
+    for (uint32_t i = b0; i < b1; ++i) {
+        gp(a.off)[i] = run;
+        run += cnt[i];
+    }
+    if (tid == 0) {
+        a.off[K] = total;
+        c->K = K;
+        c->dense_ready = 1;
+        c->emit_main = 1;
+    }
+    // guard check on the paper's M buckets (main path only): count the distinct keys
+    // of each bucket in LDS and list the keys of buckets holding more than four
+    if (c->path != P_MAIN) return;
+    const uint64_t M = c->table_M;
+    if (M > kGuardLdsBuckets) {
+        if (tid == 0) { c->guard_on = 1; c->guard_general = 1; }
+        return;
+    }
+    const CAFS_GLOBAL uint64_t* uq = gp(a.uniq);
+    __shared__ uint32_t s_nc, s_nb;
+    const uint32_t lg = log2_pow2(M);
+    for (uint32_t i = tid; i < M; i += blockDim.x) bc[i] = 0;
+    if (tid == 0) { s_nc = 0; s_nb = 0; }
+    __syncthreads();
+    for (uint32_t i = tid; i < K; i += blockDim.x) atomicAdd(&bc[phi_hash32(uq[i], lg)], 1u);
+    __syncthreads();
+    uint32_t over = 0, over_b = 0;
+    for (uint32_t i = tid; i < K; i += blockDim.x) over += bc[phi_hash32(uq[i], lg)] > kBucketCap;
+    for (uint32_t i = tid; i < M; i += blockDim.x) over_b += bc[i] > kBucketCap;
+    over = wave_sum_u32(over);
+    over_b = wave_sum_u32(over_b);
+    if (__lane_id() == 0 && over) atomicAdd(&s_nc, over);
+    if (__lane_id() == 0 && over_b) atomicAdd(&s_nb, over_b);
+    __syncthreads();
+    const uint32_t nc = s_nc;
+    if (nc > kGuardLdsKeys) {
+        // too many for the one-workgroup resolution: the general kernels recount
+        if (tid == 0) { c->guard_on = 1; c->guard_general = 1; }
+        return;
+    }
+    __syncthreads();
+    if (tid == 0) s_nc = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < K; i += blockDim.x)
+        if (bc[phi_hash32(uq[i], lg)] > kBucketCap) a.clist[atomicAdd(&s_nc, 1u)] = i;
+    if (tid == 0) {
+        c->n_contested = nc;
+        c->n_cbuckets = s_nb;
+        c->guard_on = nc > 0;
+    }
 }
 
 __device__ __forceinline__ void rank_body(const Args& a, uint32_t bid, uint32_t nblk) {
@@ -483,103 +574,20 @@ __device__ __forceinline__ void rank_body(const Args& a, uint32_t bid, uint32_t 
 }
 CAFS_KERNELS0(rank, 1024)
 
-// Run offsets of the ranked pairs and the spill guard's bucket check (one
-// workgroup).  Larger K is gathered for the radix engine in pair mode.  If no
-// bucket of the paper's table (M buckets, Eq. hash) receives more than four
-// distinct keys, nothing spills (Alg. 1) and the guard is settled here.
+// After the ranking: run offsets and the guard's bucket check, or the gather for a
+// pair sort when K is too large to rank.  One workgroup.
 __device__ __forceinline__ void compact_order_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (c->engine != E_HASH || c->overflow || c->dense_ready) return;
     const uint32_t claimed = c->claimed;
     const uint64_t ecount = c->ecount;
     const uint32_t K = claimed + (ecount > 0 ? 1u : 0u);
-    const uint32_t tid = threadIdx.x;
     if (K > kRankMax) {
-        // gather the pairs into the dense arrays and sort them there, in place, with
-        // the radix engine; the hash table is dead after the gather and serves as
-        // the radix scratch (K <= table size)
-        for (uint32_t i = tid; i < claimed; i += blockDim.x) {
-            const uint32_t h = a.claimed[i];
-            a.uniq[i] = a.gkeys[h];
-            a.cnt[i] = a.gcnt[h];
-        }
-        if (tid == 0) {
-            if (ecount) { a.uniq[claimed] = kEmpty; a.cnt[claimed] = ecount; }
-            RadixJob& j = c->rj;
-            j.src_k = a.uniq; j.src_v = a.cnt;
-            j.dst_k = a.uniq; j.dst_v = a.cnt;
-            j.tmp_k = a.gkeys; j.tmp_v = a.gcnt;
-            j.n = K;
-            j.has_vals = 1;
-            c->K = K;
-            c->pair_sort = 1;
-            c->radix_on = 1;
-            c->guard_on = (c->path == P_MAIN);
-            c->guard_general = c->guard_on;
-        }
+        gather_pairs(a, c, claimed, ecount, K);
         return;
     }
-    // exclusive scan of the counts -> run offsets; each thread takes a contiguous chunk
-    __shared__ uint64_t scan_tmp[17];
-    const CAFS_GLOBAL uint64_t* cnt = gp(a.cnt);
-    const uint32_t per = (K + blockDim.x - 1) / blockDim.x;
-    const uint32_t b0 = tid * per < K ? tid * per : K;
-    const uint32_t b1 = b0 + per < K ? b0 + per : K;
-    uint64_t local = 0;
-    for (uint32_t i = b0; i < b1; ++i) local += cnt[i];
-    uint64_t total;
-    uint64_t run = block_exclusive_scan<uint64_t>(local, scan_tmp, &total);
-    for (uint32_t i = b0; i < b1; ++i) {
-        gp(a.off)[i] = run;
-        run += cnt[i];
-    }
-    if (tid == 0) {
-        a.off[K] = total;
-        c->K = K;
-        c->dense_ready = 1;
-        c->emit_main = 1;
-    }
-    // guard check on the paper's M buckets (main path only): count the distinct keys
-    // of each bucket in LDS and list the keys of buckets holding more than four
-    if (c->path != P_MAIN) return;
-    const uint64_t M = c->table_M;
-    if (M > kGuardLdsBuckets) {
-        if (tid == 0) { c->guard_on = 1; c->guard_general = 1; }
-        return;
-    }
-    const CAFS_GLOBAL uint64_t* uq = gp(a.uniq);
     __shared__ uint32_t bc[kGuardLdsBuckets];
-    __shared__ uint32_t s_nc, s_nb;
-    const uint32_t lg = log2_pow2(M);
-    for (uint32_t i = tid; i < M; i += blockDim.x) bc[i] = 0;
-    if (tid == 0) { s_nc = 0; s_nb = 0; }
-    __syncthreads();
-    for (uint32_t i = tid; i < K; i += blockDim.x) atomicAdd(&bc[phi_hash32(uq[i], lg)], 1u);
-    __syncthreads();
-    uint32_t over = 0, over_b = 0;
-    for (uint32_t i = tid; i < K; i += blockDim.x) over += bc[phi_hash32(uq[i], lg)] > kBucketCap;
-    for (uint32_t i = tid; i < M; i += blockDim.x) over_b += bc[i] > kBucketCap;
-    over = wave_sum_u32(over);
-    over_b = wave_sum_u32(over_b);
-    if (__lane_id() == 0 && over) atomicAdd(&s_nc, over);
-    if (__lane_id() == 0 && over_b) atomicAdd(&s_nb, over_b);
-    __syncthreads();
-    const uint32_t nc = s_nc;
-    if (nc > kGuardLdsKeys) {
-        // too many for the one-workgroup resolution: the general kernels recount
-        if (tid == 0) { c->guard_on = 1; c->guard_general = 1; }
-        return;
-    }
-    __syncthreads();
-    if (tid == 0) s_nc = 0;
-    __syncthreads();
-    for (uint32_t i = tid; i < K; i += blockDim.x)
-        if (bc[phi_hash32(uq[i], lg)] > kBucketCap) a.clist[atomicAdd(&s_nc, 1u)] = i;
-    if (tid == 0) {
-        c->n_contested = nc;
-        c->n_cbuckets = s_nb;
-        c->guard_on = nc > 0;
-    }
+    offsets_and_guard_check(a, c, K, bc);
 }
 CAFS_KERNELS0(compact_order, 1024)
 
