@@ -80,7 +80,7 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-def bench_batched(ctx, n_cols=4096, total=1 << 28, reps=20, seq_reps=1):
+def bench_batched(ctx, n_cols=4096, total=1 << 28, reps=50, seq_reps=1):
     """One batched call over n_cols columns vs the same columns sorted by
     sequential single-column calls on one stream."""
     import numpy as np
@@ -159,7 +159,9 @@ def bench_batched(ctx, n_cols=4096, total=1 << 28, reps=20, seq_reps=1):
             "sequential_ms": round(seq_ms, 3), "vs_sequential": round(seq_ms / p50, 2), "graph_ok": ok_graph}
 
 
-def bench_serving(seconds, rate=10_000, budget=64 << 30):
+def bench_serving(seconds, rate=10_000, budget=64 << 30, fifo_seconds=2.0):
+    """Real-time Poisson replay through the server, then the first fifo_seconds of
+    the same trace served one request at a time with plain calls (the baseline)."""
     import numpy as np
 
     import gen
@@ -168,13 +170,111 @@ def bench_serving(seconds, rate=10_000, budget=64 << 30):
     lat = (res["t_done"] - arrival) * 1e3
     st = res["stats"]
     paths = np.bincount(res["path"], minlength=6).tolist()
+    m = int(np.searchsorted(arrival, min(fifo_seconds, seconds)))
+    fifo = gen.serve_fifo(arrival[:m], n[:m], k[:m], seeds[:m])
+    flat = (fifo["t_done"] - arrival[:m]) * 1e3
+    fifo_gk = fifo["stats"]["keys"] / fifo["stats"]["wall_s"] / 1e9
+    server_gk = st["keys"] / st["wall_s"] / 1e9
     return {"seconds": seconds, "rate_req_s": rate, "requests": int(arrival.size),
+            "fifo": {"requests": m, "gkeys_s": round(fifo_gk, 2), "served_req_s": round(m / fifo["stats"]["wall_s"], 1),
+                     "p50_ms": round(pct(flat, 50), 3), "p99_ms": round(pct(flat, 99), 3)},
+            "vs_fifo": round(server_gk / fifo_gk, 2),
             "served_req_s": round(arrival.size / st["wall_s"], 1),
             "gkeys_s": round(st["keys"] / st["wall_s"] / 1e9, 2),
             "p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3), "p999_ms": round(pct(lat, 99.9), 3),
             "batches": int(st["batches"]), "max_streams_busy": int(st["max_busy_streams"]),
             "admission_refusals": int(st["refused"]), "arena_high_water_gb": round(st["arena_high_water"] / 2**30, 2),
             "paths": dict(zip(("MONOTONE", "SMALL_N", "TINY", "HIGH_K", "MAIN", "GUARD"), paths))}
+
+
+SWEEP_N = 30_000_000
+SWEEP_KS = (4, 8, 200, 10_000, 130_000, 670_000, 3_000_000, 30_000_000)
+
+
+def run_sweep(seeds=3, steps=5, warmup=2):
+    """The dispatcher sweep (N = 3e7; K in SWEEP_KS; uniform and Zipf(1.1); seeds
+    42 + N + K + 2^32 rep), the plain column and the u64 dictionary-code variant of
+    the HBM-scale column.  Every config is checked against the oracle's report
+    (all fields) and for order on the device; prints one JSON object per config and
+    a markdown table at the end."""
+    import numpy as np
+    import torch
+
+    import gen
+    import oracle
+    import paper_2605_25040_amd as cafs
+    dev = torch.device("cuda", 0)
+    ctx = cafs.Context(0)
+    cfgs = [("plain", 1_000_000, 200, "uniform", 1.1, "random", "i64", 0)]
+    for dist in ("uniform", "zipf"):
+        for k in SWEEP_KS:
+            for rep in range(seeds):
+                cfgs.append(("sweep", SWEEP_N, k, dist, 1.1, "random", "i64", rep))
+    cfgs.append(("hbm_codes_u64", 1 << 28, 1000, "zipf", 1.0, "codes", "u64", 0))
+    rows = []
+    # the oracle's reports are computed on host threads (the library call releases
+    # the GIL) while the GPU runs the next configs
+    from concurrent.futures import ThreadPoolExecutor
+    pool = ThreadPoolExecutor(max_workers=8)
+    pending = []
+    for name, n, k, dist, s, pal, dt, rep in cfgs:
+        seed = gen.default_seed(n, k, rep)
+        x_np = gen.column(n, k, dist=dist, s=s, palette=pal, seed=seed, dtype=np.uint64)
+        unsigned = dt == "u64"
+        x = torch.from_numpy(x_np.view(np.int64)).to(dev)
+        out = torch.empty_like(x)
+        ws = ctx.workspace(ctx.workspace_bytes(n))
+        rep_t = torch.zeros(cafs.report_size(), dtype=torch.uint8, device=dev)
+        fn = ctx._lib.cafs_sort_u64 if unsigned else ctx._lib.cafs_sort_i64
+        stream = torch.cuda.current_stream(dev).cuda_stream
+
+        def step():
+            rc = fn(ctx._h, x.data_ptr(), out.data_ptr(), n, None, None, rep_t.data_ptr(), ws.data_ptr(),
+                    ws.numel(), stream)
+            if rc != 0:
+                raise RuntimeError("sort failed: %d" % rc)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        r = cafs.parse_report(rep_t)
+        o = out if not unsigned else (out ^ (-(2 ** 63)))  # unsigned order as signed order
+        ordered = bool((o[1:] >= o[:-1]).all())
+        if n <= 50_000_000:
+            fut = pool.submit(oracle.report, x_np, np.uint64 if unsigned else np.int64)
+            fields_of = (lambda r=r, fut=fut: [f for f in oracle.REPORT_FIELDS if r[f] != fut.result()[f]])
+        else:
+            est = oracle.estimate(x_np)
+            fields_of = (lambda r=r, est=est: [f for f in est if r[f] != est[f]])
+        row = {"config": name, "n": n, "k": k, "dist": dist if dist == "uniform" else "zipf(%s)" % s,
+               "values": pal, "dtype": dt, "seed": seed, "ms": round(ms, 4), "gkeys_s": round(n / ms / 1e6, 2),
+               "hbm_frac": round(16.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "path": r["path"],
+               "k_hat": r["k_hat"], "k_exact": r["k_exact"], "spill": r["spill_elems"],
+               "ordered": ordered}
+        pending.append((row, fields_of))
+        print("%s n=%d k=%d %s: %.3f ms, %s" % (name, n, k, dist, ms, r["path"]), flush=True)
+        del x, out, ws
+        ctx._ws = None
+        torch.cuda.empty_cache()
+    for row, fields_of in pending:
+        row["report_mismatch"] = fields_of()
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+    pool.shutdown()
+    print("| config | N | K | freq | values | path | K^ | K | spill | ms | Gkeys/s | % HBM | checked |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|---|---|")
+    for r in rows:
+        print("| %s | %d | %d | %s | %s %s | %s | %d | %d | %d | %.3f | %.1f | %.1f | %s |" % (
+            r["config"], r["n"], r["k"], r["dist"], r["values"], r["dtype"], r["path"], r["k_hat"], r["k_exact"],
+            r["spill"], r["ms"], r["gkeys_s"], 100 * r["hbm_frac"],
+            "ok" if r["ordered"] and not r["report_mismatch"] else "MISMATCH %s" % r["report_mismatch"]))
+    return rows
 
 
 def main():
@@ -188,6 +288,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the input (counter calibration under a profiler)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run the dispatcher sweep (checked against the oracle) instead of the bench line")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson serving replay (the configured workload is 60 s); 0 skips it")
     args = ap.parse_args()
@@ -197,6 +299,10 @@ def main():
                          "(a column would shard by an all-gather of the per-GPU (key, count) tables; "
                          "see the design notes).  Use --gpus 1.\n")
         sys.exit(2)
+
+    if args.sweep:
+        run_sweep()
+        return
 
     import numpy as np
     import torch
@@ -235,19 +341,44 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ctx.enable_timing(True)
+    # timed region: K steps, nothing else on the stream
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     ev0.record()
     for _ in range(args.steps):
         step()
     ev1.record()
     torch.cuda.synchronize()
-    ctx.enable_timing(False)
     ms = ev0.elapsed_time(ev1) / args.steps
+    value = n / (ms * 1e-3) / 1e9
+    # per-step distribution: an event pair around each call
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(args.steps)]
+    for e0, e1 in pairs:
+        e0.record()
+        step()
+        e1.record()
+    torch.cuda.synchronize()
+    per_step = [e0.elapsed_time(e1) for e0, e1 in pairs]
+    # practical peak: a plain device copy of the column (2 x 8 B per key moved)
+    cp = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gen.copy_device(out, x, torch.cuda.current_stream(dev).cuda_stream)
+        e1.record()
+        torch.cuda.synchronize()
+        cp.append(e0.elapsed_time(e1))
+    copy_gbs = 16.0 * n / (min(cp) * 1e-3) / 1e9
+    # per-stage times (HIP events the library records on the stream the kernels run
+    # on, at the stage boundaries) over the same number of steps, in a second loop so
+    # that the events do not add to the timed region
+    ctx.enable_timing(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ctx.enable_timing(False)
     stages, calls = ctx.stage_ms()
     stage_avg = {kk: v / max(calls, 1) for kk, v in stages.items()}
-    value = n / (ms * 1e-3) / 1e9
 
     if args.calibrate_copy:
         # a plain copy kernel of known size (n * 8 bytes read and written, 16-byte
@@ -293,6 +424,9 @@ def main():
                    "values": "distinct random 64-bit" if pal == "random" else pal, "seed": "42+N+K",
                    "path": r["path"], "k_hat": r["k_hat"], "k_exact": r["k_exact"]},
         "hbm_frac_path": round(16.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_ms": {"median": round(pct(per_step, 50), 4), "min": round(min(per_step), 4),
+                    "p90": round(pct(per_step, 90), 4)},
+        "copy_peak": {"gbs": round(copy_gbs, 1), "path_frac_of_copy": round(16.0 * n / (ms * 1e-3) / 1e9 / copy_gbs, 4)},
         "stages_ms": {kk: round(v, 4) for kk, v in stage_avg.items()},
         "radix_baseline": {"value": round(radix_value, 3), "unit": "Gkeys/s", "ms": round(radix_ms, 4)},
         "vs_radix": round(value / radix_value, 2),

@@ -58,6 +58,8 @@ def _load_dev():
         u64, p = ctypes.c_uint64, ctypes.c_void_p
         lib.gen_column_dev.argtypes = [p, u64, u64, ctypes.c_int, ctypes.c_double, ctypes.c_int, u64, p]
         lib.gen_column_dev.restype = ctypes.c_int
+        lib.serve_fifo.argtypes = [ctypes.c_int, p, p, p, p, u64, ctypes.c_double, p, p]
+        lib.serve_fifo.restype = ctypes.c_int
         lib.copy_dev.argtypes = [p, p, u64, p]
         lib.copy_dev.restype = ctypes.c_int
         lib.serve_replay.argtypes = [ctypes.c_int, p, p, p, p, u64, ctypes.c_double, u64, ctypes.c_uint32,
@@ -131,6 +133,22 @@ def serve_replay(arrival, n, k, seeds, zipf_s=1.1, budget=64 << 30, n_streams=4,
     keys = ["wall_s", "keys", "batches", "launched", "refused", "max_busy_streams", "arena_high_water",
             "arena_used", "queued", "max_waiting"]
     return dict(t_admit=t_admit, t_done=t_done, path=path, k_exact=kex, stats=dict(zip(keys, stats.tolist())))
+
+
+def serve_fifo(arrival, n, k, seeds, zipf_s=1.1, device=0):
+    """The trace served one request at a time with plain single-column calls."""
+    m = arrival.size
+    arrival = np.ascontiguousarray(arrival, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.uint64)
+    k = np.ascontiguousarray(k, dtype=np.uint64)
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
+    t_done = np.zeros(m)
+    stats = np.zeros(2)
+    rc = _load_dev().serve_fifo(device, arrival.ctypes.data, n.ctypes.data, k.ctypes.data, seeds.ctypes.data, m,
+                                float(zipf_s), t_done.ctypes.data, stats.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("serve_fifo failed: %d" % rc)
+    return dict(t_done=t_done, stats=dict(wall_s=float(stats[0]), keys=float(stats[1])))
 
 
 _lib = None

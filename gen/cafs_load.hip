@@ -192,4 +192,52 @@ int serve_replay(int device, const double* arrival, const uint64_t* n, const uin
     return rc;
 }
 
+// The same trace served one request at a time, in arrival order: each request's
+// input is generated, sorted with a plain single-column call and waited for before
+// the next one starts (the baseline of the serving loop).  Outputs per request:
+// t_done (seconds from the start).  stats[0..2): wall seconds, keys sorted.
+// Returns 0, or the failing cafs_status_t / HIP error.
+int serve_fifo(int device, const double* arrival, const uint64_t* n, const uint64_t* k, const uint64_t* seed,
+               uint64_t n_req, double zipf_s, double* t_done, double* stats) {
+    hipSetDevice(device);
+    cafs_ctx_t* ctx = nullptr;
+    int rc = cafs_ctx_create(&ctx, device);
+    if (rc) return rc;
+    uint64_t n_max = 1;
+    for (uint64_t i = 0; i < n_req; ++i) n_max = std::max<uint64_t>(n_max, n[i]);
+    hipStream_t s;
+    hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    void *din = nullptr, *dout = nullptr, *drep = nullptr, *dws = nullptr;
+    const size_t ws_bytes = cafs_workspace_bytes(n_max, CAFS_I64);
+    hipError_t e = hipMalloc(&din, n_max * 8);
+    if (e == hipSuccess) e = hipMalloc(&dout, n_max * 8);
+    if (e == hipSuccess) e = hipMalloc(&drep, sizeof(cafs_report_t));
+    if (e == hipSuccess) e = hipMalloc(&dws, ws_bytes);
+    if (e != hipSuccess) rc = (int)e;
+    uint64_t keys = 0;
+    const double t0 = now_s();
+    for (uint64_t i = 0; i < n_req && rc == 0; ++i) {
+        while (now_s() - t0 < arrival[i]) {
+        }
+        rc = gen_column_dev(din, n[i], k[i], 1, zipf_s, 0, seed[i], s);
+        if (rc == 0)
+            rc = cafs_sort_i64(ctx, static_cast<const int64_t*>(din), static_cast<int64_t*>(dout), n[i], nullptr,
+                               nullptr, static_cast<cafs_report_t*>(drep), dws, ws_bytes, s);
+        if (rc == 0) rc = (int)hipStreamSynchronize(s);
+        t_done[i] = now_s() - t0;
+        keys += n[i];
+    }
+    if (stats) {
+        stats[0] = now_s() - t0;
+        stats[1] = (double)keys;
+    }
+    hipFree(din);
+    hipFree(dout);
+    hipFree(drep);
+    hipFree(dws);
+    hipStreamDestroy(s);
+    cafs_ctx_destroy(ctx);
+    return rc;
+}
+
 }  // extern "C"

@@ -155,6 +155,11 @@ cafs_status_t launch_radix(const cafs::Args& a, uint64_t n_max, int cus, hipStre
     return CAFS_OK;
 }
 
+// Workgroups of the single-column ranking kernel.
+uint32_t rank_grid(uint64_t n) {
+    return grid_for(std::min<uint64_t>(n, cafs::kRankMax), cafs::kRankKeysPerBlock, 1u << 16);
+}
+
 cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void* out, uint64_t n, cafs_dtype_t dt,
                      void* uniq, uint64_t* counts, cafs_report_t* report, void* ws) {
     (void)ctx;
@@ -186,6 +191,8 @@ cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void*
     a.bfound = at<uint32_t>(ws, L.bfound);
     a.m_ws = L.m_ws;
     a.rle_tile = at<uint64_t>(ws, L.rle_tile);
+    a.rank_blocks = rank_grid(n);
+    a.rank_budget_log2 = cafs::kRankBudgetLog2;
     return a;
 }
 
@@ -245,8 +252,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     if (countable) cafs::k_hash_count<<<g_count, cafs::kCountThreads, 0, s>>>(a);
     mark(2);
     if (countable) {
-        const uint64_t k_max = std::min<uint64_t>(n, cafs::kRankMax);
-        cafs::k_rank<<<grid_for(k_max, cafs::kRankKeysPerBlock, 1u << 16), 1024, 0, s>>>(a);
+        cafs::k_rank<<<a.rank_blocks, 1024, 0, s>>>(a);
         cafs::k_compact_order<<<1, 1024, 0, s>>>(a);
     }
     mark(3);
@@ -536,6 +542,8 @@ cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uin
         const cafs_column_t& col = cols[i];
         args[i] = make_args(ctx, make_layout(col.n), col.d_in, col.d_out, col.n, (cafs_dtype_t)col.dtype,
                             col.d_uniq, col.d_counts, col.d_report, col_ws[i]);
+        args[i].rank_blocks = P.bp[i];  // the ranking kernel runs over the general block table
+        args[i].rank_budget_log2 = cafs::kRankBudgetBatchLog2;
     }
     fill_table(reinterpret_cast<uint32_t*>(h + P.off_m1), n_cols, nullptr, n_cols);
     fill_table(reinterpret_cast<uint32_t*>(h + P.off_mp), n_cols, &P.bp, P.total_p);

@@ -38,6 +38,8 @@ constexpr uint32_t kMaxTableLog2 = 22;         // largest global table (4M slots
 constexpr uint32_t kRankMax = 32768;           // K ordered by ranking (larger K: pair radix sort)
 constexpr uint32_t kRankKeysPerBlock = 64;     // keys ranked by one workgroup (16 threads each)
 constexpr uint32_t kRankTile = 8192;           // keys staged in LDS at a time while ranking
+constexpr uint32_t kRankBudgetLog2 = 24;       // compares per ranking workgroup before a pair sort wins
+constexpr uint32_t kRankBudgetBatchLog2 = 20;  // the same in a batch, where total work counts more than latency
 constexpr uint32_t kGuardLdsBuckets = 16384;   // guard bucket counts kept in LDS up to this M
 constexpr int kRadixThreads = 256;             // radix workgroup (4 waves)
 constexpr int kRadixItems = 16;                // keys per thread per tile
@@ -165,6 +167,8 @@ struct Args {
     uint32_t* clist;                  // n entries: indices of contested keys
     uint32_t* bfound;                 // m_ws entries: contested keys seen per bucket
     uint64_t m_ws;
+    uint32_t rank_blocks;             // workgroups of this column's ranking kernel
+    uint32_t rank_budget_log2;        // compares per ranking workgroup allowed
     // run-length scratch
     uint64_t* rle_tile;               // per-tile run counts
 };

@@ -443,11 +443,17 @@ CAFS_KERNELS0(hash_count, kCountThreads)
 // LDS, and writes (key, count) to its place in the dense arrays: K^2 compares spread
 // over the whole GPU instead of a sorting network in one workgroup.
 // ---------------------------------------------------------------------------
+// Ranking costs K^2 compares over the column's ranking workgroups; beyond
+// kRankMax keys, or a budget per workgroup, the pairs are radix sorted instead.
+__device__ __forceinline__ bool rank_ok(const Args& a, uint32_t K) {
+    return K <= kRankMax && (uint64_t)K * K <= ((uint64_t)a.rank_blocks << a.rank_budget_log2);
+}
+
 __device__ __forceinline__ uint64_t table_key(const Args& a, uint32_t idx, uint32_t claimed) {
     return idx < claimed ? gp(a.gkeys)[gp(a.claimed)[idx]] : kEmpty;
 }
 
-// Gather of the (key, count) pairs for the radix engine in pair mode (K > kRankMax):
+// Gather of the (key, count) pairs for the radix engine in pair mode (too many to rank):
 // the dense arrays are sorted in place, with the dead hash table as scratch
 // (K <= table size).  One workgroup.
 __device__ __forceinline__ void gather_pairs(const Args& a, Ctrl* c, uint32_t claimed, uint64_t ecount, uint32_t K) {
@@ -546,7 +552,7 @@ __device__ __forceinline__ void rank_body(const Args& a, uint32_t bid, uint32_t 
     const uint32_t claimed = c->claimed;
     const uint64_t ecount = c->ecount;
     const uint32_t K = claimed + (ecount > 0 ? 1u : 0u);
-    if (K > kRankMax || (uint64_t)bid * kRankKeysPerBlock >= K) return;
+    if (!rank_ok(a, K) || (uint64_t)bid * kRankKeysPerBlock >= K) return;
     const uint64_t flip = a.flip;
     __shared__ uint64_t sk[kRankTile];
     const uint32_t part = threadIdx.x % 16;
@@ -582,7 +588,7 @@ __device__ __forceinline__ void compact_order_body(const Args& a, uint32_t bid, 
     const uint32_t claimed = c->claimed;
     const uint64_t ecount = c->ecount;
     const uint32_t K = claimed + (ecount > 0 ? 1u : 0u);
-    if (K > kRankMax) {
+    if (!rank_ok(a, K)) {
         gather_pairs(a, c, claimed, ecount, K);
         return;
     }
