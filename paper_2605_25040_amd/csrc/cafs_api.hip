@@ -66,7 +66,7 @@ uint32_t log2_host(uint64_t p) {
 
 // Workspace of one column of n keys.  Regions are 256-byte aligned.
 struct Layout {
-    size_t ctrl, gkeys, gcnt, claimed, uniq, cnt, off, tmp_k, status, dcount, bfound, bmin, clist, first, rle_tile;
+    size_t ctrl, gkeys, gcnt, claimed, uniq, cnt, off, tmp_k, psum, status, dcount, bfound, bmin, clist, first, rle_tile;
     size_t total;
     uint32_t cap_log2;
     uint64_t status_slot;
@@ -97,6 +97,7 @@ Layout make_layout(uint64_t n) {
     L.cnt = take(nn * 8);
     L.off = take((nn + 1) * 8);
     L.tmp_k = take((nn + 2 + 2 * cafs::kMaxCountBlocks) * 8);  // also the hash count's deferral regions
+    L.psum = take(cafs::kMaxCountBlocks * 8);
     L.status = take(2 * L.status_slot * 8);
     L.dcount = take(L.m_ws * 4);
     L.bfound = take(L.m_ws * 4);
@@ -191,6 +192,7 @@ cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void*
     a.bfound = at<uint32_t>(ws, L.bfound);
     a.m_ws = L.m_ws;
     a.rle_tile = at<uint64_t>(ws, L.rle_tile);
+    a.psum = at<uint64_t>(ws, L.psum);
     a.rank_blocks = rank_grid(n);
     a.rank_budget_log2 = cafs::kRankBudgetLog2;
     return a;
@@ -271,7 +273,11 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     if (countable && !inplace) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 0u);
     mark(4);
     launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2, countable && n > cafs::kRankMax);
-    if (countable && n > cafs::kRankMax) cafs::k_pair_scan<<<1, 1024, 0, s2>>>(a);
+    if (countable && n > cafs::kRankMax) {
+        const uint32_t g_scan = std::min<uint32_t>(cus * 2, cafs::kMaxCountBlocks);
+        cafs::k_pair_sums<<<g_scan, 1024, 0, s2>>>(a);
+        cafs::k_pair_scan<<<g_scan, 1024, 0, s2>>>(a);
+    }
     cafs::k_copy_mono<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s2>>>(a);
     const uint32_t g_rle = grid_for(n, cafs::kRleTile, cus * 4);
     cafs::k_rle_count<<<g_rle, 256, 0, s2>>>(a);
@@ -567,7 +573,8 @@ cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uin
         cafs::kb_radix_pass_kv<<<TP, cafs::kRadixThreads, 0, s>>>(gp, p);
     }
     cafs::kb_radix_copy<<<TP, 256, 0, s>>>(gp);
-    cafs::kb_pair_scan<<<C, 1024, 0, s>>>(g1);
+    cafs::kb_pair_sums<<<TP, 1024, 0, s>>>(gp);
+    cafs::kb_pair_scan<<<TP, 1024, 0, s>>>(gp);
     cafs::kb_copy_mono<<<TP, 256, 0, s>>>(gp);
     cafs::kb_rle_count<<<TP, 256, 0, s>>>(gp);
     cafs::kb_rle_write<<<TP, 256, 0, s>>>(gp);

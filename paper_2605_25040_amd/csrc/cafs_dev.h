@@ -171,6 +171,7 @@ struct Args {
     uint32_t rank_budget_log2;        // compares per ranking workgroup allowed
     // run-length scratch
     uint64_t* rle_tile;               // per-tile run counts
+    uint64_t* psum;                   // kMaxCountBlocks chunk sums of the pair scan
 };
 
 // Block table of a batched launch: block b works on column col[b] as block

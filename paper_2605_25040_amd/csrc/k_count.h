@@ -417,6 +417,12 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
     // room goes to the global table.
     const uint32_t d = s_ndef;  // uniform: read after the barrier
     if (d == 0) return;
+    if (4ull * d > 2 * PP) {
+        // a quarter of this workgroup's elements found no room: K is far beyond the
+        // table, and the radix engine sorts the column instead
+        if (threadIdx.x == 0) set_overflow(c, t.inplace, t.tmp_k, t.uniq);
+        return;
+    }
     __syncthreads();  // (the workgroup reads back only its own region)
     for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
         skeys[i] = kEmpty;
@@ -455,14 +461,15 @@ __device__ __forceinline__ uint64_t table_key(const Args& a, uint32_t idx, uint3
 
 // Gather of the (key, count) pairs for the radix engine in pair mode (too many to rank):
 // the dense arrays are sorted in place, with the dead hash table as scratch
-// (K <= table size).  One workgroup.
-__device__ __forceinline__ void gather_pairs(const Args& a, Ctrl* c, uint32_t claimed, uint64_t ecount, uint32_t K) {
-    for (uint32_t i = threadIdx.x; i < claimed; i += blockDim.x) {
-        const uint32_t h = a.claimed[i];
-        a.uniq[i] = a.gkeys[h];
-        a.cnt[i] = a.gcnt[h];
+// (K <= table size).  All workgroups of the ranking launch share the gather.
+__device__ __forceinline__ void gather_pairs(const Args& a, Ctrl* c, uint32_t claimed, uint64_t ecount, uint32_t K,
+                                             uint32_t bid, uint32_t nblk) {
+    for (uint64_t i = (uint64_t)bid * blockDim.x + threadIdx.x; i < claimed; i += (uint64_t)nblk * blockDim.x) {
+        const uint32_t h = gp(a.claimed)[i];
+        gp(a.uniq)[i] = gp(a.gkeys)[h];
+        gp(a.cnt)[i] = gp(a.gcnt)[h];
     }
-    if (threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         if (ecount) { a.uniq[claimed] = kEmpty; a.cnt[claimed] = ecount; }
         RadixJob& j = c->rj;
         j.src_k = a.uniq; j.src_v = a.cnt;
@@ -552,7 +559,11 @@ __device__ __forceinline__ void rank_body(const Args& a, uint32_t bid, uint32_t 
     const uint32_t claimed = c->claimed;
     const uint64_t ecount = c->ecount;
     const uint32_t K = claimed + (ecount > 0 ? 1u : 0u);
-    if (!rank_ok(a, K) || (uint64_t)bid * kRankKeysPerBlock >= K) return;
+    if (!rank_ok(a, K)) {
+        gather_pairs(a, c, claimed, ecount, K, bid, nblk);
+        return;
+    }
+    if ((uint64_t)bid * kRankKeysPerBlock >= K) return;
     const uint64_t flip = a.flip;
     __shared__ uint64_t sk[kRankTile];
     const uint32_t part = threadIdx.x % 16;
@@ -588,35 +599,68 @@ __device__ __forceinline__ void compact_order_body(const Args& a, uint32_t bid, 
     const uint32_t claimed = c->claimed;
     const uint64_t ecount = c->ecount;
     const uint32_t K = claimed + (ecount > 0 ? 1u : 0u);
-    if (!rank_ok(a, K)) {
-        gather_pairs(a, c, claimed, ecount, K);
-        return;
-    }
+    if (!rank_ok(a, K)) return;  // gathered for the pair sort by the ranking launch
     __shared__ uint32_t bc[kGuardLdsBuckets];
     offsets_and_guard_check(a, c, K, bc);
 }
 CAFS_KERNELS0(compact_order, 1024)
 
-// Exclusive scan of the sorted counts after a pair sort (K > 8192).  One workgroup.
+// Exclusive scan of the sorted counts after a pair sort, in two launches over the
+// same grid: each workgroup sums its chunk of the counts, then each adds the sums
+// of the chunks before its own and scans its chunk.
+__device__ __forceinline__ uint64_t scan_chunk(uint64_t K, uint32_t nblk) { return (K + nblk - 1) / nblk; }
+
+__device__ __forceinline__ void pair_sums_body(const Args& a, uint32_t bid, uint32_t nblk) {
+    Ctrl* c = a.c;
+    if (!c->pair_sort || c->overflow) return;
+    const uint64_t K = c->K;
+    const uint64_t ch = scan_chunk(K, nblk);
+    const uint64_t b = (uint64_t)bid * ch < K ? (uint64_t)bid * ch : K;
+    const uint64_t e = b + ch < K ? b + ch : K;
+    uint64_t local = 0;
+    for (uint64_t i = b + threadIdx.x; i < e; i += blockDim.x) local += gp(a.cnt)[i];
+    __shared__ uint64_t s_sum;
+    if (threadIdx.x == 0) s_sum = 0;
+    __syncthreads();
+    local = wave_sum_u64(local);
+    if (__lane_id() == 0 && local) atomicAdd((unsigned long long*)&s_sum, (unsigned long long)local);
+    __syncthreads();
+    if (threadIdx.x == 0) gp(a.psum)[bid] = s_sum;
+}
+CAFS_KERNELS0(pair_sums, 1024)
+
 __device__ __forceinline__ void pair_scan_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!c->pair_sort || c->overflow) return;
     __shared__ uint64_t scan_tmp[17];
+    __shared__ uint64_t s_base;
     const uint64_t K = c->K;
-    const uint64_t per = (K + blockDim.x - 1) / blockDim.x;
-    const uint64_t b0 = threadIdx.x * per < K ? threadIdx.x * per : K;
-    const uint64_t b1 = b0 + per < K ? b0 + per : K;
+    const uint64_t ch = scan_chunk(K, nblk);
+    uint64_t before = 0;
+    for (uint32_t w = threadIdx.x; w < bid; w += blockDim.x) before += gp(a.psum)[w];
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    before = wave_sum_u64(before);
+    if (__lane_id() == 0 && before) atomicAdd((unsigned long long*)&s_base, (unsigned long long)before);
+    __syncthreads();
+    const uint64_t cb = (uint64_t)bid * ch < K ? (uint64_t)bid * ch : K;
+    const uint64_t ce = cb + ch < K ? cb + ch : K;
+    const uint64_t len = ce - cb;
+    const uint64_t per = (len + blockDim.x - 1) / blockDim.x;
+    const uint64_t b0 = cb + (threadIdx.x * per < len ? threadIdx.x * per : len);
+    const uint64_t b1 = b0 + per < ce ? b0 + per : ce;
+    const CAFS_GLOBAL uint64_t* cnt = gp(a.cnt);
     uint64_t local = 0;
-    for (uint64_t i = b0; i < b1; ++i) local += a.cnt[i];
+    for (uint64_t i = b0; i < b1; ++i) local += cnt[i];
     uint64_t total;
-    uint64_t run = block_exclusive_scan<uint64_t>(local, scan_tmp, &total);
+    uint64_t run = s_base + block_exclusive_scan<uint64_t>(local, scan_tmp, &total);
     for (uint64_t i = b0; i < b1; ++i) {
-        a.off[i] = run;
-        run += a.cnt[i];
+        gp(a.off)[i] = run;
+        run += cnt[i];
     }
-    if (threadIdx.x == 0) {
-        a.off[K] = total;
-        c->dense_ready = 1;
+    if (threadIdx.x == 0 && bid == nblk - 1) {
+        a.off[K] = s_base + total;
+        c->dense_ready = 1;  // read by the next launch (the emit), after this grid ends
     }
 }
 CAFS_KERNELS0(pair_scan, 1024)
