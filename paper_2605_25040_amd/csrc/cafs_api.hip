@@ -272,7 +272,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     const uint32_t g_emit = grid_for(n, 2 * cafs::kEmitTilePairs, cus * 4);
     if (countable && !inplace) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 0u);
     mark(4);
-    launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2, countable && n > cafs::kRankMax);
+    launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2, countable);
     if (countable && n > cafs::kRankMax) {
         const uint32_t g_scan = std::min<uint32_t>(cus * 2, cafs::kMaxCountBlocks);
         cafs::k_pair_sums<<<g_scan, 1024, 0, s2>>>(a);

@@ -32,7 +32,7 @@ constexpr uint32_t kLdsBucketSlots = 4;        // (13568 slots, 159 KiB with 32-
 constexpr uint32_t kLdsWindow = 2;             // buckets probed before an element is deferred
 constexpr uint32_t kLdsProbeBuckets = 8;       // buckets probed in the deferred pass before the global table
 constexpr uint32_t kMaxCountBlocks = 1024;     // workgroups of one hash count
-constexpr uint32_t kGlobalProbe = 4096;        // global probe limit before overflow
+constexpr uint32_t kGlobalProbe = 64;          // global probe limit before overflow (the table is sized for 1/8 load)
 constexpr uint32_t kMinTableLog2 = 12;         // smallest global table (4096 slots)
 constexpr uint32_t kMaxTableLog2 = 22;         // largest global table (4M slots, 64 MiB)
 constexpr uint32_t kRankMax = 32768;           // K ordered by ranking (larger K: pair radix sort)
@@ -73,8 +73,9 @@ struct RadixJob {
     const uint64_t* ps_v[8];
     uint64_t* pd_k[8];                // destination of active pass i
     uint64_t* pd_v[8];
-    uint32_t copy_mode;               // after the passes: 0 nothing, 1 copy src->dst, 2 tmp->dst
-    uint32_t pad;
+    uint32_t copy_mode;               // after the passes: 0 nothing, 1 copy src->dst, 2 tmp->dst,
+                                      // 3 values only (position of each key)
+    uint32_t iota_vals;               // the values are the keys' input positions (made, not read)
 };
 
 // Decisions and counters of one call, in device memory (workspace).
@@ -125,6 +126,8 @@ struct Ctrl {
     // guard
     uint32_t guard_general;           // bucket counts must be built from the dense pairs
     uint32_t guard_rounds;            // too many contested keys for one workgroup
+    uint32_t gidx_log2;               // hash index of the contested keys (0: binary search)
+    uint32_t first_known;             // first occurrences come from the stable sort with positions
     uint64_t n_contested;
     uint64_t n_cbuckets;              // buckets holding more than four distinct keys
     uint64_t buckets_done;            // of those, buckets whose first four keys are known

@@ -96,15 +96,35 @@ __device__ __forceinline__ void phase2_body(const Args& a, uint32_t bid, uint32_
 }
 CAFS_KERNELS0(phase2, 256)
 
+// Whether the radix engine should carry input positions (see set_overflow).  They
+// pay when many buckets of the paper's table are over-full, which happens when the
+// estimate is far below K: a sample with many repeated keys (f1 well below u) has a
+// heavy tail that Chao1 underestimates.  A sample of nearly all singletons comes
+// from keys spread evenly, and the first-occurrence pass then stops early.
+__device__ __forceinline__ bool positions_pay(const Ctrl* c) { return 10 * c->f1 < 9 * c->u; }
+
 // Switch to the radix engine after the global table overflowed.  In place, the
 // radix engine then sorts into scratch so that the guard can still read the input.
-__device__ __noinline__ void set_overflow(Ctrl* c, uint32_t inplace, uint64_t* tmp_k, uint64_t* uniq) {
+// The sort carries each key's input position (the dense count and offset arrays,
+// free until the run-length pass, hold them), so that a run's first position is its
+// key's first occurrence (the LSD sort is stable) and the guard needs no pass of
+// its own over the input.
+__device__ __noinline__ void set_overflow(Ctrl* c, uint32_t inplace, uint64_t* tmp_k, uint64_t* uniq,
+                                          uint64_t* cnt, uint64_t* off) {
     if (atomicExch(&c->overflow, 1u) == 0) {
         if (inplace) {
             c->rj.dst_k = tmp_k;
             c->rj.tmp_k = uniq;
             c->sorted = tmp_k;
             c->deferred_copy = 1;
+        }
+        if (positions_pay(c)) {
+            c->rj.has_vals = 1;
+            c->rj.iota_vals = 1;
+            c->rj.src_v = nullptr;
+            c->rj.dst_v = cnt;
+            c->rj.tmp_v = off;
+            c->first_known = 1;
         }
         atomicExch(&c->radix_on, 1u);
         atomicExch(&c->guard_on, 1u);
@@ -121,6 +141,8 @@ struct GTable {
     uint32_t* claimed;
     uint64_t* tmp_k;
     uint64_t* uniq;
+    uint64_t* dense_cnt;
+    uint64_t* dense_off;
     uint32_t inplace;
 };
 
@@ -132,6 +154,8 @@ __device__ __forceinline__ GTable gtable(const Args& a) {
     t.claimed = a.claimed;
     t.tmp_k = a.tmp_k;
     t.uniq = a.uniq;
+    t.dense_cnt = a.cnt;
+    t.dense_off = a.off;
     t.inplace = a.in == a.out;
     return t;
 }
@@ -153,7 +177,7 @@ __device__ __forceinline__ void global_insert(const GTable& t, uint64_t v, uint6
             if (k == kEmpty) {
                 const uint32_t idx = g_add(&c->claimed, 1u);
                 if (idx >= c->cap_limit) {
-                    set_overflow(c, t.inplace, t.tmp_k, t.uniq);
+                    set_overflow(c, t.inplace, t.tmp_k, t.uniq, t.dense_cnt, t.dense_off);
                     return;
                 }
                 gp(t.claimed)[idx] = (uint32_t)h;
@@ -167,7 +191,7 @@ __device__ __forceinline__ void global_insert(const GTable& t, uint64_t v, uint6
         }
         h = (h + 1) & mask;
     }
-    set_overflow(c, t.inplace, t.tmp_k, t.uniq);
+    set_overflow(c, t.inplace, t.tmp_k, t.uniq, t.dense_cnt, t.dense_off);
 }
 
 // ---------------------------------------------------------------------------
@@ -277,6 +301,11 @@ __device__ __forceinline__ uint64_t pairs_per_block(uint64_t P, uint32_t nblk) {
 __device__ __forceinline__ void flush_table(const GTable& t, const uint64_t* skeys, const uint32_t* scnt) {
     constexpr uint32_t S = kLdsBuckets * kLdsBucketSlots;
     for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
+        // once the table has overflowed (the radix engine takes over) the flush is moot;
+        // one lane per wave looks
+        uint32_t ov = 0;
+        if (__lane_id() == 0) ov = g_load(&t.c->overflow);
+        if (__shfl(ov, 0, 64)) break;
         const uint32_t cn = scnt[i];  // slot i / kLdsBuckets of bucket i % kLdsBuckets; never 0 once claimed
         if (cn) global_insert(t, skeys[(i % kLdsBuckets) * kLdsBucketSlots + i / kLdsBuckets], cn);
     }
@@ -371,7 +400,20 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
         }
     };
     if (base < p_end) load(base);
-    while (base < p_end) {  // uniform over the workgroup
+    uint32_t iter = 0;
+    while (base < p_end) {  // uniform over each wave
+        // every eighth batch: stop when the count has been handed to the radix engine
+        // (the flag's load overlaps this batch), or hand it over when a quarter of the
+        // elements so far found no room (K far beyond the table)
+        const bool check = (++iter & 7) == 0;
+        const uint32_t handed = check ? g_load(&c->overflow) : 0u;
+        if (check) {
+            const uint64_t seen = 2 * (base - (uint64_t)bid * PP);
+            if (4ull * s_ndef > seen && seen > 2 * PP / 8) {
+                if (lane == 0) set_overflow(c, t.inplace, t.tmp_k, t.uniq, t.dense_cnt, t.dense_off);
+                break;
+            }
+        }
         uint64_t x[NE];
 #pragma unroll
         for (int e = 0; e < NE; ++e) x[e] = v[e];
@@ -407,6 +449,7 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
             }
         }
         base = next;
+        if (handed) break;
     }
     __syncthreads();
     flush_table(t, skeys, scnt);
@@ -416,25 +459,33 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
     // (the keys that found no room are few) and a longer probe; what still finds no
     // room goes to the global table.
     const uint32_t d = s_ndef;  // uniform: read after the barrier
-    if (d == 0) return;
-    if (4ull * d > 2 * PP) {
-        // a quarter of this workgroup's elements found no room: K is far beyond the
-        // table, and the radix engine sorts the column instead
-        if (threadIdx.x == 0) set_overflow(c, t.inplace, t.tmp_k, t.uniq);
-        return;
-    }
+    if (d == 0 || g_load(&c->overflow)) return;
     __syncthreads();  // (the workgroup reads back only its own region)
     for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
         skeys[i] = kEmpty;
         scnt[i] = 0;
     }
     __syncthreads();
+    if (threadIdx.x == 0) s_ndef = 0;  // now: elements that found no room in the second table either
+    __syncthreads();
     for (uint32_t i0 = 0; i0 < d; i0 += blockDim.x) {  // one element per thread: this pass is short
         const uint32_t i = i0 + threadIdx.x;
         const uint64_t x1[1] = {i < d ? region[i] : 0};
         if (count_batch<1>(skeys, scnt, s_sink, x1, i < d ? 1u : 0u) &&
-            !lds_insert(skeys, scnt, x1[0], 1u, kLdsProbeBuckets))
+            !lds_insert(skeys, scnt, x1[0], 1u, kLdsProbeBuckets)) {
+            atomicAdd(&s_ndef, 1u);
             global_insert(t, x1[0], 1);
+        }
+        // too many keys even for a second table: per-element global inserts would cost
+        // more than sorting, so the radix engine takes over (the count is read between
+        // two barriers, so every thread takes the same decision)
+        __syncthreads();
+        const bool stop = 64ull * s_ndef > 2 * PP;
+        __syncthreads();
+        if (stop) {
+            if (threadIdx.x == 0) set_overflow(c, t.inplace, t.tmp_k, t.uniq, t.dense_cnt, t.dense_off);
+            break;
+        }
     }
     __syncthreads();
     flush_table(t, skeys, scnt);

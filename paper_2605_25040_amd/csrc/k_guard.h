@@ -40,8 +40,20 @@ __device__ __forceinline__ bool guard_general(const Ctrl* c) {
     return c->guard_on && c->guard_general && c->path == P_MAIN;
 }
 
+// In general mode the contested keys are found from the input through a hash
+// index (key -> position in the dense keys, verified against them) kept in the
+// radix scratch, sized for all K keys; 0 when the scratch still holds the sorted
+// column (in place after the radix engine) or is too small: then binary search.
+__device__ __forceinline__ uint32_t guard_index_log2(const Args& a, const Ctrl* c) {
+    if (c->deferred_copy || c->first_known) return 0;
+    const uint32_t lg = log2_pow2(bit_ceil64(2 * c->K > 64 ? 2 * c->K : 64));
+    return (1ull << lg) <= 2 * (a.n + 2) ? lg : 0;  // the scratch holds 2 (n + 2) 32-bit words
+}
+
+__device__ __forceinline__ uint32_t* guard_index(const Args& a) { return reinterpret_cast<uint32_t*>(a.tmp_k); }
+
 __device__ __forceinline__ void guard_prep_body(const Args& a, uint32_t bid, uint32_t nblk) {
-    const Ctrl* c = a.c;
+    Ctrl* c = a.c;
     if (!guard_general(c)) return;
     const uint64_t M = c->table_M;
     const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
@@ -49,6 +61,12 @@ __device__ __forceinline__ void guard_prep_body(const Args& a, uint32_t bid, uin
     for (uint64_t i = gtid; i < M; i += gstride) {
         a.dcount[i] = 0;
         for (int r = 0; r < 4; ++r) a.bmin[r * a.m_ws + i] = kNoIndex;
+    }
+    const uint32_t lg = guard_index_log2(a, c);
+    if (gtid == 0) c->gidx_log2 = lg;
+    if (lg) {
+        CAFS_GLOBAL uint32_t* tab = gp(guard_index(a));
+        for (uint64_t i = gtid; i < (1ull << lg); i += gstride) tab[i] = kNoIndex;
     }
 }
 CAFS_KERNELS0(guard_prep, 256)
@@ -65,7 +83,7 @@ __device__ __forceinline__ void guard_bucket_body(const Args& a, uint32_t bid, u
 CAFS_KERNELS0(guard_bucket, 256)
 
 // Lists the contested keys (general mode) and resets their first-occurrence
-// minima.  The minima share memory with the run offsets, so this runs after emit.
+// minima, unless the radix engine's sort with positions already gave them.
 __device__ __forceinline__ void guard_mark_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!guard_active(c)) return;
@@ -82,10 +100,16 @@ __device__ __forceinline__ void guard_mark_body(const Args& a, uint32_t bid, uin
     if (c->guard_general) {
         const uint64_t K = c->K;
         const uint32_t lg = log2_pow2(c->table_M);
+        const uint32_t glg = c->gidx_log2;
+        uint32_t* tab = guard_index(a);
         for (uint64_t j = gtid; j < K; j += gstride)
             if (a.dcount[phi_hash(a.uniq[j], lg)] > kBucketCap) {
-                a.first_idx[j] = kNoIndex;
+                if (!c->first_known) a.first_idx[j] = kNoIndex;
                 a.clist[atomicAdd((unsigned long long*)&c->n_contested, 1ull)] = (uint32_t)j;
+                if (glg) {  // index the contested key: linear probing on 32-bit slots
+                    uint64_t h = phi_hash(a.uniq[j], glg);
+                    while (atomicCAS(&tab[h], kNoIndex, (uint32_t)j) != kNoIndex) h = (h + 1) & ((1ull << glg) - 1);
+                }
             }
     } else {
         const uint64_t nc = c->n_contested;
@@ -105,6 +129,18 @@ __device__ __forceinline__ uint64_t find_key(const uint64_t* uq, uint64_t K, uin
     return lo;
 }
 
+// Position of contested key v through the hash index (it is present).
+__device__ __forceinline__ uint64_t index_find(const Args& a, uint32_t glg, uint64_t v) {
+    const CAFS_GLOBAL uint32_t* tab = gp(guard_index(a));
+    const CAFS_GLOBAL uint64_t* uq = gp(a.uniq);
+    uint64_t h = phi_hash(v, glg);
+    while (true) {
+        const uint32_t j = tab[h];
+        if (j == kNoIndex || uq[j] == v) return j;  // kNoIndex is unreachable for a contested key
+        h = (h + 1) & ((1ull << glg) - 1);
+    }
+}
+
 // First occurrences of the contested keys.  Chunks of the input are claimed in
 // increasing order and every claimed chunk is finished, so the minima found so far
 // are exact for every key seen in a claimed chunk.  A workgroup stops claiming
@@ -113,10 +149,11 @@ __device__ __forceinline__ uint64_t find_key(const uint64_t* uq, uint64_t K, uin
 // so its first occurrence (left at the maximum) does not change the spill.  With at
 // most kGuardLdsKeys contested keys each workgroup keeps them in an LDS hash table
 // with per-key minima that it merges into the global minima after each chunk;
-// otherwise each element of a contested bucket is located by binary search.
+// otherwise each element of a contested bucket is located through the hash index
+// of the contested keys (binary search when there is none).
 __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
-    if (c->path != P_MAIN || !c->guard_on) return;
+    if (c->path != P_MAIN || !c->guard_on || c->first_known) return;
     const uint64_t nc = c->n_contested;
     if (nc == 0) return;
     const uint64_t n = a.n;
@@ -124,6 +161,7 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
     const uint64_t M = c->table_M;
     const uint32_t lg = log2_pow2(M);
     const uint64_t flip = a.flip;
+    const uint32_t glg = c->guard_general ? c->gidx_log2 : 0;
     const uint64_t chunks = (n + kGuardChunk - 1) / kGuardChunk;
     constexpr uint32_t TS = 2 * kGuardLdsKeys;  // LDS table slots
     __shared__ uint64_t tkey[TS];
@@ -186,7 +224,8 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
                     h = (h + 1) & (TS - 1);
                 }
             } else if (bits || a.dcount[b] > kBucketCap) {
-                const uint64_t jj = find_key(a.uniq, K, v, flip);
+                const uint64_t jj = glg ? index_find(a, glg, v) : find_key(a.uniq, K, v, flip);
+                if (jj >= K) continue;  // not reached: every key of a contested bucket is indexed
                 const uint32_t old = atomicMin(&a.first_idx[jj], (uint32_t)i);
                 if (old == kNoIndex && atomicAdd(&a.bfound[b], 1u) == kBucketCap - 1) ++newly;
             }
