@@ -300,12 +300,12 @@ __device__ __forceinline__ uint64_t pairs_per_block(uint64_t P, uint32_t nblk) {
 
 __device__ __forceinline__ void flush_table(const GTable& t, const uint64_t* skeys, const uint32_t* scnt) {
     constexpr uint32_t S = kLdsBuckets * kLdsBucketSlots;
+    // once the table has overflowed (the radix engine takes over) the flush is moot;
+    // one lane per wave looks, once (inserts check again as they go)
+    uint32_t ov = 0;
+    if (__lane_id() == 0) ov = g_load(&t.c->overflow);
+    if (__shfl(ov, 0, 64)) return;
     for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
-        // once the table has overflowed (the radix engine takes over) the flush is moot;
-        // one lane per wave looks
-        uint32_t ov = 0;
-        if (__lane_id() == 0) ov = g_load(&t.c->overflow);
-        if (__shfl(ov, 0, 64)) break;
         const uint32_t cn = scnt[i];  // slot i / kLdsBuckets of bucket i % kLdsBuckets; never 0 once claimed
         if (cn) global_insert(t, skeys[(i % kLdsBuckets) * kLdsBucketSlots + i / kLdsBuckets], cn);
     }
