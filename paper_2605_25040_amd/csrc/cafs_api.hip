@@ -163,7 +163,6 @@ uint32_t rank_grid(uint64_t n) {
 
 cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void* out, uint64_t n, cafs_dtype_t dt,
                      void* uniq, uint64_t* counts, cafs_report_t* report, void* ws) {
-    (void)ctx;
     cafs::Args a{};
     a.in = static_cast<const uint64_t*>(in);
     a.out = static_cast<uint64_t*>(out);
@@ -195,6 +194,7 @@ cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void*
     a.psum = at<uint64_t>(ws, L.psum);
     a.rank_blocks = rank_grid(n);
     a.rank_budget_log2 = cafs::kRankBudgetLog2;
+    a.row_blocks = ctx ? (uint32_t)ctx->cus : 256u;
     return a;
 }
 
@@ -270,7 +270,10 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     // four workgroups per CU saturate the write bandwidth and leave CU slots free
     // for the side stream
     const uint32_t g_emit = grid_for(n, 2 * cafs::kEmitTilePairs, cus * 4);
-    if (countable && !inplace) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 0u);
+    if (countable && !inplace) {
+        cafs::k_emit_rows<<<std::min<uint32_t>(g_emit, cus), cafs::kEmitRowsThreads, 0, s>>>(a);
+        cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 2u);
+    }
     mark(4);
     launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2, countable);
     if (countable && n > cafs::kRankMax) {
@@ -298,7 +301,10 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     }
     (void)hipEventRecord(ctx->join, s2);
     (void)hipStreamWaitEvent(s, ctx->join, 0);
-    if (countable && inplace) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 0u);
+    if (countable && inplace) {
+        cafs::k_emit_rows<<<std::min<uint32_t>(g_emit, cus), cafs::kEmitRowsThreads, 0, s>>>(a);
+        cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 2u);
+    }
     cafs::k_finalize<<<1, 64, 0, s>>>(a);
     mark(5);
     if (!evs.empty()) ctx->calls.push_back(evs);
@@ -550,6 +556,7 @@ cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uin
                             col.d_uniq, col.d_counts, col.d_report, col_ws[i]);
         args[i].rank_blocks = P.bp[i];  // the ranking kernel runs over the general block table
         args[i].rank_budget_log2 = cafs::kRankBudgetBatchLog2;
+        args[i].row_blocks = P.bp[i];
     }
     fill_table(reinterpret_cast<uint32_t*>(h + P.off_m1), n_cols, nullptr, n_cols);
     fill_table(reinterpret_cast<uint32_t*>(h + P.off_mp), n_cols, &P.bp, P.total_p);

@@ -172,6 +172,7 @@ struct Args {
     uint64_t m_ws;
     uint32_t rank_blocks;             // workgroups of this column's ranking kernel
     uint32_t rank_budget_log2;        // compares per ranking workgroup allowed
+    uint32_t row_blocks;              // workgroups of the row emit's sweep
     // run-length scratch
     uint64_t* rle_tile;               // per-tile run counts
     uint64_t* psum;                   // kMaxCountBlocks chunk sums of the pair scan

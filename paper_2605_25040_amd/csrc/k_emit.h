@@ -43,17 +43,16 @@ __device__ __forceinline__ void store_pair(uint64_t* __restrict__ y, uint64_t n,
 // `after_pair_sort` selects the instance: one runs on the caller's stream right
 // after the single-workgroup order kernel (or the tiny branch), the other on the
 // side stream after the pair sort; exactly one of them has work.
-__device__ __forceinline__ void emit_body(const Args& a, uint32_t after_pair_sort, uint32_t bid, uint32_t nblk) {
+// The tile loop works on caller-provided LDS: kEmitLdsRuns + 1 offsets, kEmitLdsRuns
+// keys and two words for the tile's run range.
+__device__ __forceinline__ void emit_tiles(const Args& a, uint32_t bid, uint32_t nblk, uint64_t* s_off,
+                                           uint64_t* s_key, uint64_t* s_j) {
     Ctrl* c = a.c;
-    if (after_pair_sort ? !(c->pair_sort && c->dense_ready && !c->overflow) : !c->emit_main) return;
     const uint64_t n = a.n;
     const uint64_t K = c->K;
     const uint32_t head = a.out_head;
     const uint64_t P = num_pairs(n, head);
     const uint64_t tiles = (P + kEmitTilePairs - 1) / kEmitTilePairs;
-    __shared__ uint64_t s_j0, s_j1;
-    __shared__ uint64_t s_off[kEmitLdsRuns + 1];
-    __shared__ uint64_t s_key[kEmitLdsRuns];
     const uint64_t* __restrict__ off = a.off;
     const uint64_t* __restrict__ uq = a.uniq;
     for (uint64_t t = bid; t < tiles; t += nblk) {
@@ -64,11 +63,11 @@ __device__ __forceinline__ void emit_body(const Args& a, uint32_t after_pair_sor
         const uint64_t e_hi = (2 * p1 - head < n) ? 2 * p1 - head : n;  // exclusive
         if (threadIdx.x == 0) {
             const uint64_t j0 = run_of(off, 0, K - 1, e_lo);
-            s_j0 = j0;
-            s_j1 = run_of(off, j0, K - 1, e_hi - 1);
+            s_j[0] = j0;
+            s_j[1] = run_of(off, j0, K - 1, e_hi - 1);
         }
         __syncthreads();
-        const uint64_t j0 = s_j0, j1 = s_j1;
+        const uint64_t j0 = s_j[0], j1 = s_j[1];
         if (j0 == j1) {
             const uint64_t v = uq[j0];
             for (uint64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) store_pair(a.out, n, head, p, v, v);
@@ -96,7 +95,172 @@ __device__ __forceinline__ void emit_body(const Args& a, uint32_t after_pair_sor
         __syncthreads();
     }
 }
-CAFS_KERNELS1(emit, kEmitThreads, uint32_t, after_pair_sort)
+// Whether the row emit (below) writes the main instance.
+__device__ __forceinline__ bool rows_take(const Args& a, const Ctrl* c);
+
+// `mode`: 0 main instance, 1 after the pair sort, 2 main instance unless the row
+// emit takes it (single-column launch sequence).
+__device__ __forceinline__ void emit_body(const Args& a, uint32_t mode, uint32_t bid, uint32_t nblk) {
+    Ctrl* c = a.c;
+    if (mode == 1 ? !(c->pair_sort && c->dense_ready && !c->overflow) : !c->emit_main) return;
+    if (mode == 2 && rows_take(a, c)) return;
+    __shared__ uint64_t s_j[2];
+    __shared__ uint64_t s_off[kEmitLdsRuns + 1];
+    __shared__ uint64_t s_key[kEmitLdsRuns];
+    emit_tiles(a, bid, nblk, s_off, s_key, s_j);
+}
+CAFS_KERNELS1(emit, kEmitThreads, uint32_t, mode)
+
+// Row emit, the main instance for K <= kEmitRowsMaxK and N < 2^32.  HBM takes
+// writes fastest when the whole grid advances through one contiguous region at a
+// time (measured on MI355X: about 6.4 TB/s for a grid-stride fill against 5.2-5.8
+// TB/s when each workgroup streams its own tiles or chunk).  So the grid sweeps
+// the output in rows of nblk * blockDim pairs, each workgroup writing blockDim
+// consecutive pairs of every row, kEmitRowsUnroll rows per step.  Each workgroup
+// stages the run offsets and keys in LDS with an index of the run holding every
+// 2^s-th position (at most kEmitIdxSlots entries); an element's run is that
+// entry's run, or a short binary search when a run boundary falls inside the span.
+constexpr uint32_t kEmitRowsMaxK = 2040;   // 40 KB of LDS with the index: four workgroups fit a CU
+constexpr uint32_t kEmitIdxSlots = 4096;
+constexpr uint32_t kEmitRowsThreads = 256;
+constexpr int kEmitRowsUnroll = 8;
+
+// Run of position e: largest j with soff[j] <= e, between the runs at the index
+// positions around e.
+__device__ __forceinline__ uint32_t run_in(const uint32_t* sidx, const uint32_t* soff, uint32_t s, uint32_t e) {
+    const uint32_t q = e >> s;
+    uint32_t lo = sidx[q], hi = sidx[q + 1];
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (soff[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool rows_take(const Args& a, const Ctrl* c) {
+    return c->K >= 1 && c->K <= kEmitRowsMaxK && a.n < (1ull << 32);
+}
+
+__device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint32_t nblk) {
+    Ctrl* c = a.c;
+    if (!c->emit_main) return;
+    const uint64_t n = a.n;
+    const uint64_t K64 = c->K;
+    __shared__ uint32_t soff[kEmitRowsMaxK + 1];
+    __shared__ uint64_t skey[kEmitRowsMaxK];
+    __shared__ uint32_t sidx[kEmitIdxSlots + 2];
+    __shared__ uint32_t swave[kEmitRowsThreads / 64];
+    if (!rows_take(a, c) || bid >= a.row_blocks) return;  // the sweep takes row_blocks workgroups
+    nblk = a.row_blocks < nblk ? a.row_blocks : nblk;
+    const uint32_t K = (uint32_t)K64;
+    const uint32_t nn = (uint32_t)n;
+    uint32_t s = 0;  // smallest shift with ceil(n / 2^s) <= kEmitIdxSlots
+    while ((((uint64_t)nn + (1ull << s) - 1) >> s) > kEmitIdxSlots) ++s;
+    const uint32_t qn = (uint32_t)(((uint64_t)nn + (1ull << s) - 1) >> s);  // index entries inside the column
+    const uint32_t tid = threadIdx.x;
+    // stage the runs; each run marks the first index entry it holds (runs hold
+    // disjoint entry ranges), and a running maximum over the entries fills in the
+    // rest: entry q gets the last run starting at or before position q * 2^s
+    for (uint32_t q = tid; q < kEmitIdxSlots + 2; q += blockDim.x) sidx[q] = 0;
+    __syncthreads();
+    const CAFS_GLOBAL uint64_t* off = gp(a.off);
+    const CAFS_GLOBAL uint64_t* uq = gp(a.uniq);
+    for (uint32_t j = tid; j < K; j += blockDim.x) {
+        const uint32_t o0 = (uint32_t)off[j];
+        const uint32_t o1 = j + 1 < K ? (uint32_t)off[j + 1] : nn;
+        soff[j] = o0;
+        skey[j] = uq[j];
+        const uint32_t q0 = (uint32_t)(((uint64_t)o0 + (1ull << s) - 1) >> s);
+        const uint32_t q1 = (uint32_t)(((uint64_t)o1 + (1ull << s) - 1) >> s);
+        if (q0 < q1) sidx[q0] = j;
+    }
+    if (tid == 0) soff[K] = nn;
+    __syncthreads();
+    // inclusive max-scan of sidx[0, qn): each thread a contiguous chunk
+    constexpr uint32_t kPer = kEmitIdxSlots / kEmitRowsThreads;
+    static_assert(kPer * kEmitRowsThreads == kEmitIdxSlots, "index chunks");
+    uint32_t loc = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t v = sidx[tid * kPer + k];
+        loc = v > loc ? v : loc;
+    }
+    uint32_t inc = loc;  // inclusive max over the wave's threads up to this one
+    const uint32_t lane = __lane_id();
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc = o > inc ? o : inc;
+    }
+    if (lane == 63) swave[tid / 64] = inc;
+    __syncthreads();
+    uint32_t run = __shfl_up(inc, 1, 64);  // max over the earlier threads of the wave
+    if (lane == 0) run = 0;
+    for (uint32_t w = 0; w < tid / 64; ++w) run = swave[w] > run ? swave[w] : run;
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t q = tid * kPer + k;
+        const uint32_t v = sidx[q];
+        run = v > run ? v : run;
+        sidx[q] = q < qn ? run : K - 1;  // entries past the column point at the last run
+    }
+    if (tid == 0) { sidx[kEmitIdxSlots] = K - 1; sidx[kEmitIdxSlots + 1] = K - 1; }
+    __syncthreads();
+
+    const uint32_t head = a.out_head;
+    const uint64_t P = num_pairs(n, head);
+    const uint64_t row = (uint64_t)nblk * blockDim.x;
+    constexpr int U = kEmitRowsUnroll;
+    // U rows per step.  Fast case: the index span of the element holds at most one
+    // run boundary (hi <= lo + 1), so the pair's keys follow from that boundary's
+    // offset and the keys of runs lo and lo + 1: two LDS round trips for all U rows,
+    // no loop.  Spans with more boundaries take a binary search.
+    for (uint64_t p = (uint64_t)bid * blockDim.x + tid; p < P; p += U * row) {
+        int64_t e0s[U];
+        uint32_t e0[U], lo[U], hi[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t pu = p + u * row;
+            e0s[u] = (int64_t)(2 * pu) - (int64_t)head;
+            e0[u] = (pu < P && e0s[u] > 0) ? (uint32_t)e0s[u] : 0u;
+            const uint32_t q = e0[u] >> s;
+            lo[u] = sidx[q];
+            hi[u] = sidx[q + 1];
+        }
+        uint32_t nb[U];
+        uint64_t k0[U], k1[U];
+        bool slow = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            nb[u] = soff[lo[u] + 1];
+            k0[u] = skey[lo[u]];
+            k1[u] = skey[lo[u] + 1 < K ? lo[u] + 1 : lo[u]];
+            slow |= hi[u] > lo[u] + 1;
+        }
+        if (slow) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (hi[u] <= lo[u] + 1) continue;
+                uint32_t l = lo[u], h = hi[u];
+                while (l < h) {
+                    const uint32_t mid = (l + h + 1) >> 1;
+                    if (soff[mid] <= e0[u]) l = mid; else h = mid - 1;
+                }
+                // as in the fast case, from the run holding the first element
+                nb[u] = soff[l + 1];
+                k0[u] = skey[l];
+                k1[u] = skey[l + 1 < K ? l + 1 : l];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t v0 = (int64_t)e0[u] >= (int64_t)nb[u] ? k1[u] : k0[u];
+            const uint64_t v1 = e0s[u] + 1 >= (int64_t)nb[u] ? k1[u] : k0[u];
+            if (p + u * row < P) store_pair(a.out, n, head, p + u * row, v0, v1);
+        }
+    }
+}
+CAFS_KERNELS0(emit_rows, kEmitRowsThreads)
 
 // Monotone input: the output is the input.
 __device__ __forceinline__ void copy_mono_body(const Args& a, uint32_t bid, uint32_t nblk) {
