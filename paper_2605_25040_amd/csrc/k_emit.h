@@ -80,7 +80,8 @@ __device__ __forceinline__ void emit_tiles(const Args& a, uint32_t bid, uint32_t
                 const int64_t e0s = (int64_t)(2 * p) - (int64_t)head;
                 const uint64_t e0 = e0s < 0 ? 0 : (uint64_t)e0s;
                 const uint64_t r0 = run_of(s_off, 0, R - 1, e0);
-                const uint64_t r1 = (r0 + 1 < R && s_off[r0 + 1] <= e0 + 1) ? r0 + 1 : r0;
+                // the second element (e0s + 1, not e0 + 1 when the pair starts before the column)
+                const uint64_t r1 = (r0 + 1 < R && (int64_t)s_off[r0 + 1] <= e0s + 1) ? r0 + 1 : r0;
                 store_pair(a.out, n, head, p, s_key[r0], s_key[r1]);
             }
         } else {
@@ -88,7 +89,7 @@ __device__ __forceinline__ void emit_tiles(const Args& a, uint32_t bid, uint32_t
                 const int64_t e0s = (int64_t)(2 * p) - (int64_t)head;
                 const uint64_t e0 = e0s < 0 ? 0 : (uint64_t)e0s;
                 const uint64_t r0 = run_of(off, j0, j1, e0);
-                const uint64_t r1 = (r0 + 1 <= j1 && off[r0 + 1] <= e0 + 1) ? r0 + 1 : r0;
+                const uint64_t r1 = (r0 + 1 <= j1 && (int64_t)off[r0 + 1] <= e0s + 1) ? r0 + 1 : r0;
                 store_pair(a.out, n, head, p, uq[r0], uq[r1]);
             }
         }
@@ -111,17 +112,24 @@ __device__ __forceinline__ void emit_body(const Args& a, uint32_t mode, uint32_t
 }
 CAFS_KERNELS1(emit, kEmitThreads, uint32_t, mode)
 
-// Row emit, the main instance for K <= kEmitRowsMaxK and N < 2^32.  HBM takes
-// writes fastest when the whole grid advances through one contiguous region at a
-// time (measured on MI355X: about 6.4 TB/s for a grid-stride fill against 5.2-5.8
-// TB/s when each workgroup streams its own tiles or chunk).  So the grid sweeps
-// the output in rows of nblk * blockDim pairs, each workgroup writing blockDim
-// consecutive pairs of every row, kEmitRowsUnroll rows per step.  Each workgroup
-// stages the run offsets and keys in LDS with an index of the run holding every
-// 2^s-th position (at most kEmitIdxSlots entries); an element's run is that
-// entry's run, or a short binary search when a run boundary falls inside the span.
+// Row emit, the main instance for K <= kRankMax and N < 2^32.  HBM takes writes
+// fastest when few regions are written at a time (measured on MI355X: about 6.3
+// TB/s when 256 workgroups sweep the output in rows, whether as one sweep or as up
+// to 32 sweeps over separate segments, against 5.2-5.8 TB/s when each workgroup
+// streams its own tiles or chunk).  So the grid is split into S segments, S the
+// smallest power of two giving about kEmitSegRuns runs per segment (at most
+// kEmitMaxSegs), and each segment's workgroups sweep it in rows of
+// (workgroups * blockDim) pairs, each writing blockDim consecutive pairs of every
+// row, kEmitRowsUnroll rows per step.  A workgroup stages the runs overlapping its
+// segment in LDS (offsets relative to the segment start) with an index of the run
+// holding every 2^s-th position of the segment (at most kEmitIdxSlots entries); an
+// element's run is that entry's run, or a short binary search when a run boundary
+// falls inside the span.  A segment with more than kEmitRowsMaxK runs (a very
+// uneven column) searches the global offsets instead.
 constexpr uint32_t kEmitRowsMaxK = 2040;   // 40 KB of LDS with the index: four workgroups fit a CU
 constexpr uint32_t kEmitIdxSlots = 4096;
+constexpr uint32_t kEmitSegRuns = 1536;
+constexpr uint32_t kEmitMaxSegs = 32;
 constexpr uint32_t kEmitRowsThreads = 256;
 constexpr int kEmitRowsUnroll = 8;
 
@@ -138,7 +146,7 @@ __device__ __forceinline__ uint32_t run_in(const uint32_t* sidx, const uint32_t*
 }
 
 __device__ __forceinline__ bool rows_take(const Args& a, const Ctrl* c) {
-    return c->K >= 1 && c->K <= kEmitRowsMaxK && a.n < (1ull << 32);
+    return c->K >= 1 && c->K <= kRankMax && a.n < (1ull << 32);
 }
 
 __device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint32_t nblk) {
@@ -150,31 +158,69 @@ __device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint
     __shared__ uint64_t skey[kEmitRowsMaxK];
     __shared__ uint32_t sidx[kEmitIdxSlots + 2];
     __shared__ uint32_t swave[kEmitRowsThreads / 64];
+    __shared__ uint64_t s_rng[2];
     if (!rows_take(a, c) || bid >= a.row_blocks) return;  // the sweep takes row_blocks workgroups
     nblk = a.row_blocks < nblk ? a.row_blocks : nblk;
     const uint32_t K = (uint32_t)K64;
-    const uint32_t nn = (uint32_t)n;
-    uint32_t s = 0;  // smallest shift with ceil(n / 2^s) <= kEmitIdxSlots
-    while ((((uint64_t)nn + (1ull << s) - 1) >> s) > kEmitIdxSlots) ++s;
-    const uint32_t qn = (uint32_t)(((uint64_t)nn + (1ull << s) - 1) >> s);  // index entries inside the column
+    uint32_t S = 1;
+    while (S < kEmitMaxSegs && 2 * S <= nblk && K > S * kEmitSegRuns) S *= 2;
+    const uint32_t gper = nblk / S;  // workgroups per segment
+    const uint32_t seg = bid / gper, w = bid % gper;
+    if (seg >= S) return;
+    const uint32_t head = a.out_head;
+    const uint64_t P = num_pairs(n, head);
+    const uint64_t per = (P + S - 1) / S;
+    const uint64_t sp0 = (uint64_t)seg * per;
+    const uint64_t sp1 = sp0 + per < P ? sp0 + per : P;
+    if (sp0 >= sp1) return;
+    // the segment's elements [e_first, e_last] and the runs holding them
+    const int64_t ef_s = (int64_t)(2 * sp0) - (int64_t)head;
+    const uint64_t e_first = ef_s < 0 ? 0 : (uint64_t)ef_s;
+    const uint64_t el_s = 2 * sp1 - 1 - head;
+    const uint64_t e_last = el_s < n - 1 ? el_s : n - 1;
     const uint32_t tid = threadIdx.x;
+    if (tid == 0) {
+        const uint64_t jl = run_of(a.off, 0, K - 1, e_first);
+        s_rng[0] = jl;
+        s_rng[1] = run_of(a.off, jl, K - 1, e_last);
+    }
+    __syncthreads();
+    const uint32_t j_lo = (uint32_t)s_rng[0], j_hi = (uint32_t)s_rng[1];
+    const uint32_t Ks = j_hi - j_lo + 1;
+    const uint64_t row = (uint64_t)gper * blockDim.x;
+    const CAFS_GLOBAL uint64_t* off = gp(a.off);
+    const CAFS_GLOBAL uint64_t* uq = gp(a.uniq);
+    if (Ks > kEmitRowsMaxK) {
+        // too many runs to stage: each pair searches the global offsets
+        for (uint64_t p = sp0 + (uint64_t)w * blockDim.x + tid; p < sp1; p += row) {
+            const int64_t e0s = (int64_t)(2 * p) - (int64_t)head;
+            const uint64_t e0 = e0s < 0 ? 0 : (uint64_t)e0s;
+            const uint64_t r0 = run_of(a.off, j_lo, j_hi, e0);
+            const uint64_t r1 = (r0 + 1 <= j_hi && (int64_t)off[r0 + 1] <= e0s + 1) ? r0 + 1 : r0;
+            store_pair(a.out, n, head, p, uq[r0], uq[r1]);
+        }
+        return;
+    }
+    const uint32_t len = (uint32_t)(e_last - e_first + 1);  // positions below are relative to e_first
+    uint32_t s = 0;  // smallest shift with ceil(len / 2^s) <= kEmitIdxSlots
+    while ((((uint64_t)len + (1ull << s) - 1) >> s) > kEmitIdxSlots) ++s;
+    const uint32_t qn = (uint32_t)(((uint64_t)len + (1ull << s) - 1) >> s);  // index entries inside the segment
     // stage the runs; each run marks the first index entry it holds (runs hold
     // disjoint entry ranges), and a running maximum over the entries fills in the
     // rest: entry q gets the last run starting at or before position q * 2^s
     for (uint32_t q = tid; q < kEmitIdxSlots + 2; q += blockDim.x) sidx[q] = 0;
     __syncthreads();
-    const CAFS_GLOBAL uint64_t* off = gp(a.off);
-    const CAFS_GLOBAL uint64_t* uq = gp(a.uniq);
-    for (uint32_t j = tid; j < K; j += blockDim.x) {
-        const uint32_t o0 = (uint32_t)off[j];
-        const uint32_t o1 = j + 1 < K ? (uint32_t)off[j + 1] : nn;
-        soff[j] = o0;
-        skey[j] = uq[j];
+    for (uint32_t r = tid; r < Ks; r += blockDim.x) {
+        const uint64_t g0 = off[j_lo + r];
+        const uint32_t o0 = g0 > e_first ? (uint32_t)(g0 - e_first) : 0u;
+        const uint32_t o1 = r + 1 < Ks ? (uint32_t)(off[j_lo + r + 1] - e_first) : len;
+        soff[r] = o0;
+        skey[r] = uq[j_lo + r];
         const uint32_t q0 = (uint32_t)(((uint64_t)o0 + (1ull << s) - 1) >> s);
         const uint32_t q1 = (uint32_t)(((uint64_t)o1 + (1ull << s) - 1) >> s);
-        if (q0 < q1) sidx[q0] = j;
+        if (q0 < q1) sidx[q0] = r;
     }
-    if (tid == 0) soff[K] = nn;
+    if (tid == 0) soff[Ks] = len;
     __syncthreads();
     // inclusive max-scan of sidx[0, qn): each thread a contiguous chunk
     constexpr uint32_t kPer = kEmitIdxSlots / kEmitRowsThreads;
@@ -196,33 +242,30 @@ __device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint
     __syncthreads();
     uint32_t run = __shfl_up(inc, 1, 64);  // max over the earlier threads of the wave
     if (lane == 0) run = 0;
-    for (uint32_t w = 0; w < tid / 64; ++w) run = swave[w] > run ? swave[w] : run;
+    for (uint32_t v = 0; v < tid / 64; ++v) run = swave[v] > run ? swave[v] : run;
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
         const uint32_t q = tid * kPer + k;
         const uint32_t v = sidx[q];
         run = v > run ? v : run;
-        sidx[q] = q < qn ? run : K - 1;  // entries past the column point at the last run
+        sidx[q] = q < qn ? run : Ks - 1;  // entries past the segment point at its last run
     }
-    if (tid == 0) { sidx[kEmitIdxSlots] = K - 1; sidx[kEmitIdxSlots + 1] = K - 1; }
+    if (tid == 0) { sidx[kEmitIdxSlots] = Ks - 1; sidx[kEmitIdxSlots + 1] = Ks - 1; }
     __syncthreads();
 
-    const uint32_t head = a.out_head;
-    const uint64_t P = num_pairs(n, head);
-    const uint64_t row = (uint64_t)nblk * blockDim.x;
     constexpr int U = kEmitRowsUnroll;
     // U rows per step.  Fast case: the index span of the element holds at most one
     // run boundary (hi <= lo + 1), so the pair's keys follow from that boundary's
     // offset and the keys of runs lo and lo + 1: two LDS round trips for all U rows,
     // no loop.  Spans with more boundaries take a binary search.
-    for (uint64_t p = (uint64_t)bid * blockDim.x + tid; p < P; p += U * row) {
-        int64_t e0s[U];
+    for (uint64_t p = sp0 + (uint64_t)w * blockDim.x + tid; p < sp1; p += U * row) {
+        int64_t e0s[U];  // first element of the pair, relative to e_first (-1: before the column)
         uint32_t e0[U], lo[U], hi[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t pu = p + u * row;
-            e0s[u] = (int64_t)(2 * pu) - (int64_t)head;
-            e0[u] = (pu < P && e0s[u] > 0) ? (uint32_t)e0s[u] : 0u;
+            e0s[u] = (int64_t)(2 * pu) - (int64_t)head - (int64_t)e_first;
+            e0[u] = (pu < sp1 && e0s[u] > 0) ? (uint32_t)e0s[u] : 0u;
             const uint32_t q = e0[u] >> s;
             lo[u] = sidx[q];
             hi[u] = sidx[q + 1];
@@ -234,7 +277,7 @@ __device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint
         for (int u = 0; u < U; ++u) {
             nb[u] = soff[lo[u] + 1];
             k0[u] = skey[lo[u]];
-            k1[u] = skey[lo[u] + 1 < K ? lo[u] + 1 : lo[u]];
+            k1[u] = skey[lo[u] + 1 < Ks ? lo[u] + 1 : lo[u]];
             slow |= hi[u] > lo[u] + 1;
         }
         if (slow) {
@@ -249,14 +292,14 @@ __device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint
                 // as in the fast case, from the run holding the first element
                 nb[u] = soff[l + 1];
                 k0[u] = skey[l];
-                k1[u] = skey[l + 1 < K ? l + 1 : l];
+                k1[u] = skey[l + 1 < Ks ? l + 1 : l];
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t v0 = (int64_t)e0[u] >= (int64_t)nb[u] ? k1[u] : k0[u];
             const uint64_t v1 = e0s[u] + 1 >= (int64_t)nb[u] ? k1[u] : k0[u];
-            if (p + u * row < P) store_pair(a.out, n, head, p + u * row, v0, v1);
+            if (p + u * row < sp1) store_pair(a.out, n, head, p + u * row, v0, v1);
         }
     }
 }

@@ -210,3 +210,41 @@ def test_order_boundaries(ctx, k, with_marker):
     for unsigned in (False, True):
         r = check(ctx, x, unsigned, label="order k=%d marker=%s" % (k, with_marker))
         assert r["k_exact"] == k
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,k", [(300_001, 1000), (300_001, 5000), (400_001, 40_000)])
+def test_head_pair_single_first_run(ctx, n, k):
+    """Output 8 bytes off 16-byte alignment, so that the first output pair holds only
+    element 0, and the smallest key occurring exactly once (a first run of length
+    one): row emit (K <= 32768) and the pair-sort emit (K above it)."""
+    rng = np.random.default_rng(n + k)
+    pal = np.unique(rng.integers(1, 2**62, size=k + 64, dtype=np.int64))[:k]
+    rest = pal[1:][rng.integers(0, k - 1, size=n - 1)]
+    rest[: k - 1] = pal[1:]  # every key present
+    x = np.concatenate([pal[:1], rest])
+    rng.shuffle(x)
+    for shift_out in (1, 0):
+        r = check(ctx, x.view(np.uint64), False, label="head n=%d k=%d shift=%d" % (n, k, shift_out),
+                  shift_out=shift_out)
+        assert r["k_exact"] == k and r["path"] == "MAIN"
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [1_000_000, 1_000_001])
+def test_emit_crowded_segment(ctx, n):
+    """One key holds 90% of the column and sorts first; 29999 keys share the rest, so
+    the last segments of the row emit hold thousands of runs each (more than one
+    workgroup stages) and search the global run offsets."""
+    rng = np.random.default_rng(n)
+    k = 30_000
+    pal = np.unique(rng.integers(1, 2**62, size=k + 64, dtype=np.int64))[:k - 1]
+    m = n // 10
+    rest = pal[rng.integers(0, k - 1, size=m)]
+    rest[: k - 1] = pal
+    x = np.concatenate([np.full(n - m, -7, dtype=np.int64), rest])
+    rng.shuffle(x)
+    for shift_out in (0, 1):
+        r = check(ctx, x.view(np.uint64), False, label="crowded n=%d shift=%d" % (n, shift_out),
+                  shift_out=shift_out)
+        assert r["k_exact"] == k and r["path"] == "MAIN" and r["engine"] == "HASH"
