@@ -35,6 +35,7 @@ constexpr uint32_t kMaxCountBlocks = 1024;     // workgroups of one hash count
 constexpr uint32_t kGlobalProbe = 64;          // global probe limit before overflow (the table is sized for 1/8 load)
 constexpr uint32_t kMinTableLog2 = 12;         // smallest global table (4096 slots)
 constexpr uint32_t kMaxTableLog2 = 22;         // largest global table (4M slots, 64 MiB)
+constexpr uint32_t kTableFloorLog2 = 16;       // global table never smaller (64K slots) when the workspace allows
 constexpr uint32_t kRankMax = 32768;           // K ordered by ranking (larger K: pair radix sort)
 constexpr uint32_t kRankKeysPerBlock = 64;     // keys ranked by one workgroup (16 threads each)
 constexpr uint32_t kRankTile = 8192;           // keys staged in LDS at a time while ranking

@@ -116,20 +116,20 @@ CAFS_KERNELS1(emit, kEmitThreads, uint32_t, mode)
 // fastest when few regions are written at a time (measured on MI355X: about 6.3
 // TB/s when 256 workgroups sweep the output in rows, whether as one sweep or as up
 // to 32 sweeps over separate segments, against 5.2-5.8 TB/s when each workgroup
-// streams its own tiles or chunk).  So the grid is split into S segments, S the
-// smallest power of two giving about kEmitSegRuns runs per segment (at most
-// kEmitMaxSegs), and each segment's workgroups sweep it in rows of
-// (workgroups * blockDim) pairs, each writing blockDim consecutive pairs of every
-// row, kEmitRowsUnroll rows per step.  A workgroup stages the runs overlapping its
-// segment in LDS (offsets relative to the segment start) with an index of the run
-// holding every 2^s-th position of the segment (at most kEmitIdxSlots entries); an
-// element's run is that entry's run, or a short binary search when a run boundary
-// falls inside the span.  A segment with more than kEmitRowsMaxK runs (a very
-// uneven column) searches the global offsets instead.
-constexpr uint32_t kEmitRowsMaxK = 2040;   // 40 KB of LDS with the index: four workgroups fit a CU
+// streams its own tiles or chunk).  The output is cut into segments of about
+// kEmitSegRuns runs each (segment i starts at the 1 KB-aligned pair at or before
+// the first element of run i * kEmitSegRuns); each segment gets workgroups in
+// proportion to its pairs, and they sweep it in rows of (workgroups * blockDim)
+// pairs, each writing blockDim consecutive pairs of every row, kEmitRowsUnroll
+// rows per step.  A workgroup stages its segment's runs in LDS (offsets relative
+// to the segment start) with an index of the run holding every 2^s-th position of
+// the segment (at most kEmitIdxSlots entries); an element's run is that entry's
+// run, or a short binary search when run boundaries fall inside the span.
+constexpr uint32_t kEmitRowsMaxK = 2040;   // runs one workgroup stages (about 40 KB of LDS with the index)
 constexpr uint32_t kEmitIdxSlots = 4096;
-constexpr uint32_t kEmitSegRuns = 1536;
-constexpr uint32_t kEmitMaxSegs = 32;
+constexpr uint32_t kEmitAlignPairs = 64;  // segment starts: multiples of 1 KB of output
+constexpr uint32_t kEmitSegRuns = kEmitRowsMaxK - 2 * kEmitAlignPairs;  // runs starting in a segment
+constexpr uint32_t kEmitMaxSegs = (kRankMax + kEmitSegRuns - 1) / kEmitSegRuns;  // segments for K <= kRankMax
 constexpr uint32_t kEmitRowsThreads = 256;
 constexpr int kEmitRowsUnroll = 8;
 
@@ -159,39 +159,80 @@ __device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint
     __shared__ uint32_t sidx[kEmitIdxSlots + 2];
     __shared__ uint32_t swave[kEmitRowsThreads / 64];
     __shared__ uint64_t s_rng[2];
+    __shared__ uint64_t s_pb[kEmitMaxSegs + 1];  // first pair of each segment, and P
+    __shared__ uint32_t s_seg[3];
     if (!rows_take(a, c) || bid >= a.row_blocks) return;  // the sweep takes row_blocks workgroups
     nblk = a.row_blocks < nblk ? a.row_blocks : nblk;
     const uint32_t K = (uint32_t)K64;
-    uint32_t S = 1;
-    while (S < kEmitMaxSegs && 2 * S <= nblk && K > S * kEmitSegRuns) S *= 2;
-    const uint32_t gper = nblk / S;  // workgroups per segment
-    const uint32_t seg = bid / gper, w = bid % gper;
-    if (seg >= S) return;
     const uint32_t head = a.out_head;
     const uint64_t P = num_pairs(n, head);
-    const uint64_t per = (P + S - 1) / S;
-    const uint64_t sp0 = (uint64_t)seg * per;
-    const uint64_t sp1 = sp0 + per < P ? sp0 + per : P;
+    const uint32_t tid = threadIdx.x;
+    const CAFS_GLOBAL uint64_t* off = gp(a.off);
+    const CAFS_GLOBAL uint64_t* uq = gp(a.uniq);
+    // segments by run count: segment i starts at the pair holding the first element
+    // of run i * R, so it holds runs i * R - 1 .. (i + 1) * R - 1 at most
+    // (rounded down to a multiple of kEmitAlignPairs pairs, so that the stores stay
+    // aligned to whole cache lines; the rounding adds at most 2 * kEmitAlignPairs - 1
+    // elements, so at most that many runs, in front)
+    constexpr uint32_t R = kEmitSegRuns;
+    uint32_t S = (K + R - 1) / R;
+    if (S > nblk) S = 1;  // (tiny grids) one segment, searched in global memory below
+    if (tid < S)
+        s_pb[tid + 1] = tid + 1 == S ? P : (off[(tid + 1) * R] + head) / 2 / kEmitAlignPairs * kEmitAlignPairs;
+    if (tid == 0) s_pb[0] = 0;
+    __syncthreads();
+    if (tid == 0) {
+        // workgroups per segment in proportion to its pairs, at least one each
+        uint32_t acc = 0;
+        s_seg[0] = S;  // none
+        for (uint32_t i = 0; i < S; ++i) {
+            const uint64_t pairs = s_pb[i + 1] - s_pb[i];
+            const uint32_t g = 1 + (uint32_t)((uint64_t)(nblk - S) * pairs / P);
+            if (bid < acc + g) {
+                s_seg[0] = i;
+                s_seg[1] = bid - acc;
+                s_seg[2] = g;
+                break;
+            }
+            acc += g;
+        }
+    }
+    __syncthreads();
+    const uint32_t seg = s_seg[0];
+    if (seg >= S) return;
+    const uint32_t w = s_seg[1], gper = s_seg[2];
+    const uint64_t sp0 = s_pb[seg], sp1 = s_pb[seg + 1];
     if (sp0 >= sp1) return;
     // the segment's elements [e_first, e_last] and the runs holding them
     const int64_t ef_s = (int64_t)(2 * sp0) - (int64_t)head;
     const uint64_t e_first = ef_s < 0 ? 0 : (uint64_t)ef_s;
     const uint64_t el_s = 2 * sp1 - 1 - head;
     const uint64_t e_last = el_s < n - 1 ? el_s : n - 1;
-    const uint32_t tid = threadIdx.x;
     if (tid == 0) {
-        const uint64_t jl = run_of(a.off, 0, K - 1, e_first);
-        s_rng[0] = jl;
-        s_rng[1] = run_of(a.off, jl, K - 1, e_last);
+        if (S == 1) {  // the whole column
+            s_rng[0] = 0;
+            s_rng[1] = K - 1;
+        } else {
+            // the segment starts at most 2 * kEmitAlignPairs - 1 elements before run
+            // i * R, so its first run is at most that many runs before; it ends at most
+            // 2 * kEmitAlignPairs elements before run (i + 1) * R, so its last run is at
+            // most that many runs before that one
+            constexpr uint32_t back = 2 * kEmitAlignPairs - 1;
+            const uint32_t a1 = seg * R, a0 = a1 > back ? a1 - back : 0u;
+            const uint32_t b1 = seg + 1 == S ? K - 1 : (seg + 1) * R - 1;
+            const uint64_t jl = run_of(a.off, a0, a1, e_first);
+            const uint64_t b0 = b1 >= back + jl ? b1 - back : jl;
+            s_rng[0] = jl;
+            s_rng[1] = run_of(a.off, b0, b1, e_last);
+        }
     }
     __syncthreads();
     const uint32_t j_lo = (uint32_t)s_rng[0], j_hi = (uint32_t)s_rng[1];
     const uint32_t Ks = j_hi - j_lo + 1;
     const uint64_t row = (uint64_t)gper * blockDim.x;
-    const CAFS_GLOBAL uint64_t* off = gp(a.off);
-    const CAFS_GLOBAL uint64_t* uq = gp(a.uniq);
     if (Ks > kEmitRowsMaxK) {
-        // too many runs to stage: each pair searches the global offsets
+        // too many runs to stage (one segment on a tiny grid): each pair searches the
+        // global offsets
         for (uint64_t p = sp0 + (uint64_t)w * blockDim.x + tid; p < sp1; p += row) {
             const int64_t e0s = (int64_t)(2 * p) - (int64_t)head;
             const uint64_t e0 = e0s < 0 ? 0 : (uint64_t)e0s;

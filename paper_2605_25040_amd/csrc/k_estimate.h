@@ -142,6 +142,11 @@ __device__ void plan_block(const Args& a) {
             engine = E_RADIX;  // the table the estimate asks for does not fit: sort instead
             lg = a.cap_ws_log2;
         }
+        // an estimate far below K (heavy tails) would overflow a table sized by it;
+        // up to kTableFloorLog2 the space is cheap and the count's LDS tables hold
+        // that many keys anyway
+        const uint32_t floor_lg = kTableFloorLog2 < a.cap_ws_log2 ? kTableFloorLog2 : a.cap_ws_log2;
+        if (lg < floor_lg) lg = floor_lg;
         c->cap_log2 = lg;
     }
     const uint64_t cap = 1ull << c->cap_log2;
