@@ -29,7 +29,7 @@ WORKLOADS = {
 }
 # algorithmic bytes per key of each single-kernel stage
 STAGE_BYTES_PER_KEY = {"count": 8.0, "emit": 8.0}
-STAGE_KERNEL = {"count": "k_hash_count", "emit": "k_emit"}
+STAGE_KERNEL = {"count": "k_hash_count", "emit": "k_emit_rows"}
 KERNEL_SOURCES = ["paper_2605_25040_amd/csrc/cafs_dev.h", "paper_2605_25040_amd/csrc/k_count.h",
                   "paper_2605_25040_amd/csrc/k_emit.h", "paper_2605_25040_amd/csrc/cafs_api.hip"]
 
