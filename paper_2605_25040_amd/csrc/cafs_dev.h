@@ -27,8 +27,8 @@ constexpr uint64_t kEmpty = ~0ull;             // empty-slot marker of the GPU h
                                                // keys equal to it are counted apart
 constexpr uint32_t kMonoPrefix = 1u << 13;     // elements the pre kernel checks for order
 constexpr int kCountThreads = 1024;            // hash-count workgroup
-constexpr uint32_t kLdsBuckets = 3392;         // per-workgroup LDS table: 3392 buckets of 4 keys
-constexpr uint32_t kLdsBucketSlots = 4;        // (13568 slots, 159 KiB with 32-bit counts)
+constexpr uint32_t kLdsSlots = 13568;          // per-workgroup LDS table (159 KiB with 32-bit counts)
+constexpr uint64_t kLdsWideMinKhat = 1800;     // buckets of 4 keys from this estimate up, of 2 below
 constexpr uint32_t kLdsWindow = 2;             // buckets probed before an element is deferred
 constexpr uint32_t kLdsProbeBuckets = 8;       // buckets probed in the deferred pass before the global table
 constexpr uint32_t kMaxCountBlocks = 1024;     // workgroups of one hash count

@@ -197,11 +197,15 @@ __device__ __forceinline__ void global_insert(const GTable& t, uint64_t v, uint6
 // ---------------------------------------------------------------------------
 // Hash count (main path, Sec. 4.4).  The paper's hot loop updates a bucket of four
 // 64-bit keys on one cache line (Sec. 4.2, Alg. 1).  Here each workgroup owns a
-// table of 3392 such buckets in LDS (13568 keys with 32-bit counters).  An element
-// hashes to a bucket (Eq. hash, reduced to 3392 by a multiply), reads its four keys
-// with two 16-byte LDS loads and compares them with the element, the GPU analogue
-// of the paper's cmpeq + movemask + tzcnt; on a match it adds 1 to that slot's
-// counter with an LDS atomic.  Within a bucket occupied slots form a prefix and a
+// table of kLdsSlots keys with 32-bit counters in LDS, cut into buckets of W keys:
+// W = 4 (3392 buckets, like the paper's) when the estimate is large, W = 2 (6784
+// buckets) below kLdsWideMinKhat, where a bucket rarely overflows and a lookup
+// then takes one 16-byte LDS load instead of two (LDS load instructions are what
+// the loop pays for; measured crossover near K = 1800 at N = 2^28).  An element hashes to a bucket (Eq. hash, reduced to the
+// bucket count by a multiply), reads its W keys with 16-byte LDS loads and
+// compares them with the element, the GPU analogue of the paper's cmpeq +
+// movemask + tzcnt; on a match it adds 1 to that slot's counter with an LDS
+// atomic.  Within a bucket occupied slots form a prefix and a
 // key is stored in the first bucket, in probe order, that had room for it, so a
 // lookup can stop at the first bucket with a free slot.  Lookups cover the home
 // bucket and, when that one is full, the next one (the window), as straight-line
@@ -218,20 +222,31 @@ __device__ __forceinline__ void global_insert(const GTable& t, uint64_t v, uint6
 // column is tiny and the dense arrays are written here; otherwise the element set
 // has an unsampled value and the main path runs with the same estimate (Sec. 4.4).
 // ---------------------------------------------------------------------------
+template <uint32_t W>
+struct LdsGeo {
+    static constexpr uint32_t kBuckets = kLdsSlots / W;
+    static_assert(kBuckets * W == kLdsSlots, "whole buckets");
+};
+
+template <uint32_t W>
 __device__ __forceinline__ uint32_t lds_bucket(uint64_t x) {
-    return (uint32_t)(((uint64_t)phi_hash32(x, 32) * kLdsBuckets) >> 32);
+    return (uint32_t)(((uint64_t)phi_hash32(x, 32) * LdsGeo<W>::kBuckets) >> 32);
 }
 
-__device__ __forceinline__ uint32_t next_bucket(uint32_t b) { return (b + 1 == kLdsBuckets) ? 0 : b + 1; }
+template <uint32_t W>
+__device__ __forceinline__ uint32_t next_bucket(uint32_t b) {
+    return (b + 1 == LdsGeo<W>::kBuckets) ? 0 : b + 1;
+}
 
 // Find or claim a slot for x within `window` buckets from its home bucket and add
 // `add` to its counter.  Returns false when those buckets are full without x.
+template <uint32_t W>
 __device__ __forceinline__ bool lds_insert(uint64_t* skeys, uint32_t* scnt, uint64_t x, uint32_t add,
                                            uint32_t window) {
-    uint32_t b = lds_bucket(x);
+    uint32_t b = lds_bucket<W>(x);
     for (uint32_t pr = 0; pr < window; ++pr) {
-        const uint32_t base = b * kLdsBucketSlots;
-        for (uint32_t s = 0; s < kLdsBucketSlots; ++s) {
+        const uint32_t base = b * W;
+        for (uint32_t s = 0; s < W; ++s) {
             uint64_t k = __hip_atomic_load(&skeys[base + s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (k == kEmpty) {
                 k = atomicCAS((unsigned long long*)&skeys[base + s], (unsigned long long)kEmpty,
@@ -239,28 +254,35 @@ __device__ __forceinline__ bool lds_insert(uint64_t* skeys, uint32_t* scnt, uint
                 if (k == kEmpty) k = x;  // claimed; otherwise k is the key that took the slot
             }
             if (k == x) {
-                atomicAdd(&scnt[s * kLdsBuckets + b], add);
+                atomicAdd(&scnt[s * LdsGeo<W>::kBuckets + b], add);
                 return true;
             }
         }
-        b = next_bucket(b);
+        b = next_bucket<W>(b);
     }
     return false;
 }
 
-// Slot of x among the four keys of a bucket, or -1; `full` tells whether the last
+// Slot of x among the W keys of a bucket, or -1; `full` tells whether the last
 // slot is taken (then x may sit in a later bucket).
-__device__ __forceinline__ int match4(const uint64_t* skeys, uint32_t b, uint64_t x, bool& full) {
-    const u64x2 lo = *reinterpret_cast<const u64x2*>(skeys + b * kLdsBucketSlots);
-    const u64x2 hi = *reinterpret_cast<const u64x2*>(skeys + b * kLdsBucketSlots + 2);
-    full = hi.y != kEmpty;
-    return lo.x == x ? 0 : lo.y == x ? 1 : hi.x == x ? 2 : hi.y == x ? 3 : -1;
+template <uint32_t W>
+__device__ __forceinline__ int match_bucket(const uint64_t* skeys, uint32_t b, uint64_t x, bool& full) {
+    const u64x2 lo = *reinterpret_cast<const u64x2*>(skeys + b * W);
+    if constexpr (W == 2) {
+        full = lo.y != kEmpty;
+        return lo.x == x ? 0 : lo.y == x ? 1 : -1;
+    } else {
+        static_assert(W == 4, "buckets of 2 or 4 keys");
+        const u64x2 hi = *reinterpret_cast<const u64x2*>(skeys + b * W + 2);
+        full = hi.y != kEmpty;
+        return lo.x == x ? 0 : lo.y == x ? 1 : hi.x == x ? 2 : hi.y == x ? 3 : -1;
+    }
 }
 
 // Counts the elements of x selected by `want` in the LDS table, one after the
 // other (the loads of the next batch are in flight meanwhile); returns the mask of
 // those whose window was full (not counted).
-template <int NE>
+template <int NE, uint32_t W>
 __device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, uint32_t* __restrict__ scnt,
                                                 uint32_t* __restrict__ sink, const uint64_t (&x)[NE],
                                                 uint32_t want_m) {
@@ -268,19 +290,19 @@ __device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, ui
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
         const bool want = (want_m >> e) & 1u;
-        uint32_t b = lds_bucket(x[e]);
+        uint32_t b = lds_bucket<W>(x[e]);
         bool full;
-        int m = match4(skeys, b, x[e], full);
+        int m = match_bucket<W>(skeys, b, x[e], full);
         if (m < 0 && full) {  // home bucket full without x: x may be in the next one
-            b = next_bucket(b);
-            m = match4(skeys, b, x[e], full);
+            b = next_bucket<W>(b);
+            m = match_bucket<W>(skeys, b, x[e], full);
         }
         const bool hit = want && m >= 0;
-        // counters are slot-major (slot s of bucket b at s * kLdsBuckets + b) so that
+        // counters are slot-major (slot s of bucket b at s * buckets + b) so that
         // the first slots of many buckets spread over the LDS banks; lanes without a
         // hit add to their own sink word, off the counters (equal addresses in one
         // instruction serialise)
-        atomicAdd(hit ? &scnt[m * kLdsBuckets + b] : &sink[__lane_id()], 1u);
+        atomicAdd(hit ? &scnt[m * LdsGeo<W>::kBuckets + b] : &sink[__lane_id()], 1u);
         const bool miss = want && !hit;
         ins |= (miss && !full) ? (1u << e) : 0u;
         dfr |= (miss && full) ? (1u << e) : 0u;
@@ -288,7 +310,7 @@ __device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, ui
     if (ins) {
 #pragma unroll
         for (int e = 0; e < NE; ++e)
-            if (((ins >> e) & 1u) && !lds_insert(skeys, scnt, x[e], 1u, kLdsWindow)) dfr |= 1u << e;
+            if (((ins >> e) & 1u) && !lds_insert<W>(skeys, scnt, x[e], 1u, kLdsWindow)) dfr |= 1u << e;
     }
     return dfr;
 }
@@ -298,18 +320,23 @@ __device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, ui
 // so it never fills up (tmp_k has room for n + 2 + 2 * kMaxCountBlocks keys).
 __device__ __forceinline__ uint64_t pairs_per_block(uint64_t P, uint32_t nblk) { return (P + nblk - 1) / nblk; }
 
+template <uint32_t W>
 __device__ __forceinline__ void flush_table(const GTable& t, const uint64_t* skeys, const uint32_t* scnt) {
-    constexpr uint32_t S = kLdsBuckets * kLdsBucketSlots;
+    constexpr uint32_t S = kLdsSlots, B = LdsGeo<W>::kBuckets;
     // once the table has overflowed (the radix engine takes over) the flush is moot;
     // one lane per wave looks, once (inserts check again as they go)
     uint32_t ov = 0;
     if (__lane_id() == 0) ov = g_load(&t.c->overflow);
     if (__shfl(ov, 0, 64)) return;
     for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
-        const uint32_t cn = scnt[i];  // slot i / kLdsBuckets of bucket i % kLdsBuckets; never 0 once claimed
-        if (cn) global_insert(t, skeys[(i % kLdsBuckets) * kLdsBucketSlots + i / kLdsBuckets], cn);
+        const uint32_t cn = scnt[i];  // slot i / B of bucket i % B; never 0 once claimed
+        if (cn) global_insert(t, skeys[(i % B) * W + i / B], cn);
     }
 }
+
+template <uint32_t W>
+__device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, uint32_t nblk, uint64_t* skeys,
+                                                 uint32_t* scnt, uint32_t& s_ndef, uint32_t* s_sink);
 
 __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
@@ -343,7 +370,7 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
         return;
     }
 
-    constexpr uint32_t S = kLdsBuckets * kLdsBucketSlots;
+    constexpr uint32_t S = kLdsSlots;
     __shared__ __attribute__((aligned(16))) uint64_t skeys[S];
     __shared__ uint32_t scnt[S];
     __shared__ uint32_t s_ndef;
@@ -354,7 +381,17 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
     }
     if (threadIdx.x == 0) s_ndef = 0;
     __syncthreads();
+    if (c->k_hat < kLdsWideMinKhat) hash_count_table<2>(a, bid, nblk, skeys, scnt, s_ndef, s_sink);
+    else hash_count_table<4>(a, bid, nblk, skeys, scnt, s_ndef, s_sink);
+}
 
+// The count over one workgroup's range with buckets of W keys (the table in LDS
+// is cleared).
+template <uint32_t W>
+__device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, uint32_t nblk, uint64_t* skeys,
+                                                 uint32_t* scnt, uint32_t& s_ndef, uint32_t* s_sink) {
+    constexpr uint32_t S = kLdsSlots;
+    Ctrl* c = a.c;
     const GTable t = gtable(a);
     const uint64_t n = a.n;
     const CAFS_GLOBAL uint64_t* in = gp(a.in);
@@ -426,7 +463,7 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
             ecnt += is_empty_key ? 1u : 0u;
             want &= is_empty_key ? ~(1u << e) : ~0u;
         }
-        const uint32_t dfr = count_batch<NE>(skeys, scnt, s_sink, x, want);
+        const uint32_t dfr = count_batch<NE, W>(skeys, scnt, s_sink, x, want);
         if (__ballot(dfr != 0)) {
             // append the deferred elements: one LDS reservation per wave, then each
             // element's place from the ballot of its batch position
@@ -452,7 +489,7 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
         if (handed) break;
     }
     __syncthreads();
-    flush_table(t, skeys, scnt);
+    flush_table<W>(t, skeys, scnt);
     const uint32_t wsum = wave_sum_u32(ecnt);
     if (lane == 0 && wsum) g_add(&c->ecount, (uint64_t)wsum);
     // Second pass over this workgroup's deferred elements, with the table cleared
@@ -471,8 +508,8 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
     for (uint32_t i0 = 0; i0 < d; i0 += blockDim.x) {  // one element per thread: this pass is short
         const uint32_t i = i0 + threadIdx.x;
         const uint64_t x1[1] = {i < d ? region[i] : 0};
-        if (count_batch<1>(skeys, scnt, s_sink, x1, i < d ? 1u : 0u) &&
-            !lds_insert(skeys, scnt, x1[0], 1u, kLdsProbeBuckets)) {
+        if (count_batch<1, W>(skeys, scnt, s_sink, x1, i < d ? 1u : 0u) &&
+            !lds_insert<W>(skeys, scnt, x1[0], 1u, kLdsProbeBuckets)) {
             atomicAdd(&s_ndef, 1u);
             global_insert(t, x1[0], 1);
         }
@@ -488,7 +525,7 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
         }
     }
     __syncthreads();
-    flush_table(t, skeys, scnt);
+    flush_table<W>(t, skeys, scnt);
 }
 CAFS_KERNELS0(hash_count, kCountThreads)
 

@@ -117,7 +117,7 @@ CAFS_KERNELS1(emit, kEmitThreads, uint32_t, mode)
 // TB/s when 256 workgroups sweep the output in rows, whether as one sweep or as up
 // to 32 sweeps over separate segments, against 5.2-5.8 TB/s when each workgroup
 // streams its own tiles or chunk).  The output is cut into segments of about
-// kEmitSegRuns runs each (segment i starts at the 1 KB-aligned pair at or before
+// kEmitSegRuns runs each (segment i starts at the 4 KB-aligned pair at or before
 // the first element of run i * kEmitSegRuns); each segment gets workgroups in
 // proportion to its pairs, and they sweep it in rows of (workgroups * blockDim)
 // pairs, each writing blockDim consecutive pairs of every row, kEmitRowsUnroll
@@ -125,9 +125,10 @@ CAFS_KERNELS1(emit, kEmitThreads, uint32_t, mode)
 // to the segment start) with an index of the run holding every 2^s-th position of
 // the segment (at most kEmitIdxSlots entries); an element's run is that entry's
 // run, or a short binary search when run boundaries fall inside the span.
-constexpr uint32_t kEmitRowsMaxK = 2040;   // runs one workgroup stages (about 40 KB of LDS with the index)
+constexpr uint32_t kEmitRowsMaxK = 4088;   // runs one workgroup stages (64 KB of LDS with the index; one
+                                           // workgroup per CU leaves room for the side stream's kernels)
 constexpr uint32_t kEmitIdxSlots = 4096;
-constexpr uint32_t kEmitAlignPairs = 64;  // segment starts: multiples of 1 KB of output
+constexpr uint32_t kEmitAlignPairs = 256;  // segment starts: multiples of 4 KB of output
 constexpr uint32_t kEmitSegRuns = kEmitRowsMaxK - 2 * kEmitAlignPairs;  // runs starting in a segment
 constexpr uint32_t kEmitMaxSegs = (kRankMax + kEmitSegRuns - 1) / kEmitSegRuns;  // segments for K <= kRankMax
 constexpr uint32_t kEmitRowsThreads = 256;
@@ -143,6 +144,25 @@ __device__ __forceinline__ uint32_t run_in(const uint32_t* sidx, const uint32_t*
         if (soff[mid] <= e) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// Largest j in [lo, hi] with off[j] <= e (off[lo] <= e), by one whole wave: each
+// round probes 64 evenly spaced offsets at once and keeps the span between the last
+// one at or below e and the next (the predicate is monotone in j).  Every lane gets
+// the answer.
+__device__ __forceinline__ uint64_t wave_run_of(const uint64_t* off, uint64_t lo, uint64_t hi, uint64_t e) {
+    const uint32_t lane = __lane_id();
+    while (true) {
+        const uint64_t span = hi - lo + 1;
+        const uint64_t step = span <= 64 ? 1 : (span + 63) / 64;
+        const uint64_t j = lo + lane * step;
+        const bool ok = j <= hi && gp(off)[j] <= e;
+        const uint64_t m = __ballot(ok);  // a prefix of the lanes, lane 0 always set
+        const uint64_t at = lo + (uint64_t)(63 - __builtin_clzll(m)) * step;
+        if (step == 1) return at;
+        lo = at;
+        hi = at + step - 1 < hi ? at + step - 1 : hi;
+    }
 }
 
 __device__ __forceinline__ bool rows_take(const Args& a, const Ctrl* c) {
@@ -208,22 +228,27 @@ __device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint
     const uint64_t e_first = ef_s < 0 ? 0 : (uint64_t)ef_s;
     const uint64_t el_s = 2 * sp1 - 1 - head;
     const uint64_t e_last = el_s < n - 1 ? el_s : n - 1;
-    if (tid == 0) {
-        if (S == 1) {  // the whole column
+    if (S == 1) {  // the whole column
+        if (tid == 0) {
             s_rng[0] = 0;
             s_rng[1] = K - 1;
-        } else {
-            // the segment starts at most 2 * kEmitAlignPairs - 1 elements before run
-            // i * R, so its first run is at most that many runs before; it ends at most
-            // 2 * kEmitAlignPairs elements before run (i + 1) * R, so its last run is at
-            // most that many runs before that one
-            constexpr uint32_t back = 2 * kEmitAlignPairs - 1;
+        }
+    } else if (tid < 128) {
+        // the segment starts at most 2 * kEmitAlignPairs - 1 elements before run
+        // i * R, so its first run is at most that many runs before; it ends at most
+        // 2 * kEmitAlignPairs elements before run (i + 1) * R, so its last run is at
+        // most that many runs before that one (wave 0 finds the first, wave 1 the last)
+        constexpr uint32_t back = 2 * kEmitAlignPairs;
+        if (tid < 64) {
             const uint32_t a1 = seg * R, a0 = a1 > back ? a1 - back : 0u;
+            const uint64_t jl = wave_run_of(a.off, a0, a1, e_first);
+            if (tid == 0) s_rng[0] = jl;
+        } else {
             const uint32_t b1 = seg + 1 == S ? K - 1 : (seg + 1) * R - 1;
-            const uint64_t jl = run_of(a.off, a0, a1, e_first);
-            const uint64_t b0 = b1 >= back + jl ? b1 - back : jl;
-            s_rng[0] = jl;
-            s_rng[1] = run_of(a.off, b0, b1, e_last);
+            const uint32_t a0 = seg * R > back ? seg * R - back : 0u;  // at or below the first run
+            const uint32_t b0 = b1 > back && b1 - back > a0 ? b1 - back : a0;
+            const uint64_t jh = wave_run_of(a.off, b0, b1, e_last);
+            if (tid == 64) s_rng[1] = jh;
         }
     }
     __syncthreads();
