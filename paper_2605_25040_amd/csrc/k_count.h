@@ -328,9 +328,29 @@ __device__ __forceinline__ void flush_table(const GTable& t, const uint64_t* ske
     uint32_t ov = 0;
     if (__lane_id() == 0) ov = g_load(&t.c->overflow);
     if (__shfl(ov, 0, 64)) return;
-    for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
-        const uint32_t cn = scnt[i];  // slot i / B of bucket i % B; never 0 once claimed
-        if (cn) global_insert(t, skeys[(i % B) * W + i / B], cn);
+    // four slots per thread at a time: their home slots in the global table are read
+    // together, and a key already there (most are, after the first workgroups) gets
+    // its count added directly; the rest take the probing insert
+    const uint32_t lg = t.c->cap_log2;
+    constexpr int F = 4;
+    for (uint32_t i0 = threadIdx.x; i0 < S; i0 += F * blockDim.x) {
+        uint32_t cn[F], h[F];
+        uint64_t key[F], k[F];
+#pragma unroll
+        for (int u = 0; u < F; ++u) {
+            const uint32_t i = i0 + u * blockDim.x;
+            cn[u] = i < S ? scnt[i] : 0u;  // slot i / B of bucket i % B; never 0 once claimed
+            key[u] = cn[u] ? skeys[(i % B) * W + i / B] : 0;
+            h[u] = phi_hash(key[u], lg);
+        }
+#pragma unroll
+        for (int u = 0; u < F; ++u) k[u] = cn[u] ? g_load(&t.keys[h[u]]) : kEmpty;
+#pragma unroll
+        for (int u = 0; u < F; ++u) {
+            if (!cn[u]) continue;
+            if (k[u] == key[u]) g_add(&t.cnt[h[u]], (unsigned long long)cn[u]);
+            else global_insert(t, key[u], cn[u]);
+        }
     }
 }
 
@@ -505,13 +525,25 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
     __syncthreads();
     if (threadIdx.x == 0) s_ndef = 0;  // now: elements that found no room in the second table either
     __syncthreads();
-    for (uint32_t i0 = 0; i0 < d; i0 += blockDim.x) {  // one element per thread: this pass is short
-        const uint32_t i = i0 + threadIdx.x;
-        const uint64_t x1[1] = {i < d ? region[i] : 0};
-        if (count_batch<1, W>(skeys, scnt, s_sink, x1, i < d ? 1u : 0u) &&
-            !lds_insert<W>(skeys, scnt, x1[0], 1u, kLdsProbeBuckets)) {
-            atomicAdd(&s_ndef, 1u);
-            global_insert(t, x1[0], 1);
+    constexpr int D = 4;  // elements per thread per step
+    for (uint32_t i0 = 0; i0 < d; i0 += D * blockDim.x) {
+        uint64_t xd[D];
+        uint32_t want = 0;
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const uint32_t i = i0 + u * blockDim.x + threadIdx.x;
+            xd[u] = i < d ? region[i] : 0;
+            want |= (i < d ? 1u : 0u) << u;
+        }
+        const uint32_t dfr = count_batch<D, W>(skeys, scnt, s_sink, xd, want);
+        if (dfr) {
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                if (((dfr >> u) & 1u) && !lds_insert<W>(skeys, scnt, xd[u], 1u, kLdsProbeBuckets)) {
+                    atomicAdd(&s_ndef, 1u);
+                    global_insert(t, xd[u], 1);
+                }
+            }
         }
         // too many keys even for a second table: per-element global inserts would cost
         // more than sorting, so the radix engine takes over (the count is read between
