@@ -210,8 +210,22 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
         const uint64_t b0 = ch * kGuardChunk;
         const uint64_t e0 = (b0 + kGuardChunk < n) ? b0 + kGuardChunk : n;
         uint32_t newly = 0;
-        for (uint64_t i = b0 + threadIdx.x; i < e0; i += blockDim.x) {
-            const uint64_t v = gp(a.in)[i];
+        // the chunk's elements are loaded first (all in flight), then looked up; a
+        // key whose first position is already known to be earlier is skipped before
+        // the atomic (a frequent key would otherwise serialise on one address; a
+        // stale read is only ever larger, so the skip is safe)
+        constexpr uint32_t PER = kGuardChunk / 256;  // workgroups of 256 threads
+        uint64_t vv[PER];
+#pragma unroll
+        for (uint32_t u = 0; u < PER; ++u) {
+            const uint64_t i = b0 + threadIdx.x + (uint64_t)u * blockDim.x;
+            vv[u] = i < e0 ? gp(a.in)[i] : 0;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < PER; ++u) {
+            const uint64_t i = b0 + threadIdx.x + (uint64_t)u * blockDim.x;
+            if (i >= e0) continue;
+            const uint64_t v = vv[u];
             const uint32_t b = phi_hash32(v, lg);
             const bool cont = bits ? ((bflag[b >> 5] >> (b & 31)) & 1u) : (a.dcount[b] > kBucketCap);
             if (!cont) continue;
@@ -219,13 +233,18 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
                 uint32_t h = phi_hash32(v, 12);
                 while (true) {
                     const uint64_t tk = tkey[h];
-                    if (tk == v) { atomicMin(&lmin[tidx[h]], (uint32_t)i); break; }
+                    if (tk == v) {
+                        const uint32_t li = tidx[h];
+                        if (lmin[li] > (uint32_t)i) atomicMin(&lmin[li], (uint32_t)i);
+                        break;
+                    }
                     if (tk == kEmpty) break;  // unreachable: contested keys are all in the table
                     h = (h + 1) & (TS - 1);
                 }
             } else if (bits || a.dcount[b] > kBucketCap) {
                 const uint64_t jj = glg ? index_find(a, glg, v) : find_key(a.uniq, K, v, flip);
                 if (jj >= K) continue;  // not reached: every key of a contested bucket is indexed
+                if (g_load(&a.first_idx[jj]) <= (uint32_t)i) continue;
                 const uint32_t old = atomicMin(&a.first_idx[jj], (uint32_t)i);
                 if (old == kNoIndex && atomicAdd(&a.bfound[b], 1u) == kBucketCap - 1) ++newly;
             }
