@@ -33,6 +33,7 @@ constexpr uint32_t kLdsWindow = 2;             // buckets probed before an eleme
 constexpr uint32_t kLdsProbeBuckets = 8;       // buckets probed in the deferred pass before the global table
 constexpr uint32_t kMaxCountBlocks = 1024;     // workgroups of one hash count
 constexpr uint32_t kGlobalProbe = 64;          // global probe limit before overflow (the table is sized for 1/8 load)
+constexpr uint32_t kGlobalProbeCheck = 4;      // a long probe looks at the overflow flag every this many slots
 constexpr uint32_t kMinTableLog2 = 12;         // smallest global table (4096 slots)
 constexpr uint32_t kMaxTableLog2 = 22;         // largest global table (4M slots, 64 MiB)
 constexpr uint32_t kTableFloorLog2 = 16;       // global table never smaller (64K slots) when the workspace allows
@@ -74,9 +75,7 @@ struct RadixJob {
     const uint64_t* ps_v[8];
     uint64_t* pd_k[8];                // destination of active pass i
     uint64_t* pd_v[8];
-    uint32_t copy_mode;               // after the passes: 0 nothing, 1 copy src->dst, 2 tmp->dst,
-                                      // 3 values only (position of each key)
-    uint32_t iota_vals;               // the values are the keys' input positions (made, not read)
+    uint32_t copy_mode;               // after the passes: 0 nothing, 1 copy src->dst, 2 tmp->dst
 };
 
 // Decisions and counters of one call, in device memory (workspace).
@@ -128,7 +127,6 @@ struct Ctrl {
     uint32_t guard_general;           // bucket counts must be built from the dense pairs
     uint32_t guard_rounds;            // too many contested keys for one workgroup
     uint32_t gidx_log2;               // hash index of the contested keys (0: binary search)
-    uint32_t first_known;             // first occurrences come from the stable sort with positions
     uint64_t n_contested;
     uint64_t n_cbuckets;              // buckets holding more than four distinct keys
     uint64_t buckets_done;            // of those, buckets whose first four keys are known

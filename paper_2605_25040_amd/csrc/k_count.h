@@ -96,35 +96,15 @@ __device__ __forceinline__ void phase2_body(const Args& a, uint32_t bid, uint32_
 }
 CAFS_KERNELS0(phase2, 256)
 
-// Whether the radix engine should carry input positions (see set_overflow).  They
-// pay when many buckets of the paper's table are over-full, which happens when the
-// estimate is far below K: a sample with many repeated keys (f1 well below u) has a
-// heavy tail that Chao1 underestimates.  A sample of nearly all singletons comes
-// from keys spread evenly, and the first-occurrence pass then stops early.
-__device__ __forceinline__ bool positions_pay(const Ctrl* c) { return 10 * c->f1 < 9 * c->u; }
-
 // Switch to the radix engine after the global table overflowed.  In place, the
 // radix engine then sorts into scratch so that the guard can still read the input.
-// The sort carries each key's input position (the dense count and offset arrays,
-// free until the run-length pass, hold them), so that a run's first position is its
-// key's first occurrence (the LSD sort is stable) and the guard needs no pass of
-// its own over the input.
-__device__ __noinline__ void set_overflow(Ctrl* c, uint32_t inplace, uint64_t* tmp_k, uint64_t* uniq,
-                                          uint64_t* cnt, uint64_t* off) {
+__device__ __noinline__ void set_overflow(Ctrl* c, uint32_t inplace, uint64_t* tmp_k, uint64_t* uniq) {
     if (atomicExch(&c->overflow, 1u) == 0) {
         if (inplace) {
             c->rj.dst_k = tmp_k;
             c->rj.tmp_k = uniq;
             c->sorted = tmp_k;
             c->deferred_copy = 1;
-        }
-        if (positions_pay(c)) {
-            c->rj.has_vals = 1;
-            c->rj.iota_vals = 1;
-            c->rj.src_v = nullptr;
-            c->rj.dst_v = cnt;
-            c->rj.tmp_v = off;
-            c->first_known = 1;
         }
         atomicExch(&c->radix_on, 1u);
         atomicExch(&c->guard_on, 1u);
@@ -141,8 +121,6 @@ struct GTable {
     uint32_t* claimed;
     uint64_t* tmp_k;
     uint64_t* uniq;
-    uint64_t* dense_cnt;
-    uint64_t* dense_off;
     uint32_t inplace;
 };
 
@@ -154,8 +132,6 @@ __device__ __forceinline__ GTable gtable(const Args& a) {
     t.claimed = a.claimed;
     t.tmp_k = a.tmp_k;
     t.uniq = a.uniq;
-    t.dense_cnt = a.cnt;
-    t.dense_off = a.off;
     t.inplace = a.in == a.out;
     return t;
 }
@@ -163,35 +139,65 @@ __device__ __forceinline__ GTable gtable(const Args& a) {
 // Insert (v, cnt) into the global open-addressing table (linear probing, Eq. hash
 // slot).  A slot is claimed by CAS from kEmpty and never freed, so a key is either
 // in the table or (after an overflow) the whole table is abandoned for the radix
-// engine.  Claimed slots are listed so that compaction reads K entries, not the table.
-__device__ __forceinline__ void global_insert(const GTable& t, uint64_t v, uint64_t cnt) {
+// engine.  Returns the slot claimed for a new key (kNoSlot otherwise); the caller
+// lists claimed slots with list_claims, so that compaction reads K entries, not the
+// table.
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+
+// The overflow flag, read by one lane and broadcast: an agent-scope load misses the
+// XCD's L2 and goes to memory, and every lane of the GPU reading the same word
+// queues on one line.  Called with every lane of the wave active.
+__device__ __forceinline__ uint32_t wave_overflow(const Ctrl* c) {
+    uint32_t ov = 0;
+    if (__lane_id() == 0) ov = g_load(&c->overflow);
+    return __builtin_amdgcn_readfirstlane(ov);
+}
+
+// The caller checks the overflow flag (per wave) before it inserts; a long probe
+// looks again every kGlobalProbeCheck slots, so that inserts under way stop soon
+// after the table passed its load limit (they would otherwise keep claiming slots
+// and probe ever longer).
+__device__ __forceinline__ uint32_t global_insert(const GTable& t, uint64_t v, uint64_t cnt) {
     Ctrl* c = t.c;
-    if (g_load(&c->overflow)) return;
     const uint32_t lg = c->cap_log2;
     const uint64_t mask = (1ull << lg) - 1;
     uint64_t h = phi_hash(v, lg);
     for (uint32_t pr = 0; pr < kGlobalProbe; ++pr) {
+        if (pr % kGlobalProbeCheck == kGlobalProbeCheck - 1 && g_load(&c->overflow)) return kNoSlot;
         uint64_t k = g_load(&t.keys[h]);
         if (k == kEmpty) {
             k = g_cas(&t.keys[h], kEmpty, v);
             if (k == kEmpty) {
-                const uint32_t idx = g_add(&c->claimed, 1u);
-                if (idx >= c->cap_limit) {
-                    set_overflow(c, t.inplace, t.tmp_k, t.uniq, t.dense_cnt, t.dense_off);
-                    return;
-                }
-                gp(t.claimed)[idx] = (uint32_t)h;
                 g_add(&t.cnt[h], (unsigned long long)cnt);
-                return;
+                return (uint32_t)h;
             }
         }
         if (k == v) {
             g_add(&t.cnt[h], (unsigned long long)cnt);
-            return;
+            return kNoSlot;
         }
         h = (h + 1) & mask;
     }
-    set_overflow(c, t.inplace, t.tmp_k, t.uniq, t.dense_cnt, t.dense_off);
+    set_overflow(c, t.inplace, t.tmp_k, t.uniq);
+    return kNoSlot;
+}
+
+// Lists the slots the lanes of a wave claimed (kNoSlot: none) in the claimed-slot
+// list, with one update of the shared counter per wave (one per claim would
+// serialise on its address).  Past the table's load limit the radix engine takes
+// over.  Called by every lane of the wave.
+__device__ __forceinline__ void list_claims(const GTable& t, uint32_t h) {
+    const uint64_t m = __ballot(h != kNoSlot);
+    if (m == 0) return;
+    const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+    uint32_t base = 0;
+    if (__lane_id() == leader) base = g_add(&t.c->claimed, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, 64);
+    if (h == kNoSlot) return;
+    const uint32_t idx =
+        base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (idx >= t.c->cap_limit) set_overflow(t.c, t.inplace, t.tmp_k, t.uniq);
+    else gp(t.claimed)[idx] = h;
 }
 
 // ---------------------------------------------------------------------------
@@ -324,17 +330,15 @@ template <uint32_t W>
 __device__ __forceinline__ void flush_table(const GTable& t, const uint64_t* skeys, const uint32_t* scnt) {
     constexpr uint32_t S = kLdsSlots, B = LdsGeo<W>::kBuckets;
     // once the table has overflowed (the radix engine takes over) the flush is moot;
-    // one lane per wave looks, once (inserts check again as they go)
-    uint32_t ov = 0;
-    if (__lane_id() == 0) ov = g_load(&t.c->overflow);
-    if (__shfl(ov, 0, 64)) return;
+    // each wave looks before every group of inserts
     // four slots per thread at a time: their home slots in the global table are read
     // together, and a key already there (most are, after the first workgroups) gets
     // its count added directly; the rest take the probing insert
     const uint32_t lg = t.c->cap_log2;
     constexpr int F = 4;
-    for (uint32_t i0 = threadIdx.x; i0 < S; i0 += F * blockDim.x) {
-        uint32_t cn[F], h[F];
+    for (uint32_t i0 = threadIdx.x; i0 < S; i0 += F * blockDim.x) {  // uniform over each wave
+        if (wave_overflow(t.c)) return;
+        uint32_t cn[F], h[F], cl[F];
         uint64_t key[F], k[F];
 #pragma unroll
         for (int u = 0; u < F; ++u) {
@@ -347,10 +351,13 @@ __device__ __forceinline__ void flush_table(const GTable& t, const uint64_t* ske
         for (int u = 0; u < F; ++u) k[u] = cn[u] ? g_load(&t.keys[h[u]]) : kEmpty;
 #pragma unroll
         for (int u = 0; u < F; ++u) {
+            cl[u] = kNoSlot;
             if (!cn[u]) continue;
             if (k[u] == key[u]) g_add(&t.cnt[h[u]], (unsigned long long)cn[u]);
-            else global_insert(t, key[u], cn[u]);
+            else cl[u] = global_insert(t, key[u], cn[u]);
         }
+#pragma unroll
+        for (int u = 0; u < F; ++u) list_claims(t, cl[u]);  // (the loop is uniform over each wave)
     }
 }
 
@@ -463,11 +470,12 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
         // (the flag's load overlaps this batch), or hand it over when a quarter of the
         // elements so far found no room (K far beyond the table)
         const bool check = (++iter & 7) == 0;
-        const uint32_t handed = check ? g_load(&c->overflow) : 0u;
+        // (lane 0 loads the flag; the wave reads it from lane 0 after the batch)
+        const uint32_t handed = (check && __lane_id() == 0) ? g_load(&c->overflow) : 0u;
         if (check) {
             const uint64_t seen = 2 * (base - (uint64_t)bid * PP);
             if (4ull * s_ndef > seen && seen > 2 * PP / 8) {
-                if (lane == 0) set_overflow(c, t.inplace, t.tmp_k, t.uniq, t.dense_cnt, t.dense_off);
+                if (lane == 0) set_overflow(c, t.inplace, t.tmp_k, t.uniq);
                 break;
             }
         }
@@ -506,7 +514,7 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
             }
         }
         base = next;
-        if (handed) break;
+        if (__builtin_amdgcn_readfirstlane(handed)) break;  // lane 0's load (every lane is active)
     }
     __syncthreads();
     flush_table<W>(t, skeys, scnt);
@@ -516,7 +524,7 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
     // (the keys that found no room are few) and a longer probe; what still finds no
     // room goes to the global table.
     const uint32_t d = s_ndef;  // uniform: read after the barrier
-    if (d == 0 || g_load(&c->overflow)) return;
+    if (d == 0 || wave_overflow(c)) return;  // (d is uniform)
     __syncthreads();  // (the workgroup reads back only its own region)
     for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
         skeys[i] = kEmpty;
@@ -536,15 +544,21 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
             want |= (i < d ? 1u : 0u) << u;
         }
         const uint32_t dfr = count_batch<D, W>(skeys, scnt, s_sink, xd, want);
-        if (dfr) {
+        uint32_t cl[D];
+#pragma unroll
+        for (int u = 0; u < D; ++u) cl[u] = kNoSlot;
+        const uint32_t ov = wave_overflow(c);
+        if (dfr && !ov) {
 #pragma unroll
             for (int u = 0; u < D; ++u) {
                 if (((dfr >> u) & 1u) && !lds_insert<W>(skeys, scnt, xd[u], 1u, kLdsProbeBuckets)) {
                     atomicAdd(&s_ndef, 1u);
-                    global_insert(t, xd[u], 1);
+                    cl[u] = global_insert(t, xd[u], 1);
                 }
             }
         }
+#pragma unroll
+        for (int u = 0; u < D; ++u) list_claims(t, cl[u]);
         // too many keys even for a second table: per-element global inserts would cost
         // more than sorting, so the radix engine takes over (the count is read between
         // two barriers, so every thread takes the same decision)
@@ -552,7 +566,7 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
         const bool stop = 64ull * s_ndef > 2 * PP;
         __syncthreads();
         if (stop) {
-            if (threadIdx.x == 0) set_overflow(c, t.inplace, t.tmp_k, t.uniq, t.dense_cnt, t.dense_off);
+            if (threadIdx.x == 0) set_overflow(c, t.inplace, t.tmp_k, t.uniq);
             break;
         }
     }

@@ -446,7 +446,6 @@ __device__ __forceinline__ void rle_write_body(const Args& a, uint32_t bid, uint
     const CAFS_GLOBAL uint64_t* __restrict__ y = gp(c->sorted);
     CAFS_GLOBAL uint64_t* __restrict__ uq = gp(a.uniq);
     CAFS_GLOBAL uint64_t* __restrict__ off = gp(a.off);
-    const CAFS_GLOBAL uint64_t* first = c->first_known ? gp(c->rj.dst_v) : nullptr;
     const uint64_t tiles = (n + kRleTile - 1) / kRleTile;
     constexpr uint32_t per = kRleTile / 256;  // contiguous elements per thread
     __shared__ uint64_t sy[kRleTile + 1];     // sy[i + 1] = y[b + i]; sy[0] = y[b - 1]
@@ -486,8 +485,6 @@ __device__ __forceinline__ void rle_write_body(const Args& a, uint32_t bid, uint
         for (uint32_t r = threadIdx.x; r < total; r += blockDim.x) {
             uq[j0 + r] = sy[r];
             off[j0 + r] = b + spos[r];
-            // the sort carried input positions: a run's first one is its key's first occurrence
-            if (first) gp(a.first_idx)[j0 + r] = (uint32_t)first[b + spos[r]];
         }
         __syncthreads();
     }

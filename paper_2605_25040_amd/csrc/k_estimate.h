@@ -184,22 +184,10 @@ __device__ void plan_block(const Args& a) {
     j.tmp_k = a.tmp_k; j.tmp_v = nullptr;
     j.n = n;
     j.has_vals = 0;
-    j.iota_vals = 0;
     j.n_active = 0;
     j.copy_mode = 0;
     c->sorted = a.out;
     c->deferred_copy = 0;
-    c->first_known = 0;
-    if (path == P_MAIN && engine == E_RADIX && 10 * c->f1 < 9 * c->u) {
-        // the guard may need many first occurrences: sort each key's position along
-        // (see set_overflow and positions_pay)
-        j.has_vals = 1;
-        j.iota_vals = 1;
-        j.src_v = nullptr;
-        j.dst_v = a.cnt;
-        j.tmp_v = a.off;
-        c->first_known = 1;
-    }
     if (path == P_MAIN && engine == E_RADIX && a.in == a.out) {
         // in place on the main path: the guard still reads the input after the sort,
         // so sort into scratch (ping-pong with the dense key array, written later)

@@ -45,7 +45,7 @@ __device__ __forceinline__ bool guard_general(const Ctrl* c) {
 // radix scratch, sized for all K keys; 0 when the scratch still holds the sorted
 // column (in place after the radix engine) or is too small: then binary search.
 __device__ __forceinline__ uint32_t guard_index_log2(const Args& a, const Ctrl* c) {
-    if (c->deferred_copy || c->first_known) return 0;
+    if (c->deferred_copy) return 0;
     const uint32_t lg = log2_pow2(bit_ceil64(2 * c->K > 64 ? 2 * c->K : 64));
     return (1ull << lg) <= 2 * (a.n + 2) ? lg : 0;  // the scratch holds 2 (n + 2) 32-bit words
 }
@@ -83,7 +83,7 @@ __device__ __forceinline__ void guard_bucket_body(const Args& a, uint32_t bid, u
 CAFS_KERNELS0(guard_bucket, 256)
 
 // Lists the contested keys (general mode) and resets their first-occurrence
-// minima, unless the radix engine's sort with positions already gave them.
+// minima.
 __device__ __forceinline__ void guard_mark_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!guard_active(c)) return;
@@ -104,7 +104,7 @@ __device__ __forceinline__ void guard_mark_body(const Args& a, uint32_t bid, uin
         uint32_t* tab = guard_index(a);
         for (uint64_t j = gtid; j < K; j += gstride)
             if (a.dcount[phi_hash(a.uniq[j], lg)] > kBucketCap) {
-                if (!c->first_known) a.first_idx[j] = kNoIndex;
+                a.first_idx[j] = kNoIndex;
                 a.clist[atomicAdd((unsigned long long*)&c->n_contested, 1ull)] = (uint32_t)j;
                 if (glg) {  // index the contested key: linear probing on 32-bit slots
                     uint64_t h = phi_hash(a.uniq[j], glg);
@@ -153,7 +153,7 @@ __device__ __forceinline__ uint64_t index_find(const Args& a, uint32_t glg, uint
 // of the contested keys (binary search when there is none).
 __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
-    if (c->path != P_MAIN || !c->guard_on || c->first_known) return;
+    if (c->path != P_MAIN || !c->guard_on) return;
     const uint64_t nc = c->n_contested;
     if (nc == 0) return;
     const uint64_t n = a.n;

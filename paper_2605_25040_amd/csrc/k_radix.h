@@ -115,7 +115,7 @@ __device__ __forceinline__ void radix_hist_body(const Args& a, uint32_t bid, uin
             jw.pd_v[i] = to_dst ? jw.dst_v : jw.tmp_v;
             ck = jw.pd_k[i]; cv = jw.pd_v[i];
         }
-        if (np == 0) jw.copy_mode = inplace ? (jw.iota_vals ? 3u : 0u) : 1u;
+        if (np == 0) jw.copy_mode = inplace ? 0u : 1u;
         else jw.copy_mode = shift ? 2u : 0u;
     }
 }
@@ -194,7 +194,7 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
             const uint64_t pos = base + (uint64_t)wave * (64 * kRadixItems) + (uint64_t)i * 64 + lane;
             const bool ok = pos < n;
             key[i] = ok ? sk[pos] : 0;
-            if constexpr (VALS) val[i] = ok ? ((j.iota_vals && pass == 0) ? pos : sv[pos]) : 0;
+            if constexpr (VALS) val[i] = ok ? sv[pos] : 0;
             okm |= (ok ? 1u : 0u) << i;
         }
         // stable rank within the wave, item by item
@@ -297,16 +297,13 @@ __device__ __forceinline__ void radix_copy_body(const Args& a, uint32_t bid, uin
     const CAFS_GLOBAL uint64_t* sv = gp(j.copy_mode == 1 ? j.src_v : j.tmp_v);
     CAFS_GLOBAL uint64_t* dk = gp(j.dst_k);
     CAFS_GLOBAL uint64_t* dv = gp(j.dst_v);
-    const bool keys = j.copy_mode != 3;
     const bool vals = j.has_vals != 0;
-    // positions made, not copied, when no pass ran (every key equal)
-    const bool iota = j.iota_vals && j.copy_mode != 2;
     const uint64_t n = j.n;
     const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
     const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     for (uint64_t i = gtid; i < n; i += gstride) {
-        if (keys) dk[i] = sk[i];
-        if (vals) dv[i] = iota ? i : sv[i];
+        dk[i] = sk[i];
+        if (vals) dv[i] = sv[i];
     }
 }
 CAFS_KERNELS0(radix_copy, 256)
