@@ -99,10 +99,12 @@ struct Ctrl {
     uint32_t cap_limit;               // claimed slots allowed before overflow
     // tiny count
     uint64_t tiny_cnt[8];
-    // hash count
-    uint32_t overflow;
-    uint32_t claimed;
-    uint64_t ecount;                  // elements equal to kEmpty
+    // hash count.  Words that many workgroups update atomically, or poll while
+    // others update them, each get a 128-byte line of their own: a read of a line
+    // under atomic traffic waits behind it.
+    alignas(128) uint32_t overflow;
+    alignas(128) uint32_t claimed;
+    alignas(128) uint64_t ecount;     // elements equal to kEmpty
     // where the sorted column is when the radix engine ran (the output, or scratch
     // when sorting in place on the main path, copied out after the guard)
     uint64_t* sorted;
@@ -118,21 +120,21 @@ struct Ctrl {
     // radix
     RadixJob rj;
     uint64_t hist[8][256];
-    uint32_t hist_done;
-    uint32_t tile_ctr[8];
+    alignas(128) uint32_t hist_done;
+    alignas(128) uint32_t tile_ctr[8];  // (each pass's tiles are claimed from its own counter)
     // run-length pass over a sorted column
-    uint32_t rle_done;
+    alignas(128) uint32_t rle_done;
     uint32_t rle_on;
     // guard
     uint32_t guard_general;           // bucket counts must be built from the dense pairs
     uint32_t guard_rounds;            // too many contested keys for one workgroup
     uint32_t gidx_log2;               // hash index of the contested keys (0: binary search)
-    uint64_t n_contested;
+    alignas(128) uint64_t n_contested;
     uint64_t n_cbuckets;              // buckets holding more than four distinct keys
-    uint64_t buckets_done;            // of those, buckets whose first four keys are known
-    uint64_t found;
-    uint32_t chunk_ctr;
-    uint32_t guard_done;
+    alignas(128) uint64_t buckets_done;  // of those, buckets whose first four keys are known
+    alignas(128) uint64_t found;
+    alignas(128) uint32_t chunk_ctr;
+    alignas(128) uint32_t guard_done;
     uint64_t spill;
 };
 

@@ -154,7 +154,6 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
     const uint64_t tiles = (n + kRadixTile - 1) / kRadixTile;
     uint64_t* status = a.status + (pass & 1u) * a.status_slot;
     CAFS_GLOBAL uint64_t* status_next = gp(a.status) + ((pass + 1) & 1u) * a.status_slot;
-    const uint64_t* bases = c->hist[d];
 
     __shared__ uint64_t lk[kRadixTile];
     __shared__ uint64_t lv[VALS ? kRadixTile : 1];
@@ -163,6 +162,8 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
     __shared__ uint64_t gofs[256];
     __shared__ uint32_t s_tile;
     __shared__ uint32_t scan_tmp[8];
+    __shared__ uint64_t sbase[256];  // the digit's global bases, read once per workgroup
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) sbase[i] = c->hist[d][i];
 
     // clear the status words the next pass will use (the previous pass is done with them)
     {
@@ -243,7 +244,7 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
                 }
                 __hip_atomic_store(st, kStatInc | (excl + run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            gofs[dd] = bases[dd] + excl;
+            gofs[dd] = sbase[dd] + excl;
         }
         // tile-local digit offsets
         {
