@@ -116,8 +116,9 @@ void cafs_ctx_destroy(cafs_ctx_t* ctx);
  *   1 count  hash count, with its pass over deferred elements (one kernel) (Sec. 4.4)
  *   2 order  ranking of up to 32768 distinct keys, run offsets and the guard's
  *            bucket check, or the gather for a pair sort   (Alg. 4)
- *   3 emit   run expansion on the caller's stream (one kernel) (Alg. 4)
- *   4 tail   the rest until the report is written: the radix engine, the
+ *   3 emit   run expansion on the caller's stream: the row emit kernel (Alg. 4)
+ *   4 tail   the rest until the report is written: the tile emit (K > 32768
+ *            or N >= 2^32, and in-place calls, which emit after the guard), the radix engine, the
  *            larger pair sort and its emit, the monotone copy, the run-length
  *            pass and the guard run on a side stream of the context, forked
  *            after stage 2, and count here as far as they outlast the emit.

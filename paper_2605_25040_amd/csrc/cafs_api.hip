@@ -270,11 +270,10 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     // four workgroups per CU saturate the write bandwidth and leave CU slots free
     // for the side stream
     const uint32_t g_emit = grid_for(n, 2 * cafs::kEmitTilePairs, cus * 4);
-    if (countable && !inplace) {
-        cafs::k_emit_rows<<<std::min<uint32_t>(g_emit, cus), cafs::kEmitRowsThreads, 0, s>>>(a);
-        cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 2u);
-    }
+    if (countable && !inplace) cafs::k_emit_rows<<<std::min<uint32_t>(g_emit, cus), cafs::kEmitRowsThreads, 0, s>>>(a);
     mark(4);
+    // the tile emit, for the columns the row emit does not take (timed in the tail)
+    if (countable && !inplace) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 2u);
     launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2, countable);
     if (countable && n > cafs::kRankMax) {
         const uint32_t g_scan = std::min<uint32_t>(cus * 2, cafs::kMaxCountBlocks);
