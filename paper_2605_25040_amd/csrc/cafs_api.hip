@@ -257,7 +257,6 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
         cafs::k_rank<<<a.rank_blocks, 1024, 0, s>>>(a);
         cafs::k_compact_order<<<1, 1024, 0, s>>>(a);
     }
-    mark(3);
     // Fork: the branches that are idle on the common path (radix engine and pair
     // sort with their own emit, monotone copy, run-length pass, guard resolution)
     // run on the side stream and overlap the emit on the caller's stream.
@@ -267,6 +266,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     const bool inplace = (in == out);
     (void)hipEventRecord(ctx->fork, s);
     (void)hipStreamWaitEvent(s2, ctx->fork, 0);
+    mark(3);  // (after the fork record, so that the emit stage brackets the row emit only)
     // four workgroups per CU saturate the write bandwidth and leave CU slots free
     // for the side stream
     const uint32_t g_emit = grid_for(n, 2 * cafs::kEmitTilePairs, cus * 4);
