@@ -272,8 +272,10 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     const uint32_t g_emit = grid_for(n, 2 * cafs::kEmitTilePairs, cus * 4);
     if (countable && !inplace) cafs::k_emit_rows<<<std::min<uint32_t>(g_emit, cus), cafs::kEmitRowsThreads, 0, s>>>(a);
     mark(4);
-    // the tile emit, for the columns the row emit does not take (timed in the tail)
-    if (countable && !inplace) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 2u);
+    // the tile emit, for the columns the row emit does not take (N >= 2^32; timed in
+    // the tail); larger K is emitted after the pair sort on the side stream
+    const bool tile_main = n >= (1ull << 32);
+    if (countable && !inplace && tile_main) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 2u);
     launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2, countable);
     if (countable && n > cafs::kRankMax) {
         const uint32_t g_scan = std::min<uint32_t>(cus * 2, cafs::kMaxCountBlocks);
@@ -302,7 +304,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     (void)hipStreamWaitEvent(s, ctx->join, 0);
     if (countable && inplace) {
         cafs::k_emit_rows<<<std::min<uint32_t>(g_emit, cus), cafs::kEmitRowsThreads, 0, s>>>(a);
-        cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 2u);
+        if (tile_main) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 2u);
     }
     cafs::k_finalize<<<1, 64, 0, s>>>(a);
     mark(5);
