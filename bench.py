@@ -70,9 +70,19 @@ def cpu_baseline(x_np, seconds_hint):
         oracle.sort(sample)
         dt = time.perf_counter() - t0
         best = dt if best is None else min(best, dt)
+    # a plain std::sort of the same sample, one thread, beside it
+    best_std = None
+    for _ in range(2):
+        t0 = time.perf_counter()
+        oracle.std_sort_i64(sample)
+        dt = time.perf_counter() - t0
+        best_std = dt if best_std is None else min(best_std, dt)
     return {"value": m / best / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
             "sample": "first %d keys of the same column (std::map count + emit, single thread, min of 2 runs, %.2f s each)"
-                      % (m, best)}
+                      % (m, best),
+            "std_sort": {"value": m / best_std / 1e9, "unit": "Gkeys/s", "cores": 1,
+                         "sample": "the same keys, std::sort of a copy, single thread, min of 2 runs, %.2f s each"
+                                   % best_std}}
 
 
 def pct(a, q):

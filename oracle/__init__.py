@@ -46,7 +46,7 @@ def _load():
             build()
         lib = ctypes.CDLL(_LIB_PATH)
         p, u64 = ctypes.c_void_p, ctypes.c_uint64
-        for name in ("oracle_sort_i64", "oracle_sort_u64"):
+        for name in ("oracle_sort_i64", "oracle_sort_u64", "oracle_std_sort_i64"):
             getattr(lib, name).argtypes = [p, u64, p]
             getattr(lib, name).restype = None
         for name in ("oracle_counts_i64", "oracle_counts_u64"):
@@ -89,6 +89,14 @@ def sort(x, dtype=np.int64):
     y = np.empty_like(a)
     fn = _load().oracle_sort_i64 if a.dtype == np.int64 else _load().oracle_sort_u64
     fn(_ptr(a), a.size, _ptr(y))
+    return y
+
+
+def std_sort_i64(x):
+    """Sorted copy of an int64 array by a plain single-thread std::sort."""
+    a = _arr(x, np.int64)
+    y = np.empty_like(a)
+    _load().oracle_std_sort_i64(_ptr(a), a.size, _ptr(y))
     return y
 
 

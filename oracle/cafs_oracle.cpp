@@ -233,6 +233,13 @@ extern "C" {
 void oracle_sort_i64(const int64_t* x, uint64_t n, int64_t* y) { sort_by_map(x, n, y); }
 void oracle_sort_u64(const uint64_t* x, uint64_t n, uint64_t* y) { sort_by_map(x, n, y); }
 
+// A plain comparison sort of a copy (std::sort, one thread): the reference point
+// the paper times its sorts against, reported beside the oracle's own time.
+void oracle_std_sort_i64(const int64_t* x, uint64_t n, int64_t* y) {
+    std::memcpy(y, x, n * sizeof(int64_t));
+    std::sort(y, y + n);
+}
+
 uint64_t oracle_counts_i64(const int64_t* x, uint64_t n, int64_t* uniq, uint64_t* counts) {
     return counts_by_map(x, n, uniq, counts);
 }

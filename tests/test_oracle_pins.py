@@ -305,3 +305,13 @@ def test_zipf_sweep_reports_main_path():
     r = oracle.report(x)
     assert r["path"] == "MAIN" and r["k_hat"] < r["k_exact"]
     assert r["table_M"] == oracle.table_M(r["k_hat"], x.size)
+
+
+def test_std_sort_baseline_is_a_sort():
+    """The std::sort baseline the bench reports beside the oracle sorts (numpy agrees),
+    extremes and duplicates included."""
+    rng = np.random.default_rng(11)
+    x = np.concatenate([rng.integers(-2**63, 2**63 - 1, size=5000, dtype=np.int64),
+                        np.array([-2**63, 2**63 - 1, 0, -1, 0, -2**63], dtype=np.int64)])
+    assert np.array_equal(oracle.std_sort_i64(x), np.sort(x))
+    assert oracle.std_sort_i64(np.empty(0, dtype=np.int64)).size == 0
