@@ -207,13 +207,13 @@ __device__ __forceinline__ void list_claims(const GTable& t, uint32_t h) {
 // W = 4 (3392 buckets, like the paper's) when the estimate is large, W = 2 (6784
 // buckets) below kLdsWideMinKhat, where a bucket rarely overflows and a lookup
 // then takes one 16-byte LDS load instead of two (LDS load instructions are what
-// the loop pays for; measured crossover near K = 1800 at N = 2^28).  An element hashes to a bucket (Eq. hash, reduced to the
-// bucket count by a multiply), reads its W keys with 16-byte LDS loads and
-// compares them with the element, the GPU analogue of the paper's cmpeq +
-// movemask + tzcnt; on a match it adds 1 to that slot's counter with an LDS
-// atomic.  Within a bucket occupied slots form a prefix and a
-// key is stored in the first bucket, in probe order, that had room for it, so a
-// lookup can stop at the first bucket with a free slot.  Lookups cover the home
+// the loop pays for; measured crossover near K = 1800 at N = 2^28).  An element
+// hashes to a bucket (Eq. hash, reduced to the bucket count by a multiply), reads
+// its W keys with 16-byte LDS loads and compares them with the element, the GPU
+// analogue of the paper's cmpeq + movemask + tzcnt; on a match it adds 1 to that
+// slot's counter with an LDS atomic.  Within a bucket occupied slots form a
+// prefix and a key is stored in the first bucket, in probe order, that had room
+// for it, so a lookup can stop at the first bucket with a free slot.  Lookups cover the home
 // bucket and, when that one is full, the next one (the window), as straight-line
 // code for the eight keys a thread holds while the loads of its next eight keys
 // are in flight.  A key absent from a window with room is inserted by a 64-bit

@@ -94,6 +94,10 @@ SEEDED = [
     (1 << 23, 10_000, "zipf", 1.1, "random"),
     (1 << 23, 20_000, "uniform", 1.1, "random"),     # beyond the LDS table: deferred pass overflows to global
     (3_000_001, 100_000, "uniform", 1.1, "random"),  # deferral regions fill up
+    # estimates on both sides of the LDS bucket width switch (2 keys below 1800, 4 above)
+    (2_000_000, 1_700, "uniform", 1.1, "random"),
+    (2_000_000, 1_900, "uniform", 1.1, "random"),
+    (1 << 23, 20_000, "zipf", 1.1, "random"),        # estimate ~2200 for 20000 keys: table far past capacity
 ]
 
 
