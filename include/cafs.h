@@ -204,6 +204,18 @@ cafs_status_t cafs_sort_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, ui
  * autotuner (cafs_autotune_batched) picks them by timing. */
 cafs_status_t cafs_ctx_set_batch_tuning(cafs_ctx_t* ctx, uint64_t elems_per_block, uint64_t elems_per_hash_block);
 
+/* Seeds the hash of the GPU's count tables (the per-workgroup LDS tables and the
+ * global table), against the deterministic-collision attack of a fixed hash (Sec.
+ * Limitations; a randomised seed is named in Sec. Future directions).  The hash is
+ * multiply-shift: seed 0 (the default) keeps the multiplier of Eq. hash; any other
+ * seed selects the odd multiplier (SplitMix64 output of the seed) | 1, a member of
+ * the universal multiply-shift family, so that keys chosen to collide under one
+ * multiplier spread under another.  Sorted output, counts and report do not depend
+ * on the seed: the spill guard keeps Eq. hash, since the report follows the paper's
+ * bucket table (Alg. 1).  Affects calls enqueued after it on this context (single,
+ * batched and served).  CAFS_EINVAL for a null context. */
+cafs_status_t cafs_ctx_set_hash_seed(cafs_ctx_t* ctx, uint64_t seed);
+
 /* Autotuner of the batched block sizing: times the batch (synchronously, three
  * runs per candidate, candidates 2^15..2^18 and 2^17..2^20 elements per block)
  * and keeps the fastest in the context.  The batch is sorted several times, so

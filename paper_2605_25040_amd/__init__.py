@@ -23,7 +23,7 @@ STAGES = ("pre", "count", "order", "emit", "tail")
 EXPORTS = ("cafs_ctx_create", "cafs_ctx_destroy", "cafs_ctx_enable_timing", "cafs_ctx_stage_ms",
            "cafs_workspace_bytes", "cafs_estimate",
            "cafs_sort_i64", "cafs_sort_u64", "cafs_radix_sort", "cafs_batched_workspace_bytes",
-           "cafs_sort_batched", "cafs_ctx_set_batch_tuning", "cafs_autotune_batched",
+           "cafs_sort_batched", "cafs_ctx_set_batch_tuning", "cafs_autotune_batched", "cafs_ctx_set_hash_seed",
            "cafs_server_create", "cafs_server_destroy", "cafs_server_reserve", "cafs_server_submit",
            "cafs_server_poll", "cafs_server_release", "cafs_server_stats",
            "cafs_status_str", "cafs_last_error")
@@ -87,6 +87,8 @@ def load():
     lib.cafs_sort_batched.restype = i32
     lib.cafs_ctx_set_batch_tuning.argtypes = [p, u64, u64]
     lib.cafs_ctx_set_batch_tuning.restype = i32
+    lib.cafs_ctx_set_hash_seed.argtypes = [p, u64]
+    lib.cafs_ctx_set_hash_seed.restype = i32
     lib.cafs_autotune_batched.argtypes = [p, p, u32, p, ctypes.c_size_t, p, ctypes.POINTER(ctypes.c_double)]
     lib.cafs_autotune_batched.restype = i32
     lib.cafs_server_create.argtypes = [p, ctypes.c_size_t, u32, u32, ctypes.POINTER(p)]
@@ -234,6 +236,10 @@ class Context:
 
     def set_batch_tuning(self, elems_per_block, elems_per_hash_block):
         _check(self._lib.cafs_ctx_set_batch_tuning(self._h, int(elems_per_block), int(elems_per_hash_block)))
+
+    def set_hash_seed(self, seed):
+        """Seed of the count tables' hash (0: the paper's multiplier)."""
+        _check(self._lib.cafs_ctx_set_hash_seed(self._h, int(seed) & (2**64 - 1)))
 
     def autotune_batched(self, cols, ws=None):
         arr = self._columns(cols)

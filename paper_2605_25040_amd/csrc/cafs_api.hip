@@ -34,6 +34,7 @@ struct cafs_ctx {
     std::vector<void*> captured_staging;  // staging buffers referenced by captured graphs
     uint64_t batch_per_block;       // batched launch: elements per block of the general kernels
     uint64_t batch_per_hash_block;  // and of the hash count
+    uint64_t table_mul;             // odd multiplier of the count tables' hash
     bool timing;
     std::vector<hipEvent_t> pool;                 // free events
     std::vector<std::vector<hipEvent_t>> calls;   // CAFS_N_STAGES + 1 events per recorded call
@@ -195,6 +196,7 @@ cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void*
     a.rank_blocks = rank_grid(n);
     a.rank_budget_log2 = cafs::kRankBudgetLog2;
     a.row_blocks = ctx ? (uint32_t)ctx->cus : 256u;
+    a.table_mul = ctx ? ctx->table_mul : cafs::kPhi;
     return a;
 }
 
@@ -356,6 +358,7 @@ cafs_status_t cafs_ctx_create(cafs_ctx_t** ctx, int device) {
     c->staged_pending = false;
     c->batch_per_block = 1ull << 16;
     c->batch_per_hash_block = 1ull << 18;
+    c->table_mul = cafs::kPhi;
     {
         DeviceGuard dg(device);
         e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
@@ -625,6 +628,21 @@ cafs_status_t cafs_ctx_set_batch_tuning(cafs_ctx_t* ctx, uint64_t elems_per_bloc
     if (!ctx || elems_per_block == 0 || elems_per_hash_block == 0) return CAFS_EINVAL;
     ctx->batch_per_block = elems_per_block;
     ctx->batch_per_hash_block = elems_per_hash_block;
+    return CAFS_OK;
+}
+
+cafs_status_t cafs_ctx_set_hash_seed(cafs_ctx_t* ctx, uint64_t seed) {
+    if (!ctx) return CAFS_EINVAL;
+    if (seed == 0) {
+        ctx->table_mul = cafs::kPhi;
+        return CAFS_OK;
+    }
+    // SplitMix64 output for the seed (Steele, Lea and Flood), made odd
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    ctx->table_mul = z | 1ull;
     return CAFS_OK;
 }
 

@@ -174,6 +174,7 @@ struct Args {
     uint32_t rank_blocks;             // workgroups of this column's ranking kernel
     uint32_t rank_budget_log2;        // compares per ranking workgroup allowed
     uint32_t row_blocks;              // workgroups of the row emit's sweep
+    uint64_t table_mul;               // odd multiplier of the count tables' hash (kPhi unless seeded)
     // run-length scratch
     uint64_t* rle_tile;               // per-tile run counts
     uint64_t* psum;                   // kMaxCountBlocks chunk sums of the pair scan
@@ -234,6 +235,18 @@ __device__ __forceinline__ T g_load(const T* p) {
 // Multiplicative hash of Eq. hash: top `bits` bits of x * phi mod 2^64.
 __device__ __forceinline__ uint32_t phi_hash(uint64_t x, uint32_t bits) {
     return (uint32_t)((x * kPhi) >> (64 - bits));
+}
+
+// Multiply-shift with another odd multiplier `mul` (the count tables' hash; kPhi
+// gives Eq. hash), in full and on 32-bit halves for bits <= 32.
+__device__ __forceinline__ uint32_t mul_hash(uint64_t x, uint32_t bits, uint64_t mul) {
+    return (uint32_t)((x * mul) >> (64 - bits));
+}
+__device__ __forceinline__ uint32_t mul_hash32(uint64_t x, uint32_t bits, uint64_t mul) {
+    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    const uint32_t mlo = (uint32_t)mul, mhi = (uint32_t)(mul >> 32);
+    const uint32_t top = __umulhi(lo, mlo) + lo * mhi + hi * mlo;
+    return top >> (32 - bits);
 }
 
 // The same hash on 32-bit halves, for bits <= 32: only the high word of the

@@ -122,6 +122,7 @@ struct GTable {
     uint64_t* tmp_k;
     uint64_t* uniq;
     uint32_t inplace;
+    uint64_t mul;  // the count tables' hash multiplier
 };
 
 __device__ __forceinline__ GTable gtable(const Args& a) {
@@ -133,6 +134,7 @@ __device__ __forceinline__ GTable gtable(const Args& a) {
     t.tmp_k = a.tmp_k;
     t.uniq = a.uniq;
     t.inplace = a.in == a.out;
+    t.mul = a.table_mul;
     return t;
 }
 
@@ -161,7 +163,7 @@ __device__ __forceinline__ uint32_t global_insert(const GTable& t, uint64_t v, u
     Ctrl* c = t.c;
     const uint32_t lg = c->cap_log2;
     const uint64_t mask = (1ull << lg) - 1;
-    uint64_t h = phi_hash(v, lg);
+    uint64_t h = mul_hash(v, lg, t.mul);
     for (uint32_t pr = 0; pr < kGlobalProbe; ++pr) {
         if (pr % kGlobalProbeCheck == kGlobalProbeCheck - 1 && g_load(&c->overflow)) return kNoSlot;
         uint64_t k = g_load(&t.keys[h]);
@@ -235,8 +237,8 @@ struct LdsGeo {
 };
 
 template <uint32_t W>
-__device__ __forceinline__ uint32_t lds_bucket(uint64_t x) {
-    return (uint32_t)(((uint64_t)phi_hash32(x, 32) * LdsGeo<W>::kBuckets) >> 32);
+__device__ __forceinline__ uint32_t lds_bucket(uint64_t x, uint64_t mul) {
+    return (uint32_t)(((uint64_t)mul_hash32(x, 32, mul) * LdsGeo<W>::kBuckets) >> 32);
 }
 
 template <uint32_t W>
@@ -248,8 +250,8 @@ __device__ __forceinline__ uint32_t next_bucket(uint32_t b) {
 // `add` to its counter.  Returns false when those buckets are full without x.
 template <uint32_t W>
 __device__ __forceinline__ bool lds_insert(uint64_t* skeys, uint32_t* scnt, uint64_t x, uint32_t add,
-                                           uint32_t window) {
-    uint32_t b = lds_bucket<W>(x);
+                                           uint32_t window, uint64_t mul) {
+    uint32_t b = lds_bucket<W>(x, mul);
     for (uint32_t pr = 0; pr < window; ++pr) {
         const uint32_t base = b * W;
         for (uint32_t s = 0; s < W; ++s) {
@@ -291,12 +293,12 @@ __device__ __forceinline__ int match_bucket(const uint64_t* skeys, uint32_t b, u
 template <int NE, uint32_t W>
 __device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, uint32_t* __restrict__ scnt,
                                                 uint32_t* __restrict__ sink, const uint64_t (&x)[NE],
-                                                uint32_t want_m) {
+                                                uint32_t want_m, uint64_t mul) {
     uint32_t ins = 0, dfr = 0;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
         const bool want = (want_m >> e) & 1u;
-        uint32_t b = lds_bucket<W>(x[e]);
+        uint32_t b = lds_bucket<W>(x[e], mul);
         bool full;
         int m = match_bucket<W>(skeys, b, x[e], full);
         if (m < 0 && full) {  // home bucket full without x: x may be in the next one
@@ -316,7 +318,7 @@ __device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, ui
     if (ins) {
 #pragma unroll
         for (int e = 0; e < NE; ++e)
-            if (((ins >> e) & 1u) && !lds_insert<W>(skeys, scnt, x[e], 1u, kLdsWindow)) dfr |= 1u << e;
+            if (((ins >> e) & 1u) && !lds_insert<W>(skeys, scnt, x[e], 1u, kLdsWindow, mul)) dfr |= 1u << e;
     }
     return dfr;
 }
@@ -345,7 +347,7 @@ __device__ __forceinline__ void flush_table(const GTable& t, const uint64_t* ske
             const uint32_t i = i0 + u * blockDim.x;
             cn[u] = i < S ? scnt[i] : 0u;  // slot i / B of bucket i % B; never 0 once claimed
             key[u] = cn[u] ? skeys[(i % B) * W + i / B] : 0;
-            h[u] = phi_hash(key[u], lg);
+            h[u] = mul_hash(key[u], lg, t.mul);
         }
 #pragma unroll
         for (int u = 0; u < F; ++u) k[u] = cn[u] ? g_load(&t.keys[h[u]]) : kEmpty;
@@ -491,7 +493,7 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
             ecnt += is_empty_key ? 1u : 0u;
             want &= is_empty_key ? ~(1u << e) : ~0u;
         }
-        const uint32_t dfr = count_batch<NE, W>(skeys, scnt, s_sink, x, want);
+        const uint32_t dfr = count_batch<NE, W>(skeys, scnt, s_sink, x, want, t.mul);
         if (__ballot(dfr != 0)) {
             // append the deferred elements: one LDS reservation per wave, then each
             // element's place from the ballot of its batch position
@@ -543,7 +545,7 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
             xd[u] = i < d ? region[i] : 0;
             want |= (i < d ? 1u : 0u) << u;
         }
-        const uint32_t dfr = count_batch<D, W>(skeys, scnt, s_sink, xd, want);
+        const uint32_t dfr = count_batch<D, W>(skeys, scnt, s_sink, xd, want, t.mul);
         uint32_t cl[D];
 #pragma unroll
         for (int u = 0; u < D; ++u) cl[u] = kNoSlot;
@@ -551,7 +553,7 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
         if (dfr && !ov) {
 #pragma unroll
             for (int u = 0; u < D; ++u) {
-                if (((dfr >> u) & 1u) && !lds_insert<W>(skeys, scnt, xd[u], 1u, kLdsProbeBuckets)) {
+                if (((dfr >> u) & 1u) && !lds_insert<W>(skeys, scnt, xd[u], 1u, kLdsProbeBuckets, t.mul)) {
                     atomicAdd(&s_ndef, 1u);
                     cl[u] = global_insert(t, xd[u], 1);
                 }

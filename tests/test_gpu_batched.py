@@ -108,3 +108,32 @@ def test_batch_equals_single_calls(ctx):
     # oracle on a sample of columns
     sub = [cols[i] for i in range(0, m, 29)]
     check_cols(sub, "sample")
+
+
+def test_batch_hash_seed(ctx):
+    """A seeded context hashes every column of a batch with its multiplier: keys
+    that all collide under Eq. hash stay on the hash count, and the outputs,
+    counts and reports equal the oracle's."""
+    import paper_2605_25040_amd as cafs
+    phi = 0x9E3779B97F4A7C15
+    inv = pow(phi, -1, 1 << 64)
+    pal = np.array([(((0x3C3C3C3C << 32) + i) * inv) % (1 << 64) for i in range(1500)], dtype=np.uint64)
+    rng = np.random.default_rng(8)
+    arrays = []
+    for n in (400_000, 90_000, 700_001):
+        x = pal[rng.integers(0, pal.size, size=n)]
+        x[: pal.size] = pal
+        arrays.append(x)
+    spec = gen.batch_spec(40, seed=21, n_lo=1e3, n_hi=3e5, k_cap=3e4)
+    arrays += [gen.column(c["n"], c["k"], dist=c["dist"], s=c["s"], seed=c["seed"], dtype=np.uint64) for c in spec]
+    m = len(arrays)
+    try:
+        ctx.set_hash_seed(99)
+        cols = make_cols(arrays, [True] * m, [True] * m, [True] * m)
+        ctx.sort_batched(cols)
+        check_cols(cols, "seeded")
+        for c in cols[:3]:
+            r = cafs.parse_report(c["report"])
+            assert r["engine"] == "HASH" and not (r["flags"] & 1), r
+    finally:
+        ctx.set_hash_seed(0)

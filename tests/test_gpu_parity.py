@@ -252,3 +252,38 @@ def test_emit_crowded_segment(ctx, n):
         r = check(ctx, x.view(np.uint64), False, label="crowded n=%d shift=%d" % (n, shift_out),
                   shift_out=shift_out)
         assert r["k_exact"] == k and r["path"] == "MAIN" and r["engine"] == "HASH"
+
+
+def _colliding_keys(k):
+    """k distinct keys whose products with the multiplier of Eq. hash share their top
+    32 bits (y * phi^-1 mod 2^64 for y with equal high words): one bucket of every
+    table hashed with that multiplier."""
+    phi = 0x9E3779B97F4A7C15
+    inv = pow(phi, -1, 1 << 64)
+    top = 0x5A5A5A5A << 32
+    return np.array([((top + i) * inv) % (1 << 64) for i in range(k)], dtype=np.uint64)
+
+
+@pytest.mark.gpu
+def test_hash_seed(ctx):
+    """Seeded count tables: outputs, counts and reports equal the oracle's for any
+    seed; keys that all collide under the paper's multiplier overflow the tables
+    without a seed and stay on the hash count with one."""
+    rng = np.random.default_rng(77)
+    pal = _colliding_keys(2000)
+    x_col = pal[rng.integers(0, pal.size, size=1_000_000)]
+    x_col[: pal.size] = pal
+    cols = [gen.column(1_000_000, 1000, dist="zipf", s=1.0, palette="random", dtype=np.uint64),
+            gen.column(1 << 22, 12_000, dist="uniform", palette="random", dtype=np.uint64),
+            gen.column(2_000_000, 200_000, dist="zipf", s=1.1, palette="random", dtype=np.uint64)]
+    try:
+        r0 = check(ctx, x_col, True, label="colliding, default multiplier")
+        assert r0["flags"] & 1, "colliding keys were expected to overflow the fixed-multiplier tables"
+        for seed in (1, 2**63 + 5, 123456789):
+            ctx.set_hash_seed(seed)
+            r = check(ctx, x_col, True, label="colliding, seed %d" % seed)
+            assert r["engine"] == "HASH" and not (r["flags"] & 1), r
+            for i, x in enumerate(cols):
+                check(ctx, x, False, label="seed %d column %d" % (seed, i))
+    finally:
+        ctx.set_hash_seed(0)
