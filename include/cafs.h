@@ -27,8 +27,12 @@
  *     nothing has been enqueued, except CAFS_EHIP, which reports a failed
  *     launch; cafs_last_error() then holds the HIP error string.
  *   - Keys are 64-bit.  CAFS_I64 orders them as signed integers, CAFS_U64 as
- *     unsigned; equality (used by the estimate, the counts and the guard's
- *     buckets) is on the raw 64-bit pattern.
+ *     unsigned, CAFS_F64 as IEEE 754 doubles in totalOrder (-NaN < -inf < ...
+ *     < -0 < +0 < ... < +inf < +NaN; NaNs by payload: the floating-point variant
+ *     through the bit pattern that the paper lists as future work, Sec. Future
+ *     directions); equality (used by the estimate, the counts and the guard's
+ *     buckets) is on the raw 64-bit pattern, so -0 and +0 are distinct keys and
+ *     so are NaNs with different payloads.
  *   - N must be below 2^32.
  */
 #ifndef CAFS_H
@@ -53,7 +57,7 @@ typedef enum {
     CAFS_EBUSY = -6         /* server: the request does not fit the memory budget now */
 } cafs_status_t;
 
-typedef enum { CAFS_I64 = 0, CAFS_U64 = 1 } cafs_dtype_t;
+typedef enum { CAFS_I64 = 0, CAFS_U64 = 1, CAFS_F64 = 2 } cafs_dtype_t;
 
 /* Branch chosen by the dispatcher (Alg. 3), in the order it tests them. */
 typedef enum {
@@ -160,6 +164,10 @@ cafs_status_t cafs_sort_i64(cafs_ctx_t* ctx, const int64_t* d_in, int64_t* d_out
                             void* d_ws, size_t ws_bytes, void* stream);
 cafs_status_t cafs_sort_u64(cafs_ctx_t* ctx, const uint64_t* d_in, uint64_t* d_out, uint64_t n,
                             uint64_t* d_uniq, uint64_t* d_counts, cafs_report_t* d_report,
+                            void* d_ws, size_t ws_bytes, void* stream);
+/* Doubles in totalOrder (CAFS_F64); d_uniq receives the distinct values. */
+cafs_status_t cafs_sort_f64(cafs_ctx_t* ctx, const double* d_in, double* d_out, uint64_t n,
+                            double* d_uniq, uint64_t* d_counts, cafs_report_t* d_report,
                             void* d_ws, size_t ws_bytes, void* stream);
 
 /* The fallback engine on its own: LSD radix sort with 8-bit digits and decoupled

@@ -46,16 +46,16 @@ def _load():
             build()
         lib = ctypes.CDLL(_LIB_PATH)
         p, u64 = ctypes.c_void_p, ctypes.c_uint64
-        for name in ("oracle_sort_i64", "oracle_sort_u64", "oracle_std_sort_i64"):
+        for name in ("oracle_sort_i64", "oracle_sort_u64", "oracle_sort_f64", "oracle_std_sort_i64"):
             getattr(lib, name).argtypes = [p, u64, p]
             getattr(lib, name).restype = None
-        for name in ("oracle_counts_i64", "oracle_counts_u64"):
+        for name in ("oracle_counts_i64", "oracle_counts_u64", "oracle_counts_f64"):
             getattr(lib, name).argtypes = [p, u64, p, p]
             getattr(lib, name).restype = u64
-        for name in ("oracle_is_monotone_i64", "oracle_is_monotone_u64"):
+        for name in ("oracle_is_monotone_i64", "oracle_is_monotone_u64", "oracle_is_monotone_f64"):
             getattr(lib, name).argtypes = [p, u64]
             getattr(lib, name).restype = ctypes.c_int
-        for name in ("oracle_estimate", "oracle_report_i64", "oracle_report_u64"):
+        for name in ("oracle_estimate", "oracle_report_i64", "oracle_report_u64", "oracle_report_f64"):
             getattr(lib, name).argtypes = [p, u64, p]
             getattr(lib, name).restype = None
         lib.oracle_sample_keys.argtypes = [p, u64, p]
@@ -73,10 +73,17 @@ def _load():
 def _arr(x, dtype):
     a = np.ascontiguousarray(x)
     if a.dtype != dtype:
-        if a.dtype.itemsize != 8 or a.dtype.kind not in "iu":
-            raise TypeError("oracle takes 64-bit integer arrays")
+        if a.dtype.itemsize != 8 or a.dtype.kind not in "iuf":
+            raise TypeError("oracle takes 64-bit integer or float64 arrays")
         a = a.view(dtype)
     return a
+
+
+def _kind(dtype):
+    """Suffix of the oracle function for ``dtype``: int64, uint64 or float64 (IEEE
+    754 totalOrder on the bit patterns)."""
+    d = np.dtype(dtype)
+    return {"i": "i64", "u": "u64", "f": "f64"}[d.kind]
 
 
 def _ptr(a):
@@ -87,8 +94,7 @@ def sort(x, dtype=np.int64):
     """Sorted copy of ``x`` (nondecreasing in ``dtype``'s order)."""
     a = _arr(x, dtype)
     y = np.empty_like(a)
-    fn = _load().oracle_sort_i64 if a.dtype == np.int64 else _load().oracle_sort_u64
-    fn(_ptr(a), a.size, _ptr(y))
+    getattr(_load(), "oracle_sort_" + _kind(dtype))(_ptr(a), a.size, _ptr(y))
     return y
 
 
@@ -105,15 +111,13 @@ def counts(x, dtype=np.int64):
     a = _arr(x, dtype)
     uniq = np.empty_like(a)
     cnt = np.empty(a.size, dtype=np.uint64)
-    fn = _load().oracle_counts_i64 if a.dtype == np.int64 else _load().oracle_counts_u64
-    k = fn(_ptr(a), a.size, _ptr(uniq), _ptr(cnt))
+    k = getattr(_load(), "oracle_counts_" + _kind(dtype))(_ptr(a), a.size, _ptr(uniq), _ptr(cnt))
     return uniq[:k].copy(), cnt[:k].copy()
 
 
 def is_monotone(x, dtype=np.int64):
     a = _arr(x, dtype)
-    fn = _load().oracle_is_monotone_i64 if a.dtype == np.int64 else _load().oracle_is_monotone_u64
-    return bool(fn(_ptr(a), a.size))
+    return bool(getattr(_load(), "oracle_is_monotone_" + _kind(dtype))(_ptr(a), a.size))
 
 
 def estimate(x):
@@ -151,8 +155,7 @@ def report(x, dtype=np.int64):
     """Full dispatcher report (Alg. 3 + Alg. 4) as a dict with a path name."""
     a = _arr(x, dtype)
     out = np.zeros(12, dtype=np.uint64)
-    fn = _load().oracle_report_i64 if a.dtype == np.int64 else _load().oracle_report_u64
-    fn(_ptr(a), a.size, _ptr(out))
+    getattr(_load(), "oracle_report_" + _kind(dtype))(_ptr(a), a.size, _ptr(out))
     r = {k: int(v) for k, v in zip(REPORT_FIELDS, out)}
     r["path"] = PATHS[r["path"]]
     return r

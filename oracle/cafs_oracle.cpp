@@ -108,6 +108,24 @@ bool is_monotone(const T* x, uint64_t n) {
     return true;
 }
 
+// IEEE 754 double in totalOrder (IEEE 754-2008, Sec. 5.10), held as its bit
+// pattern: a set sign bit orders before a clear one; among values with a clear
+// sign bit a larger pattern is a larger value (+0 < subnormals < normals < +inf <
+// NaNs by payload), among values with a set sign bit a larger pattern is a
+// smaller value.  Two doubles are equal exactly when their patterns are, so -0
+// and +0 are distinct keys, as are NaNs with different payloads.  This is the
+// floating-point variant through the bit pattern that the paper names as future
+// work (Sec. Future directions).
+struct TotalF64 {
+    uint64_t bits;
+    bool operator<(const TotalF64& o) const {
+        const bool na = (bits >> 63) != 0, nb = (o.bits >> 63) != 0;
+        if (na != nb) return na;
+        return na ? bits > o.bits : bits < o.bits;
+    }
+};
+static_assert(sizeof(TotalF64) == 8, "same layout as the column");
+
 struct Estimate {
     uint64_t k_hat, u, f1, f2, n_samples, stride, saturated;
     std::vector<uint64_t> sample_keys;  // distinct sampled values (bit patterns)
@@ -269,6 +287,18 @@ uint64_t oracle_hash(uint64_t v, uint64_t M) { return bucket_of(v, M); }
 uint64_t oracle_spill(const uint64_t* x, uint64_t n, uint64_t M) { return simulate_spill(x, n, M); }
 
 void oracle_report_i64(const int64_t* x, uint64_t n, uint64_t* out) { flatten(dispatch(x, n), out); }
+void oracle_report_f64(const uint64_t* x, uint64_t n, uint64_t* out) {
+    flatten(dispatch(reinterpret_cast<const TotalF64*>(x), n), out);
+}
+void oracle_sort_f64(const uint64_t* x, uint64_t n, uint64_t* y) {
+    sort_by_map(reinterpret_cast<const TotalF64*>(x), n, reinterpret_cast<TotalF64*>(y));
+}
+uint64_t oracle_counts_f64(const uint64_t* x, uint64_t n, uint64_t* uniq, uint64_t* counts) {
+    return counts_by_map(reinterpret_cast<const TotalF64*>(x), n, reinterpret_cast<TotalF64*>(uniq), counts);
+}
+int oracle_is_monotone_f64(const uint64_t* x, uint64_t n) {
+    return is_monotone(reinterpret_cast<const TotalF64*>(x), n) ? 1 : 0;
+}
 void oracle_report_u64(const uint64_t* x, uint64_t n, uint64_t* out) { flatten(dispatch(x, n), out); }
 
 }  // extern "C"

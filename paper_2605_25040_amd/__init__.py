@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libcafs.so")
 
 PATHS = ("MONOTONE", "SMALL_N", "TINY", "HIGH_K", "MAIN", "GUARD")
 ENGINES = ("NONE", "TINY", "HASH", "RADIX")
-I64, U64 = 0, 1
+I64, U64, F64 = 0, 1, 2
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "HIP error", -4: "unsupported", -5: "nomem",
           -6: "busy"}
 
@@ -22,7 +22,7 @@ STAGES = ("pre", "count", "order", "emit", "tail")
 
 EXPORTS = ("cafs_ctx_create", "cafs_ctx_destroy", "cafs_ctx_enable_timing", "cafs_ctx_stage_ms",
            "cafs_workspace_bytes", "cafs_estimate",
-           "cafs_sort_i64", "cafs_sort_u64", "cafs_radix_sort", "cafs_batched_workspace_bytes",
+           "cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64", "cafs_radix_sort", "cafs_batched_workspace_bytes",
            "cafs_sort_batched", "cafs_ctx_set_batch_tuning", "cafs_autotune_batched", "cafs_ctx_set_hash_seed",
            "cafs_server_create", "cafs_server_destroy", "cafs_server_reserve", "cafs_server_submit",
            "cafs_server_poll", "cafs_server_release", "cafs_server_stats",
@@ -76,7 +76,7 @@ def load():
     lib.cafs_workspace_bytes.restype = ctypes.c_size_t
     lib.cafs_estimate.argtypes = [p, p, u64, p, p]
     lib.cafs_estimate.restype = i32
-    for name in ("cafs_sort_i64", "cafs_sort_u64"):
+    for name in ("cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64"):
         getattr(lib, name).argtypes = [p, p, p, u64, p, p, p, p, ctypes.c_size_t, p]
         getattr(lib, name).restype = i32
     lib.cafs_radix_sort.argtypes = [p, p, p, u64, i32, p, ctypes.c_size_t, p]
@@ -180,22 +180,24 @@ class Context:
         return {k: int(getattr(e, k)) for k, _ in Estimate._fields_ if k != "pad"}
 
     def sort(self, x, unsigned=False, out=None, counts=False, report=True, ws=None):
-        """Sort a 1-D int64 tensor on the GPU (uint64 order if ``unsigned``).
+        """Sort a 1-D int64 tensor on the GPU (uint64 order if ``unsigned``), or a
+        float64 tensor in IEEE 754 totalOrder.
 
         Returns (out, report_tensor, uniq, counts); uniq/counts are None unless
         ``counts``.  Call ``parse_report`` on the report tensor after a sync.
         """
         n = x.numel()
-        if x.dtype != torch.int64 or not x.is_cuda:
-            raise CafsError("sort takes a CUDA int64 tensor")
+        if x.dtype not in (torch.int64, torch.float64) or not x.is_cuda:
+            raise CafsError("sort takes a CUDA int64 or float64 tensor")
         if out is None:
             out = torch.empty_like(x)
         rep = torch.zeros(ctypes.sizeof(Report), dtype=torch.uint8, device=self.device) if (report or counts) else None
         uq = torch.empty_like(x) if counts else None
-        ct = torch.empty_like(x) if counts else None
+        ct = torch.empty(n, dtype=torch.int64, device=x.device) if counts else None
         if ws is None:
             ws = self.workspace(self.workspace_bytes(n))
-        fn = self._lib.cafs_sort_u64 if unsigned else self._lib.cafs_sort_i64
+        fn = (self._lib.cafs_sort_f64 if x.dtype == torch.float64 else
+              self._lib.cafs_sort_u64 if unsigned else self._lib.cafs_sort_i64)
         _check(fn(self._h, _ptr(x), _ptr(out), n, _ptr(uq), _ptr(ct), _ptr(rep), _ptr(ws), ws.numel(),
                   _stream(self.device)))
         return out, rep, uq, ct
@@ -206,7 +208,8 @@ class Context:
             out = torch.empty_like(x)
         if ws is None:
             ws = self.workspace(self.workspace_bytes(n))
-        _check(self._lib.cafs_radix_sort(self._h, _ptr(x), _ptr(out), n, U64 if unsigned else I64, _ptr(ws),
+        dt = F64 if x.dtype == torch.float64 else U64 if unsigned else I64
+        _check(self._lib.cafs_radix_sort(self._h, _ptr(x), _ptr(out), n, dt, _ptr(ws),
                                          ws.numel(), _stream(self.device)))
         return out
 
@@ -220,7 +223,7 @@ class Context:
             arr[i].d_in = cdesc["in"].data_ptr()
             arr[i].d_out = cdesc["out"].data_ptr()
             arr[i].n = cdesc["in"].numel()
-            arr[i].dtype = U64 if cdesc.get("unsigned") else I64
+            arr[i].dtype = F64 if cdesc["in"].dtype == torch.float64 else U64 if cdesc.get("unsigned") else I64
             arr[i].flags = 0
             arr[i].d_uniq = cdesc["uniq"].data_ptr() if cdesc.get("uniq") is not None else None
             arr[i].d_counts = cdesc["counts"].data_ptr() if cdesc.get("counts") is not None else None

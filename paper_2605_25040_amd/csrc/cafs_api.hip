@@ -162,13 +162,16 @@ uint32_t rank_grid(uint64_t n) {
     return grid_for(std::min<uint64_t>(n, cafs::kRankMax), cafs::kRankKeysPerBlock, 1u << 16);
 }
 
+bool dtype_ok(cafs_dtype_t dt) { return dt == CAFS_I64 || dt == CAFS_U64 || dt == CAFS_F64; }
+
 cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void* out, uint64_t n, cafs_dtype_t dt,
                      void* uniq, uint64_t* counts, cafs_report_t* report, void* ws) {
     cafs::Args a{};
     a.in = static_cast<const uint64_t*>(in);
     a.out = static_cast<uint64_t*>(out);
     a.n = n;
-    a.flip = (dt == CAFS_I64) ? (1ull << 63) : 0ull;
+    a.flip = (dt == CAFS_I64 || dt == CAFS_F64) ? (1ull << 63) : 0ull;
+    a.fneg = (dt == CAFS_F64) ? ~0ull : 0ull;
     a.in_head = (reinterpret_cast<uintptr_t>(in) % 16) ? 1u : 0u;
     a.out_head = (reinterpret_cast<uintptr_t>(out) % 16) ? 1u : 0u;
     a.want_report = report != nullptr;
@@ -211,7 +214,7 @@ cafs_status_t check_buffers(const void* in, const void* out, uint64_t n) {
 cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, cafs_dtype_t dt, void* uniq,
                         uint64_t* counts, cafs_report_t* report, void* ws, size_t ws_bytes, void* stream) {
     if (!ctx) return CAFS_EINVAL;
-    if (dt != CAFS_I64 && dt != CAFS_U64) return CAFS_EINVAL;
+    if (!dtype_ok(dt)) return CAFS_EINVAL;
     cafs_status_t st = check_buffers(in, out, n);
     if (st != CAFS_OK) return st;
     if ((uniq || counts) && !report) return CAFS_EINVAL;
@@ -445,10 +448,15 @@ cafs_status_t cafs_sort_u64(cafs_ctx_t* ctx, const uint64_t* d_in, uint64_t* d_o
     return sort_impl(ctx, d_in, d_out, n, CAFS_U64, d_uniq, d_counts, d_report, d_ws, ws_bytes, stream);
 }
 
+cafs_status_t cafs_sort_f64(cafs_ctx_t* ctx, const double* d_in, double* d_out, uint64_t n, double* d_uniq,
+                            uint64_t* d_counts, cafs_report_t* d_report, void* d_ws, size_t ws_bytes, void* stream) {
+    return sort_impl(ctx, d_in, d_out, n, CAFS_F64, d_uniq, d_counts, d_report, d_ws, ws_bytes, stream);
+}
+
 cafs_status_t cafs_radix_sort(cafs_ctx_t* ctx, const void* d_in, void* d_out, uint64_t n, cafs_dtype_t dtype,
                               void* d_ws, size_t ws_bytes, void* stream) {
     if (!ctx) return CAFS_EINVAL;
-    if (dtype != CAFS_I64 && dtype != CAFS_U64) return CAFS_EINVAL;
+    if (!dtype_ok(dtype)) return CAFS_EINVAL;
     cafs_status_t st = check_buffers(d_in, d_out, n);
     if (st != CAFS_OK) return st;
     if (n == 0) return CAFS_OK;
@@ -538,7 +546,7 @@ cafs_status_t check_columns(const cafs_column_t* cols, uint32_t n_cols, std::vec
     ns.resize(n_cols);
     for (uint32_t i = 0; i < n_cols; ++i) {
         const cafs_column_t& col = cols[i];
-        if (col.flags != 0 || (col.dtype != CAFS_I64 && col.dtype != CAFS_U64)) return CAFS_EINVAL;
+        if (col.flags != 0 || !dtype_ok((cafs_dtype_t)col.dtype)) return CAFS_EINVAL;
         cafs_status_t st = check_buffers(col.d_in, col.d_out, col.n);
         if (st != CAFS_OK) return st;
         if ((col.d_uniq || col.d_counts) && !col.d_report) return CAFS_EINVAL;
@@ -875,7 +883,7 @@ void cafs_server_destroy(cafs_server_t* sv) {
 
 cafs_status_t cafs_server_reserve(cafs_server_t* sv, uint64_t n, int32_t dtype, uint64_t* h_ticket, void** h_d_in,
                                   void** h_d_out, cafs_report_t** h_d_report) {
-    if (!sv || !h_ticket || n >= (1ull << 32) || (dtype != CAFS_I64 && dtype != CAFS_U64)) return CAFS_EINVAL;
+    if (!sv || !h_ticket || n >= (1ull << 32) || !dtype_ok((cafs_dtype_t)dtype)) return CAFS_EINVAL;
     const bool bufs = h_d_in && h_d_out && h_d_report;
     const size_t data = bufs ? 2 * align_up(n * 8) + align_up(sizeof(cafs_report_t)) : 0;
     const size_t bytes = data + align_up(make_layout(n).total);

@@ -143,7 +143,8 @@ struct Args {
     const uint64_t* in;
     uint64_t* out;
     uint64_t n;
-    uint64_t flip;                    // 1<<63 for int64 (signed order), 0 for uint64
+    uint64_t flip;                    // 1<<63 for int64 and float64, 0 for uint64
+    uint64_t fneg;                    // all ones for float64, 0 otherwise (see okey)
     uint32_t in_head;                 // 1 if in is 8- but not 16-byte aligned
     uint32_t out_head;
     uint32_t want_report;
@@ -230,6 +231,18 @@ __device__ __forceinline__ T g_cas(T* p, T expected, T desired) {
 template <class T>
 __device__ __forceinline__ T g_load(const T* p) {
     return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Order key: the unsigned integer whose order is the column's order.  int64: bit 63
+// flipped; uint64: the bits themselves; float64 in IEEE 754 totalOrder (-NaN <
+// -inf < ... < -0 < +0 < ... < +inf < +NaN): bit 63 flipped for a clear sign bit,
+// every bit flipped for a set one.  Equality stays on the raw bits.
+__device__ __forceinline__ uint64_t okey(uint64_t x, uint64_t flip, uint64_t fneg) {
+    return x ^ (flip | (fneg & (uint64_t)((int64_t)x >> 63)));
+}
+// Inverse of okey (a float64 key with bit 63 set came from a clear sign bit).
+__device__ __forceinline__ uint64_t okey_inv(uint64_t k, uint64_t flip, uint64_t fneg) {
+    return k ^ (flip | (fneg & ~(uint64_t)((int64_t)k >> 63)));
 }
 
 // Multiplicative hash of Eq. hash: top `bits` bits of x * phi mod 2^64.

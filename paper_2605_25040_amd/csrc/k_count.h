@@ -700,18 +700,18 @@ __device__ __forceinline__ void rank_body(const Args& a, uint32_t bid, uint32_t 
         return;
     }
     if ((uint64_t)bid * kRankKeysPerBlock >= K) return;
-    const uint64_t flip = a.flip;
+    const uint64_t flip = a.flip, fneg = a.fneg;
     __shared__ uint64_t sk[kRankTile];
     const uint32_t part = threadIdx.x % 16;
     for (uint32_t i0 = bid * kRankKeysPerBlock; i0 < K; i0 += nblk * kRankKeysPerBlock) {  // uniform
         const uint32_t i = i0 + threadIdx.x / 16;
         const bool have = i < K;
-        const uint64_t ki = (have ? table_key(a, i, claimed) : 0) ^ flip;
+        const uint64_t ki = okey(have ? table_key(a, i, claimed) : 0, flip, fneg);
         uint32_t r = 0;
         for (uint32_t j0 = 0; j0 < K; j0 += kRankTile) {
             const uint32_t jn = K - j0 < kRankTile ? K - j0 : kRankTile;
             __syncthreads();
-            for (uint32_t j = threadIdx.x; j < jn; j += blockDim.x) sk[j] = table_key(a, j0 + j, claimed) ^ flip;
+            for (uint32_t j = threadIdx.x; j < jn; j += blockDim.x) sk[j] = okey(table_key(a, j0 + j, claimed), flip, fneg);
             __syncthreads();
             for (uint32_t j = part; j < jn; j += 16) r += sk[j] < ki ? 1u : 0u;
         }
@@ -720,7 +720,7 @@ __device__ __forceinline__ void rank_body(const Args& a, uint32_t bid, uint32_t 
         r += __shfl_xor(r, 2, 16);
         r += __shfl_xor(r, 1, 16);
         if (have && part == 0) {
-            gp(a.uniq)[r] = ki ^ flip;
+            gp(a.uniq)[r] = okey_inv(ki, flip, fneg);
             gp(a.cnt)[r] = i < claimed ? gp(a.gcnt)[gp(a.claimed)[i]] : ecount;
         }
     }

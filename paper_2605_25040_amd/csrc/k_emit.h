@@ -422,14 +422,28 @@ __device__ __forceinline__ void rle_count_body(const Args& a, uint32_t bid, uint
     const uint64_t per = (tiles + blockDim.x - 1) / blockDim.x;
     const uint64_t b0 = threadIdx.x * per < tiles ? threadIdx.x * per : tiles;
     const uint64_t b1 = b0 + per < tiles ? b0 + per : tiles;
+    // (loads in groups of 8 in flight: one after the other, device-scope loads
+    // queue for microseconds each)
+    constexpr uint32_t G = 8;
     uint64_t local = 0;
-    for (uint64_t i = b0; i < b1; ++i) local += atomic_load_agent(&a.rle_tile[i]);
+    for (uint64_t i = b0; i < b1; i += G) {
+        uint64_t v[G];
+#pragma unroll
+        for (uint32_t u = 0; u < G; ++u) v[u] = i + u < b1 ? atomic_load_agent(&a.rle_tile[i + u]) : 0;
+#pragma unroll
+        for (uint32_t u = 0; u < G; ++u) local += v[u];
+    }
     uint64_t total;
     uint64_t run = block_exclusive_scan<uint64_t>(local, scan_tmp, &total);
-    for (uint64_t i = b0; i < b1; ++i) {
-        const uint64_t v = atomic_load_agent(&a.rle_tile[i]);
-        a.rle_tile[i] = run;
-        run += v;
+    for (uint64_t i = b0; i < b1; i += G) {
+        uint64_t v[G];
+#pragma unroll
+        for (uint32_t u = 0; u < G; ++u) v[u] = i + u < b1 ? atomic_load_agent(&a.rle_tile[i + u]) : 0;
+#pragma unroll
+        for (uint32_t u = 0; u < G; ++u) {
+            if (i + u < b1) a.rle_tile[i + u] = run;
+            run += v[u];
+        }
     }
     if (threadIdx.x == 0) c->K = total;
 }

@@ -27,7 +27,7 @@ __device__ __forceinline__ uint64_t chao1_sample(const uint64_t* x, uint64_t n) 
     return threadIdx.x < ns ? gp(x)[threadIdx.x * stride] : 0;
 }
 
-__device__ void chao1_block(uint64_t v_mine, uint64_t n, uint64_t flip, Chao1Result* res) {
+__device__ void chao1_block(uint64_t v_mine, uint64_t n, uint64_t flip, uint64_t fneg, Chao1Result* res) {
     __shared__ uint64_t fkeys[1u << kFreqSlotsLog2];
     __shared__ uint32_t fcnt[1u << kFreqSlotsLog2];
     __shared__ uint32_t s_e, s_u, s_f1, s_f2, s_ns;
@@ -98,7 +98,7 @@ __device__ void chao1_block(uint64_t v_mine, uint64_t n, uint64_t flip, Chao1Res
         for (uint32_t i = 0; i < m; ++i) {
             uint64_t v = s_small[i];
             uint32_t j = i;
-            while (j > 0 && (s_small[j - 1] ^ flip) > (v ^ flip)) { s_small[j] = s_small[j - 1]; --j; }
+            while (j > 0 && okey(s_small[j - 1], flip, fneg) > okey(v, flip, fneg)) { s_small[j] = s_small[j - 1]; --j; }
             s_small[j] = v;
         }
         res->n_small = m;
@@ -216,7 +216,7 @@ __device__ __forceinline__ void pre_body(const Args& a, uint32_t bid, uint32_t n
 #pragma unroll
     for (uint32_t k = 0; k <= kPer; ++k) {
         const uint64_t i = (uint64_t)threadIdx.x * kPer + k;
-        pv[k] = i < lim ? in[i] ^ a.flip : 0;
+        pv[k] = i < lim ? okey(in[i], a.flip, a.fneg) : 0;
     }
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
@@ -224,7 +224,7 @@ __device__ __forceinline__ void pre_body(const Args& a, uint32_t bid, uint32_t n
         inv |= (i + 1 < lim && pv[k] > pv[k + 1]) ? 1u : 0u;
     }
     if (inv) s_inv = 1;
-    chao1_block(v_sample, a.n, a.flip, &s_res);  // contains __syncthreads
+    chao1_block(v_sample, a.n, a.flip, a.fneg, &s_res);  // contains __syncthreads
     const bool settled = s_inv || a.n <= kMonoPrefix;
     if (threadIdx.x == 0) {
         c->inversion = s_inv;
@@ -247,7 +247,7 @@ CAFS_KERNELS0(pre, 1024)
 __global__ __launch_bounds__(1024) void k_estimate_only(const uint64_t* x, uint64_t n,
                                                         cafs_estimate_t* out) {
     __shared__ Chao1Result s_res;
-    chao1_block(chao1_sample(x, n), n, 0, &s_res);
+    chao1_block(chao1_sample(x, n), n, 0, 0, &s_res);
     if (threadIdx.x == 0) {
         cafs_estimate_t e;
         e.k_hat = s_res.k_hat; e.u = s_res.u; e.f1 = s_res.f1; e.f2 = s_res.f2;
@@ -272,7 +272,7 @@ __device__ __forceinline__ void mono_full_body(const Args& a, uint32_t bid, uint
         uint32_t inv = 0;
         const uint64_t end = (base + chunk < n - 1) ? base + chunk : n - 1;  // pairs (i, i+1), i < end
         for (uint64_t i = base + threadIdx.x; i < end; i += 256)
-            inv |= (a.in[i] ^ a.flip) > (a.in[i + 1] ^ a.flip);
+            inv |= okey(a.in[i], a.flip, a.fneg) > okey(a.in[i + 1], a.flip, a.fneg);
         if (__any(inv) && __lane_id() == 0) atomicOr(&c->inversion, 1u);
         __syncthreads();
     }

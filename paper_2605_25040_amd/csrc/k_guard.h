@@ -102,15 +102,26 @@ __device__ __forceinline__ void guard_mark_body(const Args& a, uint32_t bid, uin
         const uint32_t lg = log2_pow2(c->table_M);
         const uint32_t glg = c->gidx_log2;
         uint32_t* tab = guard_index(a);
-        for (uint64_t j = gtid; j < K; j += gstride)
-            if (a.dcount[phi_hash(a.uniq[j], lg)] > kBucketCap) {
-                a.first_idx[j] = kNoIndex;
-                a.clist[atomicAdd((unsigned long long*)&c->n_contested, 1ull)] = (uint32_t)j;
-                if (glg) {  // index the contested key: linear probing on 32-bit slots
-                    uint64_t h = phi_hash(a.uniq[j], glg);
-                    while (atomicCAS(&tab[h], kNoIndex, (uint32_t)j) != kNoIndex) h = (h + 1) & ((1ull << glg) - 1);
-                }
+        for (uint64_t j = gtid; j < K; j += gstride) {
+            const bool cont = a.dcount[phi_hash(a.uniq[j], lg)] > kBucketCap;
+            // list places: one update of the shared counter per wave (one per key
+            // serialised on its address)
+            const uint64_t m = __ballot(cont);
+            if (m == 0) continue;
+            const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+            uint32_t base = 0;
+            if (__lane_id() == leader)
+                base = (uint32_t)atomicAdd((unsigned long long*)&c->n_contested, (unsigned long long)__popcll(m));
+            base = __shfl(base, leader, 64);
+            if (!cont) continue;
+            a.first_idx[j] = kNoIndex;
+            a.clist[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                (uint32_t)j;
+            if (glg) {  // index the contested key: linear probing on 32-bit slots
+                uint64_t h = phi_hash(a.uniq[j], glg);
+                while (atomicCAS(&tab[h], kNoIndex, (uint32_t)j) != kNoIndex) h = (h + 1) & ((1ull << glg) - 1);
             }
+        }
     } else {
         const uint64_t nc = c->n_contested;
         for (uint64_t li = gtid; li < nc; li += gstride) a.first_idx[a.clist[li]] = kNoIndex;
@@ -119,12 +130,13 @@ __device__ __forceinline__ void guard_mark_body(const Args& a, uint32_t bid, uin
 CAFS_KERNELS0(guard_mark, 256)
 
 // Position of key v in the sorted distinct keys (it is present).
-__device__ __forceinline__ uint64_t find_key(const uint64_t* uq, uint64_t K, uint64_t v, uint64_t flip) {
+__device__ __forceinline__ uint64_t find_key(const uint64_t* uq, uint64_t K, uint64_t v, uint64_t flip,
+                                             uint64_t fneg) {
     uint64_t lo = 0, hi = K - 1;
-    const uint64_t ov = v ^ flip;
+    const uint64_t ov = okey(v, flip, fneg);
     while (lo < hi) {
         const uint64_t mid = lo + (hi - lo) / 2;
-        if ((uq[mid] ^ flip) < ov) lo = mid + 1; else hi = mid;
+        if (okey(uq[mid], flip, fneg) < ov) lo = mid + 1; else hi = mid;
     }
     return lo;
 }
@@ -242,7 +254,7 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
                     h = (h + 1) & (TS - 1);
                 }
             } else if (bits || a.dcount[b] > kBucketCap) {
-                const uint64_t jj = glg ? index_find(a, glg, v) : find_key(a.uniq, K, v, flip);
+                const uint64_t jj = glg ? index_find(a, glg, v) : find_key(a.uniq, K, v, flip, a.fneg);
                 if (jj >= K) continue;  // not reached: every key of a contested bucket is indexed
                 if (g_load(&a.first_idx[jj]) <= (uint32_t)i) continue;
                 const uint32_t old = atomicMin(&a.first_idx[jj], (uint32_t)i);

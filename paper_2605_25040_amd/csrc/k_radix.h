@@ -13,14 +13,15 @@
 //                  runs.  Claiming tiles in order means a tile only ever waits for
 //                  tiles already held by running workgroups.
 //   k_radix_copy   final copy when the passes end in the scratch buffer.
-// Signed keys (int64) are ordered by flipping bit 63 in the digit extraction.
+// Digits are taken from the order key (okey), so int64 and float64 columns sort
+// in their own order.
 #pragma once
 #include "cafs_dev.h"
 
 namespace cafs {
 
-__device__ __forceinline__ uint32_t digit_of(uint64_t key, uint64_t flip, uint32_t d) {
-    return (uint32_t)(((key ^ flip) >> (8 * d)) & 255u);
+__device__ __forceinline__ uint32_t digit_of(uint64_t key, uint64_t flip, uint64_t fneg, uint32_t d) {
+    return (uint32_t)((okey(key, flip, fneg) >> (8 * d)) & 255u);
 }
 
 __device__ __forceinline__ void radix_hist_body(const Args& a, uint32_t bid, uint32_t nblk) {
@@ -29,7 +30,7 @@ __device__ __forceinline__ void radix_hist_body(const Args& a, uint32_t bid, uin
     const RadixJob& j = c->rj;
     const uint64_t n = j.n;
     const CAFS_GLOBAL uint64_t* __restrict__ src = gp(j.src_k);
-    const uint64_t flip = a.flip;
+    const uint64_t flip = a.flip, fneg = a.fneg;
     __shared__ uint32_t lh[8][256];
     __shared__ uint32_t s_last;
     for (uint32_t i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&lh[0][0])[i] = 0;
@@ -56,7 +57,7 @@ __device__ __forceinline__ void radix_hist_body(const Args& a, uint32_t bid, uin
         const uint64_t act = __ballot(ok);
         if (act == 0) continue;
         for (uint32_t d = 0; d < 8; ++d) {
-            const uint32_t dg = digit_of(v, flip, d);
+            const uint32_t dg = digit_of(v, flip, fneg, d);
             const uint32_t first = __shfl(dg, (int)(__ffsll((unsigned long long)act) - 1), 64);
             const uint64_t same = __ballot(ok && dg == first);
             if (same == act) {
@@ -80,19 +81,37 @@ __device__ __forceinline__ void radix_hist_body(const Args& a, uint32_t bid, uin
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    // last workgroup: digit bases (exclusive scans) and the pass plan
+    // last workgroup: digit bases (exclusive scans) and the pass plan.  Each of the
+    // 256 threads loads 8 consecutive bins of one digit at once (read one after the
+    // other, the device-scope loads took most of a millisecond) and 32 lanes scan
+    // each digit in registers.
     __shared__ uint32_t s_active[8];
-    if (threadIdx.x < 8) {
-        const uint32_t d = threadIdx.x;
-        uint64_t run = 0;
+    {
+        const uint32_t d = threadIdx.x >> 5, q = threadIdx.x & 31;  // blockDim.x == 256
+        uint64_t h[8];
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) h[j] = atomic_load_agent(&c->hist[d][q * 8 + j]);
+        uint64_t loc = 0;
         bool constant = false;
-        for (uint32_t b = 0; b < 256; ++b) {
-            const uint64_t h = atomic_load_agent(&c->hist[d][b]);
-            if (h == n) constant = true;
-            c->hist[d][b] = run;
-            run += h;
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) {
+            constant |= (h[j] == n);
+            loc += h[j];
         }
-        s_active[d] = (!constant && n > 0) ? 1u : 0u;
+        uint64_t inc = loc;
+#pragma unroll
+        for (uint32_t o = 1; o < 32; o <<= 1) {
+            const uint64_t t = __shfl_up(inc, o, 32);
+            if (q >= o) inc += t;
+        }
+        uint64_t run = inc - loc;
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) {
+            c->hist[d][q * 8 + j] = run;
+            run += h[j];
+        }
+        const uint64_t cm = __ballot(constant);  // this digit's 32 lanes are one half of the wave
+        if (q == 0) s_active[d] = ((cm >> (threadIdx.x & 32)) & 0xFFFFFFFFull) == 0 && n > 0 ? 1u : 0u;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -146,7 +165,7 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
     if ((j.has_vals != 0) != VALS || pass >= j.n_active) return;
     const uint64_t n = j.n;
     const uint32_t d = j.digit[pass];
-    const uint64_t flip = a.flip;
+    const uint64_t flip = a.flip, fneg = a.fneg;
     const CAFS_GLOBAL uint64_t* __restrict__ sk = gp(j.ps_k[pass]);
     const CAFS_GLOBAL uint64_t* __restrict__ sv = gp(j.ps_v[pass]);
     CAFS_GLOBAL uint64_t* __restrict__ dk = gp(j.pd_k[pass]);
@@ -202,7 +221,7 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
 #pragma unroll
         for (int i = 0; i < kRadixItems; ++i) {
             const bool ok = (okm >> i) & 1u;
-            const uint32_t dg = digit_of(key[i], flip, d);
+            const uint32_t dg = digit_of(key[i], flip, fneg, d);
             const uint64_t act = __ballot(ok);
             const uint64_t peers = match_digit(dg, act);
             uint32_t before = 0;
@@ -259,7 +278,7 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
 #pragma unroll
         for (int i = 0; i < kRadixItems; ++i) {
             if ((okm >> i) & 1u) {
-                const uint32_t dg = digit_of(key[i], flip, d);
+                const uint32_t dg = digit_of(key[i], flip, fneg, d);
                 const uint32_t q = toff[dg] + wcnt[wave][dg] + ((rank2[i >> 1] >> (16 * (i & 1))) & 0xFFFFu);
                 if (q < kRadixTile) {  // always true when the ranks are consistent
                     lk[q] = key[i];
@@ -271,7 +290,7 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
         const uint32_t cnt = (uint32_t)((n - base) < kRadixTile ? (n - base) : kRadixTile);
         for (uint32_t q = tid; q < cnt; q += blockDim.x) {
             const uint64_t k = lk[q];
-            const uint64_t g = gofs[digit_of(k, flip, d)] + q;
+            const uint64_t g = gofs[digit_of(k, flip, fneg, d)] + q;
             if (g < n) {  // always true when the look-back prefixes are consistent
                 dk[g] = k;
                 if constexpr (VALS) dv[g] = lv[q];

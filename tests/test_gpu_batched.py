@@ -137,3 +137,40 @@ def test_batch_hash_seed(ctx):
             assert r["engine"] == "HASH" and not (r["flags"] & 1), r
     finally:
         ctx.set_hash_seed(0)
+
+
+def test_batch_f64_columns(ctx):
+    """float64 columns (totalOrder) mixed with int64 and uint64 ones in one batch."""
+    rng = np.random.default_rng(12)
+    arrays, kinds = [], []
+    for i in range(24):
+        n = int(rng.integers(1000, 300_000)); k = int(rng.integers(2, max(3, n // 4)))
+        pal = rng.normal(size=k) * 10.0 ** rng.uniform(-8, 8, size=k)
+        pal[: min(k, 3)] = np.array([0x0, 0x8000000000000000, 0x7FF8000000000000], dtype=np.uint64)[: min(k, 3)].view(np.float64)
+        arrays.append(pal[rng.integers(0, k, size=n)]); kinds.append("f")
+    spec = gen.batch_spec(16, seed=4, n_lo=1e3, n_hi=2e5, k_cap=2e4)
+    for c in spec:
+        arrays.append(gen.column(c["n"], c["k"], dist=c["dist"], s=c["s"], seed=c["seed"], dtype=np.uint64)); kinds.append("u")
+    cols = []
+    import paper_2605_25040_amd as cafs
+    for x, kd in zip(arrays, kinds):
+        n = x.size
+        t = torch.from_numpy(x.copy()).to("cuda:0") if kd == "f" else torch.from_numpy(x.view(np.int64).copy()).to("cuda:0")
+        cols.append(dict(**{"in": t}, out=torch.empty_like(t), unsigned=(kd == "u"),
+                         uniq=torch.empty_like(t), counts=torch.empty(n, dtype=torch.int64, device="cuda:0"),
+                         report=torch.zeros(cafs.report_size(), dtype=torch.uint8, device="cuda:0"), src=x, kind=kd))
+    ctx.sort_batched(cols)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cols):
+        dt = np.float64 if c["kind"] == "f" else np.uint64
+        x = c["src"].view(dt)
+        y = c["out"].cpu().numpy().view(np.uint64)
+        assert np.array_equal(y, oracle.sort(x, dt).view(np.uint64)), i
+        r = cafs.parse_report(c["report"])
+        ro = oracle.report(x, dt)
+        for f in oracle.REPORT_FIELDS:
+            assert r[f] == ro[f], (i, f, r[f], ro[f])
+        uo, co = oracle.counts(x, dt)
+        k = r["k_exact"]
+        assert np.array_equal(c["uniq"][:k].cpu().numpy().view(np.uint64), uo.view(np.uint64)), i
+        assert np.array_equal(c["counts"][:k].cpu().numpy().view(np.uint64), co), i

@@ -287,3 +287,69 @@ def test_hash_seed(ctx):
                 check(ctx, x, False, label="seed %d column %d" % (seed, i))
     finally:
         ctx.set_hash_seed(0)
+
+
+# ---- float64 keys (IEEE 754 totalOrder) --------------------------------------
+
+def _f64_column(n, k, dist, seed, specials=False):
+    """n doubles from a palette of k values (normal times a power of ten, optionally
+    with signed zeros, infinities, subnormals and NaNs of both signs), drawn with
+    the generator's frequency model over dictionary codes."""
+    rng = np.random.default_rng(seed)
+    pal = rng.normal(size=k) * 10.0 ** rng.uniform(-30, 30, size=k)
+    if specials and k >= 12:
+        sp = np.array([0x0, 0x8000000000000000, 0x7FF0000000000000, 0xFFF0000000000000, 0x1, 0x8000000000000001,
+                       0x7FF8000000000000, 0xFFF8000000000000, 0x7FF8000000000005], dtype=np.uint64)
+        pal[:sp.size] = sp.view(np.float64)
+    pal = np.unique(pal.view(np.uint64)).view(np.float64)  # distinct bit patterns
+    codes = gen.column(n, pal.size, dist=dist, s=1.1, palette="codes", seed=seed, dtype=np.uint64)
+    return pal[codes.astype(np.int64)]
+
+
+def check_f64(ctx, x, label):
+    import paper_2605_25040_amd as cafs
+    xt = torch.from_numpy(x.copy()).to("cuda:0")
+    out, rep, uq, ct = ctx.sort(xt, counts=True)
+    torch.cuda.synchronize()
+    r = cafs.parse_report(rep)
+    y = out.cpu().numpy()
+    want = oracle.sort(x, np.float64)
+    assert np.array_equal(y.view(np.uint64), want.view(np.uint64)), "%s: sorted output differs" % label
+    ro = oracle.report(x, np.float64)
+    for f in ORACLE_FIELDS:
+        assert r[f] == ro[f], "%s: report field %s gpu=%r oracle=%r" % (label, f, r[f], ro[f])
+    k = r["k_exact"]
+    uo, co = oracle.counts(x, np.float64)
+    assert np.array_equal(uq[:k].cpu().numpy().view(np.uint64), uo.view(np.uint64)), "%s: distinct keys" % label
+    assert np.array_equal(ct[:k].cpu().numpy().view(np.uint64), co), "%s: counts" % label
+    return r
+
+
+F64_CASES = [
+    # n, k, dist, specials: every dispatcher path and both engines
+    (1500, 40, "uniform", True),          # N < 2048: radix engine
+    (300_000, 5, "uniform", False),       # tiny
+    (400_000, 12, "zipf", True),          # tiny check misses an unsampled NaN or zero: main path
+    (1_000_000, 300, "zipf", True),       # main path, ranking
+    (2_000_000, 3000, "uniform", True),   # 4-key LDS buckets
+    (600_000, 20_000, "uniform", True),   # pair sort (K above the ranking limit)
+    (2_000_000, 200_000, "zipf", True),   # table overflow: radix engine, general guard
+    (200_000, 150_000, "uniform", True),  # high K
+]
+
+
+@pytest.mark.parametrize("n,k,dist,specials", F64_CASES)
+def test_f64_columns(ctx, n, k, dist, specials):
+    x = _f64_column(n, k, dist, seed=n + k, specials=specials)
+    check_f64(ctx, x, "f64 n=%d k=%d %s" % (n, k, dist))
+
+
+def test_f64_monotone_and_radix_api(ctx):
+    x = np.sort(_f64_column(300_000, 500, "uniform", seed=9, specials=True))
+    x = oracle.sort(x, np.float64)  # totalOrder, which places -0, +0 and NaNs by bits
+    r = check_f64(ctx, x, "f64 sorted")
+    assert r["path"] == "MONOTONE"
+    y = _f64_column(1_000_003, 70_000, "zipf", seed=10, specials=True)
+    out = ctx.radix_sort(torch.from_numpy(y.copy()).to("cuda:0"))
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), oracle.sort(y, np.float64).view(np.uint64))

@@ -315,3 +315,69 @@ def test_std_sort_baseline_is_a_sort():
                         np.array([-2**63, 2**63 - 1, 0, -1, 0, -2**63], dtype=np.int64)])
     assert np.array_equal(oracle.std_sort_i64(x), np.sort(x))
     assert oracle.std_sort_i64(np.empty(0, dtype=np.int64)).size == 0
+
+
+# ---- float64 keys in IEEE 754 totalOrder ------------------------------------
+
+def _f64(bits):
+    return np.array(bits, dtype=np.uint64).view(np.float64)
+
+
+def test_f64_total_order_special_values():
+    """The order that IEEE 754-2008 (Sec. 5.10, totalOrder) fixes for signed zeros,
+    infinities, subnormals and NaNs of either sign."""
+    neg_nan, pos_nan = 0xFFF8000000000000, 0x7FF8000000000000
+    neg_nan_payload = 0xFFF8000000000001   # larger payload: further below
+    pos_nan_payload = 0x7FF8000000000001   # larger payload: further above
+    want_bits = [neg_nan_payload, neg_nan, 0xFFF0000000000000,               # -NaN(1) < -NaN < -inf
+                 np.float64(-1.5).view(np.uint64), 0x8000000000000001,       # -1.5 < -min subnormal
+                 0x8000000000000000, 0x0000000000000000,                     # -0 < +0
+                 0x0000000000000001, np.float64(2.0).view(np.uint64),        # +min subnormal < 2
+                 0x7FF0000000000000, pos_nan, pos_nan_payload]               # +inf < +NaN < +NaN(1)
+    want = np.array(want_bits, dtype=np.uint64)
+    rng = np.random.default_rng(3)
+    x = want[rng.permutation(want.size)]
+    got = oracle.sort(x.view(np.float64), np.float64).view(np.uint64)
+    assert np.array_equal(got, want)
+    assert oracle.is_monotone(want.view(np.float64), np.float64)
+    assert not oracle.is_monotone(want[::-1].copy().view(np.float64), np.float64)
+
+
+def test_f64_sort_matches_numpy_on_ordinary_values():
+    """Away from zeros and NaNs totalOrder is the numeric order, which numpy's sort
+    gives; repeated values keep their multiplicities."""
+    rng = np.random.default_rng(11)
+    pal = rng.normal(size=300) * 10.0 ** rng.uniform(-300, 300, size=300)
+    pal = np.concatenate([pal, [np.inf, -np.inf, 5e-324, -5e-324]])
+    x = pal[rng.integers(0, pal.size, size=20_000)]
+    assert np.array_equal(oracle.sort(x, np.float64), np.sort(x))
+    u, c = oracle.counts(x, np.float64)
+    nu, nc = np.unique(x, return_counts=True)
+    assert np.array_equal(u, nu) and np.array_equal(c, nc.astype(np.uint64))
+
+
+def test_f64_zeros_and_nans_are_distinct_keys():
+    """Equality is on the bit pattern: -0 and +0 count apart, NaNs with different
+    payloads count apart."""
+    bits = np.array([0x0, 0x8000000000000000, 0x0, 0x7FF8000000000000, 0x7FF8000000000002,
+                     0x7FF8000000000000, 0xFFF8000000000000], dtype=np.uint64)
+    u, c = oracle.counts(bits.view(np.float64), np.float64)
+    assert list(u.view(np.uint64)) == [0xFFF8000000000000, 0x8000000000000000, 0x0,
+                                       0x7FF8000000000000, 0x7FF8000000000002]
+    assert list(c) == [1, 1, 2, 2, 1]
+
+
+def test_f64_report_follows_the_bits():
+    """Estimate, tiny check, bucket table and spill act on bit patterns, so a
+    float64 column reports what the same bits report as uint64 (the order matters
+    only to the monotone test)."""
+    rng = np.random.default_rng(5)
+    for n, k in ((50_000, 6), (60_000, 900), (40_000, 30_000)):
+        pal = rng.normal(size=k)
+        x = pal[rng.integers(0, k, size=n)]
+        rf = oracle.report(x, np.float64)
+        ru = oracle.report(x.view(np.uint64), np.uint64)
+        assert rf == ru, (n, k)
+    s = np.sort(rng.normal(size=5000))
+    assert oracle.report(s, np.float64)["path"] == "MONOTONE"
+    assert oracle.report(-s, np.float64)["path"] != "MONOTONE"
