@@ -28,6 +28,9 @@ constexpr uint64_t kEmpty = ~0ull;             // empty-slot marker of the GPU h
 constexpr uint32_t kMonoPrefix = 1u << 13;     // elements the pre kernel checks for order
 constexpr int kCountThreads = 1024;            // hash-count workgroup
 constexpr uint32_t kLdsSlots = 13568;          // per-workgroup LDS table (159 KiB with 32-bit counts)
+constexpr uint32_t kRleProbePairs = 16;        // run-length path for a batch when this many of the 64 pairs of its
+                                              // first slice hold two equal elements
+constexpr uint32_t kRleMinMerged = 16;         // and, per slice, when its 128 elements merge at least this many
 constexpr uint64_t kLdsWideMinKhat = 1800;     // buckets of 4 keys from this estimate up, of 2 below
 constexpr uint32_t kLdsWindow = 2;             // buckets probed before an element is deferred
 constexpr uint32_t kLdsProbeBuckets = 8;       // buckets probed in the deferred pass before the global table

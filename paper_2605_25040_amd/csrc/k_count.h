@@ -293,7 +293,7 @@ __device__ __forceinline__ int match_bucket(const uint64_t* skeys, uint32_t b, u
 template <int NE, uint32_t W>
 __device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, uint32_t* __restrict__ scnt,
                                                 uint32_t* __restrict__ sink, const uint64_t (&x)[NE],
-                                                uint32_t want_m, uint64_t mul) {
+                                                uint32_t want_m, uint64_t mul, const uint32_t (&add)[NE]) {
     uint32_t ins = 0, dfr = 0;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
@@ -310,7 +310,7 @@ __device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, ui
         // the first slots of many buckets spread over the LDS banks; lanes without a
         // hit add to their own sink word, off the counters (equal addresses in one
         // instruction serialise)
-        atomicAdd(hit ? &scnt[m * LdsGeo<W>::kBuckets + b] : &sink[__lane_id()], 1u);
+        atomicAdd(hit ? &scnt[m * LdsGeo<W>::kBuckets + b] : &sink[__lane_id()], add[e]);
         const bool miss = want && !hit;
         ins |= (miss && !full) ? (1u << e) : 0u;
         dfr |= (miss && full) ? (1u << e) : 0u;
@@ -318,9 +318,58 @@ __device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, ui
     if (ins) {
 #pragma unroll
         for (int e = 0; e < NE; ++e)
-            if (((ins >> e) & 1u) && !lds_insert<W>(skeys, scnt, x[e], 1u, kLdsWindow, mul)) dfr |= 1u << e;
+            if (((ins >> e) & 1u) && !lds_insert<W>(skeys, scnt, x[e], add[e], kLdsWindow, mul)) dfr |= 1u << e;
     }
     return dfr;
+}
+
+// 64-bit value of the previous lane (lane 0: 0), by a whole-wave DPP shift (no LDS
+// traffic).  Every lane of the wave must be active.
+__device__ __forceinline__ uint64_t wave_shr1(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, 0x138, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), 0x138, 0xF, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Run-length injection (the main path's RLE pass, Sec. 4.4): a run of r equal
+// consecutive elements takes one table update of r instead of r updates of 1.  Pair
+// u of lane i holds elements 2p and 2p+1 of pair p = (batch base) + u * blockDim +
+// thread, so the 64 lanes of a wave hold 128 consecutive elements per u.  An element
+// heads a run unless it equals the element before it in that slice (lane i's first
+// element follows lane i-1's second, taken by a lane shift); a head gets the
+// distance to the next head (or to the slice's end) as its count, the others get 0.
+// Runs that cross a slice boundary are cut there.  The batch is first probed on
+// its first slice: unless kRleProbePairs of its 64 pairs hold two equal elements
+// (random columns rarely have any) every element counts 1 and nothing more is spent.
+// Otherwise a slice takes the path when it is fully in range and at least
+// kRleMinMerged of its elements merge.  Every test is wave-uniform.  Returns whether
+// any slice of the batch took the path.
+template <int NE>
+__device__ __forceinline__ bool run_lengths(const uint64_t (&x)[NE], uint32_t want, uint32_t (&add)[NE]) {
+    const uint32_t lane = __lane_id();
+    bool any = false;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) add[e] = 1u;
+    if ((uint32_t)__popcll(__ballot((want & 3u) == 3u && x[0] == x[1])) < kRleProbePairs) return false;
+#pragma unroll
+    for (int u = 0; u < NE / 2; ++u) {
+        add[2 * u] = 1u;
+        add[2 * u + 1] = 1u;
+        if (__ballot(((want >> (2 * u)) & 3u) != 3u) != 0) continue;
+        const uint64_t a = x[2 * u], b = x[2 * u + 1];
+        const uint64_t prev = wave_shr1(b);
+        const bool ha = lane == 0 || a != prev;
+        const bool hb = b != a;
+        const uint64_t he = __ballot(ha), ho = __ballot(hb);
+        if (128u - (uint32_t)__popcll(he) - (uint32_t)__popcll(ho) < kRleMinMerged) continue;
+        const uint64_t later = lane == 63 ? 0ull : (he | ho) & (~0ull << (lane + 1));
+        const uint32_t j = later ? (uint32_t)__builtin_ctzll(later) : 64u;
+        const uint32_t nxt = j == 64u ? 128u : 2u * j + (((he >> (j & 63u)) & 1ull) ? 0u : 1u);
+        add[2 * u] = ha ? (hb ? 1u : nxt - 2u * lane) : 0u;
+        add[2 * u + 1] = hb ? nxt - (2u * lane + 1u) : 0u;
+        any = true;
+    }
+    return any;
 }
 
 // Each workgroup of the first pass reads one contiguous range of ceil(P / nblk)
@@ -493,7 +542,30 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
             ecnt += is_empty_key ? 1u : 0u;
             want &= is_empty_key ? ~(1u << e) : ~0u;
         }
-        const uint32_t dfr = count_batch<NE, W>(skeys, scnt, s_sink, x, want, t.mul);
+        uint32_t add[NE];
+        const bool rle = run_lengths<NE>(x, want, add);
+        if (rle) {
+            // merged elements are counted by their run's head
+#pragma unroll
+            for (int e = 0; e < NE; ++e) want &= add[e] ? ~0u : ~(1u << e);
+            const uint32_t dfr = count_batch<NE, W>(skeys, scnt, s_sink, x, want, t.mul, add);
+            // a deferred head stands for its whole run: that many copies go to the region
+            // (the region has room for every element of the workgroup's range)
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                if ((dfr >> e) & 1u) {
+                    const uint32_t at = atomicAdd(&s_ndef, add[e]);
+                    for (uint32_t r = 0; r < add[e]; ++r) region[at + r] = x[e];
+                }
+            }
+            base = next;
+            if (__builtin_amdgcn_readfirstlane(handed)) break;
+            continue;
+        }
+        uint32_t ones[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) ones[e] = 1u;
+        const uint32_t dfr = count_batch<NE, W>(skeys, scnt, s_sink, x, want, t.mul, ones);
         if (__ballot(dfr != 0)) {
             // append the deferred elements: one LDS reservation per wave, then each
             // element's place from the ballot of its batch position
@@ -545,7 +617,10 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
             xd[u] = i < d ? region[i] : 0;
             want |= (i < d ? 1u : 0u) << u;
         }
-        const uint32_t dfr = count_batch<D, W>(skeys, scnt, s_sink, xd, want, t.mul);
+        uint32_t ones[D];
+#pragma unroll
+        for (int u = 0; u < D; ++u) ones[u] = 1u;
+        const uint32_t dfr = count_batch<D, W>(skeys, scnt, s_sink, xd, want, t.mul, ones);
         uint32_t cl[D];
 #pragma unroll
         for (int u = 0; u < D; ++u) cl[u] = kNoSlot;

@@ -353,3 +353,38 @@ def test_f64_monotone_and_radix_api(ctx):
     out = ctx.radix_sort(torch.from_numpy(y.copy()).to("cuda:0"))
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint64), oracle.sort(y, np.float64).view(np.uint64))
+
+
+# ---- run-length injection (structured inputs) --------------------------------
+
+RLE_CASES = [
+    # n, K, dist: runs of mean length n / (4K) ("runs"), sorted-by-group runs of
+    # n / K ("grouped", random palette: not monotone), 1% swaps of those ("almost_sorted")
+    (1 << 22, 64, "runs"),           # runs of ~16k: whole slices merge
+    (1 << 22, 10_000, "runs"),       # runs of ~100: cut at slice ends
+    (1 << 22, 300_000, "runs"),      # runs of 1-6: mostly below the merge threshold
+    (1 << 23, 20_000, "runs"),       # beyond the LDS table: deferred heads carry their runs
+    (1 << 22, 1000, "grouped"),
+    (3_000_001, 5000, "almost_sorted"),
+    (1 << 22, 7, "runs"),            # tiny path
+]
+
+
+@pytest.mark.parametrize("n,k,dist", RLE_CASES)
+def test_run_length_inputs(ctx, n, k, dist):
+    x = gen.column(n, k, dist=dist, s=1.1, palette="random", dtype=np.uint64)
+    check(ctx, x, True, label="%s n=%d k=%d" % (dist, n, k))
+    check(ctx, x, False, label="%s n=%d k=%d signed" % (dist, n, k))
+
+
+def test_runs_of_every_length_across_slices(ctx):
+    """Runs of lengths 1..300 in a shuffled order, so that heads fall at every
+    position of a wave's 128-element slice, next to single elements."""
+    rng = np.random.default_rng(21)
+    lens = np.concatenate([np.arange(1, 301), rng.integers(1, 300, size=6000)])
+    rng.shuffle(lens)
+    vals = rng.integers(0, 2**63, size=500, dtype=np.int64).view(np.uint64)
+    keys = vals[rng.integers(0, vals.size, size=lens.size)]
+    x = np.repeat(keys, lens)
+    check(ctx, x, True, label="mixed runs")
+    check(ctx, x[::-1].copy(), False, label="mixed runs reversed")
