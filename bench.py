@@ -175,6 +175,41 @@ def bench_batched(ctx, n_cols=4096, total=1 << 28, reps=50, seq_reps=1):
             "sequential_ms": round(seq_ms, 3), "vs_sequential": round(seq_ms / p50, 2), "graph_ok": ok_graph}
 
 
+def bench_structured(ctx, n=1 << 28, steps=10):
+    """Columns made of runs of equal keys (mean run length n / (4K), random 64-bit
+    values), where the count's run-length injection merges elements: Gkeys/s per
+    column shape, inputs resident."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2605_25040_amd as cafs
+    res = {}
+    for dist, k in (("runs", 64), ("runs", 10_000)):
+        h = gen.column(n, k, dist=dist, palette="random", dtype=np.int64)
+        x = torch.from_numpy(h).to("cuda")
+        del h
+        out = torch.empty_like(x)
+        ws = ctx.workspace(ctx.workspace_bytes(n))
+        for _ in range(2):
+            _, rep, _, _ = ctx.sort(x, out=out, ws=ws)
+        torch.cuda.synchronize()
+        r = cafs.parse_report(rep)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            ctx.sort(x, out=out, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res["%s_k%d" % (dist, k)] = {"n": n, "ms": round(ms, 4), "gkeys_s": round(n / ms / 1e6, 2),
+                                     "path": r["path"], "k_exact": r["k_exact"]}
+        del x, out, ws
+        ctx._ws = None
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_serving(seconds, rate=10_000, budget=64 << 30, fifo_seconds=2.0):
     """Real-time Poisson replay through the server, then the first fifo_seconds of
     the same trace served one request at a time with plain calls (the baseline)."""
@@ -302,6 +337,8 @@ def main():
     ap.add_argument("--radix-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-structured", action="store_true",
+                    help="skip the run-shaped columns (run-length injection)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the input (counter calibration under a profiler)")
     ap.add_argument("--sweep", action="store_true",
@@ -451,6 +488,8 @@ def main():
     del x, out, ws
     ctx._ws = None
     torch.cuda.empty_cache()
+    if not args.no_structured:
+        line["structured"] = bench_structured(ctx)
     if not args.no_batched:
         line["batched"] = bench_batched(ctx)
     if args.serve_seconds > 0:
