@@ -141,16 +141,20 @@ __device__ __forceinline__ uint64_t find_key(const uint64_t* uq, uint64_t K, uin
     return lo;
 }
 
-// Position of contested key v through the hash index (it is present).
-__device__ __forceinline__ uint64_t index_find(const Args& a, uint32_t glg, uint64_t v) {
+// Position of contested key v through the hash index (it is present), probing
+// from slot h on.
+__device__ __forceinline__ uint64_t index_probe(const Args& a, uint32_t glg, uint64_t v, uint64_t h) {
     const CAFS_GLOBAL uint32_t* tab = gp(guard_index(a));
     const CAFS_GLOBAL uint64_t* uq = gp(a.uniq);
-    uint64_t h = phi_hash(v, glg);
     while (true) {
         const uint32_t j = tab[h];
         if (j == kNoIndex || uq[j] == v) return j;  // kNoIndex is unreachable for a contested key
         h = (h + 1) & ((1ull << glg) - 1);
     }
+}
+
+__device__ __forceinline__ uint64_t index_find(const Args& a, uint32_t glg, uint64_t v) {
+    return index_probe(a, glg, v, phi_hash(v, glg));
 }
 
 // First occurrences of the contested keys.  Chunks of the input are claimed in
@@ -162,7 +166,13 @@ __device__ __forceinline__ uint64_t index_find(const Args& a, uint32_t glg, uint
 // most kGuardLdsKeys contested keys each workgroup keeps them in an LDS hash table
 // with per-key minima that it merges into the global minima after each chunk;
 // otherwise each element of a contested bucket is located through the hash index
-// of the contested keys (binary search when there is none).
+// of the contested keys (binary search when there is none).  With kPhased (the
+// batched kernel, where a column has few workgroups and each one's chain of
+// dependent loads sets the launch's length) each lookup step of the general mode
+// is taken for all of a thread's elements before the next step, so that their
+// loads are in flight together; the single-column kernel keeps the element-wise
+// loop, which shares the memory system better with the emit running beside it.
+template <bool kPhased>
 __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (c->path != P_MAIN || !c->guard_on) return;
@@ -233,6 +243,42 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
             const uint64_t i = b0 + threadIdx.x + (uint64_t)u * blockDim.x;
             vv[u] = i < e0 ? gp(a.in)[i] : 0;
         }
+        if (kPhased && !small) {
+            const CAFS_GLOBAL uint32_t* tab = gp(guard_index(a));
+            const uint64_t imask = glg ? (1ull << glg) - 1 : 0;
+            uint32_t bb[PER], dc[PER], jt[PER];
+#pragma unroll
+            for (uint32_t u = 0; u < PER; ++u) {
+                const uint64_t i = b0 + threadIdx.x + (uint64_t)u * blockDim.x;
+                bb[u] = phi_hash32(vv[u], lg);
+                dc[u] = i < e0 ? a.dcount[bb[u]] : 0u;
+            }
+            if (glg) {
+#pragma unroll
+                for (uint32_t u = 0; u < PER; ++u) jt[u] = dc[u] > kBucketCap ? tab[phi_hash(vv[u], glg)] : kNoIndex;
+                uint64_t kk[PER];
+#pragma unroll
+                for (uint32_t u = 0; u < PER; ++u) kk[u] = jt[u] != kNoIndex ? a.uniq[jt[u]] : 0;
+#pragma unroll
+                for (uint32_t u = 0; u < PER; ++u)
+                    if (jt[u] != kNoIndex && kk[u] != vv[u])  // not in its home slot: probe on
+                        jt[u] = (uint32_t)index_probe(a, glg, vv[u], (phi_hash(vv[u], glg) + 1) & imask);
+            } else {
+#pragma unroll
+                for (uint32_t u = 0; u < PER; ++u)
+                    jt[u] = dc[u] > kBucketCap ? (uint32_t)find_key(a.uniq, K, vv[u], flip, a.fneg) : kNoIndex;
+            }
+            uint32_t fi[PER];
+#pragma unroll
+            for (uint32_t u = 0; u < PER; ++u) fi[u] = jt[u] < K ? g_load(&a.first_idx[jt[u]]) : 0u;
+#pragma unroll
+            for (uint32_t u = 0; u < PER; ++u) {
+                const uint64_t i = b0 + threadIdx.x + (uint64_t)u * blockDim.x;
+                if (jt[u] >= K || fi[u] <= (uint32_t)i) continue;
+                const uint32_t old = atomicMin(&a.first_idx[jt[u]], (uint32_t)i);
+                if (old == kNoIndex && atomicAdd(&a.bfound[bb[u]], 1u) == kBucketCap - 1) ++newly;
+            }
+        } else {
 #pragma unroll
         for (uint32_t u = 0; u < PER; ++u) {
             const uint64_t i = b0 + threadIdx.x + (uint64_t)u * blockDim.x;
@@ -261,6 +307,7 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
                 if (old == kNoIndex && atomicAdd(&a.bfound[b], 1u) == kBucketCap - 1) ++newly;
             }
         }
+        }
         if (small) {
             __syncthreads();
             for (uint32_t li = threadIdx.x; li < nc; li += blockDim.x) {
@@ -280,7 +327,11 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
         __syncthreads();
     }
 }
-CAFS_KERNELS0(guard_first, 256)
+__global__ __launch_bounds__(256) void k_guard_first(Args a) { guard_first_body<false>(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(256) void kb_guard_first(BatchGrid g) {
+    const uint32_t col = g.col[blockIdx.x];
+    guard_first_body<true>(g.args[col], blockIdx.x - g.first[col], g.count[col]);
+}
 
 // Rank of each contested key within its bucket by first occurrence, for at most
 // kGuardLdsKeys contested keys: sort (bucket, first occurrence) in LDS; position p
