@@ -348,9 +348,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        sys.stderr.write("bench.py runs on one GPU only: this build has no multi-GPU path "
-                         "(a column would shard by an all-gather of the per-GPU (key, count) tables; "
-                         "see the design notes).  Use --gpus 1.\n")
+        sys.stderr.write("bench.py runs on one GPU only: the library has no multi-GPU path "
+                         "(a column would shard by an all-gather of the per-GPU (key, count) tables).  "
+                         "Use --gpus 1.\n")
         sys.exit(2)
 
     if args.sweep:
