@@ -174,3 +174,36 @@ def test_batch_f64_columns(ctx):
         k = r["k_exact"]
         assert np.array_equal(c["uniq"][:k].cpu().numpy().view(np.uint64), uo.view(np.uint64)), i
         assert np.array_equal(c["counts"][:k].cpu().numpy().view(np.uint64), co), i
+
+
+def test_batch_graph_capture_replays(ctx):
+    """A captured batched call replays correctly with new column contents (same
+    sizes) copied in between replays, eager batched calls in between too."""
+    import paper_2605_25040_amd as cafs
+    spec = gen.batch_spec(48, seed=31, n_lo=1e3, n_hi=4e5, k_cap=5e4)
+    rounds = []
+    for r in range(3):
+        rounds.append([gen.column(c["n"], c["k"], dist=c["dist"], s=c["s"], seed=c["seed"] + 977 * r,
+                                  dtype=np.uint64) for c in spec])
+    m = len(spec)
+    cols = make_cols(rounds[0], [True] * m, [True] * m, [True] * m)
+    ws = ctx.workspace(ctx.batched_workspace_bytes([c["in"].numel() for c in cols]))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ctx.sort_batched(cols, ws=ws)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            ctx.sort_batched(cols, ws=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for r, arrays in enumerate(rounds + rounds[:1]):
+        for c, x in zip(cols, arrays):
+            c["in"].copy_(torch.from_numpy(x.view(np.int64).copy()))
+            c["src"] = x
+        torch.cuda.synchronize()
+        g.replay()
+        check_cols(cols, "replay %d" % r)
+        ctx.sort_batched(cols, ws=ws)
+        check_cols(cols, "eager %d" % r)

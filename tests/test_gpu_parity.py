@@ -388,3 +388,51 @@ def test_runs_of_every_length_across_slices(ctx):
     x = np.repeat(keys, lens)
     check(ctx, x, True, label="mixed runs")
     check(ctx, x[::-1].copy(), False, label="mixed runs reversed")
+
+
+# ---- HIP graph capture ---------------------------------------------------------
+
+def test_graph_capture_replays(ctx):
+    """A captured call replays correctly: other columns (other dispatcher paths and
+    engines) are copied into the captured input buffer between replays, with eager
+    calls and synchronisations in between, and every replay is checked against the
+    oracle."""
+    import paper_2605_25040_amd as cafs
+    n = 1_000_003
+    shapes = ((1000, "zipf"), (5, "uniform"), (20_000, "uniform"), (300_000, "uniform"), (64, "runs"))
+    cols = [gen.column(n, k, dist=d, s=1.1, palette="random", dtype=np.uint64) for k, d in shapes]
+    x = torch.empty(n, dtype=torch.int64, device="cuda:0")
+    out = torch.empty_like(x)
+    ws = ctx.workspace(ctx.workspace_bytes(n))
+    x.copy_(torch.from_numpy(cols[0].view(np.int64).copy()))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ctx.sort(x, unsigned=True, out=out, counts=True, ws=ws)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            res = ctx.sort(x, unsigned=True, out=out, counts=True, ws=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    _, rep_g, uq_g, ct_g = res
+    for rnd in range(2):
+        for (k, d), c in zip(shapes, cols):
+            label = "replay %d %s k=%d" % (rnd, d, k)
+            x.copy_(torch.from_numpy(c.view(np.int64).copy()))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy().view(np.uint64), oracle.sort(c, np.uint64)), label
+            r = cafs.parse_report(rep_g)
+            ro = oracle.report(c, np.uint64)
+            for f in ORACLE_FIELDS:
+                assert r[f] == ro[f], (label, f, r[f], ro[f])
+            uo, co = oracle.counts(c, np.uint64)
+            kk = r["k_exact"]
+            assert np.array_equal(uq_g[:kk].cpu().numpy().view(np.uint64), uo), label
+            assert np.array_equal(ct_g[:kk].cpu().numpy().view(np.uint64), co), label
+            # eager work on the same workspace between replays
+            y, _, _, _ = ctx.sort(x, unsigned=True, ws=ws)
+            torch.cuda.synchronize()
+            assert np.array_equal(y.cpu().numpy().view(np.uint64), oracle.sort(c, np.uint64)), label + " eager"
