@@ -338,6 +338,8 @@ def main():
     ap.add_argument("--radix-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serve-low-rate", type=float, default=4000.0,
+                    help="second serving replay at this rate (req/s; 0: skip)")
     ap.add_argument("--no-structured", action="store_true",
                     help="skip the run-shaped columns (run-length injection)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -495,6 +497,11 @@ def main():
         line["batched"] = bench_batched(ctx)
     if args.serve_seconds > 0:
         line["serving"] = bench_serving(args.serve_seconds)
+        if args.serve_low_rate > 0:
+            # the same request law at a rate the GPU sustains: request latency without
+            # the queue that grows at 10^4 req/s
+            line["serving_low_rate"] = bench_serving(min(args.serve_seconds, 5.0), rate=args.serve_low_rate,
+                                                     fifo_seconds=0.5)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x_np, 20)
     print(json.dumps(line), flush=True)
