@@ -64,6 +64,18 @@ def measured_traffic(kernel, n):
     return e.get("bytes_per_launch")
 
 
+def _cpu_model():
+    """Model name of the host CPU (first /proc/cpuinfo entry), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(x_np, seconds_hint):
     import numpy as np
 
@@ -83,7 +95,8 @@ def cpu_baseline(x_np, seconds_hint):
         oracle.std_sort_i64(sample)
         dt = time.perf_counter() - t0
         best_std = dt if best_std is None else min(best_std, dt)
-    return {"value": m / best / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+    host = {"cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+    return {"value": m / best / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle", "host": host,
             "sample": "first %d keys of the same column (std::map count + emit, single thread, min of 2 runs, %.2f s each)"
                       % (m, best),
             "std_sort": {"value": m / best_std / 1e9, "unit": "Gkeys/s", "cores": 1,
