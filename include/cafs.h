@@ -113,11 +113,12 @@ typedef struct cafs_ctx cafs_ctx_t;
 cafs_status_t cafs_ctx_create(cafs_ctx_t** ctx, int device);
 void cafs_ctx_destroy(cafs_ctx_t* ctx);
 
-/* Per-stage timing.  While enabled, every cafs_sort_i64/u64 call on the context
+/* Per-stage timing.  While enabled, every cafs_sort_i64/u64/f64 call on the context
  * records HIP events on its stream at the stage boundaries:
  *   0 pre    order check, Chao1 estimate, dispatch, table
  *            initialisation and tiny count                 (Alg. 2, Alg. 3, Sec. 4.4)
- *   1 count  hash count, with its pass over deferred elements (one kernel) (Sec. 4.4)
+ *   1 count  hash count with run-length injection, and its pass over
+ *            deferred elements (one kernel)                (Sec. 4.4)
  *   2 order  ranking of up to 32768 distinct keys, run offsets and the guard's
  *            bucket check, or the gather for a pair sort   (Alg. 4)
  *   3 emit   run expansion on the caller's stream: the row emit kernel (Alg. 4)

@@ -353,8 +353,6 @@ __device__ __forceinline__ bool run_lengths(const uint64_t (&x)[NE], uint32_t wa
     if ((uint32_t)__popcll(__ballot((want & 3u) == 3u && x[0] == x[1])) < kRleProbePairs) return false;
 #pragma unroll
     for (int u = 0; u < NE / 2; ++u) {
-        add[2 * u] = 1u;
-        add[2 * u + 1] = 1u;
         if (__ballot(((want >> (2 * u)) & 3u) != 3u) != 0) continue;
         const uint64_t a = x[2 * u], b = x[2 * u + 1];
         const uint64_t prev = wave_shr1(b);
