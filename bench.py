@@ -224,6 +224,55 @@ def bench_structured(ctx, n=1 << 28, steps=10):
     return res
 
 
+def bench_variants(ctx, n=1 << 28, k=1000, steps=10):
+    """The headline column shape (N = 2^28, K = 1000, Zipf(1.0)) as float64 keys
+    (IEEE 754 totalOrder; a palette of normal doubles over the same rank stream) and
+    as int64 keys through a context with a seeded count-table hash."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2605_25040_amd as cafs
+
+    def timed(x, unsigned=False):
+        out = torch.empty_like(x)
+        ws = ctx.workspace(ctx.workspace_bytes(n))
+        for _ in range(2):
+            _, rep, _, _ = ctx.sort(x, unsigned=unsigned, out=out, ws=ws)
+        torch.cuda.synchronize()
+        r = cafs.parse_report(rep)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            ctx.sort(x, unsigned=unsigned, out=out, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        del out
+        return {"n": n, "ms": round(ms, 4), "gkeys_s": round(n / ms / 1e6, 2), "path": r["path"],
+                "k_exact": r["k_exact"]}
+
+    res = {}
+    codes = torch.empty(n, dtype=torch.int64, device="cuda")
+    gen.column_device(codes, k, dist="zipf", s=1.0, palette="codes")
+    pal = torch.from_numpy(np.random.default_rng(7).normal(size=k) * 1e3).to("cuda")
+    x = pal[codes]
+    del codes
+    res["float64_k%d" % k] = timed(x)
+    del x
+    x = torch.empty(n, dtype=torch.int64, device="cuda")
+    gen.column_device(x, k, dist="zipf", s=1.0, palette="random")
+    ctx.set_hash_seed(0x5EED)
+    try:
+        res["seeded_hash_k%d" % k] = timed(x)
+    finally:
+        ctx.set_hash_seed(0)
+    del x
+    ctx._ws = None
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_serving(seconds, rate=10_000, budget=64 << 30, fifo_seconds=2.0):
     """Real-time Poisson replay through the server, then the first fifo_seconds of
     the same trace served one request at a time with plain calls (the baseline)."""
@@ -354,7 +403,7 @@ def main():
     ap.add_argument("--serve-low-rate", type=float, default=4000.0,
                     help="second serving replay at this rate (req/s; 0: skip)")
     ap.add_argument("--no-structured", action="store_true",
-                    help="skip the run-shaped columns (run-length injection)")
+                    help="skip the run-shaped, float64 and seeded-hash columns")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the input (counter calibration under a profiler)")
     ap.add_argument("--sweep", action="store_true",
@@ -506,6 +555,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_structured:
         line["structured"] = bench_structured(ctx)
+        line["variants"] = bench_variants(ctx)
     if not args.no_batched:
         line["batched"] = bench_batched(ctx)
     if args.serve_seconds > 0:
