@@ -436,3 +436,23 @@ def test_graph_capture_replays(ctx):
             y, _, _, _ = ctx.sort(x, unsigned=True, ws=ws)
             torch.cuda.synchronize()
             assert np.array_equal(y.cpu().numpy().view(np.uint64), oracle.sort(c, np.uint64)), label + " eager"
+
+
+def test_empty_marker_pattern_in_every_shape(ctx):
+    """The all-ones pattern (the count tables' empty-slot marker, a negative NaN as
+    float64, -1 as int64) mixed with extreme patterns, as float64 on every path and
+    in long runs (the run-length path skips slices that hold it)."""
+    ext = np.array([0xFFFFFFFFFFFFFFFF, 0x7FFFFFFFFFFFFFFF, 0x8000000000000000, 0x0, 0xFFF0000000000000,
+                    0x7FF0000000000000, 0x1, 0xFFFFFFFFFFFFFFFE], dtype=np.uint64)
+    rng = np.random.default_rng(44)
+    for n, kk in ((1000, 8), (50_000, 3), (50_000, 8), (80_000, 1000), (1_000_000, 5000)):
+        extra = (rng.normal(size=max(0, kk - ext.size)) * 1e6).view(np.uint64)
+        pal = np.concatenate([ext, extra])[:max(kk, 3)]
+        x = pal[rng.integers(0, pal.size, size=n)]
+        check_f64(ctx, x.view(np.float64), "f64 extremes n=%d k=%d" % (n, kk))
+    lens = rng.integers(1, 5000, size=400)
+    keys = ext[rng.integers(0, ext.size, size=lens.size)]
+    x = np.repeat(keys, lens)
+    check_f64(ctx, x.view(np.float64), "f64 runs of extremes")
+    check(ctx, x, False, label="i64 runs of extremes")
+    check(ctx, x, True, label="u64 runs of extremes")
