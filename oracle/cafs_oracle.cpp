@@ -27,7 +27,10 @@
 // Parity status: every function here is pinned by the CPU tests (library
 // sort, brute force over small alphabets, closed forms of Eq. chao1, Eq. hash
 // and Eq. Msize with the paper's worked sizes, crafted bucket collisions with
-// hand-derived spill counts, a Poisson check of the bucket model).
+// hand-derived spill counts, a Poisson check of the bucket model).  The float64
+// order (TotalF64) is pinned to the IEEE 754 totalOrder of signed zeros,
+// infinities, subnormals and NaNs of both signs, and to numpy's sort on ordinary
+// values.
 
 #include <cstdint>
 #include <cstring>
