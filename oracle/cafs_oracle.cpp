@@ -129,6 +129,12 @@ struct TotalF64 {
 };
 static_assert(sizeof(TotalF64) == 8, "same layout as the column");
 
+std::vector<TotalF64> as_total(const uint64_t* x, uint64_t n) {
+    std::vector<TotalF64> v(n);
+    if (n) std::memcpy(v.data(), x, n * sizeof(uint64_t));
+    return v;
+}
+
 struct Estimate {
     uint64_t k_hat, u, f1, f2, n_samples, stride, saturated;
     std::vector<uint64_t> sample_keys;  // distinct sampled values (bit patterns)
@@ -208,12 +214,13 @@ struct Report {
 };
 
 // Dispatcher (Alg. 3) with the tiny-count verification of Sec. 4.4 and the
-// reconstruction guard of Alg. 4.
+// reconstruction guard of Alg. 4.  `x` gives the column's order, `bits` the same
+// elements as 64-bit patterns (equality, the estimate, the tiny check and the spill
+// act on the patterns).
 template <class T>
-Report dispatch(const T* x, uint64_t n) {
+Report dispatch(const T* x, const uint64_t* bits, uint64_t n) {
     Report r{};
     r.k_exact = distinct_count(x, n);
-    const uint64_t* bits = reinterpret_cast<const uint64_t*>(x);
     if (is_monotone(x, n)) { r.path = O_MONOTONE; return r; }
     if (n < kSmallN) { r.path = O_SMALL_N; return r; }
     r.est = chao1(bits, n);
@@ -289,19 +296,34 @@ uint64_t oracle_table_M(uint64_t k_hat, uint64_t n) { return table_buckets(k_hat
 uint64_t oracle_hash(uint64_t v, uint64_t M) { return bucket_of(v, M); }
 uint64_t oracle_spill(const uint64_t* x, uint64_t n, uint64_t M) { return simulate_spill(x, n, M); }
 
-void oracle_report_i64(const int64_t* x, uint64_t n, uint64_t* out) { flatten(dispatch(x, n), out); }
+void oracle_report_i64(const int64_t* x, uint64_t n, uint64_t* out) {
+    std::vector<uint64_t> bits(n);
+    if (n) std::memcpy(bits.data(), x, n * sizeof(uint64_t));
+    flatten(dispatch(x, bits.data(), n), out);
+}
+// float64 entry points: the bit patterns are copied into TotalF64 objects (and
+// back), so that no storage is read through a type it does not hold.
 void oracle_report_f64(const uint64_t* x, uint64_t n, uint64_t* out) {
-    flatten(dispatch(reinterpret_cast<const TotalF64*>(x), n), out);
+    const std::vector<TotalF64> v = as_total(x, n);
+    flatten(dispatch(v.data(), x, n), out);
 }
 void oracle_sort_f64(const uint64_t* x, uint64_t n, uint64_t* y) {
-    sort_by_map(reinterpret_cast<const TotalF64*>(x), n, reinterpret_cast<TotalF64*>(y));
+    const std::vector<TotalF64> v = as_total(x, n);
+    std::vector<TotalF64> w(n);
+    sort_by_map(v.data(), n, w.data());
+    if (n) std::memcpy(y, w.data(), n * sizeof(uint64_t));
 }
 uint64_t oracle_counts_f64(const uint64_t* x, uint64_t n, uint64_t* uniq, uint64_t* counts) {
-    return counts_by_map(reinterpret_cast<const TotalF64*>(x), n, reinterpret_cast<TotalF64*>(uniq), counts);
+    const std::vector<TotalF64> v = as_total(x, n);
+    std::vector<TotalF64> u(uniq ? n : 0);
+    const uint64_t k = counts_by_map(v.data(), n, uniq ? u.data() : nullptr, counts);
+    if (uniq && k) std::memcpy(uniq, u.data(), k * sizeof(uint64_t));
+    return k;
 }
 int oracle_is_monotone_f64(const uint64_t* x, uint64_t n) {
-    return is_monotone(reinterpret_cast<const TotalF64*>(x), n) ? 1 : 0;
+    const std::vector<TotalF64> v = as_total(x, n);
+    return is_monotone(v.data(), n) ? 1 : 0;
 }
-void oracle_report_u64(const uint64_t* x, uint64_t n, uint64_t* out) { flatten(dispatch(x, n), out); }
+void oracle_report_u64(const uint64_t* x, uint64_t n, uint64_t* out) { flatten(dispatch(x, x, n), out); }
 
 }  // extern "C"
