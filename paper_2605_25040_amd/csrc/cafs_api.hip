@@ -480,6 +480,8 @@ cafs_status_t cafs_radix_sort(cafs_ctx_t* ctx, const void* d_in, void* d_out, ui
 // uploaded with one asynchronous copy.  Each column has its own single-column
 // workspace.
 
+}  // extern "C"
+
 namespace {
 
 constexpr uint32_t kBatchMaxBlocks = 64;  // per column and kernel
@@ -626,6 +628,8 @@ size_t batch_ws_layout(const uint64_t* ns, uint32_t n_cols, std::vector<size_t>*
 }
 
 }  // namespace
+
+extern "C" {
 
 size_t cafs_batched_workspace_bytes(const uint64_t* h_ns, uint32_t n_cols) {
     if (n_cols > 0 && !h_ns) return 0;
@@ -793,6 +797,8 @@ struct cafs_server {
     uint64_t n_batches = 0, n_launched = 0, n_refused = 0, max_busy = 0;
 };
 
+}  // extern "C"
+
 namespace {
 
 bool arena_alloc(cafs_server* sv, size_t bytes, size_t* off) {
@@ -829,6 +835,8 @@ void arena_free(cafs_server* sv, size_t off, size_t bytes) {
 }
 
 }  // namespace
+
+extern "C" {
 
 cafs_status_t cafs_server_create(cafs_ctx_t* ctx, size_t hbm_budget, uint32_t n_streams, uint32_t max_batch,
                                  cafs_server_t** out) {
