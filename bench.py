@@ -331,6 +331,7 @@ def run_sweep(seeds=3, steps=5, warmup=2):
     from concurrent.futures import ThreadPoolExecutor
     pool = ThreadPoolExecutor(max_workers=8)
     pending = []
+    flush = torch.empty(1 << 27, dtype=torch.int64, device=dev)  # 1 GiB, written before each cold call
     for name, n, k, dist, s, pal, dt, rep in cfgs:
         seed = gen.default_seed(n, k, rep)
         x_np = gen.column(n, k, dist=dist, s=s, palette=pal, seed=seed, dtype=np.uint64)
@@ -357,6 +358,18 @@ def run_sweep(seeds=3, steps=5, warmup=2):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
+        # cold: the 256 MB last-level cache (MALL) is flushed by writing a 1 GiB buffer
+        # before each call, which is timed on its own
+        cold = []
+        for _ in range(steps):
+            flush.fill_(1)
+            c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            c0.record()
+            step()
+            c1.record()
+            torch.cuda.synchronize()
+            cold.append(c0.elapsed_time(c1))
+        ms_cold = float(np.median(cold))
         r = cafs.parse_report(rep_t)
         o = out if not unsigned else (out ^ (-(2 ** 63)))  # unsigned order as signed order
         ordered = bool((o[1:] >= o[:-1]).all())
@@ -367,7 +380,8 @@ def run_sweep(seeds=3, steps=5, warmup=2):
             est = oracle.estimate(x_np)
             fields_of = (lambda r=r, est=est: [f for f in est if r[f] != est[f]])
         row = {"config": name, "n": n, "k": k, "dist": dist if dist == "uniform" else "zipf(%s)" % s,
-               "values": pal, "dtype": dt, "seed": seed, "ms": round(ms, 4), "gkeys_s": round(n / ms / 1e6, 2),
+               "values": pal, "dtype": dt, "seed": seed, "ms": round(ms, 4), "ms_cold": round(ms_cold, 4),
+               "gkeys_s": round(n / ms / 1e6, 2),
                "hbm_frac": round(16.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "path": r["path"],
                "k_hat": r["k_hat"], "k_exact": r["k_exact"], "spill": r["spill_elems"],
                "ordered": ordered}
@@ -381,12 +395,12 @@ def run_sweep(seeds=3, steps=5, warmup=2):
         print(json.dumps(row), flush=True)
         rows.append(row)
     pool.shutdown()
-    print("| config | N | K | freq | values | path | K^ | K | spill | ms | Gkeys/s | % HBM | checked |")
-    print("|---|---|---|---|---|---|---|---|---|---|---|---|---|")
+    print("| config | N | K | freq | values | path | K^ | K | spill | ms | ms cold | Gkeys/s | % HBM | checked |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|---|---|---|")
     for r in rows:
-        print("| %s | %d | %d | %s | %s %s | %s | %d | %d | %d | %.3f | %.1f | %.1f | %s |" % (
+        print("| %s | %d | %d | %s | %s %s | %s | %d | %d | %d | %.3f | %.3f | %.1f | %.1f | %s |" % (
             r["config"], r["n"], r["k"], r["dist"], r["values"], r["dtype"], r["path"], r["k_hat"], r["k_exact"],
-            r["spill"], r["ms"], r["gkeys_s"], 100 * r["hbm_frac"],
+            r["spill"], r["ms"], r["ms_cold"], r["gkeys_s"], 100 * r["hbm_frac"],
             "ok" if r["ordered"] and not r["report_mismatch"] else "MISMATCH %s" % r["report_mismatch"]))
     return rows
 
