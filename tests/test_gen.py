@@ -52,3 +52,26 @@ def test_structured_shapes():
     assert np.count_nonzero(runs[1:] != runs[:-1]) < n // 2
     almost = gen.column(n, k, dist="almost_sorted")
     assert np.unique(almost).size <= k
+
+
+def test_runs_recipe_mean_length():
+    """Run-shaped columns: runs of random length 1..2L-1 (mean L = N / (4K)), one
+    palette value per run (neighbouring runs merge when they draw the same value,
+    with probability 1/K)."""
+    n, k = 1 << 20, 64
+    x = gen.column(n, k, dist="runs", dtype=np.uint64)
+    boundaries = np.count_nonzero(x[1:] != x[:-1])
+    mean_len = n / (boundaries + 1)
+    L = n / (4 * k)
+    assert 0.85 * L <= mean_len <= 1.3 * L, (mean_len, L)
+    assert np.unique(x).size <= k
+
+
+def test_almost_sorted_recipe_swaps():
+    """Almost sorted: the sorted-by-group column with N/100 random transpositions,
+    so at most 2% of the positions differ from it."""
+    n, k = 200_000, 300
+    g = gen.column(n, k, dist="grouped", dtype=np.uint64)
+    a = gen.column(n, k, dist="almost_sorted", dtype=np.uint64)
+    assert np.array_equal(np.sort(a), np.sort(g))
+    assert 0 < np.count_nonzero(a != g) <= 2 * (n // 100)
