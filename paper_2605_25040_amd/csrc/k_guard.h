@@ -398,15 +398,29 @@ CAFS_KERNELS0(guard_resolve, 1024)
 __device__ __forceinline__ void guard_round_body(const Args& a, uint32_t r, uint32_t bid, uint32_t nblk) {
     const Ctrl* c = a.c;
     if (!guard_active(c) || !c->guard_rounds) return;
-    const uint64_t K = c->K;
+    // The rounds run in general mode only, where the contested list holds every key
+    // of an over-full bucket: walk it (not all K keys), four keys per thread with
+    // their loads in flight together.
+    const uint64_t nc = c->n_contested;
     const uint32_t lg = log2_pow2(c->table_M);
     const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
     const uint64_t gstride = (uint64_t)nblk * blockDim.x;
-    for (uint64_t j = gtid; j < K; j += gstride) {
-        const uint32_t b = phi_hash(a.uniq[j], lg);
-        if (a.dcount[b] <= kBucketCap) continue;
-        const uint32_t f = a.first_idx[j];
-        if (r == 0 || f > a.bmin[(r - 1) * a.m_ws + b]) atomicMin(&a.bmin[r * a.m_ws + b], f);
+    constexpr uint32_t U = 4;
+    for (uint64_t l0 = gtid; l0 < nc; l0 += U * gstride) {
+        uint32_t j[U], b[U], f[U], pm[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) j[u] = l0 + u * gstride < nc ? a.clist[l0 + u * gstride] : 0u;
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const bool in = l0 + u * gstride < nc;
+            b[u] = in ? phi_hash(a.uniq[j[u]], lg) : 0u;
+            f[u] = in ? a.first_idx[j[u]] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) pm[u] = (r > 0 && l0 + u * gstride < nc) ? a.bmin[(r - 1) * a.m_ws + b[u]] : 0u;
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u)
+            if (l0 + u * gstride < nc && (r == 0 || f[u] > pm[u])) atomicMin(&a.bmin[r * a.m_ws + b[u]], f[u]);
     }
 }
 CAFS_KERNELS1(guard_round, 256, uint32_t, r)
@@ -415,14 +429,28 @@ __device__ __forceinline__ void guard_final_body(const Args& a, uint32_t bid, ui
     Ctrl* c = a.c;
     if (!guard_active(c) || !c->guard_rounds) return;
     __shared__ uint32_t s_last;
-    const uint64_t K = c->K;
     const uint32_t lg = log2_pow2(c->table_M);
     const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
     const uint64_t gstride = (uint64_t)nblk * blockDim.x;
+    // (the contested list, as in the rounds)
+    const uint64_t nc = c->n_contested;
+    constexpr uint32_t U = 4;
     uint64_t local = 0;
-    for (uint64_t j = gtid; j < K; j += gstride) {
-        const uint32_t b = phi_hash(a.uniq[j], lg);
-        if (a.dcount[b] > kBucketCap && a.first_idx[j] > a.bmin[3 * a.m_ws + b]) local += a.cnt[j];
+    for (uint64_t l0 = gtid; l0 < nc; l0 += U * gstride) {
+        uint32_t j[U], b[U], f[U], m4[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) j[u] = l0 + u * gstride < nc ? a.clist[l0 + u * gstride] : 0u;
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const bool in = l0 + u * gstride < nc;
+            b[u] = in ? phi_hash(a.uniq[j[u]], lg) : 0u;
+            f[u] = in ? a.first_idx[j[u]] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) m4[u] = l0 + u * gstride < nc ? a.bmin[3 * a.m_ws + b[u]] : kNoIndex;
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u)
+            if (l0 + u * gstride < nc && f[u] > m4[u]) local += a.cnt[j[u]];
     }
     local = wave_sum_u64(local);
     if (__lane_id() == 0 && local) atomicAdd((unsigned long long*)&c->spill, (unsigned long long)local);
