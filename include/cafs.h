@@ -33,7 +33,10 @@
  *     directions); equality (used by the estimate, the counts and the guard's
  *     buckets) is on the raw 64-bit pattern, so -0 and +0 are distinct keys and
  *     so are NaNs with different payloads.
- *   - N must be below 2^32.
+ *   - N must be below 2^32 (CAFS_EINVAL otherwise).  Positions, run offsets and
+ *     the per-workgroup counters are 32-bit where that saves registers or LDS;
+ *     with its workspace (about 47 bytes per key, cafs_workspace_bytes) and its
+ *     input and output, a column of 2^32 keys would fill nearly all of a 288 GB GPU.
  */
 #ifndef CAFS_H
 #define CAFS_H
@@ -122,8 +125,8 @@ void cafs_ctx_destroy(cafs_ctx_t* ctx);
  *   2 order  ranking of up to 32768 distinct keys, run offsets and the guard's
  *            bucket check, or the gather for a pair sort   (Alg. 4)
  *   3 emit   run expansion on the caller's stream: the row emit kernel (Alg. 4)
- *   4 tail   the rest until the report is written: the tile emit (K > 32768
- *            or N >= 2^32, and in-place calls, which emit after the guard), the radix engine, the
+ *   4 tail   the rest until the report is written: the tile emit (K > 32768),
+ *            the row emit of in-place calls (after the guard), the radix engine, the
  *            larger pair sort and its emit, the monotone copy, the run-length
  *            pass and the guard run on a side stream of the context, forked
  *            after stage 2, and count here as far as they outlast the emit.
@@ -143,9 +146,11 @@ size_t cafs_workspace_bytes(uint64_t n, cafs_dtype_t dtype);
 
 /* Chao1 estimate of the distinct-value count of d_keys[0..n) (Alg. 2).
  * Writes one cafs_estimate_t to device memory d_out.  Uses no workspace.
- * The estimate ignores signedness.  n = 0 gives the all-zero estimate with
- * stride 1. */
-cafs_status_t cafs_estimate(cafs_ctx_t* ctx, const void* d_keys, uint64_t n,
+ * dtype names the column's key type (CAFS_I64, CAFS_U64 or CAFS_F64; anything
+ * else is CAFS_EINVAL); the estimate compares keys by their 64-bit patterns only,
+ * so its result is the same for every dtype.  n = 0 gives the all-zero estimate
+ * with stride 1. */
+cafs_status_t cafs_estimate(cafs_ctx_t* ctx, const void* d_keys, uint64_t n, cafs_dtype_t dtype,
                             cafs_estimate_t* d_out, void* stream);
 
 /* Sorts d_in[0..n) into d_out[0..n) (nondecreasing in the dtype's order) along

@@ -58,8 +58,6 @@ def _load():
         for name in ("oracle_estimate", "oracle_report_i64", "oracle_report_u64", "oracle_report_f64"):
             getattr(lib, name).argtypes = [p, u64, p]
             getattr(lib, name).restype = None
-        lib.oracle_sample_keys.argtypes = [p, u64, p]
-        lib.oracle_sample_keys.restype = u64
         lib.oracle_table_M.argtypes = [u64, u64]
         lib.oracle_table_M.restype = u64
         lib.oracle_hash.argtypes = [u64, u64]
@@ -126,13 +124,6 @@ def estimate(x):
     out = np.zeros(7, dtype=np.uint64)
     _load().oracle_estimate(_ptr(a), a.size, _ptr(out))
     return {k: int(v) for k, v in zip(ESTIMATE_FIELDS, out)}
-
-
-def sample_keys(x):
-    a = _arr(x, np.uint64)
-    keys = np.empty(1024, dtype=np.uint64)
-    k = _load().oracle_sample_keys(_ptr(a), a.size, _ptr(keys))
-    return keys[:k].copy()
 
 
 def table_M(k_hat, n):

@@ -285,13 +285,6 @@ void oracle_estimate(const uint64_t* x, uint64_t n, uint64_t* out) {
     out[4] = e.n_samples; out[5] = e.stride; out[6] = e.saturated;
 }
 
-// Distinct sampled values (at most 1024), ascending as unsigned bit patterns.
-uint64_t oracle_sample_keys(const uint64_t* x, uint64_t n, uint64_t* keys) {
-    const Estimate e = chao1(x, n);
-    for (size_t j = 0; j < e.sample_keys.size(); ++j) keys[j] = e.sample_keys[j];
-    return e.sample_keys.size();
-}
-
 uint64_t oracle_table_M(uint64_t k_hat, uint64_t n) { return table_buckets(k_hat, n); }
 uint64_t oracle_hash(uint64_t v, uint64_t M) { return bucket_of(v, M); }
 uint64_t oracle_spill(const uint64_t* x, uint64_t n, uint64_t M) { return simulate_spill(x, n, M); }

@@ -74,7 +74,7 @@ def load():
     lib.cafs_ctx_stage_ms.restype = i32
     lib.cafs_workspace_bytes.argtypes = [u64, i32]
     lib.cafs_workspace_bytes.restype = ctypes.c_size_t
-    lib.cafs_estimate.argtypes = [p, p, u64, p, p]
+    lib.cafs_estimate.argtypes = [p, p, u64, i32, p, p]
     lib.cafs_estimate.restype = i32
     for name in ("cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64"):
         getattr(lib, name).argtypes = [p, p, p, u64, p, p, p, p, ctypes.c_size_t, p]
@@ -172,10 +172,12 @@ class Context:
             self._ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
         return self._ws
 
-    def estimate(self, x):
-        """Chao1 estimate of x (int64 tensor) as a dict."""
+    def estimate(self, x, unsigned=False):
+        """Chao1 estimate of x (int64 or float64 tensor; ``unsigned`` names an int64
+        tensor holding uint64 keys) as a dict."""
         out = torch.zeros(ctypes.sizeof(Estimate), dtype=torch.uint8, device=self.device)
-        _check(self._lib.cafs_estimate(self._h, _ptr(x), x.numel(), _ptr(out), _stream(self.device)))
+        dt = F64 if x.dtype == torch.float64 else (U64 if unsigned else I64)
+        _check(self._lib.cafs_estimate(self._h, _ptr(x), x.numel(), dt, _ptr(out), _stream(self.device)))
         e = Estimate.from_buffer_copy(bytes(out.cpu().numpy()))
         return {k: int(getattr(e, k)) for k, _ in Estimate._fields_ if k != "pad"}
 
@@ -303,7 +305,12 @@ class Server:
 
 def parse_report(rep):
     """Report tensor (device, after a sync) -> dict with the oracle's field names."""
-    r = Report.from_buffer_copy(bytes(rep.cpu().numpy()))
+    return parse_report_bytes(bytes(rep.cpu().numpy()))
+
+
+def parse_report_bytes(raw):
+    """A report's bytes (host copy) -> dict with the oracle's field names."""
+    r = Report.from_buffer_copy(raw)
     d = {k: int(getattr(r.est, k)) for k, _ in Estimate._fields_ if k != "pad"}
     d.update(path=PATHS[r.path], tiny_miss=int(r.tiny_miss), table_M=int(r.table_M),
              spill_elems=int(r.spill_elems), k_exact=int(r.k_exact), engine=ENGINES[r.engine],

@@ -51,15 +51,15 @@ cafs_status_t hip_fail(hipError_t e, const char* where) {
 
 constexpr size_t kAlign = 256;
 
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+constexpr size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-uint64_t bit_ceil_host(uint64_t v) {
+constexpr uint64_t bit_ceil_host(uint64_t v) {
     uint64_t p = 1;
     while (p < v) p <<= 1;
     return p;
 }
 
-uint32_t log2_host(uint64_t p) {
+constexpr uint32_t log2_host(uint64_t p) {
     uint32_t m = 0;
     while ((1ull << m) < p) ++m;
     return m;
@@ -74,7 +74,7 @@ struct Layout {
     uint64_t m_ws;
 };
 
-Layout make_layout(uint64_t n) {
+constexpr Layout make_layout(uint64_t n) {
     Layout L{};
     const uint64_t nn = n > 0 ? n : 1;
     // the global table never needs more than bit_ceil(n) slots (K <= n); the device
@@ -277,10 +277,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     const uint32_t g_emit = grid_for(n, 2 * cafs::kEmitTilePairs, cus * 4);
     if (countable && !inplace) cafs::k_emit_rows<<<std::min<uint32_t>(g_emit, cus), cafs::kEmitRowsThreads, 0, s>>>(a);
     mark(4);
-    // the tile emit, for the columns the row emit does not take (N >= 2^32; timed in
-    // the tail); larger K is emitted after the pair sort on the side stream
-    const bool tile_main = n >= (1ull << 32);
-    if (countable && !inplace && tile_main) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 2u);
+    // (K > 32768 is emitted by the tile emit after the pair sort on the side stream)
     launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2, countable);
     if (countable && n > cafs::kRankMax) {
         const uint32_t g_scan = std::min<uint32_t>(cus * 2, cafs::kMaxCountBlocks);
@@ -307,10 +304,8 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     }
     (void)hipEventRecord(ctx->join, s2);
     (void)hipStreamWaitEvent(s, ctx->join, 0);
-    if (countable && inplace) {
+    if (countable && inplace)
         cafs::k_emit_rows<<<std::min<uint32_t>(g_emit, cus), cafs::kEmitRowsThreads, 0, s>>>(a);
-        if (tile_main) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s>>>(a, 2u);
-    }
     cafs::k_finalize<<<1, 64, 0, s>>>(a);
     mark(5);
     if (!evs.empty()) ctx->calls.push_back(evs);
@@ -427,8 +422,10 @@ size_t cafs_workspace_bytes(uint64_t n, cafs_dtype_t dtype) {
     return make_layout(n).total;
 }
 
-cafs_status_t cafs_estimate(cafs_ctx_t* ctx, const void* d_keys, uint64_t n, cafs_estimate_t* d_out, void* stream) {
+cafs_status_t cafs_estimate(cafs_ctx_t* ctx, const void* d_keys, uint64_t n, cafs_dtype_t dtype,
+                            cafs_estimate_t* d_out, void* stream) {
     if (!ctx || !d_out || (n > 0 && !d_keys) || reinterpret_cast<uintptr_t>(d_keys) % 8) return CAFS_EINVAL;
+    if (!dtype_ok(dtype)) return CAFS_EINVAL;
     if (n >= (1ull << 32)) return CAFS_EINVAL;
     DeviceGuard dg(ctx->device);
     (void)hipGetLastError();

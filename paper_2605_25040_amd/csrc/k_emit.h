@@ -96,15 +96,11 @@ __device__ __forceinline__ void emit_tiles(const Args& a, uint32_t bid, uint32_t
         __syncthreads();
     }
 }
-// Whether the row emit (below) writes the main instance.
-__device__ __forceinline__ bool rows_take(const Args& a, const Ctrl* c);
-
-// `mode`: 0 main instance, 1 after the pair sort, 2 main instance unless the row
-// emit takes it (single-column launch sequence).
+// `mode`: 0 main instance (batched launches, which have no row emit), 1 after the
+// pair sort.
 __device__ __forceinline__ void emit_body(const Args& a, uint32_t mode, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (mode == 1 ? !(c->pair_sort && c->dense_ready && !c->overflow) : !c->emit_main) return;
-    if (mode == 2 && rows_take(a, c)) return;
     __shared__ uint64_t s_j[2];
     __shared__ uint64_t s_off[kEmitLdsRuns + 1];
     __shared__ uint64_t s_key[kEmitLdsRuns];
@@ -112,7 +108,7 @@ __device__ __forceinline__ void emit_body(const Args& a, uint32_t mode, uint32_t
 }
 CAFS_KERNELS1(emit, kEmitThreads, uint32_t, mode)
 
-// Row emit, the main instance for K <= kRankMax and N < 2^32.  HBM takes writes
+// Row emit, the main instance of a single-column call (K <= kRankMax).  HBM takes writes
 // fastest when few regions are written at a time (measured on MI355X: about 6.3
 // TB/s when 256 workgroups sweep the output in rows, whether as one sweep or as up
 // to 32 sweeps over separate segments, against 5.2-5.8 TB/s when each workgroup
@@ -166,7 +162,7 @@ __device__ __forceinline__ uint64_t wave_run_of(const uint64_t* off, uint64_t lo
 }
 
 __device__ __forceinline__ bool rows_take(const Args& a, const Ctrl* c) {
-    return c->K >= 1 && c->K <= kRankMax && a.n < (1ull << 32);
+    return c->K >= 1 && c->K <= kRankMax;  // (columns hold fewer than 2^32 keys)
 }
 
 __device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint32_t nblk) {

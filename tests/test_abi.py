@@ -57,7 +57,7 @@ def test_argument_errors_without_gpu(lib):
     # NULL context
     assert lib.cafs_sort_i64(None, p(16), p(16), 10, None, None, None, p(256), 1 << 20, None) == -1
     assert lib.cafs_radix_sort(None, p(16), p(16), 10, 0, p(256), 1 << 20, None) == -1
-    assert lib.cafs_estimate(None, p(16), 10, p(16), None) == -1
+    assert lib.cafs_estimate(None, p(16), 10, 0, p(16), None) == -1
     assert lib.cafs_sort_f64(None, p(16), p(16), 10, None, None, None, p(256), 1 << 20, None) == -1
     assert lib.cafs_ctx_set_hash_seed(None, 5) == -1
     h = ctypes.c_void_p()
