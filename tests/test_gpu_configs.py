@@ -25,7 +25,7 @@ import oracle
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-_POOL = cf.ThreadPoolExecutor(max_workers=12)
+_POOL = cf.ThreadPoolExecutor(max_workers=14)
 
 
 @pytest.fixture(scope="module")
@@ -90,15 +90,29 @@ def test_hbm_scale_column(ctx, variant):
     torch.cuda.empty_cache()
 
 
+SWEEP_N = 30_000_000
 SWEEP_K = [4, 8, 200, 10_000, 130_000, 670_000, 3_000_000, 30_000_000]
+SWEEP_DISTS = ["uniform", "zipf"]
 
 
-@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+@pytest.fixture(scope="module")
+def sweep_oracle():
+    """Every sweep column and its oracle futures, submitted at once (the largest
+    configs take the oracle about a minute), so that the oracle runs ahead of the
+    GPU tests."""
+    cols = {}
+    for k in sorted(SWEEP_K, reverse=True):
+        for dist in SWEEP_DISTS:
+            x = gen.column(SWEEP_N, k, dist=dist, s=1.1, palette="random", dtype=np.int64)
+            cols[(k, dist)] = (x, oracle_async(x, np.int64))
+    yield cols
+    cols.clear()
+
+
+@pytest.mark.parametrize("dist", SWEEP_DISTS)
 @pytest.mark.parametrize("k", SWEEP_K)
-def test_dispatcher_sweep(ctx, k, dist):
-    n = 30_000_000
-    x = gen.column(n, k, dist=dist, s=1.1, palette="random", dtype=np.int64)
-    futs = oracle_async(x, np.int64)
+def test_dispatcher_sweep(ctx, sweep_oracle, k, dist):
+    x, futs = sweep_oracle[(k, dist)]
     y, r, u, c = sort_on_gpu(ctx, x, False)
     compare("sweep K=%d %s" % (k, dist), y, r, u, c, futs)
 
