@@ -176,6 +176,23 @@ cafs_status_t cafs_sort_f64(cafs_ctx_t* ctx, const double* d_in, double* d_out, 
                             double* d_uniq, uint64_t* d_counts, cafs_report_t* d_report,
                             void* d_ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory or pass a workspace (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): the
+ * sort of cafs_sort_i64 / _u64 / _f64 (dtype selects which) with the same buffer
+ * rules, outputs and report, but without a workspace argument.  Its workspace is a
+ * static device array sized for CAFS_NOALLOC_MAX_N keys
+ * (cafs_workspace_bytes(CAFS_NOALLOC_MAX_N) bytes, about 67 MiB), one copy per
+ * GPU, held from the library's load until the process ends; its address is looked
+ * up when the first context on the device is created.  The call allocates nothing
+ * (no hipMalloc, no events; stage timing does not apply).  n > CAFS_NOALLOC_MAX_N is
+ * CAFS_EINVAL.  Every call on one GPU shares that array: calls that overlap on a GPU
+ * (on different streams, or different contexts, without ordering between them) race
+ * and give wrong results.  The array needs no clearing: every call writes what it
+ * reads (its contents on entry do not matter, as for a caller's workspace). */
+#define CAFS_NOALLOC_MAX_N (1u << 20)
+cafs_status_t cafs_sort_noalloc(cafs_ctx_t* ctx, const void* d_in, void* d_out, uint64_t n, cafs_dtype_t dtype,
+                                void* d_uniq, uint64_t* d_counts, cafs_report_t* d_report, void* stream);
+
 /* The fallback engine on its own: LSD radix sort with 8-bit digits and decoupled
  * look-back (digits on which every key agrees are skipped).  It is the GPU
  * baseline the CAFS path is measured against.  Same buffer rules as above;

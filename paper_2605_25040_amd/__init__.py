@@ -22,7 +22,7 @@ STAGES = ("pre", "count", "order", "emit", "tail")
 
 EXPORTS = ("cafs_ctx_create", "cafs_ctx_destroy", "cafs_ctx_enable_timing", "cafs_ctx_stage_ms",
            "cafs_workspace_bytes", "cafs_estimate",
-           "cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64", "cafs_radix_sort", "cafs_batched_workspace_bytes",
+           "cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64", "cafs_sort_noalloc", "cafs_radix_sort", "cafs_batched_workspace_bytes",
            "cafs_sort_batched", "cafs_ctx_set_batch_tuning", "cafs_autotune_batched", "cafs_ctx_set_hash_seed",
            "cafs_server_create", "cafs_server_destroy", "cafs_server_reserve", "cafs_server_submit",
            "cafs_server_poll", "cafs_server_release", "cafs_server_stats",
@@ -79,6 +79,8 @@ def load():
     for name in ("cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64"):
         getattr(lib, name).argtypes = [p, p, p, u64, p, p, p, p, ctypes.c_size_t, p]
         getattr(lib, name).restype = i32
+    lib.cafs_sort_noalloc.argtypes = [p, p, p, u64, i32, p, p, p, p]
+    lib.cafs_sort_noalloc.restype = i32
     lib.cafs_radix_sort.argtypes = [p, p, p, u64, i32, p, ctypes.c_size_t, p]
     lib.cafs_radix_sort.restype = i32
     lib.cafs_batched_workspace_bytes.argtypes = [p, u32]

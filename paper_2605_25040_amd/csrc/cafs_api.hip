@@ -9,6 +9,7 @@
 #include <chrono>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <unordered_map>
 #include <cstdint>
 #include <cstring>
@@ -35,6 +36,7 @@ struct cafs_ctx {
     uint64_t batch_per_block;       // batched launch: elements per block of the general kernels
     uint64_t batch_per_hash_block;  // and of the hash count
     uint64_t table_mul;             // odd multiplier of the count tables' hash
+    void* scratch;                  // this device's address of the static workspace (cafs_sort_noalloc)
     bool timing;
     std::vector<hipEvent_t> pool;                 // free events
     std::vector<std::vector<hipEvent_t>> calls;   // CAFS_N_STAGES + 1 events per recorded call
@@ -112,6 +114,41 @@ constexpr Layout make_layout(uint64_t n) {
 
 template <class T>
 T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
+
+// Workspace of the allocation-free entry point: one column of up to CAFS_NOALLOC_MAX_N
+// keys, in a file-scope device array.  Each GPU the library runs on holds its own
+// copy until the process ends.  Host code never passes the array's name to a kernel
+// (on the host it is only a stand-in for the symbol): each device's address is
+// looked up once, with hipGetSymbolAddress, when the first context on that device is
+// created, and only that address is used.
+constexpr size_t kNoAllocWsBytes = make_layout(CAFS_NOALLOC_MAX_N).total;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocWsBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device, nullptr until looked up
+
+// Called with `device` current.
+cafs_status_t scratch_address(int device, int n_devices, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() < n_devices) g_scratch_ptr.resize(n_devices, nullptr);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || reinterpret_cast<uintptr_t>(p) % kAlign) {
+            g_last_error = "static workspace: unexpected address";
+            return CAFS_EHIP;
+        }
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return CAFS_OK;
+}
 
 bool overlaps(const void* a, const void* b, uint64_t n) {
     const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
@@ -212,7 +249,8 @@ cafs_status_t check_buffers(const void* in, const void* out, uint64_t n) {
 }
 
 cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, cafs_dtype_t dt, void* uniq,
-                        uint64_t* counts, cafs_report_t* report, void* ws, size_t ws_bytes, void* stream) {
+                        uint64_t* counts, cafs_report_t* report, void* ws, size_t ws_bytes, void* stream,
+                        bool may_time = true) {
     if (!ctx) return CAFS_EINVAL;
     if (!dtype_ok(dt)) return CAFS_EINVAL;
     cafs_status_t st = check_buffers(in, out, n);
@@ -230,7 +268,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     const cafs::Args a = make_args(ctx, L, in, out, n, dt, uniq, counts, report, ws);
     const int cus = ctx->cus;
     std::vector<hipEvent_t> evs;
-    if (ctx->timing) {
+    if (ctx->timing && may_time) {
         for (int i = 0; i <= CAFS_N_STAGES; ++i) {
             hipEvent_t e;
             if (!ctx->pool.empty()) {
@@ -357,8 +395,14 @@ cafs_status_t cafs_ctx_create(cafs_ctx_t** ctx, int device) {
     c->batch_per_block = 1ull << 16;
     c->batch_per_hash_block = 1ull << 18;
     c->table_mul = cafs::kPhi;
+    c->scratch = nullptr;
     {
         DeviceGuard dg(device);
+        cafs_status_t st = scratch_address(device, count, &c->scratch);
+        if (st != CAFS_OK) {
+            delete c;
+            return st;
+        }
         e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
@@ -448,6 +492,17 @@ cafs_status_t cafs_sort_u64(cafs_ctx_t* ctx, const uint64_t* d_in, uint64_t* d_o
 cafs_status_t cafs_sort_f64(cafs_ctx_t* ctx, const double* d_in, double* d_out, uint64_t n, double* d_uniq,
                             uint64_t* d_counts, cafs_report_t* d_report, void* d_ws, size_t ws_bytes, void* stream) {
     return sort_impl(ctx, d_in, d_out, n, CAFS_F64, d_uniq, d_counts, d_report, d_ws, ws_bytes, stream);
+}
+
+cafs_status_t cafs_sort_noalloc(cafs_ctx_t* ctx, const void* d_in, void* d_out, uint64_t n, cafs_dtype_t dtype,
+                                void* d_uniq, uint64_t* d_counts, cafs_report_t* d_report, void* stream) {
+    if (!ctx) return CAFS_EINVAL;
+    if (n > CAFS_NOALLOC_MAX_N) {
+        g_last_error = "cafs_sort_noalloc: n exceeds CAFS_NOALLOC_MAX_N";
+        return CAFS_EINVAL;
+    }
+    return sort_impl(ctx, d_in, d_out, n, dtype, d_uniq, d_counts, d_report, ctx->scratch, kNoAllocWsBytes, stream,
+                     false);
 }
 
 cafs_status_t cafs_radix_sort(cafs_ctx_t* ctx, const void* d_in, void* d_out, uint64_t n, cafs_dtype_t dtype,
