@@ -181,7 +181,7 @@ cafs_status_t cafs_sort_f64(cafs_ctx_t* ctx, const double* d_in, double* d_out, 
  * sort of cafs_sort_i64 / _u64 / _f64 (dtype selects which) with the same buffer
  * rules, outputs and report, but without a workspace argument.  Its workspace is a
  * static device array sized for CAFS_NOALLOC_MAX_N keys
- * (cafs_workspace_bytes(CAFS_NOALLOC_MAX_N) bytes, about 67 MiB), one copy per
+ * (cafs_workspace_bytes(CAFS_NOALLOC_MAX_N) bytes, about 92 MiB), one copy per
  * GPU, held from the library's load until the process ends; its address is looked
  * up when the first context on the device is created.  The call allocates nothing
  * (no hipMalloc, no events; stage timing does not apply).  n > CAFS_NOALLOC_MAX_N is
@@ -234,6 +234,17 @@ cafs_status_t cafs_sort_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, ui
  * in the hash count.  Affects speed only.  Defaults 65536 and 262144; the
  * autotuner (cafs_autotune_batched) picks them by timing. */
 cafs_status_t cafs_ctx_set_batch_tuning(cafs_ctx_t* ctx, uint64_t elems_per_block, uint64_t elems_per_hash_block);
+
+/* Geometry of the hash count (affects speed only; outputs and reports do not depend
+ * on it).  part_keys: estimated distinct keys per hash partition (the column is
+ * scattered into up to 16 partition buckets when the estimate exceeds twice this;
+ * at least 256).  wide_min: the estimate per partition from which the LDS table's
+ * buckets hold 4 keys instead of 2.  table_slots: global table slots per estimated
+ * key (2 to 256; half the slots may be claimed, keys past that go to the spill
+ * list).  Defaults 6000, 1800 and 32; cafs_autotune_batched tunes them for a
+ * batch.  Applies to calls enqueued afterwards on the context.  CAFS_EINVAL for a
+ * null context or values out of range. */
+cafs_status_t cafs_ctx_set_count_geometry(cafs_ctx_t* ctx, uint64_t part_keys, uint64_t wide_min, uint64_t table_slots);
 
 /* Seeds the hash of the GPU's count tables (the per-workgroup LDS tables and the
  * global table), against the deterministic-collision attack of a fixed hash (Sec.

@@ -23,7 +23,7 @@ STAGES = ("pre", "count", "order", "emit", "tail")
 EXPORTS = ("cafs_ctx_create", "cafs_ctx_destroy", "cafs_ctx_enable_timing", "cafs_ctx_stage_ms",
            "cafs_workspace_bytes", "cafs_estimate",
            "cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64", "cafs_sort_noalloc", "cafs_radix_sort", "cafs_batched_workspace_bytes",
-           "cafs_sort_batched", "cafs_ctx_set_batch_tuning", "cafs_autotune_batched", "cafs_ctx_set_hash_seed",
+           "cafs_sort_batched", "cafs_ctx_set_batch_tuning", "cafs_autotune_batched", "cafs_ctx_set_hash_seed", "cafs_ctx_set_count_geometry",
            "cafs_server_create", "cafs_server_destroy", "cafs_server_reserve", "cafs_server_submit",
            "cafs_server_poll", "cafs_server_release", "cafs_server_stats",
            "cafs_status_str", "cafs_last_error")
@@ -89,6 +89,8 @@ def load():
     lib.cafs_sort_batched.restype = i32
     lib.cafs_ctx_set_batch_tuning.argtypes = [p, u64, u64]
     lib.cafs_ctx_set_batch_tuning.restype = i32
+    lib.cafs_ctx_set_count_geometry.argtypes = [p, u64, u64, u64]
+    lib.cafs_ctx_set_count_geometry.restype = i32
     lib.cafs_ctx_set_hash_seed.argtypes = [p, u64]
     lib.cafs_ctx_set_hash_seed.restype = i32
     lib.cafs_autotune_batched.argtypes = [p, p, u32, p, ctypes.c_size_t, p, ctypes.POINTER(ctypes.c_double)]
@@ -243,6 +245,11 @@ class Context:
 
     def set_batch_tuning(self, elems_per_block, elems_per_hash_block):
         _check(self._lib.cafs_ctx_set_batch_tuning(self._h, int(elems_per_block), int(elems_per_hash_block)))
+
+    def set_count_geometry(self, part_keys=6000, wide_min=1800, table_slots=32):
+        """Hash-count geometry (speed only): keys per partition, the 4-key bucket
+        threshold per partition and global table slots per estimated key."""
+        _check(self._lib.cafs_ctx_set_count_geometry(self._h, int(part_keys), int(wide_min), int(table_slots)))
 
     def set_hash_seed(self, seed):
         """Seed of the count tables' hash (0: the paper's multiplier)."""

@@ -37,6 +37,9 @@ struct cafs_ctx {
     uint64_t batch_per_hash_block;  // and of the hash count
     uint64_t table_mul;             // odd multiplier of the count tables' hash
     void* scratch;                  // this device's address of the static workspace (cafs_sort_noalloc)
+    uint64_t part_keys;             // count geometry: estimated keys per hash partition
+    uint64_t wide_min;              // and the estimate per partition from which LDS buckets hold 4 keys
+    uint64_t table_slots;           // global table slots per estimated key
     bool timing;
     std::vector<hipEvent_t> pool;                 // free events
     std::vector<std::vector<hipEvent_t>> calls;   // CAFS_N_STAGES + 1 events per recorded call
@@ -69,7 +72,9 @@ constexpr uint32_t log2_host(uint64_t p) {
 
 // Workspace of one column of n keys.  Regions are 256-byte aligned.
 struct Layout {
-    size_t ctrl, gkeys, gcnt, claimed, uniq, cnt, off, tmp_k, psum, status, dcount, bfound, bmin, clist, first, rle_tile;
+    size_t ctrl, gkeys, gcnt, claimed, uniq, cnt, off, tmp_k, psum, status, dcount, bfound, bmin, clist, first, rle_tile,
+        spill_k, spill_v, pbuf;
+    uint64_t pbuf_elems;
     size_t total;
     uint32_t cap_log2;
     uint64_t status_slot;
@@ -99,8 +104,11 @@ constexpr Layout make_layout(uint64_t n) {
     L.uniq = take(nn * 8);
     L.cnt = take(nn * 8);
     L.off = take((nn + 1) * 8);
-    L.tmp_k = take((nn + 2 + 2 * cafs::kMaxCountBlocks) * 8);  // also the hash count's deferral regions
-    L.psum = take(cafs::kMaxCountBlocks * 8);
+    // radix scratch; also the hash count's deferral regions, one per item at the
+    // item's place in the column or in the partition buckets
+    L.pbuf_elems = nn + nn / 8 + cafs::kMaxParts * (cafs::kScatterChunk + 32);
+    L.tmp_k = take(std::max<uint64_t>(nn + 2 + 2 * cafs::kMaxCountBlocks, L.pbuf_elems) * 8);
+    L.psum = take(2 * cafs::kMaxCountBlocks * 8);
     L.status = take(2 * L.status_slot * 8);
     L.dcount = take(L.m_ws * 4);
     L.bfound = take(L.m_ws * 4);
@@ -108,6 +116,10 @@ constexpr Layout make_layout(uint64_t n) {
     L.clist = take(nn * 4);
     L.first = take(nn * 4);
     L.rle_tile = take(rle_tiles * 8);
+    L.spill_k = take(nn * 8);
+    L.spill_v = take(nn * 8);
+    // partition buckets: an eighth more than the column plus a scatter chunk per bucket
+    L.pbuf = take(L.pbuf_elems * 8);
     L.total = o;
     return L;
 }
@@ -199,6 +211,18 @@ uint32_t rank_grid(uint64_t n) {
     return grid_for(std::min<uint64_t>(n, cafs::kRankMax), cafs::kRankKeysPerBlock, 1u << 16);
 }
 
+// Workgroups of the single-column hash count: one per CU (the LDS table takes the
+// CU), fewer for short columns; a multiple of 8 * 16 or a power of two, so that
+// the work items of every partition count divide evenly.
+uint32_t count_grid(uint64_t n, int cus) {
+    uint32_t g = grid_for(n, cafs::kCountThreads * 8, std::min<uint32_t>(cus, cafs::kMaxCountBlocks));
+    const uint32_t q = cafs::kXcds << cafs::kMaxPartLog2;
+    if (g >= q) return g / q * q;
+    uint32_t p = 1;
+    while (2 * p <= g) p *= 2;
+    return p;
+}
+
 bool dtype_ok(cafs_dtype_t dt) { return dt == CAFS_I64 || dt == CAFS_U64 || dt == CAFS_F64; }
 
 cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void* out, uint64_t n, cafs_dtype_t dt,
@@ -233,6 +257,13 @@ cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void*
     a.m_ws = L.m_ws;
     a.rle_tile = at<uint64_t>(ws, L.rle_tile);
     a.psum = at<uint64_t>(ws, L.psum);
+    a.spill_k = at<uint64_t>(ws, L.spill_k);
+    a.spill_v = at<uint64_t>(ws, L.spill_v);
+    a.pbuf = at<uint64_t>(ws, L.pbuf);
+    a.pbuf_elems = L.pbuf_elems;
+    a.part_keys = ctx ? ctx->part_keys : cafs::kPartKeys;
+    a.wide_min = ctx ? ctx->wide_min : cafs::kLdsWideMinKhat;
+    a.table_slots = ctx ? ctx->table_slots : cafs::kTableSlotsPerKey;
     a.rank_blocks = rank_grid(n);
     a.rank_budget_log2 = cafs::kRankBudgetLog2;
     a.row_blocks = ctx ? (uint32_t)ctx->cus : 256u;
@@ -290,11 +321,13 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     if (n > cafs::kMonoPrefix) cafs::k_mono_full<<<grid_for(n, 256 * 16, cus * 4), 256, 0, s>>>(a);
     const bool countable = n >= cafs::kSmallN;  // tiny and main need N >= 2048
     if (countable)
-        cafs::k_phase2<<<grid_for(std::max<uint64_t>(n / 2, cap_ws), 256 * 8, cus * 2), 256, 0, s>>>(a);
+        cafs::k_phase2<<<grid_for(std::max<uint64_t>(n / 2, cap_ws), 256 * 4, cus * 4), 256, 0, s>>>(a);
     mark(1);
-    // one workgroup per CU (the LDS table takes the CU)
-    const uint32_t g_count = grid_for(n, cafs::kCountThreads * 8, std::min<uint32_t>(cus, cafs::kMaxCountBlocks));
-    if (countable) cafs::k_hash_count<<<g_count, cafs::kCountThreads, 0, s>>>(a);
+    const uint32_t g_count = count_grid(n, cus);
+    if (countable) {
+        cafs::k_part_scatter<<<grid_for(n, cafs::kScatterChunk * 4, cus * 2), cafs::kScatterThreads, 0, s>>>(a);
+        cafs::k_hash_count<<<g_count, cafs::kCountThreads, 0, s>>>(a);
+    }
     mark(2);
     if (countable) {
         cafs::k_rank<<<a.rank_blocks, 1024, 0, s>>>(a);
@@ -317,10 +350,11 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     mark(4);
     // (K > 32768 is emitted by the tile emit after the pair sort on the side stream)
     launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2, countable);
-    if (countable && n > cafs::kRankMax) {
+    if (countable) {
+        // (a spill can reach the pair sort at any N)
         const uint32_t g_scan = std::min<uint32_t>(cus * 2, cafs::kMaxCountBlocks);
-        cafs::k_pair_sums<<<g_scan, 1024, 0, s2>>>(a);
-        cafs::k_pair_scan<<<g_scan, 1024, 0, s2>>>(a);
+        cafs::k_fold_sums<<<g_scan, 1024, 0, s2>>>(a);
+        cafs::k_fold_write<<<g_scan, 1024, 0, s2>>>(a);
     }
     cafs::k_copy_mono<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s2>>>(a);
     const uint32_t g_rle = grid_for(n, cafs::kRleTile, cus * 4);
@@ -338,7 +372,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
         cafs::k_guard_final<<<g, 256, 0, s2>>>(a);
         // outputs written after the guard: it reads the input, which an in-place sort overwrites
         cafs::k_copy_deferred<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s2>>>(a);
-        if (n > cafs::kRankMax) cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s2>>>(a, 1u);
+        cafs::k_emit<<<g_emit, cafs::kEmitThreads, 0, s2>>>(a, 1u);
     }
     (void)hipEventRecord(ctx->join, s2);
     (void)hipStreamWaitEvent(s, ctx->join, 0);
@@ -396,6 +430,9 @@ cafs_status_t cafs_ctx_create(cafs_ctx_t** ctx, int device) {
     c->batch_per_hash_block = 1ull << 18;
     c->table_mul = cafs::kPhi;
     c->scratch = nullptr;
+    c->part_keys = cafs::kPartKeys;
+    c->wide_min = cafs::kLdsWideMinKhat;
+    c->table_slots = cafs::kTableSlotsPerKey;
     {
         DeviceGuard dg(device);
         cafs_status_t st = scratch_address(device, count, &c->scratch);
@@ -637,6 +674,7 @@ cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uin
     cafs::kb_pre<<<C, 1024, 0, s>>>(g1);
     cafs::kb_mono_full<<<TP, 256, 0, s>>>(gp);
     cafs::kb_phase2<<<TP, 256, 0, s>>>(gp);
+    cafs::kb_part_scatter<<<TP, cafs::kScatterThreads, 0, s>>>(gp);
     cafs::kb_hash_count<<<TH, cafs::kCountThreads, 0, s>>>(gh);
     cafs::kb_rank<<<TP, 1024, 0, s>>>(gp);
     cafs::kb_compact_order<<<C, 1024, 0, s>>>(g1);
@@ -646,8 +684,8 @@ cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uin
         cafs::kb_radix_pass_kv<<<TP, cafs::kRadixThreads, 0, s>>>(gp, p);
     }
     cafs::kb_radix_copy<<<TP, 256, 0, s>>>(gp);
-    cafs::kb_pair_sums<<<TP, 1024, 0, s>>>(gp);
-    cafs::kb_pair_scan<<<TP, 1024, 0, s>>>(gp);
+    cafs::kb_fold_sums<<<TP, 1024, 0, s>>>(gp);
+    cafs::kb_fold_write<<<TP, 1024, 0, s>>>(gp);
     cafs::kb_copy_mono<<<TP, 256, 0, s>>>(gp);
     cafs::kb_rle_count<<<TP, 256, 0, s>>>(gp);
     cafs::kb_rle_write<<<TP, 256, 0, s>>>(gp);
@@ -692,6 +730,14 @@ cafs_status_t cafs_ctx_set_batch_tuning(cafs_ctx_t* ctx, uint64_t elems_per_bloc
     if (!ctx || elems_per_block == 0 || elems_per_hash_block == 0) return CAFS_EINVAL;
     ctx->batch_per_block = elems_per_block;
     ctx->batch_per_hash_block = elems_per_hash_block;
+    return CAFS_OK;
+}
+
+cafs_status_t cafs_ctx_set_count_geometry(cafs_ctx_t* ctx, uint64_t part_keys, uint64_t wide_min, uint64_t table_slots) {
+    if (!ctx || part_keys < 256 || table_slots < 2 || table_slots > 256) return CAFS_EINVAL;
+    ctx->part_keys = part_keys;
+    ctx->wide_min = wide_min;
+    ctx->table_slots = table_slots;
     return CAFS_OK;
 }
 

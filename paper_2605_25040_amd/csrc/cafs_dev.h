@@ -35,8 +35,19 @@ constexpr uint64_t kLdsWideMinKhat = 1800;     // buckets of 4 keys from this es
 constexpr uint32_t kLdsWindow = 2;             // buckets probed before an element is deferred
 constexpr uint32_t kLdsProbeBuckets = 8;       // buckets probed in the deferred pass before the global table
 constexpr uint32_t kMaxCountBlocks = 1024;     // workgroups of one hash count
-constexpr uint32_t kGlobalProbe = 64;          // global probe limit before overflow (the table is sized for 1/8 load)
+constexpr uint32_t kGlobalProbe = 16;          // global probe limit: a key not found or placed by then spills
+constexpr uint32_t kClosedProbe = 4;           // the same once the table has reached its load limit
+constexpr uint32_t kSpillBelow = 4;            // a closed table's flush spills counts below this unprobed
 constexpr uint32_t kGlobalProbeCheck = 4;      // a long probe looks at the overflow flag every this many slots
+constexpr uint32_t kMaxPartLog2 = 4;           // hash partitions of the column before the count: at most 16
+constexpr uint32_t kMaxParts = 1u << kMaxPartLog2;
+constexpr uint64_t kTableSlotsPerKey = 32;     // default: global table slots per estimated key
+constexpr uint64_t kPartKeys = 6000;           // default: distinct keys per partition the estimate aims at
+                                               // (no partitions up to twice that)
+constexpr uint32_t kScatterThreads = 1024;     // partition scatter workgroup
+constexpr uint32_t kScatterChunk = kScatterThreads * 8;  // elements staged per step
+constexpr uint32_t kXcds = 8;                  // accelerator dies
+constexpr uint32_t kSpillFracDiv = 4;          // the radix engine takes over when the spill passes N / this
 constexpr uint32_t kMinTableLog2 = 12;         // smallest global table (4096 slots)
 constexpr uint32_t kMaxTableLog2 = 22;         // largest global table (4M slots, 64 MiB)
 constexpr uint32_t kTableFloorLog2 = 16;       // global table never smaller (64K slots) when the workspace allows
@@ -54,6 +65,10 @@ constexpr uint32_t kGuardChunk = 4096;         // elements per first-occurrence 
 constexpr uint32_t kGuardLdsKeys = 2048;       // contested keys resolved in LDS
 
 enum Path : int32_t { P_MONOTONE = 0, P_SMALL_N = 1, P_TINY = 2, P_HIGH_K = 3, P_MAIN = 4, P_GUARD = 5 };
+// Report flags (what ran on the GPU; the oracle does not model them).
+constexpr uint32_t kFlagOverflow = 1u;  // the radix engine sorted the column instead of the count
+constexpr uint32_t kFlagGuardFirst = 2u;  // the guard needed the first-occurrence pass
+constexpr uint32_t kFlagSpill = 4u;     // keys went to the spill list, which was sorted and folded
 enum Engine : uint32_t { E_NONE = 0, E_TINY = 1, E_HASH = 2, E_RADIX = 3 };
 
 // Look-back status word of the radix passes: two flag bits over a 62-bit value.
@@ -99,15 +114,22 @@ struct Ctrl {
     uint32_t flags;                   // report flags
     uint64_t table_M;                 // Eq. Msize
     uint32_t cap_log2;                // GPU global table size (log2 slots)
-    uint32_t cap_limit;               // claimed slots allowed before overflow
-    // tiny count
-    uint64_t tiny_cnt[8];
+    uint32_t cap_limit;               // claimed slots allowed; keys arriving later spill
+    uint32_t part_log2;               // hash partitions of the count workgroups (log2)
+    uint32_t lds_wide;                // LDS buckets of 4 keys (else 2)
+    // tiny count: each key's counter on a line of its own (every workgroup adds to them)
+    alignas(128) uint64_t tiny_cnt[8][16];
     // hash count.  Words that many workgroups update atomically, or poll while
     // others update them, each get a 128-byte line of their own: a read of a line
     // under atomic traffic waits behind it.
     alignas(128) uint32_t overflow;
     alignas(128) uint32_t claimed;
+    alignas(128) uint32_t closed;     // the global table reached its load limit (written once)
     alignas(128) uint64_t ecount;     // elements equal to kEmpty
+    alignas(128) uint64_t nspill;     // (key, count) pairs on the spill list
+    uint64_t spill_limit;             // past this many the radix engine takes over
+    uint64_t pcap;                    // elements each partition's bucket holds
+    alignas(128) uint32_t pfill[kMaxParts][32];  // elements scattered to each bucket (one line each)
     // where the sorted column is when the radix engine ran (the output, or scratch
     // when sorting in place on the main path, copied out after the guard)
     uint64_t* sorted;
@@ -117,7 +139,9 @@ struct Ctrl {
     uint64_t K;
     uint32_t emit_main;               // dense arrays from the tiny branch or the rank order
     uint32_t dense_ready;
-    uint32_t pair_sort;
+    uint32_t pair_sort;               // the pairs are radix sorted, then folded and scanned
+    const uint64_t* fold_k;           // the sorted pairs the fold reads
+    const uint64_t* fold_v;
     uint32_t radix_on;
     uint32_t guard_on;
     // radix
@@ -179,9 +203,20 @@ struct Args {
     uint32_t rank_budget_log2;        // compares per ranking workgroup allowed
     uint32_t row_blocks;              // workgroups of the row emit's sweep
     uint64_t table_mul;               // odd multiplier of the count tables' hash (kPhi unless seeded)
+    // count geometry (tunable): distinct keys per hash partition the estimate aims
+    // at, and the estimate per partition from which LDS buckets hold 4 keys
+    uint64_t part_keys;
+    uint64_t wide_min;
+    uint64_t table_slots;             // global table slots per estimated key (rounded up to a power of two)
     // run-length scratch
     uint64_t* rle_tile;               // per-tile run counts
-    uint64_t* psum;                   // kMaxCountBlocks chunk sums of the pair scan
+    uint64_t* psum;                   // 2 * kMaxCountBlocks: head counts and count sums of the fold's chunks
+    // spill list: (key, count) pairs, n entries each
+    uint64_t* spill_k;
+    uint64_t* spill_v;
+    // the column scattered into hash-partition buckets (pbuf_elems entries in all)
+    uint64_t* pbuf;
+    uint64_t pbuf_elems;
 };
 
 // Block table of a batched launch: block b works on column col[b] as block

@@ -29,9 +29,10 @@ __device__ __forceinline__ void load_pair(const uint64_t* __restrict__ x, uint64
 // ---------------------------------------------------------------------------
 // Phase 2: initialise the global table (tiny and hash engines) and run the
 // tiny count (Sec. 4.4): one counter per sampled key, every element compared
-// with every key.  The GPU form of the paper's eight branchless counters is a
-// wave ballot: v_cmp_eq_u64 gives a 64-lane mask per key whose population count
-// is added to a wave-uniform (scalar) counter.
+// with every key, branch-free.  Each lane keeps its own eight counters in
+// registers (a compare and an add per key and element) and the wave sums them
+// once at the end, so the loop costs two vector instructions per key and element
+// and nothing waits on a cross-lane result.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void phase2_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
@@ -49,20 +50,25 @@ __device__ __forceinline__ void phase2_body(const Args& a, uint32_t bid, uint32_
     uint64_t key[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) key[j] = c->tiny_keys[j];
-    uint32_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // per wave, fits: a wave sees < 2^32 elements
+    // absent keys compare against a key no element can match below: the slot of a
+    // missing key gets key[0] again and its counter is dropped
+#pragma unroll
+    for (int j = 1; j < 8; ++j) key[j] = j < (int)nk ? key[j] : key[0];
+    uint32_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // per lane: a lane sees < 2^32 elements
     const uint32_t head = a.in_head;
     const uint64_t P = num_pairs(a.n, head);
     const uint64_t Pf = (a.n + head) / 2;
-    constexpr int U = 8;  // pairs in flight per lane
-    // every lane of a wave runs the same iterations so that each ballot sees the whole wave
+    constexpr int U = 4;  // pairs per lane per batch; the next batch's loads are in flight while one is counted
     const uint64_t waves_total = gstride / 64;
     const uint64_t wave_id = gtid / 64;
+    const uint64_t step = waves_total * 64 * U;
     const uint32_t lane = __lane_id();
-    for (uint64_t pb = wave_id * 64 * U; pb < P; pb += waves_total * 64 * U) {
-        uint64_t v[2 * U];
-        uint32_t okm = 0;
+    const CAFS_GLOBAL uint64_t* in = gp(a.in);
+    uint64_t v[2 * U];
+    uint32_t okm = 0;
+    auto load = [&](uint64_t pb) {
         if (pb >= head && pb + 64 * U <= Pf) {
-            const u64x2* src = reinterpret_cast<const u64x2*>(a.in + 2 * (pb + lane) - head);
+            const CAFS_GLOBAL u64x2* src = reinterpret_cast<const CAFS_GLOBAL u64x2*>(in + 2 * (pb + lane) - head);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const u64x2 w = src[u * 64];
@@ -71,6 +77,7 @@ __device__ __forceinline__ void phase2_body(const Args& a, uint32_t bid, uint32_
             }
             okm = (1u << (2 * U)) - 1;
         } else {
+            okm = 0;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint64_t p = pb + (uint64_t)u * 64 + lane;
@@ -81,22 +88,46 @@ __device__ __forceinline__ void phase2_body(const Args& a, uint32_t bid, uint32_
                 okm |= (o1 ? 1u : 0u) << (2 * u + 1);
             }
         }
+    };
+    uint64_t pb = wave_id * 64 * U;
+    if (pb < P) load(pb);
+    while (pb < P) {
+        uint64_t x[2 * U];
 #pragma unroll
-        for (int e = 0; e < 2 * U; ++e) {
-            const bool in = (okm >> e) & 1u;
+        for (int e = 0; e < 2 * U; ++e) x[e] = v[e];
+        const uint32_t m = okm;
+        pb += step;
+        if (pb < P) load(pb);
+        if (m == (1u << (2 * U)) - 1) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (j < (int)nk) cnt[j] += (uint32_t)__popcll(__ballot(in && v[e] == key[j]));
+            for (int e = 0; e < 2 * U; ++e)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) cnt[j] += x[e] == key[j] ? 1u : 0u;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 2 * U; ++e)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) cnt[j] += (((m >> e) & 1u) && x[e] == key[j]) ? 1u : 0u;
         }
     }
-    if (lane == 0) {
-        for (uint32_t j = 0; j < nk; ++j)
-            if (cnt[j]) atomicAdd((unsigned long long*)&c->tiny_cnt[j], (unsigned long long)cnt[j]);
+    // one device-scope update per key and workgroup (per wave, thousands of them
+    // queued on the same lines)
+    __shared__ uint32_t s_cnt[8];
+    if (threadIdx.x < 8) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t w = wave_sum_u32(cnt[j]);
+        if (lane == 0 && j < (int)nk && w) atomicAdd(&s_cnt[j], w);
     }
+    __syncthreads();
+    if (threadIdx.x < nk && s_cnt[threadIdx.x])
+        atomicAdd((unsigned long long*)&c->tiny_cnt[threadIdx.x][0], (unsigned long long)s_cnt[threadIdx.x]);
 }
 CAFS_KERNELS0(phase2, 256)
 
-// Switch to the radix engine after the global table overflowed.  In place, the
+// Switch to the radix engine (the spill grew past its limit, Sec. 4.5's guard aside:
+// sorting the spilled pairs would cost more than sorting the column).  In place, the
 // radix engine then sorts into scratch so that the guard can still read the input.
 __device__ __noinline__ void set_overflow(Ctrl* c, uint32_t inplace, uint64_t* tmp_k, uint64_t* uniq) {
     if (atomicExch(&c->overflow, 1u) == 0) {
@@ -109,11 +140,11 @@ __device__ __noinline__ void set_overflow(Ctrl* c, uint32_t inplace, uint64_t* t
         atomicExch(&c->radix_on, 1u);
         atomicExch(&c->guard_on, 1u);
         atomicExch(&c->guard_general, 1u);
-        atomicOr(&c->flags, 1u);
+        atomicOr(&c->flags, kFlagOverflow);
     }
 }
 
-// The global (key, count) table of one column.
+// The global (key, count) table of one column, and its spill list.
 struct GTable {
     Ctrl* c;
     uint64_t* keys;
@@ -121,6 +152,9 @@ struct GTable {
     uint32_t* claimed;
     uint64_t* tmp_k;
     uint64_t* uniq;
+    uint64_t* spill_k;
+    uint64_t* spill_v;
+    uint64_t spill_cap;  // entries of the spill list (n)
     uint32_t inplace;
     uint64_t mul;  // the count tables' hash multiplier
 };
@@ -133,18 +167,27 @@ __device__ __forceinline__ GTable gtable(const Args& a) {
     t.claimed = a.claimed;
     t.tmp_k = a.tmp_k;
     t.uniq = a.uniq;
+    t.spill_k = a.spill_k;
+    t.spill_v = a.spill_v;
+    t.spill_cap = a.n;
     t.inplace = a.in == a.out;
     t.mul = a.table_mul;
     return t;
 }
 
-// Insert (v, cnt) into the global open-addressing table (linear probing, Eq. hash
-// slot).  A slot is claimed by CAS from kEmpty and never freed, so a key is either
-// in the table or (after an overflow) the whole table is abandoned for the radix
-// engine.  Returns the slot claimed for a new key (kNoSlot otherwise); the caller
-// lists claimed slots with list_claims, so that compaction reads K entries, not the
-// table.
+// Insert (v, cnt) into the global open-addressing table (linear probing from the
+// multiply-shift slot).  A slot is claimed by CAS from kEmpty and never freed.  New
+// keys are placed only while `may_claim` (the table is below its load limit, read
+// by the wave beforehand, so the limit is approximate); after that the table is
+// closed: a lookup stops after kClosedProbe slots, otherwise after kGlobalProbe,
+// and a key not found by then goes to the spill list with its count.  A key may
+// then be counted in the table and on the list, which the fold of the order stage
+// sums.
+// Returns the slot claimed for a new key, kNoSlot when the count was added to a
+// key already there, kFail when the caller must spill (v, cnt).  The caller lists
+// claimed slots with list_claims, so that compaction reads K entries, not the table.
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+constexpr uint32_t kFail = 0xFFFFFFFEu;
 
 // The overflow flag, read by one lane and broadcast: an agent-scope load misses the
 // XCD's L2 and goes to memory, and every lane of the GPU reading the same word
@@ -155,19 +198,27 @@ __device__ __forceinline__ uint32_t wave_overflow(const Ctrl* c) {
     return __builtin_amdgcn_readfirstlane(ov);
 }
 
-// The caller checks the overflow flag (per wave) before it inserts; a long probe
-// looks again every kGlobalProbeCheck slots, so that inserts under way stop soon
-// after the table passed its load limit (they would otherwise keep claiming slots
-// and probe ever longer).
-__device__ __forceinline__ uint32_t global_insert(const GTable& t, uint64_t v, uint64_t cnt) {
+// Whether the wave may still place new keys in the global table (one lane reads the
+// closed flag, which list_claims raises once the claimed count passes the load
+// limit; the count's own line is under constant atomic traffic, and a read of it
+// waits behind that).  Called with every lane of the wave active.
+__device__ __forceinline__ bool wave_may_claim(const Ctrl* c) {
+    uint32_t cl = 0;
+    if (__lane_id() == 0) cl = g_load(&c->closed);
+    return __builtin_amdgcn_readfirstlane(cl) == 0;
+}
+
+__device__ __forceinline__ uint32_t global_insert(const GTable& t, uint64_t v, uint64_t cnt, bool may_claim) {
     Ctrl* c = t.c;
     const uint32_t lg = c->cap_log2;
     const uint64_t mask = (1ull << lg) - 1;
     uint64_t h = mul_hash(v, lg, t.mul);
-    for (uint32_t pr = 0; pr < kGlobalProbe; ++pr) {
+    const uint32_t limit = may_claim ? kGlobalProbe : kClosedProbe;
+    for (uint32_t pr = 0; pr < limit; ++pr) {
         if (pr % kGlobalProbeCheck == kGlobalProbeCheck - 1 && g_load(&c->overflow)) return kNoSlot;
         uint64_t k = g_load(&t.keys[h]);
         if (k == kEmpty) {
+            if (!may_claim) return kFail;  // v is not in the table (slots fill in probe order)
             k = g_cas(&t.keys[h], kEmpty, v);
             if (k == kEmpty) {
                 g_add(&t.cnt[h], (unsigned long long)cnt);
@@ -180,51 +231,151 @@ __device__ __forceinline__ uint32_t global_insert(const GTable& t, uint64_t v, u
         }
         h = (h + 1) & mask;
     }
-    set_overflow(c, t.inplace, t.tmp_k, t.uniq);
-    return kNoSlot;
+    return kFail;
 }
 
-// Lists the slots the lanes of a wave claimed (kNoSlot: none) in the claimed-slot
-// list, with one update of the shared counter per wave (one per claim would
-// serialise on its address).  Past the table's load limit the radix engine takes
-// over.  Called by every lane of the wave.
+// Lists the slots the lanes of a wave claimed (kNoSlot or kFail: none) in the
+// claimed-slot list, with one update of the shared counter per wave (one per claim
+// would serialise on its address).  The list has room for every slot of the table.
+// Called by every lane of the wave.
 __device__ __forceinline__ void list_claims(const GTable& t, uint32_t h) {
-    const uint64_t m = __ballot(h != kNoSlot);
+    const bool mine = h < kFail;
+    const uint64_t m = __ballot(mine);
     if (m == 0) return;
     const uint32_t leader = (uint32_t)__builtin_ctzll(m);
     uint32_t base = 0;
-    if (__lane_id() == leader) base = g_add(&t.c->claimed, (uint32_t)__popcll(m));
+    if (__lane_id() == leader) {
+        const uint32_t k = (uint32_t)__popcll(m);
+        base = g_add(&t.c->claimed, k);
+        const uint32_t lim = t.c->cap_limit;
+        if (base < lim && base + k >= lim) __hip_atomic_store(gp(&t.c->closed), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     base = __shfl(base, leader, 64);
-    if (h == kNoSlot) return;
+    if (!mine) return;
     const uint32_t idx =
         base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    if (idx >= t.c->cap_limit) set_overflow(t.c, t.inplace, t.tmp_k, t.uniq);
-    else gp(t.claimed)[idx] = h;
+    if (idx < (1u << t.c->cap_log2)) gp(t.claimed)[idx] = h;
+}
+
+// Appends (key, cnt) of the lanes with `mine` to the spill list (Alg. 4's spill),
+// one update of the shared counter per wave.  Each pair stands for elements no
+// other pair holds, so the list never needs more than n entries.  When the list
+// grows past its limit the radix engine takes the column over.  Called by every
+// lane of the wave.
+__device__ __forceinline__ void spill_pairs(const GTable& t, bool mine, uint64_t key, uint64_t cnt) {
+    const uint64_t m = __ballot(mine);
+    if (m == 0) return;
+    Ctrl* c = t.c;
+    const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+    uint64_t base = 0;
+    if (__lane_id() == leader) {
+        const uint64_t nm = (uint64_t)__popcll(m);
+        base = g_add(&c->nspill, nm);
+        if (base == 0) atomicOr(&c->flags, kFlagSpill);
+        if (base + nm > c->spill_limit) set_overflow(c, t.inplace, t.tmp_k, t.uniq);
+    }
+    base = __shfl(base, leader, 64);
+    if (!mine) return;
+    const uint64_t idx =
+        base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (idx < t.spill_cap) {
+        gp(t.spill_k)[idx] = key;
+        gp(t.spill_v)[idx] = cnt;
+    }
+}
+
+// spill_pairs for F pairs per lane at once (bit u of `mine` selects pair u): one
+// update of the shared counter for all of them.  Called by every lane of the wave.
+template <int F>
+__device__ __forceinline__ void spill_pairs_n(const GTable& t, uint32_t mine, const uint64_t (&key)[F],
+                                              const uint64_t (&cnt)[F]) {
+    uint64_t bal[F];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int u = 0; u < F; ++u) {
+        bal[u] = __ballot((mine >> u) & 1u);
+        tot += (uint32_t)__popcll(bal[u]);
+    }
+    if (tot == 0) return;
+    Ctrl* c = t.c;
+    uint64_t base = 0;
+    if (__lane_id() == 0) {
+        base = g_add(&c->nspill, (uint64_t)tot);
+        if (base == 0) atomicOr(&c->flags, kFlagSpill);
+        if (base + tot > c->spill_limit) set_overflow(c, t.inplace, t.tmp_k, t.uniq);
+    }
+    uint64_t run = __shfl(base, 0, 64);
+#pragma unroll
+    for (int u = 0; u < F; ++u) {
+        const uint64_t idx = run + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[u] >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal[u], 0u));
+        if (((mine >> u) & 1u) && idx < t.spill_cap) {
+            gp(t.spill_k)[idx] = key[u];
+            gp(t.spill_v)[idx] = cnt[u];
+        }
+        run += (uint64_t)__popcll(bal[u]);
+    }
+}
+
+// Global insert of element u of each lane where bit u of `mine` is set (count
+// add[u] when `use_add`, else 1), spilling what finds no room.  Once the table is
+// closed these go to the spill list without probing it (the elements that reach
+// here are the rare keys, which the closed table mostly lacks).  Called by every
+// lane of the wave.
+template <int F>
+__device__ __forceinline__ void insert_or_spill_n(const GTable& t, uint32_t mine, const uint64_t (&key)[F],
+                                                  const uint32_t (&add)[F], bool use_add) {
+    const bool may = wave_may_claim(t.c);
+    uint64_t cnt[F];
+    uint32_t spill = 0;
+#pragma unroll
+    for (int u = 0; u < F; ++u) {
+        cnt[u] = use_add ? add[u] : 1u;
+        const bool m = (mine >> u) & 1u;
+        uint32_t h = kNoSlot;
+        if (m) h = may ? global_insert(t, key[u], cnt[u], true) : kFail;
+        list_claims(t, h);
+        spill |= (h == kFail) ? (1u << u) : 0u;
+    }
+    spill_pairs_n<F>(t, spill, key, cnt);
 }
 
 // ---------------------------------------------------------------------------
 // Hash count (main path, Sec. 4.4).  The paper's hot loop updates a bucket of four
 // 64-bit keys on one cache line (Sec. 4.2, Alg. 1).  Here each workgroup owns a
 // table of kLdsSlots keys with 32-bit counters in LDS, cut into buckets of W keys:
-// W = 4 (3392 buckets, like the paper's) when the estimate is large, W = 2 (6784
-// buckets) below kLdsWideMinKhat, where a bucket rarely overflows and a lookup
-// then takes one 16-byte LDS load instead of two (LDS load instructions are what
-// the loop pays for; measured crossover near K = 1800 at N = 2^28).  An element
-// hashes to a bucket (Eq. hash, reduced to the bucket count by a multiply), reads
-// its W keys with 16-byte LDS loads and compares them with the element, the GPU
-// analogue of the paper's cmpeq + movemask + tzcnt; on a match it adds 1 to that
-// slot's counter with an LDS atomic.  Within a bucket occupied slots form a
-// prefix and a key is stored in the first bucket, in probe order, that had room
-// for it, so a lookup can stop at the first bucket with a free slot.  Lookups cover the home
+// W = 4 (3392 buckets, like the paper's) when the estimate per partition is
+// large, W = 2 (6784 buckets) below the geometry's threshold, where a bucket
+// rarely overflows and a lookup then takes one 16-byte LDS load instead of two
+// (LDS load instructions are what the loop pays for).  An element hashes to a
+// bucket (multiply-shift, reduced to the bucket count by a multiply), reads its W
+// keys with 16-byte LDS loads and compares them with the element, the GPU analogue
+// of the paper's cmpeq + movemask + tzcnt; on a match it adds to that slot's
+// counter with an LDS atomic.  Within a bucket occupied slots form a prefix and a
+// key is stored in the first bucket, in probe order, that had room for it, so a
+// lookup can stop at the first bucket with a free slot.  Lookups cover the home
 // bucket and, when that one is full, the next one (the window), as straight-line
 // code for the eight keys a thread holds while the loads of its next eight keys
 // are in flight.  A key absent from a window with room is inserted by a 64-bit
-// LDS CAS on the first free slot.  An element whose window is full is deferred:
-// the wave appends it to its workgroup's region of a scratch array, and a second
-// pass counts the deferred elements with a fresh table.  Deferring keeps the
-// rare long probes out of the wave-wide lockstep of the hot loop.  At the end
-// each workgroup flushes its occupied slots to the global table (Eq. hash slot,
-// linear probing).  Elements equal to the empty marker are counted in registers.
+// LDS CAS on the first free slot.
+//
+// Hash partitions.  One LDS table holds about 10^4 keys, so for a larger estimate
+// the column is first scattered into P = 2^p buckets by the top p bits of each
+// element's 32-bit hash (part_scatter), and each workgroup counts a range of one
+// bucket, whose keys are a P-th of the column's: the bits below the partition bits
+// pick the LDS bucket.  (Masking the other partitions' elements inside one pass
+// instead costs the LDS instructions of every element in every workgroup.)
+//
+// Beyond the table (Alg. 4's spill).  An element whose window is full is deferred:
+// the wave appends it to its workgroup's region of a scratch array (bounded), and a
+// second pass counts the deferred elements with a fresh table.  What finds no room
+// there either, or no room in the region, goes to the global table directly.  At
+// the end each workgroup flushes its occupied slots to the global table.  The global
+// table takes new keys up to its load limit; a key that finds no room there goes,
+// with its count, to the spill list of (key, count) pairs, which the order stage
+// sorts and folds with the table's pairs.  Only a spill past N / kSpillFracDiv
+// hands the column to the radix engine (overflow).  Elements equal to the empty
+// marker are counted in registers.
 //
 // The first pass also resolves the tiny branch: if the tiny counters sum to N the
 // column is tiny and the dense arrays are written here; otherwise the element set
@@ -236,9 +387,11 @@ struct LdsGeo {
     static_assert(kBuckets * W == kLdsSlots, "whole buckets");
 };
 
+// Bucket of a key from the bits of its 32-bit hash below the partition bits
+// (`hb` = hash << partition bits).
 template <uint32_t W>
-__device__ __forceinline__ uint32_t lds_bucket(uint64_t x, uint64_t mul) {
-    return (uint32_t)(((uint64_t)mul_hash32(x, 32, mul) * LdsGeo<W>::kBuckets) >> 32);
+__device__ __forceinline__ uint32_t lds_bucket(uint32_t hb) {
+    return (uint32_t)(((uint64_t)hb * LdsGeo<W>::kBuckets) >> 32);
 }
 
 template <uint32_t W>
@@ -249,9 +402,9 @@ __device__ __forceinline__ uint32_t next_bucket(uint32_t b) {
 // Find or claim a slot for x within `window` buckets from its home bucket and add
 // `add` to its counter.  Returns false when those buckets are full without x.
 template <uint32_t W>
-__device__ __forceinline__ bool lds_insert(uint64_t* skeys, uint32_t* scnt, uint64_t x, uint32_t add,
-                                           uint32_t window, uint64_t mul) {
-    uint32_t b = lds_bucket<W>(x, mul);
+__device__ __forceinline__ bool lds_insert(uint64_t* skeys, uint32_t* scnt, uint64_t x, uint32_t hb, uint32_t add,
+                                           uint32_t window) {
+    uint32_t b = lds_bucket<W>(hb);
     for (uint32_t pr = 0; pr < window; ++pr) {
         const uint32_t base = b * W;
         for (uint32_t s = 0; s < W; ++s) {
@@ -287,18 +440,22 @@ __device__ __forceinline__ int match_bucket(const uint64_t* skeys, uint32_t b, u
     }
 }
 
-// Counts the elements of x selected by `want` in the LDS table, one after the
+// Counts the elements of x selected by `want_m` in the LDS table, one after the
 // other (the loads of the next batch are in flight meanwhile); returns the mask of
-// those whose window was full (not counted).
+// those whose window was full (not counted).  The top `pl` bits of a key's 32-bit
+// multiply-shift hash name its partition (the same for every key of the range),
+// the bits below them its LDS bucket.  (`part` is unused: the ranges hold one
+// partition each.)
 template <int NE, uint32_t W>
 __device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, uint32_t* __restrict__ scnt,
-                                                uint32_t* __restrict__ sink, const uint64_t (&x)[NE],
-                                                uint32_t want_m, uint64_t mul, const uint32_t (&add)[NE]) {
+                                                uint32_t* __restrict__ sink, const uint64_t (&x)[NE], uint64_t mul,
+                                                uint32_t pl, uint32_t part, uint32_t want_m,
+                                                const uint32_t (&add)[NE]) {
     uint32_t ins = 0, dfr = 0;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
         const bool want = (want_m >> e) & 1u;
-        uint32_t b = lds_bucket<W>(x[e], mul);
+        uint32_t b = lds_bucket<W>(mul_hash32(x[e], 32, mul) << pl);
         bool full;
         int m = match_bucket<W>(skeys, b, x[e], full);
         if (m < 0 && full) {  // home bucket full without x: x may be in the next one
@@ -318,7 +475,9 @@ __device__ __forceinline__ uint32_t count_batch(uint64_t* __restrict__ skeys, ui
     if (ins) {
 #pragma unroll
         for (int e = 0; e < NE; ++e)
-            if (((ins >> e) & 1u) && !lds_insert<W>(skeys, scnt, x[e], add[e], kLdsWindow, mul)) dfr |= 1u << e;
+            if (((ins >> e) & 1u) && !lds_insert<W>(skeys, scnt, x[e], mul_hash32(x[e], 32, mul) << pl, add[e],
+                                                    kLdsWindow))
+                dfr |= 1u << e;
     }
     return dfr;
 }
@@ -370,10 +529,32 @@ __device__ __forceinline__ bool run_lengths(const uint64_t (&x)[NE], uint32_t wa
     return any;
 }
 
-// Each workgroup of the first pass reads one contiguous range of ceil(P / nblk)
-// pairs; its region of the deferred-element scratch (tmp_k) holds that many pairs,
-// so it never fills up (tmp_k has room for n + 2 + 2 * kMaxCountBlocks keys).
+// The count's work items: with P = 2^pl partitions, item i is the range s of S of
+// bucket q = i mod P, s = i div P, with S = max(1, nblk / P); workgroup b takes items
+// b, b + nblk, ...  Without partitions item b is the b-th of nblk ranges of the
+// column.  Ranges are whole 16-byte pairs of their array.
+__device__ __forceinline__ uint32_t count_item_total(uint32_t pl, uint32_t nblk) {
+    const uint32_t P = 1u << pl;
+    const uint32_t S = nblk / P > 1 ? nblk / P : 1u;
+    return pl ? P * S : nblk;
+}
+
+// Each range of a workgroup's region of the deferred-element scratch (tmp_k) holds
+// 2 ceil(pairs / nblk) elements (tmp_k has room for n + 2 + 2 * kMaxCountBlocks
+// keys); deferrals past it go to the global table directly.
 __device__ __forceinline__ uint64_t pairs_per_block(uint64_t P, uint32_t nblk) { return (P + nblk - 1) / nblk; }
+
+// Stable match of equal partition numbers (pl bits) across the wave: the lanes
+// (within `act`) whose partition equals this lane's.
+__device__ __forceinline__ uint64_t match_part(uint32_t q, uint32_t pl, uint64_t act) {
+    uint64_t peers = act;
+    for (uint32_t b = 0; b < pl; ++b) {
+        const bool bit = (q >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
 
 template <uint32_t W>
 __device__ __forceinline__ void flush_table(const GTable& t, const uint64_t* skeys, const uint32_t* scnt) {
@@ -382,19 +563,27 @@ __device__ __forceinline__ void flush_table(const GTable& t, const uint64_t* ske
     // each wave looks before every group of inserts
     // four slots per thread at a time: their home slots in the global table are read
     // together, and a key already there (most are, after the first workgroups) gets
-    // its count added directly; the rest take the probing insert
+    // its count added directly; the rest take the probing insert, and what finds no
+    // room in the global table goes to the spill list with its count
+    // Once the table is closed (at its load limit) it takes no new keys, and a
+    // small count most likely belongs to one of the rare keys that it lacks: such
+    // entries go to the spill list without probing (if the key is in the table after
+    // all, the fold sums both).
     const uint32_t lg = t.c->cap_log2;
     constexpr int F = 4;
     for (uint32_t i0 = threadIdx.x; i0 < S; i0 += F * blockDim.x) {  // uniform over each wave
         if (wave_overflow(t.c)) return;
+        const bool may = wave_may_claim(t.c);
         uint32_t cn[F], h[F], cl[F];
-        uint64_t key[F], k[F];
+        uint64_t key[F], k[F], cv[F];
+        uint32_t spill = 0;
 #pragma unroll
         for (int u = 0; u < F; ++u) {
             const uint32_t i = i0 + u * blockDim.x;
             cn[u] = i < S ? scnt[i] : 0u;  // slot i / B of bucket i % B; never 0 once claimed
             key[u] = cn[u] ? skeys[(i % B) * W + i / B] : 0;
             h[u] = mul_hash(key[u], lg, t.mul);
+            cv[u] = cn[u];
         }
 #pragma unroll
         for (int u = 0; u < F; ++u) k[u] = cn[u] ? g_load(&t.keys[h[u]]) : kEmpty;
@@ -403,32 +592,135 @@ __device__ __forceinline__ void flush_table(const GTable& t, const uint64_t* ske
             cl[u] = kNoSlot;
             if (!cn[u]) continue;
             if (k[u] == key[u]) g_add(&t.cnt[h[u]], (unsigned long long)cn[u]);
-            else cl[u] = global_insert(t, key[u], cn[u]);
+            else if (!may && cn[u] < kSpillBelow) cl[u] = kFail;
+            else cl[u] = global_insert(t, key[u], cn[u], may);
+            spill |= (cl[u] == kFail) ? (1u << u) : 0u;
         }
 #pragma unroll
         for (int u = 0; u < F; ++u) list_claims(t, cl[u]);  // (the loop is uniform over each wave)
+        spill_pairs_n<F>(t, spill, key, cv);
     }
 }
 
-template <uint32_t W>
-__device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, uint32_t nblk, uint64_t* skeys,
-                                                 uint32_t* scnt, uint32_t& s_ndef, uint32_t* s_sink);
+// Workgroup-uniform read of the overflow flag: thread 0 reads it into LDS between
+// two barriers.  Called by every thread of the workgroup.
+__device__ __forceinline__ bool block_overflow(const Ctrl* c, uint32_t* s_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) *s_flag = g_load(&c->overflow);
+    __syncthreads();
+    return *s_flag != 0;
+}
 
-__device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uint32_t nblk) {
+// Partition scatter (before the count, when the plan has partitions): the column
+// in chunks of kScatterChunk elements; each chunk's elements are ranked within their
+// partition (a wave matches equal partitions by ballots and takes one LDS counter
+// update per partition), staged in LDS in partition order, given a place in each
+// bucket by one atomic per partition and chunk, and written out as runs of
+// consecutive elements.  A bucket holds pcap elements (an eighth more than an even
+// share, plus a chunk); elements past it go to the spill list.
+__device__ __forceinline__ void part_scatter_body(const Args& a, uint32_t bid, uint32_t nblk) {
+    Ctrl* c = a.c;
+    if (c->engine != E_HASH || c->part_log2 == 0) return;
+    const uint32_t pl = c->part_log2;
+    const uint64_t pcap = c->pcap;
+    const uint64_t mul = a.table_mul;
+    const GTable t = gtable(a);
+    const uint64_t n = a.n;
+    const CAFS_GLOBAL uint64_t* in = gp(a.in);
+    CAFS_GLOBAL uint64_t* pbuf = gp(a.pbuf);
+    __shared__ uint64_t stage[kScatterChunk];
+    __shared__ uint32_t lcnt[kMaxParts];
+    __shared__ uint32_t loff[kMaxParts];
+    __shared__ uint64_t gbase[kMaxParts];
+    const uint32_t tid = threadIdx.x, lane = __lane_id();
+    const uint64_t lt = (1ull << lane) - 1;
+    const uint64_t chunks = (n + kScatterChunk - 1) / kScatterChunk;
+    constexpr int U = kScatterChunk / kScatterThreads;
+    for (uint64_t ch = bid; ch < chunks; ch += nblk) {  // uniform
+        if (tid < kMaxParts) lcnt[tid] = 0;
+        __syncthreads();
+        const uint64_t base = ch * kScatterChunk;
+        uint64_t x[U];
+        uint32_t q[U], r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = base + (uint64_t)u * kScatterThreads + tid;
+            x[u] = i < n ? in[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = base + (uint64_t)u * kScatterThreads + tid < n;
+            q[u] = mul_hash32(x[u], 32, mul) >> (32 - pl);
+            const uint64_t peers = match_part(q[u], pl, __ballot(ok));
+            const uint32_t leader = peers ? (uint32_t)__builtin_ctzll(peers) : 0u;
+            uint32_t rb = 0;
+            if (ok && lane == leader) rb = atomicAdd(&lcnt[q[u]], (uint32_t)__popcll(peers));
+            rb = __shfl(rb, (int)leader, 64);
+            r[u] = rb + (uint32_t)__popcll(peers & lt);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t run = 0;
+            for (uint32_t qq = 0; qq < (1u << pl); ++qq) {
+                loff[qq] = run;
+                run += lcnt[qq];
+            }
+        }
+        if (tid < (1u << pl)) gbase[tid] = lcnt[tid] ? atomicAdd(&c->pfill[tid][0], lcnt[tid]) : 0u;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (base + (uint64_t)u * kScatterThreads + tid < n) stage[loff[q[u]] + r[u]] = x[u];
+        __syncthreads();
+        const uint32_t cnt = (uint32_t)(n - base < kScatterChunk ? n - base : kScatterChunk);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {  // uniform: every lane takes part in the spill's ballot
+            const uint32_t i = (uint32_t)u * kScatterThreads + tid;
+            const bool ok = i < cnt;
+            const uint64_t v = ok ? stage[i] : 0;
+            const uint32_t qq = mul_hash32(v, 32, mul) >> (32 - pl);
+            const uint64_t dst = ok ? gbase[qq] + (i - loff[qq]) : 0;
+            const bool fits = dst < pcap;
+            if (ok && fits) pbuf[qq * pcap + dst] = v;
+            spill_pairs(t, ok && !fits, v, 1);
+        }
+        __syncthreads();
+    }
+}
+CAFS_KERNELS0(part_scatter, kScatterThreads)
+
+template <uint32_t W>
+__device__ __forceinline__ void count_range(const Args& a, const GTable& t, uint64_t* skeys, uint32_t* scnt,
+                                            uint32_t& s_ndef, uint32_t* s_sink, uint32_t* s_flag,
+                                            const uint64_t* src, uint64_t n, uint32_t head, uint64_t p_begin,
+                                            uint64_t p_end, uint32_t pl, CAFS_GLOBAL uint64_t* region,
+                                            uint32_t region_cap);
+
+template <uint32_t W, bool PARTS>
+__device__ __forceinline__ void count_items(const Args& a, uint32_t bid, uint32_t nblk, uint64_t* skeys, uint32_t* scnt,
+                                            uint32_t& s_ndef, uint32_t& s_flag, uint32_t* s_sink);
+
+// Two instances: the count without partitions (PARTS false: the partition bits are
+// the constant 0 in its hot loop) and the count over partition buckets, chosen once
+// at the top of the kernel.  The first also resolves the tiny branch (a tiny plan
+// has no partitions).
+template <bool PARTS>
+__device__ __forceinline__ void hash_count_impl(const Args& a, uint32_t bid, uint32_t nblk, uint64_t* skeys,
+                                                uint32_t* scnt, uint32_t& s_ndef, uint32_t& s_flag, uint32_t* s_sink) {
     Ctrl* c = a.c;
     const uint32_t engine = c->engine;
     if (engine == E_TINY) {
         const uint32_t nk = c->n_tiny;
         uint64_t tot = 0;
-        for (uint32_t j = 0; j < nk; ++j) tot += c->tiny_cnt[j];
+        for (uint32_t j = 0; j < nk; ++j) tot += c->tiny_cnt[j][0];
         if (tot == a.n) {
             if (bid == 0 && threadIdx.x == 0) {
                 uint64_t run = 0;
                 for (uint32_t j = 0; j < nk; ++j) {
                     a.uniq[j] = c->tiny_keys[j];
-                    a.cnt[j] = c->tiny_cnt[j];
+                    a.cnt[j] = c->tiny_cnt[j][0];
                     a.off[j] = run;
-                    run += c->tiny_cnt[j];
+                    run += c->tiny_cnt[j][0];
                 }
                 a.off[nk] = run;
                 c->K = nk;
@@ -446,44 +738,90 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
         return;
     }
 
-    constexpr uint32_t S = kLdsSlots;
-    __shared__ __attribute__((aligned(16))) uint64_t skeys[S];
-    __shared__ uint32_t scnt[S];
+    if (c->lds_wide) count_items<4, PARTS>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
+    else count_items<2, PARTS>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
+}
+__device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uint32_t nblk) {
+    __shared__ __attribute__((aligned(16))) uint64_t skeys[kLdsSlots];
+    __shared__ uint32_t scnt[kLdsSlots];
     __shared__ uint32_t s_ndef;
+    __shared__ uint32_t s_flag;
     __shared__ uint32_t s_sink[64];  // target of the atomics of lanes without a hit
-    for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
-        skeys[i] = kEmpty;
-        scnt[i] = 0;
-    }
-    if (threadIdx.x == 0) s_ndef = 0;
-    __syncthreads();
-    if (c->k_hat < kLdsWideMinKhat) hash_count_table<2>(a, bid, nblk, skeys, scnt, s_ndef, s_sink);
-    else hash_count_table<4>(a, bid, nblk, skeys, scnt, s_ndef, s_sink);
+    if (a.c->part_log2) hash_count_impl<true>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
+    else hash_count_impl<false>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
 }
 
-// The count over one workgroup's range with buckets of W keys (the table in LDS
-// is cleared).
-template <uint32_t W>
-__device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, uint32_t nblk, uint64_t* skeys,
-                                                 uint32_t* scnt, uint32_t& s_ndef, uint32_t* s_sink) {
-    constexpr uint32_t S = kLdsSlots;
+// This workgroup's work items (count_item_total) with LDS buckets of W keys.
+template <uint32_t W, bool PARTS>
+__device__ __forceinline__ void count_items(const Args& a, uint32_t bid, uint32_t nblk, uint64_t* skeys, uint32_t* scnt,
+                                            uint32_t& s_ndef, uint32_t& s_flag, uint32_t* s_sink) {
     Ctrl* c = a.c;
+    constexpr uint32_t S = kLdsSlots;
     const GTable t = gtable(a);
     const uint64_t n = a.n;
-    const CAFS_GLOBAL uint64_t* in = gp(a.in);
+    const uint32_t pl = PARTS ? c->part_log2 : 0u;
+    const uint32_t items = PARTS ? count_item_total(pl, nblk) : nblk;
+    for (uint32_t it = bid; it < items; it += nblk) {  // uniform over the workgroup
+        const uint64_t* src;
+        uint64_t ns, pb, pe, roff;  // roff: where the item's deferral region starts in tmp_k
+        uint32_t head;
+        if (!PARTS) {
+            src = a.in;
+            ns = n;
+            head = a.in_head;
+            const uint64_t P = num_pairs(n, head), PS = pairs_per_block(P, nblk);
+            pb = (uint64_t)it * PS < P ? (uint64_t)it * PS : P;
+            pe = pb + PS < P ? pb + PS : P;
+            roff = 2 * pb;
+        } else {
+            const uint32_t P = 1u << pl, Sn = items / P;
+            const uint32_t q = it % P, sidx = it / P;
+            const uint64_t fill = c->pfill[q][0];
+            ns = fill < c->pcap ? fill : c->pcap;
+            src = a.pbuf + (uint64_t)q * c->pcap;  // 256-byte aligned buckets (pcap is a multiple of 32)
+            head = 0;
+            const uint64_t Pq = num_pairs(ns, 0), PS = (Pq + Sn - 1) / Sn;
+            pb = (uint64_t)sidx * PS < Pq ? (uint64_t)sidx * PS : Pq;
+            pe = pb + PS < Pq ? pb + PS : Pq;
+            roff = (uint64_t)q * c->pcap + 2 * pb;
+        }
+        // the region holds every element of the item (tmp_k covers the column and
+        // every bucket), so a deferral always finds room
+        CAFS_GLOBAL uint64_t* region = gp(a.tmp_k) + roff;
+        const uint32_t region_cap = (uint32_t)(2 * (pe - pb));
+        for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
+            skeys[i] = kEmpty;
+            scnt[i] = 0;
+        }
+        if (threadIdx.x == 0) s_ndef = 0;
+        __syncthreads();
+        count_range<W>(a, t, skeys, scnt, s_ndef, s_sink, &s_flag, src, ns, head, pb, pe, pl, region, region_cap);
+        __syncthreads();
+    }
+}
+
+// The count over pairs [p_begin, p_end) of src[0..n) (head: src is 8- but not
+// 16-byte aligned) with buckets of W keys (the LDS table is cleared): the first pass
+// with its deferrals, the flush, the second pass over the deferred elements and its
+// flush.  Called by every thread of the workgroup.
+template <uint32_t W>
+__device__ __forceinline__ void count_range(const Args& a, const GTable& t, uint64_t* skeys, uint32_t* scnt,
+                                            uint32_t& s_ndef, uint32_t* s_sink, uint32_t* s_flag,
+                                            const uint64_t* src_, uint64_t n, uint32_t head, uint64_t p_begin,
+                                            uint64_t p_end, uint32_t pl, CAFS_GLOBAL uint64_t* region,
+                                            uint32_t region_cap) {
+    constexpr uint32_t S = kLdsSlots;
+    Ctrl* c = a.c;
+    const CAFS_GLOBAL uint64_t* in = gp(src_);
     const uint32_t lane = __lane_id();
+    const uint64_t mul = t.mul;
     uint32_t ecnt = 0;
-    const uint32_t head = a.in_head;
-    const uint64_t P = num_pairs(n, head);
     const uint64_t Pf = (n + head) / 2;  // pairs [head, Pf) hold two in-range elements
-    const uint64_t PP = pairs_per_block(P, nblk);
-    const uint64_t p_end = (uint64_t)(bid + 1) * PP < P ? (uint64_t)(bid + 1) * PP : P;
     const uint64_t p_full = p_end < Pf ? p_end : Pf;
-    CAFS_GLOBAL uint64_t* region = gp(a.tmp_k) + (uint64_t)bid * 2 * PP;
     constexpr int U = 4;                 // pairs per thread per step
     constexpr int NE = 2 * U;
     const uint64_t span = (uint64_t)blockDim.x * U;
-    uint64_t base = (uint64_t)bid * PP;
+    uint64_t base = p_begin;
     uint64_t v[NE];
     uint32_t okm = 0;  // bit e: element e of the batch is in range
     auto load = [&](uint64_t b) {
@@ -516,18 +854,10 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
     uint32_t iter = 0;
     while (base < p_end) {  // uniform over each wave
         // every eighth batch: stop when the count has been handed to the radix engine
-        // (the flag's load overlaps this batch), or hand it over when a quarter of the
-        // elements so far found no room (K far beyond the table)
+        // (the flag's load overlaps this batch; lane 0 loads it, the wave reads it from
+        // lane 0 after the batch)
         const bool check = (++iter & 7) == 0;
-        // (lane 0 loads the flag; the wave reads it from lane 0 after the batch)
         const uint32_t handed = (check && __lane_id() == 0) ? g_load(&c->overflow) : 0u;
-        if (check) {
-            const uint64_t seen = 2 * (base - (uint64_t)bid * PP);
-            if (4ull * s_ndef > seen && seen > 2 * PP / 8) {
-                if (lane == 0) set_overflow(c, t.inplace, t.tmp_k, t.uniq);
-                break;
-            }
-        }
         uint64_t x[NE];
 #pragma unroll
         for (int e = 0; e < NE; ++e) x[e] = v[e];
@@ -546,9 +876,8 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
             // merged elements are counted by their run's head
 #pragma unroll
             for (int e = 0; e < NE; ++e) want &= add[e] ? ~0u : ~(1u << e);
-            const uint32_t dfr = count_batch<NE, W>(skeys, scnt, s_sink, x, want, t.mul, add);
+            const uint32_t dfr = count_batch<NE, W>(skeys, scnt, s_sink, x, mul, pl, 0u, want, add);
             // a deferred head stands for its whole run: that many copies go to the region
-            // (the region has room for every element of the workgroup's range)
 #pragma unroll
             for (int e = 0; e < NE; ++e) {
                 if ((dfr >> e) & 1u) {
@@ -563,7 +892,7 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
         uint32_t ones[NE];
 #pragma unroll
         for (int e = 0; e < NE; ++e) ones[e] = 1u;
-        const uint32_t dfr = count_batch<NE, W>(skeys, scnt, s_sink, x, want, t.mul, ones);
+        const uint32_t dfr = count_batch<NE, W>(skeys, scnt, s_sink, x, mul, pl, 0u, want, ones);
         if (__ballot(dfr != 0)) {
             // append the deferred elements: one LDS reservation per wave, then each
             // element's place from the ballot of its batch position
@@ -588,25 +917,23 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
         base = next;
         if (__builtin_amdgcn_readfirstlane(handed)) break;  // lane 0's load (every lane is active)
     }
-    __syncthreads();
-    flush_table<W>(t, skeys, scnt);
     const uint32_t wsum = wave_sum_u32(ecnt);
     if (lane == 0 && wsum) g_add(&c->ecount, (uint64_t)wsum);
-    // Second pass over this workgroup's deferred elements, with the table cleared
-    // (the keys that found no room are few) and a longer probe; what still finds no
-    // room goes to the global table.
-    const uint32_t d = s_ndef;  // uniform: read after the barrier
-    if (d == 0 || wave_overflow(c)) return;  // (d is uniform)
-    __syncthreads();  // (the workgroup reads back only its own region)
+    if (block_overflow(c, s_flag)) return;  // (uniform: every thread read the same word)
+    flush_table<W>(t, skeys, scnt);
+    // Second pass over the deferred elements, with the table cleared (the keys that
+    // found no room are few) and a longer probe; what still finds no room goes to the
+    // global table.
+    if (block_overflow(c, s_flag)) return;
+    const uint32_t d = s_ndef;  // uniform: read after the barrier (at most region_cap)
+    if (d == 0) return;
     for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
         skeys[i] = kEmpty;
         scnt[i] = 0;
     }
     __syncthreads();
-    if (threadIdx.x == 0) s_ndef = 0;  // now: elements that found no room in the second table either
-    __syncthreads();
     constexpr int D = 4;  // elements per thread per step
-    for (uint32_t i0 = 0; i0 < d; i0 += D * blockDim.x) {
+    for (uint32_t i0 = 0; i0 < d; i0 += D * blockDim.x) {  // uniform
         uint64_t xd[D];
         uint32_t want = 0;
 #pragma unroll
@@ -618,34 +945,23 @@ __device__ __forceinline__ void hash_count_table(const Args& a, uint32_t bid, ui
         uint32_t ones[D];
 #pragma unroll
         for (int u = 0; u < D; ++u) ones[u] = 1u;
-        const uint32_t dfr = count_batch<D, W>(skeys, scnt, s_sink, xd, want, t.mul, ones);
-        uint32_t cl[D];
+        const uint32_t dfr = count_batch<D, W>(skeys, scnt, s_sink, xd, mul, pl, 0u, want, ones);
+        uint32_t left = 0;
+        if (dfr) {
 #pragma unroll
-        for (int u = 0; u < D; ++u) cl[u] = kNoSlot;
-        const uint32_t ov = wave_overflow(c);
-        if (dfr && !ov) {
-#pragma unroll
-            for (int u = 0; u < D; ++u) {
-                if (((dfr >> u) & 1u) && !lds_insert<W>(skeys, scnt, xd[u], 1u, kLdsProbeBuckets, t.mul)) {
-                    atomicAdd(&s_ndef, 1u);
-                    cl[u] = global_insert(t, xd[u], 1);
-                }
-            }
+            for (int u = 0; u < D; ++u)
+                if (((dfr >> u) & 1u) &&
+                    !lds_insert<W>(skeys, scnt, xd[u], mul_hash32(xd[u], 32, mul) << pl, 1u, kLdsProbeBuckets))
+                    left |= 1u << u;
         }
+        if (__ballot(left != 0) && !wave_overflow(c)) {
+            uint32_t ones[D];
 #pragma unroll
-        for (int u = 0; u < D; ++u) list_claims(t, cl[u]);
-        // too many keys even for a second table: per-element global inserts would cost
-        // more than sorting, so the radix engine takes over (the count is read between
-        // two barriers, so every thread takes the same decision)
-        __syncthreads();
-        const bool stop = 64ull * s_ndef > 2 * PP;
-        __syncthreads();
-        if (stop) {
-            if (threadIdx.x == 0) set_overflow(c, t.inplace, t.tmp_k, t.uniq);
-            break;
+            for (int u = 0; u < D; ++u) ones[u] = 1u;
+            insert_or_spill_n<D>(t, left, xd, ones, false);
         }
     }
-    __syncthreads();
+    if (block_overflow(c, s_flag)) return;
     flush_table<W>(t, skeys, scnt);
 }
 CAFS_KERNELS0(hash_count, kCountThreads)
@@ -686,7 +1002,39 @@ __device__ __forceinline__ void gather_pairs(const Args& a, Ctrl* c, uint32_t cl
         j.tmp_k = a.gkeys; j.tmp_v = a.gcnt;
         j.n = K;
         j.has_vals = 1;
-        c->K = K;
+        c->fold_k = a.uniq;
+        c->fold_v = a.cnt;
+        c->pair_sort = 1;
+        c->radix_on = 1;
+        c->guard_on = (c->path == P_MAIN);
+        c->guard_general = c->guard_on;
+    }
+}
+
+// Alg. 4 with a spill: the table's pairs (and the empty marker's) are appended to the
+// spill list, and the radix engine sorts all of them by key; the fold then sums equal
+// neighbours (a key may sit in the table and on the list, and on the list several
+// times) into the dense arrays.  The spill list has room for them: every pair holds
+// elements no other pair holds.
+__device__ __forceinline__ void gather_spill(const Args& a, Ctrl* c, uint32_t claimed, uint64_t ecount,
+                                             uint64_t nspill, uint32_t bid, uint32_t nblk) {
+    CAFS_GLOBAL uint64_t* sk = gp(a.spill_k) + nspill;
+    CAFS_GLOBAL uint64_t* sv = gp(a.spill_v) + nspill;
+    for (uint64_t i = (uint64_t)bid * blockDim.x + threadIdx.x; i < claimed; i += (uint64_t)nblk * blockDim.x) {
+        const uint32_t h = gp(a.claimed)[i];
+        sk[i] = gp(a.gkeys)[h];
+        sv[i] = gp(a.gcnt)[h];
+    }
+    if (bid == 0 && threadIdx.x == 0) {
+        if (ecount) { sk[claimed] = kEmpty; sv[claimed] = ecount; }
+        RadixJob& j = c->rj;
+        j.src_k = a.spill_k; j.src_v = a.spill_v;
+        j.dst_k = a.spill_k; j.dst_v = a.spill_v;
+        j.tmp_k = a.tmp_k; j.tmp_v = a.off;  // (the offsets are written by the fold, after the sort)
+        j.n = nspill + claimed + (ecount ? 1u : 0u);
+        j.has_vals = 1;
+        c->fold_k = a.spill_k;
+        c->fold_v = a.spill_v;
         c->pair_sort = 1;
         c->radix_on = 1;
         c->guard_on = (c->path == P_MAIN);
@@ -767,6 +1115,17 @@ __device__ __forceinline__ void rank_body(const Args& a, uint32_t bid, uint32_t 
     if (c->engine != E_HASH || c->overflow || c->dense_ready) return;
     const uint32_t claimed = c->claimed;
     const uint64_t ecount = c->ecount;
+    const uint64_t nspill = c->nspill;
+    if (nspill) {
+        // (the pairs never outnumber the elements; the radix engine would take over
+        // if they did)
+        if (nspill + claimed + 1 > a.n) {
+            if (bid == 0 && threadIdx.x == 0) set_overflow(c, a.in == a.out, a.tmp_k, a.uniq);
+            return;
+        }
+        gather_spill(a, c, claimed, ecount, nspill, bid, nblk);
+        return;
+    }
     const uint32_t K = claimed + (ecount > 0 ? 1u : 0u);
     if (!rank_ok(a, K)) {
         gather_pairs(a, c, claimed, ecount, K, bid, nblk);
@@ -804,7 +1163,7 @@ CAFS_KERNELS0(rank, 1024)
 // pair sort when K is too large to rank.  One workgroup.
 __device__ __forceinline__ void compact_order_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
-    if (c->engine != E_HASH || c->overflow || c->dense_ready) return;
+    if (c->engine != E_HASH || c->overflow || c->dense_ready || c->pair_sort) return;
     const uint32_t claimed = c->claimed;
     const uint64_t ecount = c->ecount;
     const uint32_t K = claimed + (ecount > 0 ? 1u : 0u);
@@ -814,64 +1173,112 @@ __device__ __forceinline__ void compact_order_body(const Args& a, uint32_t bid, 
 }
 CAFS_KERNELS0(compact_order, 1024)
 
-// Exclusive scan of the sorted counts after a pair sort, in two launches over the
-// same grid: each workgroup sums its chunk of the counts, then each adds the sums
-// of the chunks before its own and scans its chunk.
-__device__ __forceinline__ uint64_t scan_chunk(uint64_t K, uint32_t nblk) { return (K + nblk - 1) / nblk; }
+// Fold and scan of the sorted pairs after a pair sort (Alg. 4: fold equal
+// neighbours, then the running offset of each key), in two launches over the same
+// grid.  Pair i heads a run when its key differs from pair i - 1's; each run becomes
+// one distinct key whose count is the sum of the run's counts and whose offset is the
+// sum of the counts before it.  Launch 1: each workgroup counts the heads of its
+// chunk and sums its counts.  Launch 2: each workgroup adds the totals of the chunks
+// before its own, scans its chunk, and the thread holding a head sums its run (which
+// may reach into the next chunks) and writes the key, count and offset.  Without a
+// spill the keys are distinct (every pair heads its run) and the pairs are folded in
+// place.
+__device__ __forceinline__ uint64_t scan_chunk(uint64_t T, uint32_t nblk) { return (T + nblk - 1) / nblk; }
 
-__device__ __forceinline__ void pair_sums_body(const Args& a, uint32_t bid, uint32_t nblk) {
-    Ctrl* c = a.c;
-    if (!c->pair_sort || c->overflow) return;
-    const uint64_t K = c->K;
-    const uint64_t ch = scan_chunk(K, nblk);
-    const uint64_t b = (uint64_t)bid * ch < K ? (uint64_t)bid * ch : K;
-    const uint64_t e = b + ch < K ? b + ch : K;
-    uint64_t local = 0;
-    for (uint64_t i = b + threadIdx.x; i < e; i += blockDim.x) local += gp(a.cnt)[i];
-    __shared__ uint64_t s_sum;
-    if (threadIdx.x == 0) s_sum = 0;
-    __syncthreads();
-    local = wave_sum_u64(local);
-    if (__lane_id() == 0 && local) atomicAdd((unsigned long long*)&s_sum, (unsigned long long)local);
-    __syncthreads();
-    if (threadIdx.x == 0) gp(a.psum)[bid] = s_sum;
+__device__ __forceinline__ bool is_head(const CAFS_GLOBAL uint64_t* fk, uint64_t i) {
+    return i == 0 || fk[i] != fk[i - 1];
 }
-CAFS_KERNELS0(pair_sums, 1024)
 
-__device__ __forceinline__ void pair_scan_body(const Args& a, uint32_t bid, uint32_t nblk) {
+__device__ __forceinline__ void fold_sums_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!c->pair_sort || c->overflow) return;
-    __shared__ uint64_t scan_tmp[17];
-    __shared__ uint64_t s_base;
-    const uint64_t K = c->K;
-    const uint64_t ch = scan_chunk(K, nblk);
-    uint64_t before = 0;
-    for (uint32_t w = threadIdx.x; w < bid; w += blockDim.x) before += gp(a.psum)[w];
-    if (threadIdx.x == 0) s_base = 0;
+    const uint64_t T = c->rj.n;
+    const CAFS_GLOBAL uint64_t* fk = gp(c->fold_k);
+    const CAFS_GLOBAL uint64_t* fv = gp(c->fold_v);
+    const uint64_t ch = scan_chunk(T, nblk);
+    const uint64_t b = (uint64_t)bid * ch < T ? (uint64_t)bid * ch : T;
+    const uint64_t e = b + ch < T ? b + ch : T;
+    uint64_t heads = 0, sum = 0;
+    for (uint64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+        heads += is_head(fk, i) ? 1u : 0u;
+        sum += fv[i];
+    }
+    __shared__ uint64_t s_h, s_v;
+    if (threadIdx.x == 0) { s_h = 0; s_v = 0; }
     __syncthreads();
-    before = wave_sum_u64(before);
-    if (__lane_id() == 0 && before) atomicAdd((unsigned long long*)&s_base, (unsigned long long)before);
+    heads = wave_sum_u64(heads);
+    sum = wave_sum_u64(sum);
+    if (__lane_id() == 0) {
+        if (heads) atomicAdd((unsigned long long*)&s_h, (unsigned long long)heads);
+        if (sum) atomicAdd((unsigned long long*)&s_v, (unsigned long long)sum);
+    }
     __syncthreads();
-    const uint64_t cb = (uint64_t)bid * ch < K ? (uint64_t)bid * ch : K;
-    const uint64_t ce = cb + ch < K ? cb + ch : K;
+    if (threadIdx.x == 0) {
+        gp(a.psum)[bid] = s_h;
+        gp(a.psum)[kMaxCountBlocks + bid] = s_v;
+    }
+}
+CAFS_KERNELS0(fold_sums, 1024)
+
+__device__ __forceinline__ void fold_write_body(const Args& a, uint32_t bid, uint32_t nblk) {
+    Ctrl* c = a.c;
+    if (!c->pair_sort || c->overflow) return;
+    __shared__ uint64_t scan_h[17], scan_v[17];
+    __shared__ uint64_t s_bh, s_bv;
+    const uint64_t T = c->rj.n;
+    const CAFS_GLOBAL uint64_t* fk = gp(c->fold_k);
+    const CAFS_GLOBAL uint64_t* fv = gp(c->fold_v);
+    const uint64_t ch = scan_chunk(T, nblk);
+    uint64_t bh = 0, bv = 0;
+    for (uint32_t w = threadIdx.x; w < bid; w += blockDim.x) {
+        bh += gp(a.psum)[w];
+        bv += gp(a.psum)[kMaxCountBlocks + w];
+    }
+    if (threadIdx.x == 0) { s_bh = 0; s_bv = 0; }
+    __syncthreads();
+    bh = wave_sum_u64(bh);
+    bv = wave_sum_u64(bv);
+    if (__lane_id() == 0) {
+        if (bh) atomicAdd((unsigned long long*)&s_bh, (unsigned long long)bh);
+        if (bv) atomicAdd((unsigned long long*)&s_bv, (unsigned long long)bv);
+    }
+    __syncthreads();
+    const uint64_t cb = (uint64_t)bid * ch < T ? (uint64_t)bid * ch : T;
+    const uint64_t ce = cb + ch < T ? cb + ch : T;
     const uint64_t len = ce - cb;
     const uint64_t per = (len + blockDim.x - 1) / blockDim.x;
     const uint64_t b0 = cb + (threadIdx.x * per < len ? threadIdx.x * per : len);
     const uint64_t b1 = b0 + per < ce ? b0 + per : ce;
-    const CAFS_GLOBAL uint64_t* cnt = gp(a.cnt);
-    uint64_t local = 0;
-    for (uint64_t i = b0; i < b1; ++i) local += cnt[i];
-    uint64_t total;
-    uint64_t run = s_base + block_exclusive_scan<uint64_t>(local, scan_tmp, &total);
+    uint64_t lh = 0, lv = 0;
     for (uint64_t i = b0; i < b1; ++i) {
-        gp(a.off)[i] = run;
-        run += cnt[i];
+        lh += is_head(fk, i) ? 1u : 0u;
+        lv += fv[i];
+    }
+    uint64_t th, tv;
+    uint64_t j = s_bh + block_exclusive_scan<uint64_t>(lh, scan_h, &th);
+    uint64_t pos = s_bv + block_exclusive_scan<uint64_t>(lv, scan_v, &tv);
+    // (in place there is no spill: every pair is its own run and is written back
+    // where it was, so a read by a neighbour sees the same value either way)
+    for (uint64_t i = b0; i < b1; ++i) {
+        const uint64_t k = fk[i];
+        const uint64_t v = fv[i];
+        if (is_head(fk, i)) {
+            uint64_t sum = v;
+            for (uint64_t i2 = i + 1; i2 < T && fk[i2] == k; ++i2) sum += fv[i2];
+            gp(a.uniq)[j] = k;
+            gp(a.cnt)[j] = sum;
+            gp(a.off)[j] = pos;
+            ++j;
+        }
+        pos += v;
     }
     if (threadIdx.x == 0 && bid == nblk - 1) {
-        a.off[K] = s_base + total;
+        const uint64_t K = s_bh + th;
+        a.off[K] = s_bv + tv;
+        c->K = K;
         c->dense_ready = 1;  // read by the next launch (the emit), after this grid ends
     }
 }
-CAFS_KERNELS0(pair_scan, 1024)
+CAFS_KERNELS0(fold_write, 1024)
 
 }  // namespace cafs

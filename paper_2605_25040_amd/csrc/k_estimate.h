@@ -134,30 +134,54 @@ __device__ void plan_block(const Args& a) {
     else { path = P_MAIN; engine = E_HASH; }
     c->table_M = 0;
     c->cap_log2 = kMinTableLog2;
+    c->part_log2 = 0;
+    c->pcap = 0;
+    c->lds_wide = 0;
     if (path == P_TINY || path == P_MAIN) {
-        c->table_M = paper_table_M(c->k_hat, n);
-        uint32_t lg = log2_pow2(bit_ceil64(8 * c->k_hat));
+        const uint64_t kh = c->k_hat;
+        c->table_M = paper_table_M(kh, n);
+        // the hash count: partitions of about part_keys estimated keys each (at most
+        // 2^kMaxPartLog2), LDS buckets of 4 keys when a partition's share of the
+        // estimate reaches wide_min
+        // (no partitions up to twice part_keys: one LDS table holds that many keys,
+        // and partitions cost a scatter pass over the column)
+        const uint64_t parts = kh <= 2 * a.part_keys ? 1 : (kh + a.part_keys - 1) / a.part_keys;
+        uint32_t pl = parts <= 1 ? 0u : log2_pow2(bit_ceil64(parts));
+        if (pl > kMaxPartLog2) pl = kMaxPartLog2;
+        // each bucket: an eighth more than an even share and a scatter chunk, a
+        // multiple of 32 elements (256 bytes)
+        const uint64_t share = n >> pl;
+        const uint64_t pcap = (share + share / 8 + kScatterChunk + 31) / 32 * 32;
+        if (pl && (pcap << pl) > a.pbuf_elems) pl = 0;
+        c->part_log2 = pl;
+        c->pcap = pcap;
+        c->lds_wide = (kh >> pl) >= a.wide_min ? 1u : 0u;
+        // the global table: table_slots K^ slots (half of them may be claimed); keys
+        // past that spill
+        uint32_t lg = log2_pow2(bit_ceil64(a.table_slots * kh));
         if (lg < kMinTableLog2) lg = kMinTableLog2;
-        if (lg > a.cap_ws_log2) {
-            engine = E_RADIX;  // the table the estimate asks for does not fit: sort instead
-            lg = a.cap_ws_log2;
-        }
-        // an estimate far below K (heavy tails) would overflow a table sized by it;
-        // up to kTableFloorLog2 the space is cheap and the count's LDS tables hold
-        // that many keys anyway
         const uint32_t floor_lg = kTableFloorLog2 < a.cap_ws_log2 ? kTableFloorLog2 : a.cap_ws_log2;
         if (lg < floor_lg) lg = floor_lg;
+        if (lg > a.cap_ws_log2) lg = a.cap_ws_log2;
+        // more keys than the partitions' LDS tables or the global table hold (the
+        // estimate is close to K for flat frequencies, and there most elements of
+        // the keys beyond would spill): the radix engine sorts instead
+        if (kh > (a.part_keys << (kMaxPartLog2 + 1)) || 2 * kh > (1ull << a.cap_ws_log2)) engine = E_RADIX;
         c->cap_log2 = lg;
     }
     const uint64_t cap = 1ull << c->cap_log2;
     c->cap_limit = (uint32_t)(cap / 2);  // linear probing stays short up to half load
+    c->nspill = 0;
+    c->spill_limit = n / kSpillFracDiv;
+    for (uint32_t q = 0; q < kMaxParts; ++q) c->pfill[q][0] = 0;
     c->path = path;
     c->engine = engine;
     c->tiny_miss = 0;
     c->flags = 0;
-    for (int j = 0; j < 8; ++j) { c->tiny_cnt[j] = 0; c->tile_ctr[j] = 0; }
+    for (int j = 0; j < 8; ++j) { c->tiny_cnt[j][0] = 0; c->tile_ctr[j] = 0; }
     c->overflow = 0;
     c->claimed = 0;
+    c->closed = 0;
     c->ecount = 0;
     c->K = 0;
     c->emit_main = 0;

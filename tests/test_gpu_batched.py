@@ -104,7 +104,9 @@ def test_batch_equals_single_calls(ctx):
         out, rep, _, _ = ctx.sort(c["in"].clone())
         torch.cuda.synchronize()
         assert torch.equal(out, c["out"]), i
-        assert cafs.parse_report(rep) == cafs.parse_report(c["report"]), i
+        ra, rb = cafs.parse_report(rep), cafs.parse_report(c["report"])
+        # (engine and flags tell what ran; a spill of a few keys can depend on timing)
+        assert all(ra[f] == rb[f] for f in oracle.REPORT_FIELDS), (i, ra, rb)
     # oracle on a sample of columns
     sub = [cols[i] for i in range(0, m, 29)]
     check_cols(sub, "sample")

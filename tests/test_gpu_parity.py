@@ -98,6 +98,15 @@ SEEDED = [
     (2_000_000, 1_700, "uniform", 1.1, "random"),
     (2_000_000, 1_900, "uniform", 1.1, "random"),
     (1 << 23, 20_000, "zipf", 1.1, "random"),        # estimate ~2200 for 20000 keys: table far past capacity
+    # hash partitions of the count workgroups (2, 8 and 16 partitions)
+    (1 << 24, 10_000, "uniform", 1.1, "random"),
+    (1 << 24, 30_000, "uniform", 1.1, "random"),
+    (1 << 24, 100_000, "uniform", 1.1, "codes"),
+    (1_500_001, 150_000, "uniform", 1.1, "random"),
+    # heavy tails far past the estimate: keys beyond the global table's limit spill
+    (1 << 22, 300_000, "zipf", 1.1, "random"),
+    (1 << 22, 1_000_000, "zipf", 1.1, "random"),
+    (3_000_000, 3_000_000, "zipf", 1.1, "random"),
 ]
 
 
@@ -456,3 +465,45 @@ def test_empty_marker_pattern_in_every_shape(ctx):
     check_f64(ctx, x.view(np.float64), "f64 runs of extremes")
     check(ctx, x, False, label="i64 runs of extremes")
     check(ctx, x, True, label="u64 runs of extremes")
+
+
+def test_spill_list_then_fold(ctx):
+    """A column of 2^18 keys whose estimate is 1 (every sampled position, and most
+    others, hold one value) with 80000 distinct values elsewhere: more keys than the
+    global table has slots (2^16), so at least 14464 of them spill (at most 47232,
+    below the radix hand-over at n / 4), and the spill list is sorted and folded with
+    the table's pairs (report flag 4).  (The paper's table has M = 8 buckets; its
+    spill, about 80000 elements, stays below n / 2, so the path is MAIN.)"""
+    rng = np.random.default_rng(77)
+    n = 1 << 18
+    stride = n // 1024
+    x = np.full(n, 12345, dtype=np.uint64)
+    pos = rng.choice(np.setdiff1d(np.arange(n), np.arange(0, n, stride)), size=80_000, replace=False)
+    x[pos] = rng.integers(1 << 20, 2**64, size=pos.size, dtype=np.uint64)
+    for unsigned in (False, True):
+        r = check(ctx, x, unsigned, label="spill")
+        assert r["engine"] == "HASH" and r["flags"] & 4 and not r["flags"] & 1, r
+        assert r["path"] == "MAIN" and r["tiny_miss"] == 1, r
+    # the same in place
+    y, r, _, _ = run_gpu(ctx, x, False, inplace=True)
+    assert np.array_equal(y, oracle.sort(x.view(np.int64), np.int64)) and r["flags"] & 4
+
+
+def test_spill_past_quarter_goes_to_radix(ctx):
+    """2000 keys built to share one slot of every table hashed with the paper's
+    multiplier: they overfill the LDS buckets and the global table's probe window,
+    so their elements spill one by one; past n / 4 spilled pairs the radix engine
+    sorts the column instead (report flag 1)."""
+    rng = np.random.default_rng(78)
+    pal = _colliding_keys(2000)
+    x = pal[rng.integers(0, pal.size, size=200_000)]
+    x[: pal.size] = pal
+    r = check(ctx, x, False, label="spill overflow")
+    assert r["flags"] & 1, r  # (the engine field keeps the plan's engine; flag 1 names the hand-over)
+
+
+@pytest.mark.parametrize("n,k,dist", [(1 << 22, 300_000, "zipf"), (1 << 24, 30_000, "uniform")])
+def test_spill_and_partitions_in_place_and_misaligned(ctx, n, k, dist):
+    x = gen.column(n, k, dist=dist, s=1.1, dtype=np.uint64)
+    check(ctx, x, False, label="in place", inplace=True)
+    check(ctx, x, True, label="misaligned", shift_in=1, shift_out=1)

@@ -79,7 +79,8 @@ def test_noalloc_equals_workspace_call(ctx, first, second):
         (y0, u0, c0, r0), (y1, u1, c1, r1) = run_both(ctx, x, dtype)
         assert np.array_equal(y1, y0), (n, k)
         assert np.array_equal(u1, u0) and np.array_equal(c1, c0), (n, k)
-        assert r1 == r0, (n, k, r0, r1)
+        # (engine and flags tell what ran; a spill of a few keys can depend on timing)
+        assert all(r1[f] == r0[f] for f in oracle.REPORT_FIELDS), (n, k, r0, r1)
         dt = np.uint64 if dtype == U64 else np.int64
         assert np.array_equal(y1.view(dt), oracle.sort(x.view(dt), dt)), (n, k)
 
@@ -90,7 +91,8 @@ def test_noalloc_float64_and_ragged(ctx):
     for n in (400_000, 3):
         x = pal[rng.integers(0, pal.size, size=n)].view(np.uint64)
         (y0, u0, c0, r0), (y1, u1, c1, r1) = run_both(ctx, x, F64)
-        assert np.array_equal(y1, y0) and np.array_equal(u1, u0) and np.array_equal(c1, c0) and r1 == r0
+        assert np.array_equal(y1, y0) and np.array_equal(u1, u0) and np.array_equal(c1, c0)
+        assert all(r1[f] == r0[f] for f in oracle.REPORT_FIELDS), (n, r0, r1)
 
 
 def test_noalloc_limit(ctx):
