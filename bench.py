@@ -132,7 +132,8 @@ def bench_batched(ctx, n_cols=4096, total=1 << 28, reps=50, seq_reps=1):
     cols = [{"in": x[offs[i]:offs[i + 1]], "out": y[offs[i]:offs[i + 1]], "report": reps_t[i]}
             for i in range(n_cols)]
     ws = torch.empty(ctx.batched_workspace_bytes(ns), dtype=torch.uint8, device=dev)
-    ctx.autotune_batched(cols, ws=ws)
+    tuned_ms = ctx.autotune_batched(cols, ws=ws)
+    tuning = ctx.tuning()
     for _ in range(2):
         ctx.sort_batched(cols, ws=ws)
     torch.cuda.synchronize()
@@ -186,7 +187,8 @@ def bench_batched(ctx, n_cols=4096, total=1 << 28, reps=50, seq_reps=1):
     return {"columns": n_cols, "keys": total_keys, "p50_ms": round(p50, 3), "p99_ms": round(pct(lat, 99), 3),
             "gkeys_s": round(total_keys / p50 / 1e6, 2),
             "graph_p50_ms": round(pct(glat, 50), 3), "graph_p99_ms": round(pct(glat, 99), 3),
-            "sequential_ms": round(seq_ms, 3), "vs_sequential": round(seq_ms / p50, 2), "graph_ok": ok_graph}
+            "sequential_ms": round(seq_ms, 3), "vs_sequential": round(seq_ms / p50, 2), "graph_ok": ok_graph,
+            "tuning": tuning, "tuned_ms": round(tuned_ms, 3)}
 
 
 def bench_structured(ctx, n=1 << 28, steps=10):

@@ -258,12 +258,22 @@ cafs_status_t cafs_ctx_set_count_geometry(cafs_ctx_t* ctx, uint64_t part_keys, u
  * batched and served).  CAFS_EINVAL for a null context. */
 cafs_status_t cafs_ctx_set_hash_seed(cafs_ctx_t* ctx, uint64_t seed);
 
-/* Autotuner of the batched block sizing: times the batch (synchronously, three
- * runs per candidate, candidates 2^15..2^18 and 2^17..2^20 elements per block)
- * and keeps the fastest in the context.  The batch is sorted several times, so
- * in-place columns are timed as already sorted after the first run. */
+/* Autotuner of batched calls: times the batch (synchronously; per candidate a
+ * warm-up run and the faster of two timed runs) and keeps the fastest settings in
+ * the context.  First the workgroups per column (2^15..2^18 elements per block of
+ * the general kernels, 2^17..2^20 of the hash count, all 16 pairs), then the count
+ * geometry of cafs_ctx_set_count_geometry one parameter at a time (keys per
+ * partition 4500/6000/9000, 4-key LDS buckets from an estimate per partition of
+ * 1200/1800/2600, 16/32/64 global table slots per estimated key).  The batch is
+ * sorted many times, so in-place columns are timed as already sorted after the
+ * first run.  *h_best_ms receives the best batch time. */
 cafs_status_t cafs_autotune_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, uint32_t n_cols, void* d_ws,
                                     size_t ws_bytes, void* stream, double* h_best_ms);
+
+/* The context's tuning, into h_vals[0..n): elements per block of the batched
+ * general kernels and of the batched hash count, keys per partition, the 4-key
+ * bucket threshold and global table slots per estimated key. */
+cafs_status_t cafs_ctx_get_tuning(cafs_ctx_t* ctx, uint64_t* h_vals, uint32_t n);
 
 /* ---- Serving: continuous batching under an HBM budget ------------------------
  * A server owns one device arena of hbm_budget bytes (allocated at create) and

@@ -23,7 +23,7 @@ STAGES = ("pre", "count", "order", "emit", "tail")
 EXPORTS = ("cafs_ctx_create", "cafs_ctx_destroy", "cafs_ctx_enable_timing", "cafs_ctx_stage_ms",
            "cafs_workspace_bytes", "cafs_estimate",
            "cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64", "cafs_sort_noalloc", "cafs_radix_sort", "cafs_batched_workspace_bytes",
-           "cafs_sort_batched", "cafs_ctx_set_batch_tuning", "cafs_autotune_batched", "cafs_ctx_set_hash_seed", "cafs_ctx_set_count_geometry",
+           "cafs_sort_batched", "cafs_ctx_set_batch_tuning", "cafs_autotune_batched", "cafs_ctx_set_hash_seed", "cafs_ctx_set_count_geometry", "cafs_ctx_get_tuning",
            "cafs_server_create", "cafs_server_destroy", "cafs_server_reserve", "cafs_server_submit",
            "cafs_server_poll", "cafs_server_release", "cafs_server_stats",
            "cafs_status_str", "cafs_last_error")
@@ -91,6 +91,8 @@ def load():
     lib.cafs_ctx_set_batch_tuning.restype = i32
     lib.cafs_ctx_set_count_geometry.argtypes = [p, u64, u64, u64]
     lib.cafs_ctx_set_count_geometry.restype = i32
+    lib.cafs_ctx_get_tuning.argtypes = [p, ctypes.POINTER(u64), u32]
+    lib.cafs_ctx_get_tuning.restype = i32
     lib.cafs_ctx_set_hash_seed.argtypes = [p, u64]
     lib.cafs_ctx_set_hash_seed.restype = i32
     lib.cafs_autotune_batched.argtypes = [p, p, u32, p, ctypes.c_size_t, p, ctypes.POINTER(ctypes.c_double)]
@@ -250,6 +252,14 @@ class Context:
         """Hash-count geometry (speed only): keys per partition, the 4-key bucket
         threshold per partition and global table slots per estimated key."""
         _check(self._lib.cafs_ctx_set_count_geometry(self._h, int(part_keys), int(wide_min), int(table_slots)))
+
+    TUNING = ("batch_elems_per_block", "batch_elems_per_hash_block", "part_keys", "wide_min", "table_slots")
+
+    def tuning(self):
+        """The context's batched block sizing and count geometry (as the autotuner left them)."""
+        arr = (ctypes.c_uint64 * len(self.TUNING))()
+        _check(self._lib.cafs_ctx_get_tuning(self._h, arr, len(self.TUNING)))
+        return {k: int(v) for k, v in zip(self.TUNING, arr)}
 
     def set_hash_seed(self, seed):
         """Seed of the count tables' hash (0: the paper's multiplier)."""

@@ -822,37 +822,69 @@ cafs_status_t cafs_autotune_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventCreate");
+    cafs_status_t st = CAFS_OK;
+    // one candidate: a warm-up run, then the faster of two timed runs
+    auto time_batch = [&](double* out_ms) {
+        float best = 1e30f;
+        for (int rep = 0; rep < 3 && st == CAFS_OK; ++rep) {
+            (void)hipEventRecord(e0, s);
+            st = cafs_sort_batched(ctx, h_cols, n_cols, d_ws, ws_bytes, stream);
+            (void)hipEventRecord(e1, s);
+            hipError_t e = hipEventSynchronize(e1);
+            if (e != hipSuccess && st == CAFS_OK) st = hip_fail(e, "hipEventSynchronize");
+            float ms = 0.f;
+            if (st == CAFS_OK && rep > 0 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) best = std::min(best, ms);
+        }
+        *out_ms = best;
+    };
+    double best = 1e30;
+    // stage 1: workgroups per column (elements per block of the general kernels and of
+    // the hash count)
     const uint64_t per[] = {1ull << 15, 1ull << 16, 1ull << 17, 1ull << 18};
     const uint64_t per_h[] = {1ull << 17, 1ull << 18, 1ull << 19, 1ull << 20};
-    double best = 1e30;
     uint64_t bp = ctx->batch_per_block, bh = ctx->batch_per_hash_block;
-    cafs_status_t st = CAFS_OK;
     for (uint64_t p : per) {
         for (uint64_t q : per_h) {
             ctx->batch_per_block = p;
             ctx->batch_per_hash_block = q;
-            float ms_min = 1e30f;
-            for (int rep = 0; rep < 3 && st == CAFS_OK; ++rep) {
-                (void)hipEventRecord(e0, s);
-                st = cafs_sort_batched(ctx, h_cols, n_cols, d_ws, ws_bytes, stream);
-                (void)hipEventRecord(e1, s);
-                hipError_t e = hipEventSynchronize(e1);
-                if (e != hipSuccess) st = hip_fail(e, "hipEventSynchronize");
-                float ms = 0.f;
-                if (st == CAFS_OK && rep > 0 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
-                    ms_min = std::min(ms_min, ms);
-            }
+            double ms;
+            time_batch(&ms);
             if (st != CAFS_OK) break;
-            if (ms_min < best) { best = ms_min; bp = p; bh = q; }
+            if (ms < best) { best = ms; bp = p; bh = q; }
         }
         if (st != CAFS_OK) break;
     }
     ctx->batch_per_block = bp;
     ctx->batch_per_hash_block = bh;
+    // stages 2-4: the count geometry, one parameter at a time with the others at their
+    // best so far (partition size, LDS bucket width threshold, global table size)
+    const uint64_t part_c[] = {4500, 6000, 9000};
+    const uint64_t wide_c[] = {1200, 1800, 2600};
+    const uint64_t slots_c[] = {16, 32, 64};
+    uint64_t* params[] = {&ctx->part_keys, &ctx->wide_min, &ctx->table_slots};
+    const uint64_t* cands[] = {part_c, wide_c, slots_c};
+    for (int g = 0; g < 3 && st == CAFS_OK; ++g) {
+        uint64_t keep = *params[g];
+        for (int i = 0; i < 3 && st == CAFS_OK; ++i) {
+            *params[g] = cands[g][i];
+            double ms;
+            time_batch(&ms);
+            if (st == CAFS_OK && ms < best) { best = ms; keep = cands[g][i]; }
+        }
+        *params[g] = keep;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (h_best_ms) *h_best_ms = best;
     return st;
+}
+
+cafs_status_t cafs_ctx_get_tuning(cafs_ctx_t* ctx, uint64_t* h_vals, uint32_t n) {
+    if (!ctx || (n > 0 && !h_vals)) return CAFS_EINVAL;
+    const uint64_t v[] = {ctx->batch_per_block, ctx->batch_per_hash_block, ctx->part_keys, ctx->wide_min,
+                          ctx->table_slots};
+    for (uint32_t i = 0; i < n && i < sizeof(v) / sizeof(v[0]); ++i) h_vals[i] = v[i];
+    return CAFS_OK;
 }
 
 // ---- serving -------------------------------------------------------------------

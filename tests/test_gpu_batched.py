@@ -7,6 +7,7 @@ import pytest
 import gen
 import oracle
 from tests import crafted
+from tests.test_gpu_parity import check as check_single
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -209,3 +210,32 @@ def test_batch_graph_capture_replays(ctx):
         check_cols(cols, "replay %d" % r)
         ctx.sort_batched(cols, ws=ws)
         check_cols(cols, "eager %d" % r)
+
+
+def test_autotune_and_geometry_extremes(ctx):
+    """The autotuner leaves a tuning drawn from its candidates, and outputs, counts
+    and reports stay equal to the oracle's under it and under extreme count
+    geometries: partitions from an estimate of 512 up, 4-key LDS buckets for every
+    estimate, the smallest global tables (so that many keys spill)."""
+    spec = gen.batch_spec(96, seed=41, n_lo=1e3, n_hi=2e6, k_cap=6e4)
+    arrays = [gen.column(c["n"], c["k"], dist=c["dist"], s=c["s"], seed=c["seed"], dtype=np.uint64) for c in spec]
+    m = len(arrays)
+    cols = make_cols(arrays, [False] * m, [True] * m, [True] * m)
+    try:
+        best = ctx.autotune_batched(cols)
+        t = ctx.tuning()
+        assert best > 0
+        assert t["part_keys"] in (4500, 6000, 9000) and t["wide_min"] in (1200, 1800, 2600), t
+        assert t["table_slots"] in (16, 32, 64), t
+        ctx.sort_batched(cols)
+        check_cols(cols, "tuned")
+        for geo in (dict(part_keys=256, wide_min=0, table_slots=2), dict(part_keys=100_000, wide_min=1 << 40,
+                                                                           table_slots=256)):
+            ctx.set_count_geometry(**geo)
+            ctx.sort_batched(cols)
+            check_cols(cols, "geometry %r" % geo)
+            for x in arrays[:12]:
+                check_single(ctx, x, False, label="single, geometry %r" % geo)
+    finally:
+        ctx.set_count_geometry()
+        ctx.set_batch_tuning(1 << 16, 1 << 18)
