@@ -46,24 +46,30 @@ def _load():
             build()
         lib = ctypes.CDLL(_LIB_PATH)
         p, u64 = ctypes.c_void_p, ctypes.c_uint64
-        for name in ("oracle_sort_i64", "oracle_sort_u64", "oracle_sort_f64", "oracle_std_sort_i64"):
+        for name in ("oracle_sort_i64", "oracle_sort_u64", "oracle_sort_f64", "oracle_std_sort_i64",
+                     "oracle_sort_i32", "oracle_sort_u32"):
             getattr(lib, name).argtypes = [p, u64, p]
             getattr(lib, name).restype = None
-        for name in ("oracle_counts_i64", "oracle_counts_u64", "oracle_counts_f64"):
+        for name in ("oracle_counts_i64", "oracle_counts_u64", "oracle_counts_f64", "oracle_counts_i32",
+                     "oracle_counts_u32"):
             getattr(lib, name).argtypes = [p, u64, p, p]
             getattr(lib, name).restype = u64
-        for name in ("oracle_is_monotone_i64", "oracle_is_monotone_u64", "oracle_is_monotone_f64"):
+        for name in ("oracle_is_monotone_i64", "oracle_is_monotone_u64", "oracle_is_monotone_f64",
+                     "oracle_is_monotone_i32", "oracle_is_monotone_u32"):
             getattr(lib, name).argtypes = [p, u64]
             getattr(lib, name).restype = ctypes.c_int
-        for name in ("oracle_estimate", "oracle_report_i64", "oracle_report_u64", "oracle_report_f64"):
+        for name in ("oracle_estimate", "oracle_report_i64", "oracle_report_u64", "oracle_report_f64",
+                     "oracle_report_i32", "oracle_report_u32"):
             getattr(lib, name).argtypes = [p, u64, p]
             getattr(lib, name).restype = None
-        lib.oracle_table_M.argtypes = [u64, u64]
-        lib.oracle_table_M.restype = u64
+        for name in ("oracle_table_M", "oracle_table_M32"):
+            getattr(lib, name).argtypes = [u64, u64]
+            getattr(lib, name).restype = u64
         lib.oracle_hash.argtypes = [u64, u64]
         lib.oracle_hash.restype = u64
-        lib.oracle_spill.argtypes = [p, u64, u64]
-        lib.oracle_spill.restype = u64
+        for name in ("oracle_spill", "oracle_spill32"):
+            getattr(lib, name).argtypes = [p, u64, u64]
+            getattr(lib, name).restype = u64
         _lib = lib
     return _lib
 
@@ -71,17 +77,17 @@ def _load():
 def _arr(x, dtype):
     a = np.ascontiguousarray(x)
     if a.dtype != dtype:
-        if a.dtype.itemsize != 8 or a.dtype.kind not in "iuf":
-            raise TypeError("oracle takes 64-bit integer or float64 arrays")
+        if a.dtype.itemsize != np.dtype(dtype).itemsize or a.dtype.kind not in "iuf":
+            raise TypeError("oracle takes 64-bit or 32-bit integer or float64 arrays of the dtype's width")
         a = a.view(dtype)
     return a
 
 
 def _kind(dtype):
-    """Suffix of the oracle function for ``dtype``: int64, uint64 or float64 (IEEE
-    754 totalOrder on the bit patterns)."""
+    """Suffix of the oracle function for ``dtype``: int64, uint64, float64 (IEEE 754
+    totalOrder on the bit patterns), int32 or uint32."""
     d = np.dtype(dtype)
-    return {"i": "i64", "u": "u64", "f": "f64"}[d.kind]
+    return {("i", 8): "i64", ("u", 8): "u64", ("f", 8): "f64", ("i", 4): "i32", ("u", 4): "u32"}[(d.kind, d.itemsize)]
 
 
 def _ptr(a):
@@ -126,9 +132,11 @@ def estimate(x):
     return {k: int(v) for k, v in zip(ESTIMATE_FIELDS, out)}
 
 
-def table_M(k_hat, n):
-    """Bucket count of Eq. Msize (cap 4, clamped to [8, bit_ceil(N/4)])."""
-    return int(_load().oracle_table_M(int(k_hat), int(n)))
+def table_M(k_hat, n, cap=4):
+    """Bucket count of Eq. Msize (cap 4 for 64-bit keys, 8 for 32-bit keys; clamped
+    to [8, bit_ceil(N/cap)])."""
+    fn = {4: _load().oracle_table_M, 8: _load().oracle_table_M32}[cap]
+    return int(fn(int(k_hat), int(n)))
 
 
 def hash_bucket(v, M):
@@ -136,10 +144,12 @@ def hash_bucket(v, M):
     return int(_load().oracle_hash(int(v) & (2**64 - 1), int(M)))
 
 
-def spill(x, M):
-    """Literal bucket simulation (Alg. 1 + RLE): spilled element count."""
+def spill(x, M, cap=4):
+    """Literal bucket simulation (Alg. 1 + RLE) with buckets of `cap` keys over the
+    64-bit values x: spilled element count."""
     a = _arr(x, np.uint64)
-    return int(_load().oracle_spill(_ptr(a), a.size, int(M)))
+    fn = {4: _load().oracle_spill, 8: _load().oracle_spill32}[cap]
+    return int(fn(_ptr(a), a.size, int(M)))
 
 
 def report(x, dtype=np.int64):

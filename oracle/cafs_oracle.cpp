@@ -55,6 +55,7 @@ constexpr uint64_t kSamples      = 1024;                 // s, Sec. 4.3
 constexpr uint64_t kSmallN       = 2048;                 // Table dispatcher
 constexpr uint64_t kTinyK        = 8;                    // Table dispatcher
 constexpr uint64_t kBucketCap    = 4;                    // 64-bit keys per bucket, Sec. 4.2
+constexpr uint64_t kBucketCap32  = 8;                    // 32-bit keys per bucket, Sec. 4.2
 constexpr uint64_t kLoadMul      = 8;                    // Eq. Msize numerator
 constexpr uint64_t kMinBuckets   = 8;                    // Eq. Msize lower clamp
 constexpr uint64_t kInvGolden    = 0x9E3779B97F4A7C15ull;  // Eq. hash multiplier
@@ -168,10 +169,11 @@ Estimate chao1(const uint64_t* x, uint64_t n) {
     return e;
 }
 
-// Eq. Msize with cap = 4 (64-bit keys), clamped to [8, bit_ceil(N/cap)].
-uint64_t table_buckets(uint64_t k_hat, uint64_t n) {
-    uint64_t m = bit_ceil_u64(kLoadMul * k_hat / kBucketCap);
-    m = std::min<uint64_t>(m, bit_ceil_u64(n / kBucketCap));
+// Eq. Msize, clamped to [8, bit_ceil(N/cap)]: cap = 4 for 64-bit keys, 8 for
+// 32-bit keys (a bucket of one cache line holds that many keys, Sec. 4.2).
+uint64_t table_buckets(uint64_t k_hat, uint64_t n, uint64_t cap) {
+    uint64_t m = bit_ceil_u64(kLoadMul * k_hat / cap);
+    m = std::min<uint64_t>(m, bit_ceil_u64(n / cap));
     m = std::max<uint64_t>(m, kMinBuckets);
     return m;
 }
@@ -187,7 +189,7 @@ uint64_t bucket_of(uint64_t v, uint64_t M) {
 // is claimed once and never freed because counters only grow).  A run of r equal
 // neighbours is one update(v, r); when the bucket is full and does not hold v,
 // the run goes to the spill, counted in elements.  Returns |spill|.
-uint64_t simulate_spill(const uint64_t* x, uint64_t n, uint64_t M) {
+uint64_t simulate_spill(const uint64_t* x, uint64_t n, uint64_t M, uint64_t cap) {
     std::vector<std::vector<uint64_t>> buckets(M);
     uint64_t spill = 0;
     uint64_t i = 0;
@@ -198,12 +200,25 @@ uint64_t simulate_spill(const uint64_t* x, uint64_t n, uint64_t M) {
         std::vector<uint64_t>& b = buckets[bucket_of(v, M)];
         const bool hit = std::find(b.begin(), b.end(), v) != b.end();
         if (!hit) {
-            if (b.size() < kBucketCap) b.push_back(v);  // claim an empty slot
+            if (b.size() < cap) b.push_back(v);  // claim an empty slot
             else spill += r;                              // full bucket: spill
         }
         i += r;
     }
     return spill;
+}
+
+// The 64-bit values the estimate, the hash and the spill simulation see for a column
+// of 32-bit keys: each key's 32-bit pattern, zero-extended.
+template <class T>
+std::vector<uint64_t> widen32(const T* x, uint64_t n) {
+    std::vector<uint64_t> b(n);
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t u;
+        std::memcpy(&u, &x[i], sizeof(u));
+        b[i] = u;
+    }
+    return b;
 }
 
 struct Report {
@@ -218,7 +233,7 @@ struct Report {
 // elements as 64-bit patterns (equality, the estimate, the tiny check and the spill
 // act on the patterns).
 template <class T>
-Report dispatch(const T* x, const uint64_t* bits, uint64_t n) {
+Report dispatch(const T* x, const uint64_t* bits, uint64_t n, uint64_t cap) {
     Report r{};
     r.k_exact = distinct_count(x, n);
     if (is_monotone(x, n)) { r.path = O_MONOTONE; return r; }
@@ -238,8 +253,8 @@ Report dispatch(const T* x, const uint64_t* bits, uint64_t n) {
         to_main = true;
     }
     if (!to_main && 2 * r.est.k_hat > n) { r.path = O_HIGH_K; return r; }
-    r.table_M = table_buckets(r.est.k_hat, n);
-    r.spill_elems = simulate_spill(bits, n, r.table_M);
+    r.table_M = table_buckets(r.est.k_hat, n, cap);
+    r.spill_elems = simulate_spill(bits, n, r.table_M, cap);
     r.path = (2 * r.spill_elems > n) ? O_GUARD : O_MAIN;  // |spill| > N/2
     return r;
 }
@@ -285,20 +300,22 @@ void oracle_estimate(const uint64_t* x, uint64_t n, uint64_t* out) {
     out[4] = e.n_samples; out[5] = e.stride; out[6] = e.saturated;
 }
 
-uint64_t oracle_table_M(uint64_t k_hat, uint64_t n) { return table_buckets(k_hat, n); }
+uint64_t oracle_table_M(uint64_t k_hat, uint64_t n) { return table_buckets(k_hat, n, kBucketCap); }
+uint64_t oracle_table_M32(uint64_t k_hat, uint64_t n) { return table_buckets(k_hat, n, kBucketCap32); }
 uint64_t oracle_hash(uint64_t v, uint64_t M) { return bucket_of(v, M); }
-uint64_t oracle_spill(const uint64_t* x, uint64_t n, uint64_t M) { return simulate_spill(x, n, M); }
+uint64_t oracle_spill(const uint64_t* x, uint64_t n, uint64_t M) { return simulate_spill(x, n, M, kBucketCap); }
+uint64_t oracle_spill32(const uint64_t* x, uint64_t n, uint64_t M) { return simulate_spill(x, n, M, kBucketCap32); }
 
 void oracle_report_i64(const int64_t* x, uint64_t n, uint64_t* out) {
     std::vector<uint64_t> bits(n);
     if (n) std::memcpy(bits.data(), x, n * sizeof(uint64_t));
-    flatten(dispatch(x, bits.data(), n), out);
+    flatten(dispatch(x, bits.data(), n, kBucketCap), out);
 }
 // float64 entry points: the bit patterns are copied into TotalF64 objects (and
 // back), so that no storage is read through a type it does not hold.
 void oracle_report_f64(const uint64_t* x, uint64_t n, uint64_t* out) {
     const std::vector<TotalF64> v = as_total(x, n);
-    flatten(dispatch(v.data(), x, n), out);
+    flatten(dispatch(v.data(), x, n, kBucketCap), out);
 }
 void oracle_sort_f64(const uint64_t* x, uint64_t n, uint64_t* y) {
     const std::vector<TotalF64> v = as_total(x, n);
@@ -317,6 +334,29 @@ int oracle_is_monotone_f64(const uint64_t* x, uint64_t n) {
     const std::vector<TotalF64> v = as_total(x, n);
     return is_monotone(v.data(), n) ? 1 : 0;
 }
-void oracle_report_u64(const uint64_t* x, uint64_t n, uint64_t* out) { flatten(dispatch(x, x, n), out); }
+void oracle_report_u64(const uint64_t* x, uint64_t n, uint64_t* out) { flatten(dispatch(x, x, n, kBucketCap), out); }
+
+// 32-bit keys (the paper's int32 specialization, Sec. 4.2, and its unsigned twin).
+// Equality, the estimate, the tiny check and the spill simulation act on each key's
+// 32-bit pattern zero-extended to 64 bits (Eq. hash on that value); the order is the
+// key type's; M and the spill use buckets of 8 keys.
+void oracle_sort_i32(const int32_t* x, uint64_t n, int32_t* y) { sort_by_map(x, n, y); }
+void oracle_sort_u32(const uint32_t* x, uint64_t n, uint32_t* y) { sort_by_map(x, n, y); }
+uint64_t oracle_counts_i32(const int32_t* x, uint64_t n, int32_t* uniq, uint64_t* counts) {
+    return counts_by_map(x, n, uniq, counts);
+}
+uint64_t oracle_counts_u32(const uint32_t* x, uint64_t n, uint32_t* uniq, uint64_t* counts) {
+    return counts_by_map(x, n, uniq, counts);
+}
+int oracle_is_monotone_i32(const int32_t* x, uint64_t n) { return is_monotone(x, n) ? 1 : 0; }
+int oracle_is_monotone_u32(const uint32_t* x, uint64_t n) { return is_monotone(x, n) ? 1 : 0; }
+void oracle_report_i32(const int32_t* x, uint64_t n, uint64_t* out) {
+    const std::vector<uint64_t> bits = widen32(x, n);
+    flatten(dispatch(x, bits.data(), n, kBucketCap32), out);
+}
+void oracle_report_u32(const uint32_t* x, uint64_t n, uint64_t* out) {
+    const std::vector<uint64_t> bits = widen32(x, n);
+    flatten(dispatch(x, bits.data(), n, kBucketCap32), out);
+}
 
 }  // extern "C"

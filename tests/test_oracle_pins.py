@@ -381,3 +381,124 @@ def test_f64_report_follows_the_bits():
     s = np.sort(rng.normal(size=5000))
     assert oracle.report(s, np.float64)["path"] == "MONOTONE"
     assert oracle.report(-s, np.float64)["path"] != "MONOTONE"
+
+
+# --------------------------------------------------------------------------
+# 32-bit keys (Sec. 4.2's int32 specialization): sort, counts, Eq. Msize with
+# cap 8, buckets of eight keys, the estimate on the 32-bit patterns
+# --------------------------------------------------------------------------
+
+I32_MIN, I32_MAX = -(1 << 31), (1 << 31) - 1
+
+
+def _col32(n, k, seed, signed):
+    rng = np.random.default_rng(seed)
+    if signed:
+        pal = rng.integers(I32_MIN, I32_MAX, size=k, endpoint=True, dtype=np.int64).astype(np.int32)
+    else:
+        pal = rng.integers(0, 1 << 32, size=k, dtype=np.uint64).astype(np.uint32)
+    return pal[rng.integers(0, k, size=n)]
+
+
+@pytest.mark.parametrize("signed", [True, False])
+@pytest.mark.parametrize("n,k", [(0, 1), (1, 1), (9, 4), (5000, 200), (100_000, 3000), (40_000, 40_000)])
+def test_sort32_equals_numpy_sort(signed, n, k):
+    dt = np.int32 if signed else np.uint32
+    x = _col32(n, k, n + k, signed)
+    y = oracle.sort(x, dt)
+    assert y.dtype == dt and np.array_equal(y, np.sort(x, kind="stable"))
+    u, c = oracle.counts(x, dt)
+    uu, cc = np.unique(x, return_counts=True)
+    assert np.array_equal(u, uu) and np.array_equal(c, cc.astype(np.uint64))
+    assert int(c.sum()) == n
+    assert oracle.is_monotone(y, dt) and (n < 2 or not oracle.is_monotone(np.sort(x)[::-1].copy(), dt)
+                                          or np.unique(x).size == 1)
+
+
+def test_bruteforce_small_alphabets_32():
+    alph = {np.int32: [I32_MIN, -1, 0, 1, I32_MAX], np.uint32: [0, 1, (1 << 31) - 1, 1 << 31, (1 << 32) - 1]}
+    for dt, vals in alph.items():
+        for length in range(0, 6):
+            for combo in itertools.product(vals, repeat=length):
+                x = np.array(combo, dtype=dt)
+                assert oracle.sort(x, dt).tolist() == sorted(combo), (dt, combo)
+                u, c = oracle.counts(x, dt)
+                assert u.tolist() == sorted(set(combo)), (dt, combo)
+                assert c.tolist() == [combo.count(v) for v in sorted(set(combo))]
+                assert oracle.is_monotone(x, dt) == (list(combo) == sorted(combo))
+
+
+def test_signedness_32():
+    # the same bits order as signed or unsigned 32-bit integers
+    x = np.array([0xFFFFFFFF, 0, 0x80000000, 5], dtype=np.uint32)
+    assert oracle.sort(x, np.uint32).tolist() == [0, 5, 0x80000000, 0xFFFFFFFF]
+    assert oracle.sort(x.view(np.int32), np.int32).tolist() == [I32_MIN, -1, 0, 5]
+    assert oracle.is_monotone(np.array([-1, 0], dtype=np.int32), np.int32)
+    assert not oracle.is_monotone(np.array([0xFFFFFFFF, 0], dtype=np.uint32), np.uint32)
+
+
+def test_table_M_cap8_closed_forms():
+    cap = GOLDEN["bucket_cap_32"]["cap"]
+    assert cap == 8 and GOLDEN["bucket_cap_32"]["cap_64"] == 4
+    n = 1 << 26
+    # M = bit_ceil(8 K^ / 8) = bit_ceil(K^): half the 64-bit table of the same estimate
+    for kh, m in ((200, 256), (1000, 1024), (4000, 4096), (10_000, 16_384), (1_000_000, 1 << 20)):
+        assert oracle.table_M(kh, n, cap=8) == m
+        assert oracle.table_M(kh, n, cap=4) == 2 * m
+    assert oracle.table_M(1, 10**6, cap=8) == 8       # lower clamp
+    assert oracle.table_M(7, 10**6, cap=8) == 8
+    assert oracle.table_M(9, 10**6, cap=8) == 16
+    assert oracle.table_M(1000, 2048, cap=8) == 256   # upper clamp bit_ceil(N/8) = 256
+    assert oracle.table_M(1000, 2055, cap=8) == 256   # integer N/8 = 256
+    assert oracle.table_M(1000, 2056, cap=8) == 512   # N/8 = 257 -> 512
+
+
+def _keys32_in_bucket(b, M, count, start=1):
+    """The first `count` 32-bit values from `start` whose Eq. hash (on the
+    zero-extended pattern) lands in bucket b of M, found by scanning."""
+    out, v = [], start
+    while len(out) < count:
+        if oracle.hash_bucket(v, M) == b:
+            out.append(v)
+        v += 1
+    return out
+
+
+def test_spill_cap8_first_eight_claim():
+    M = 8
+    ks = _keys32_in_bucket(3, M, 11)
+    # first-occurrence order k0..k10 with counts 1..11: k8, k9, k10 spill with cap 8
+    seq = []
+    for i, k in enumerate(ks):
+        seq += [k] * (i + 1)
+    x = np.array(seq, dtype=np.uint64)
+    assert oracle.spill(x, M, cap=8) == 9 + 10 + 11
+    # the same keys with cap 4: k4..k10 spill
+    assert oracle.spill(x, M, cap=4) == sum(range(5, 12))
+    # eight keys in every bucket: nothing spills with cap 8
+    full = [k for b in range(M) for k in _keys32_in_bucket(b, M, 8)]
+    assert oracle.spill(np.array(full * 2, dtype=np.uint64), M, cap=8) == 0
+
+
+def test_report32_reads_patterns_and_cap8():
+    """A 32-bit column's estimate is the estimate of its zero-extended patterns;
+    M and the spill come from buckets of eight: a crafted column where 12 keys share
+    one of M = 8 buckets spills exactly the elements of keys 9..12."""
+    M = 8
+    ks = _keys32_in_bucket(6, M, 12, start=1 << 31)  # patterns with bit 31 set: negative as int32
+    # N = 2560 > 2048, stride 2; every sampled (even) position holds ks[0]: u = 1, K^ = 1
+    n = 2560
+    x = np.full(n, ks[0], dtype=np.uint64)
+    odd = np.arange(1, n, 2)
+    for i, k in enumerate(ks[1:]):
+        x[odd[i * 100:(i + 1) * 100]] = k  # 100 copies each, in first-occurrence order
+    x32 = x.astype(np.uint32)
+    for dt in (np.uint32, np.int32):
+        r = oracle.report(x32.view(dt), dt)
+        assert (r["k_hat"], r["u"], r["f1"], r["f2"], r["n_samples"], r["stride"]) == (1, 1, 0, 0, 1024, 2)
+        assert r["tiny_miss"] == 1 and r["table_M"] == 8, r
+        assert r["spill_elems"] == 4 * 100, r          # keys 9..12 (indices 8..11), 100 each
+        assert r["path"] == "MAIN" and r["k_exact"] == 12
+    # with 64-bit keys of the same values the buckets hold four: keys 5..12 spill
+    r64 = oracle.report(x, np.uint64)
+    assert r64["spill_elems"] == 8 * 100 and r64["table_M"] == 8
