@@ -26,8 +26,13 @@
  *   - Errors are returned as cafs_status_t and never thrown.  On any error
  *     nothing has been enqueued, except CAFS_EHIP, which reports a failed
  *     launch; cafs_last_error() then holds the HIP error string.
- *   - Keys are 64-bit.  CAFS_I64 orders them as signed integers, CAFS_U64 as
- *     unsigned, CAFS_F64 as IEEE 754 doubles in totalOrder (-NaN < -inf < ...
+ *   - Keys are 64-bit, or 32-bit for CAFS_I32 and CAFS_U32 (the paper's int32
+ *     specialization, Sec. 4.2: its bucket holds eight keys, so Eq. Msize and the
+ *     spill guard use cap = 8; equality, the estimate and the hashes act on the
+ *     32-bit pattern zero-extended to 64 bits; column, output and distinct-key
+ *     arrays hold 4-byte keys, counts stay 64-bit).  CAFS_I64 and CAFS_I32 order
+ *     keys as signed integers, CAFS_U64 and CAFS_U32 as unsigned, CAFS_F64 as IEEE
+ *     754 doubles in totalOrder (-NaN < -inf < ...
  *     < -0 < +0 < ... < +inf < +NaN; NaNs by payload: the floating-point variant
  *     through the bit pattern that the paper lists as future work, Sec. Future
  *     directions); equality (used by the estimate, the counts and the guard's
@@ -60,7 +65,7 @@ typedef enum {
     CAFS_EBUSY = -6         /* server: the request does not fit the memory budget now */
 } cafs_status_t;
 
-typedef enum { CAFS_I64 = 0, CAFS_U64 = 1, CAFS_F64 = 2 } cafs_dtype_t;
+typedef enum { CAFS_I64 = 0, CAFS_U64 = 1, CAFS_F64 = 2, CAFS_I32 = 3, CAFS_U32 = 4 } cafs_dtype_t;
 
 /* Branch chosen by the dispatcher (Alg. 3), in the order it tests them. */
 typedef enum {
@@ -170,6 +175,16 @@ cafs_status_t cafs_sort_i64(cafs_ctx_t* ctx, const int64_t* d_in, int64_t* d_out
                             void* d_ws, size_t ws_bytes, void* stream);
 cafs_status_t cafs_sort_u64(cafs_ctx_t* ctx, const uint64_t* d_in, uint64_t* d_out, uint64_t n,
                             uint64_t* d_uniq, uint64_t* d_counts, cafs_report_t* d_report,
+                            void* d_ws, size_t ws_bytes, void* stream);
+/* 32-bit keys (CAFS_I32, CAFS_U32): the same call on 4-byte keys, which must be
+ * 4-byte aligned; d_uniq receives 4-byte keys, d_counts 64-bit counts; the report's
+ * table_M and spill_elems follow the paper's 32-bit bucket of eight keys.  The
+ * workspace is cafs_workspace_bytes(n) as for 64-bit keys. */
+cafs_status_t cafs_sort_i32(cafs_ctx_t* ctx, const int32_t* d_in, int32_t* d_out, uint64_t n,
+                            int32_t* d_uniq, uint64_t* d_counts, cafs_report_t* d_report,
+                            void* d_ws, size_t ws_bytes, void* stream);
+cafs_status_t cafs_sort_u32(cafs_ctx_t* ctx, const uint32_t* d_in, uint32_t* d_out, uint64_t n,
+                            uint32_t* d_uniq, uint64_t* d_counts, cafs_report_t* d_report,
                             void* d_ws, size_t ws_bytes, void* stream);
 /* Doubles in totalOrder (CAFS_F64); d_uniq receives the distinct values. */
 cafs_status_t cafs_sort_f64(cafs_ctx_t* ctx, const double* d_in, double* d_out, uint64_t n,

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libcafs.so")
 
 PATHS = ("MONOTONE", "SMALL_N", "TINY", "HIGH_K", "MAIN", "GUARD")
 ENGINES = ("NONE", "TINY", "HASH", "RADIX")
-I64, U64, F64 = 0, 1, 2
+I64, U64, F64, I32, U32 = 0, 1, 2, 3, 4
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "HIP error", -4: "unsupported", -5: "nomem",
           -6: "busy"}
 
@@ -22,7 +22,7 @@ STAGES = ("pre", "count", "order", "emit", "tail")
 
 EXPORTS = ("cafs_ctx_create", "cafs_ctx_destroy", "cafs_ctx_enable_timing", "cafs_ctx_stage_ms",
            "cafs_workspace_bytes", "cafs_estimate",
-           "cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64", "cafs_sort_noalloc", "cafs_radix_sort", "cafs_batched_workspace_bytes",
+           "cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64", "cafs_sort_i32", "cafs_sort_u32", "cafs_sort_noalloc", "cafs_radix_sort", "cafs_batched_workspace_bytes",
            "cafs_sort_batched", "cafs_ctx_set_batch_tuning", "cafs_autotune_batched", "cafs_ctx_set_hash_seed", "cafs_ctx_set_count_geometry", "cafs_ctx_get_tuning",
            "cafs_server_create", "cafs_server_destroy", "cafs_server_reserve", "cafs_server_submit",
            "cafs_server_poll", "cafs_server_release", "cafs_server_stats",
@@ -76,7 +76,7 @@ def load():
     lib.cafs_workspace_bytes.restype = ctypes.c_size_t
     lib.cafs_estimate.argtypes = [p, p, u64, i32, p, p]
     lib.cafs_estimate.restype = i32
-    for name in ("cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64"):
+    for name in ("cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64", "cafs_sort_i32", "cafs_sort_u32"):
         getattr(lib, name).argtypes = [p, p, p, u64, p, p, p, p, ctypes.c_size_t, p]
         getattr(lib, name).restype = i32
     lib.cafs_sort_noalloc.argtypes = [p, p, p, u64, i32, p, p, p, p]
@@ -126,6 +126,16 @@ def _check(rc):
         msg = lib.cafs_status_str(rc).decode()
         detail = lib.cafs_last_error().decode()
         raise CafsError("cafs error %d (%s) %s" % (rc, msg, detail))
+
+
+def _dtype_code(x, unsigned):
+    """The cafs_dtype_t of a tensor: float64, int64 (uint64 keys when `unsigned`),
+    int32 (uint32 keys when `unsigned`)."""
+    if x.dtype == torch.float64:
+        return F64
+    if x.dtype == torch.int32:
+        return U32 if unsigned else I32
+    return U64 if unsigned else I64
 
 
 def _ptr(t):
@@ -179,24 +189,24 @@ class Context:
         return self._ws
 
     def estimate(self, x, unsigned=False):
-        """Chao1 estimate of x (int64 or float64 tensor; ``unsigned`` names an int64
-        tensor holding uint64 keys) as a dict."""
+        """Chao1 estimate of x (int64, int32 or float64 tensor; ``unsigned`` names an
+        integer tensor holding unsigned keys) as a dict."""
         out = torch.zeros(ctypes.sizeof(Estimate), dtype=torch.uint8, device=self.device)
-        dt = F64 if x.dtype == torch.float64 else (U64 if unsigned else I64)
+        dt = _dtype_code(x, unsigned)
         _check(self._lib.cafs_estimate(self._h, _ptr(x), x.numel(), dt, _ptr(out), _stream(self.device)))
         e = Estimate.from_buffer_copy(bytes(out.cpu().numpy()))
         return {k: int(getattr(e, k)) for k, _ in Estimate._fields_ if k != "pad"}
 
     def sort(self, x, unsigned=False, out=None, counts=False, report=True, ws=None):
-        """Sort a 1-D int64 tensor on the GPU (uint64 order if ``unsigned``), or a
-        float64 tensor in IEEE 754 totalOrder.
+        """Sort a 1-D int64 or int32 tensor on the GPU (unsigned order if
+        ``unsigned``), or a float64 tensor in IEEE 754 totalOrder.
 
         Returns (out, report_tensor, uniq, counts); uniq/counts are None unless
         ``counts``.  Call ``parse_report`` on the report tensor after a sync.
         """
         n = x.numel()
-        if x.dtype not in (torch.int64, torch.float64) or not x.is_cuda:
-            raise CafsError("sort takes a CUDA int64 or float64 tensor")
+        if x.dtype not in (torch.int64, torch.float64, torch.int32) or not x.is_cuda:
+            raise CafsError("sort takes a CUDA int64, int32 or float64 tensor")
         if out is None:
             out = torch.empty_like(x)
         rep = torch.zeros(ctypes.sizeof(Report), dtype=torch.uint8, device=self.device) if (report or counts) else None
@@ -204,8 +214,8 @@ class Context:
         ct = torch.empty(n, dtype=torch.int64, device=x.device) if counts else None
         if ws is None:
             ws = self.workspace(self.workspace_bytes(n))
-        fn = (self._lib.cafs_sort_f64 if x.dtype == torch.float64 else
-              self._lib.cafs_sort_u64 if unsigned else self._lib.cafs_sort_i64)
+        fn = {F64: self._lib.cafs_sort_f64, U64: self._lib.cafs_sort_u64, I64: self._lib.cafs_sort_i64,
+              U32: self._lib.cafs_sort_u32, I32: self._lib.cafs_sort_i32}[_dtype_code(x, unsigned)]
         _check(fn(self._h, _ptr(x), _ptr(out), n, _ptr(uq), _ptr(ct), _ptr(rep), _ptr(ws), ws.numel(),
                   _stream(self.device)))
         return out, rep, uq, ct
@@ -216,7 +226,7 @@ class Context:
             out = torch.empty_like(x)
         if ws is None:
             ws = self.workspace(self.workspace_bytes(n))
-        dt = F64 if x.dtype == torch.float64 else U64 if unsigned else I64
+        dt = _dtype_code(x, unsigned)
         _check(self._lib.cafs_radix_sort(self._h, _ptr(x), _ptr(out), n, dt, _ptr(ws),
                                          ws.numel(), _stream(self.device)))
         return out
@@ -231,7 +241,7 @@ class Context:
             arr[i].d_in = cdesc["in"].data_ptr()
             arr[i].d_out = cdesc["out"].data_ptr()
             arr[i].n = cdesc["in"].numel()
-            arr[i].dtype = F64 if cdesc["in"].dtype == torch.float64 else U64 if cdesc.get("unsigned") else I64
+            arr[i].dtype = _dtype_code(cdesc["in"], cdesc.get("unsigned"))
             arr[i].flags = 0
             arr[i].d_uniq = cdesc["uniq"].data_ptr() if cdesc.get("uniq") is not None else None
             arr[i].d_counts = cdesc["counts"].data_ptr() if cdesc.get("counts") is not None else None

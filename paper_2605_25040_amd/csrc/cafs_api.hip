@@ -112,7 +112,7 @@ constexpr Layout make_layout(uint64_t n) {
     L.status = take(2 * L.status_slot * 8);
     L.dcount = take(L.m_ws * 4);
     L.bfound = take(L.m_ws * 4);
-    L.bmin = take(L.m_ws * 16);
+    L.bmin = take(L.m_ws * 4 * cafs::kMaxBucketCap);  // the guard rounds' minima: cap per bucket
     L.clist = take(nn * 4);
     L.first = take(nn * 4);
     L.rle_tile = take(rle_tiles * 8);
@@ -162,9 +162,9 @@ cafs_status_t scratch_address(int device, int n_devices, void** out) {
     return CAFS_OK;
 }
 
-bool overlaps(const void* a, const void* b, uint64_t n) {
+bool overlaps(const void* a, const void* b, uint64_t n, uint32_t ew) {
     const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
-    const uintptr_t bytes = n * 8;
+    const uintptr_t bytes = n * ew;
     return x != y && x < y + bytes && y < x + bytes;
 }
 
@@ -223,7 +223,11 @@ uint32_t count_grid(uint64_t n, int cus) {
     return p;
 }
 
-bool dtype_ok(cafs_dtype_t dt) { return dt == CAFS_I64 || dt == CAFS_U64 || dt == CAFS_F64; }
+bool dtype_ok(cafs_dtype_t dt) {
+    return dt == CAFS_I64 || dt == CAFS_U64 || dt == CAFS_F64 || dt == CAFS_I32 || dt == CAFS_U32;
+}
+
+uint32_t elem_bytes(cafs_dtype_t dt) { return (dt == CAFS_I32 || dt == CAFS_U32) ? 4u : 8u; }
 
 cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void* out, uint64_t n, cafs_dtype_t dt,
                      void* uniq, uint64_t* counts, cafs_report_t* report, void* ws) {
@@ -231,15 +235,21 @@ cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void*
     a.in = static_cast<const uint64_t*>(in);
     a.out = static_cast<uint64_t*>(out);
     a.n = n;
-    a.flip = (dt == CAFS_I64 || dt == CAFS_F64) ? (1ull << 63) : 0ull;
+    a.flip = (dt == CAFS_I64 || dt == CAFS_F64) ? (1ull << 63) : dt == CAFS_I32 ? (1ull << 31) : 0ull;
+    a.ew = elem_bytes(dt);
+    a.cap = a.ew == 4 ? cafs::kBucketCap32 : cafs::kBucketCap;
     a.fneg = (dt == CAFS_F64) ? ~0ull : 0ull;
-    a.in_head = (reinterpret_cast<uintptr_t>(in) % 16) ? 1u : 0u;
-    a.out_head = (reinterpret_cast<uintptr_t>(out) % 16) ? 1u : 0u;
+    // (the pair layout of 64-bit keys; 32-bit keys are accessed one by one)
+    a.in_head = (a.ew == 8 && reinterpret_cast<uintptr_t>(in) % 16) ? 1u : 0u;
+    a.out_head = (a.ew == 8 && reinterpret_cast<uintptr_t>(out) % 16) ? 1u : 0u;
     a.want_report = report != nullptr;
     a.want_counts = (uniq != nullptr) || (counts != nullptr);
     a.report = report;
     a.c = at<cafs::Ctrl>(ws, L.ctrl);
-    a.uniq = uniq ? static_cast<uint64_t*>(uniq) : at<uint64_t>(ws, L.uniq);
+    // 32-bit keys: the distinct keys are built as 64-bit values in the workspace and
+    // copied into the caller's array at the end
+    a.uniq = (uniq && a.ew == 8) ? static_cast<uint64_t*>(uniq) : at<uint64_t>(ws, L.uniq);
+    a.uniq_out = a.ew == 4 ? uniq : nullptr;
     a.cnt = counts ? counts : at<uint64_t>(ws, L.cnt);
     a.off = at<uint64_t>(ws, L.off);
     a.gkeys = at<uint64_t>(ws, L.gkeys);
@@ -271,11 +281,11 @@ cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void*
     return a;
 }
 
-cafs_status_t check_buffers(const void* in, const void* out, uint64_t n) {
+cafs_status_t check_buffers(const void* in, const void* out, uint64_t n, uint32_t ew) {
     if (n >= (1ull << 32)) return CAFS_EINVAL;
     if (n > 0 && (!in || !out)) return CAFS_EINVAL;
-    if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) % 8) return CAFS_EINVAL;
-    if (overlaps(in, out, n)) return CAFS_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) % ew) return CAFS_EINVAL;
+    if (overlaps(in, out, n, ew)) return CAFS_EINVAL;
     return CAFS_OK;
 }
 
@@ -284,7 +294,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
                         bool may_time = true) {
     if (!ctx) return CAFS_EINVAL;
     if (!dtype_ok(dt)) return CAFS_EINVAL;
-    cafs_status_t st = check_buffers(in, out, n);
+    cafs_status_t st = check_buffers(in, out, n, elem_bytes(dt));
     if (st != CAFS_OK) return st;
     if ((uniq || counts) && !report) return CAFS_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -368,7 +378,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
         cafs::k_guard_mark<<<g, 256, 0, s2>>>(a);
         cafs::k_guard_first<<<grid_for(n, cafs::kGuardChunk, cus), 256, 0, s2>>>(a);
         cafs::k_guard_resolve<<<1, 1024, 0, s2>>>(a);
-        for (uint32_t r = 0; r < 4; ++r) cafs::k_guard_round<<<g, 256, 0, s2>>>(a, r);
+        for (uint32_t r = 0; r < a.cap; ++r) cafs::k_guard_round<<<g, 256, 0, s2>>>(a, r);
         cafs::k_guard_final<<<g, 256, 0, s2>>>(a);
         // outputs written after the guard: it reads the input, which an in-place sort overwrites
         cafs::k_copy_deferred<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s2>>>(a);
@@ -378,6 +388,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     (void)hipStreamWaitEvent(s, ctx->join, 0);
     if (countable && inplace)
         cafs::k_emit_rows<<<std::min<uint32_t>(g_emit, cus), cafs::kEmitRowsThreads, 0, s>>>(a);
+    if (a.uniq_out) cafs::k_uniq_out<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s>>>(a);
     cafs::k_finalize<<<1, 64, 0, s>>>(a);
     mark(5);
     if (!evs.empty()) ctx->calls.push_back(evs);
@@ -402,6 +413,8 @@ __global__ void k_radix_setup(cafs::Args a) {
     j.has_vals = 0;
     j.n_active = 0;
     j.copy_mode = 0;
+    j.src_ew = a.ew;
+    j.dst_ew = a.ew;
 }
 
 }  // namespace
@@ -505,13 +518,13 @@ size_t cafs_workspace_bytes(uint64_t n, cafs_dtype_t dtype) {
 
 cafs_status_t cafs_estimate(cafs_ctx_t* ctx, const void* d_keys, uint64_t n, cafs_dtype_t dtype,
                             cafs_estimate_t* d_out, void* stream) {
-    if (!ctx || !d_out || (n > 0 && !d_keys) || reinterpret_cast<uintptr_t>(d_keys) % 8) return CAFS_EINVAL;
-    if (!dtype_ok(dtype)) return CAFS_EINVAL;
+    if (!ctx || !d_out || (n > 0 && !d_keys) || !dtype_ok(dtype)) return CAFS_EINVAL;
+    if (reinterpret_cast<uintptr_t>(d_keys) % elem_bytes(dtype)) return CAFS_EINVAL;
     if (n >= (1ull << 32)) return CAFS_EINVAL;
     DeviceGuard dg(ctx->device);
     (void)hipGetLastError();
     cafs::k_estimate_only<<<1, 1024, 0, static_cast<hipStream_t>(stream)>>>(static_cast<const uint64_t*>(d_keys), n,
-                                                                            d_out);
+                                                                            elem_bytes(dtype), d_out);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? CAFS_OK : hip_fail(e, "launch");
 }
@@ -531,6 +544,16 @@ cafs_status_t cafs_sort_f64(cafs_ctx_t* ctx, const double* d_in, double* d_out, 
     return sort_impl(ctx, d_in, d_out, n, CAFS_F64, d_uniq, d_counts, d_report, d_ws, ws_bytes, stream);
 }
 
+cafs_status_t cafs_sort_i32(cafs_ctx_t* ctx, const int32_t* d_in, int32_t* d_out, uint64_t n, int32_t* d_uniq,
+                            uint64_t* d_counts, cafs_report_t* d_report, void* d_ws, size_t ws_bytes, void* stream) {
+    return sort_impl(ctx, d_in, d_out, n, CAFS_I32, d_uniq, d_counts, d_report, d_ws, ws_bytes, stream);
+}
+
+cafs_status_t cafs_sort_u32(cafs_ctx_t* ctx, const uint32_t* d_in, uint32_t* d_out, uint64_t n, uint32_t* d_uniq,
+                            uint64_t* d_counts, cafs_report_t* d_report, void* d_ws, size_t ws_bytes, void* stream) {
+    return sort_impl(ctx, d_in, d_out, n, CAFS_U32, d_uniq, d_counts, d_report, d_ws, ws_bytes, stream);
+}
+
 cafs_status_t cafs_sort_noalloc(cafs_ctx_t* ctx, const void* d_in, void* d_out, uint64_t n, cafs_dtype_t dtype,
                                 void* d_uniq, uint64_t* d_counts, cafs_report_t* d_report, void* stream) {
     if (!ctx) return CAFS_EINVAL;
@@ -546,7 +569,7 @@ cafs_status_t cafs_radix_sort(cafs_ctx_t* ctx, const void* d_in, void* d_out, ui
                               void* d_ws, size_t ws_bytes, void* stream) {
     if (!ctx) return CAFS_EINVAL;
     if (!dtype_ok(dtype)) return CAFS_EINVAL;
-    cafs_status_t st = check_buffers(d_in, d_out, n);
+    cafs_status_t st = check_buffers(d_in, d_out, n, elem_bytes(dtype));
     if (st != CAFS_OK) return st;
     if (n == 0) return CAFS_OK;
     const Layout L = make_layout(n);
@@ -638,7 +661,7 @@ cafs_status_t check_columns(const cafs_column_t* cols, uint32_t n_cols, std::vec
     for (uint32_t i = 0; i < n_cols; ++i) {
         const cafs_column_t& col = cols[i];
         if (col.flags != 0 || !dtype_ok((cafs_dtype_t)col.dtype)) return CAFS_EINVAL;
-        cafs_status_t st = check_buffers(col.d_in, col.d_out, col.n);
+        cafs_status_t st = check_buffers(col.d_in, col.d_out, col.n, elem_bytes((cafs_dtype_t)col.dtype));
         if (st != CAFS_OK) return st;
         if ((col.d_uniq || col.d_counts) && !col.d_report) return CAFS_EINVAL;
         ns[i] = col.n;
@@ -695,12 +718,13 @@ cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uin
     cafs::kb_guard_mark<<<TP, 256, 0, s>>>(gp);
     cafs::kb_guard_first<<<TP, 256, 0, s>>>(gp);
     cafs::kb_guard_resolve<<<C, 1024, 0, s>>>(g1);
-    for (uint32_t r = 0; r < 4; ++r) cafs::kb_guard_round<<<TP, 256, 0, s>>>(gp, r);
+    for (uint32_t r = 0; r < cafs::kMaxBucketCap; ++r) cafs::kb_guard_round<<<TP, 256, 0, s>>>(gp, r);
     cafs::kb_guard_final<<<TP, 256, 0, s>>>(gp);
     // outputs written after the guard: it reads the input, which an in-place sort overwrites
     cafs::kb_copy_deferred<<<TP, 256, 0, s>>>(gp);
     cafs::kb_emit<<<TP, cafs::kEmitThreads, 0, s>>>(gp, 1u);
     cafs::kb_emit<<<TP, cafs::kEmitThreads, 0, s>>>(gp, 0u);
+    cafs::kb_uniq_out<<<TP, 256, 0, s>>>(gp);
     cafs::kb_finalize<<<C, 64, 0, s>>>(g1);
     e = hipGetLastError();
     return e == hipSuccess ? CAFS_OK : hip_fail(e, "launch");
@@ -1022,8 +1046,9 @@ void cafs_server_destroy(cafs_server_t* sv) {
 cafs_status_t cafs_server_reserve(cafs_server_t* sv, uint64_t n, int32_t dtype, uint64_t* h_ticket, void** h_d_in,
                                   void** h_d_out, cafs_report_t** h_d_report) {
     if (!sv || !h_ticket || n >= (1ull << 32) || !dtype_ok((cafs_dtype_t)dtype)) return CAFS_EINVAL;
+    const uint64_t eb = elem_bytes((cafs_dtype_t)dtype);
     const bool bufs = h_d_in && h_d_out && h_d_report;
-    const size_t data = bufs ? 2 * align_up(n * 8) + align_up(sizeof(cafs_report_t)) : 0;
+    const size_t data = bufs ? 2 * align_up(n * eb) + align_up(sizeof(cafs_report_t)) : 0;
     const size_t bytes = data + align_up(make_layout(n).total);
     size_t off = 0;
     if (!arena_alloc(sv, bytes, &off)) {
@@ -1040,8 +1065,8 @@ cafs_status_t cafs_server_reserve(cafs_server_t* sv, uint64_t n, int32_t dtype, 
     r.col.dtype = dtype;
     if (bufs) {
         r.col.d_in = base;
-        r.col.d_out = base + align_up(n * 8);
-        r.col.d_report = reinterpret_cast<cafs_report_t*>(base + 2 * align_up(n * 8));
+        r.col.d_out = base + align_up(n * eb);
+        r.col.d_report = reinterpret_cast<cafs_report_t*>(base + 2 * align_up(n * eb));
         *h_d_in = const_cast<void*>(r.col.d_in);
         *h_d_out = r.col.d_out;
         *h_d_report = r.col.d_report;
@@ -1060,7 +1085,7 @@ cafs_status_t cafs_server_submit(cafs_server_t* sv, uint64_t ticket, const cafs_
     cafs_server::Req& r = it->second;
     if (col) {
         if (col->n != r.n || col->dtype != r.dtype || col->flags != 0) return CAFS_EINVAL;
-        cafs_status_t st = check_buffers(col->d_in, col->d_out, col->n);
+        cafs_status_t st = check_buffers(col->d_in, col->d_out, col->n, elem_bytes((cafs_dtype_t)col->dtype));
         if (st != CAFS_OK) return st;
         if ((col->d_uniq || col->d_counts) && !col->d_report) return CAFS_EINVAL;
         r.col = *col;

@@ -21,6 +21,8 @@ constexpr uint64_t kSmallN = 2048;             // Table dispatcher: N < 2048 -> 
 constexpr uint64_t kTinyK = 8;                 // Table dispatcher: K^ <= 8 and u <= 8
 constexpr uint64_t kPhi = 0x9E3779B97F4A7C15ull;  // Eq. hash multiplier
 constexpr uint32_t kBucketCap = 4;             // keys per 64-bit bucket (Sec. 4.2)
+constexpr uint32_t kBucketCap32 = 8;           // keys per 32-bit bucket (Sec. 4.2)
+constexpr uint32_t kMaxBucketCap = 8;
 
 // ---- GPU design constants (not from the paper) ----------------------------
 constexpr uint64_t kEmpty = ~0ull;             // empty-slot marker of the GPU hash tables;
@@ -94,6 +96,8 @@ struct RadixJob {
     uint64_t* pd_k[8];                // destination of active pass i
     uint64_t* pd_v[8];
     uint32_t copy_mode;               // after the passes: 0 nothing, 1 copy src->dst, 2 tmp->dst
+    uint32_t src_ew, dst_ew;          // element bytes of src and dst (tmp always holds 8-byte keys)
+    uint32_t ps_w[8], pd_w[8];        // element bytes of each active pass's source and destination
 };
 
 // Decisions and counters of one call, in device memory (workspace).
@@ -133,6 +137,7 @@ struct Ctrl {
     // where the sorted column is when the radix engine ran (the output, or scratch
     // when sorting in place on the main path, copied out after the guard)
     uint64_t* sorted;
+    uint32_t sorted_ew;               // element bytes of `sorted`
     uint32_t deferred_copy;
     uint32_t pad0;
     // dense (key, count) arrays
@@ -170,8 +175,11 @@ struct Args {
     const uint64_t* in;
     uint64_t* out;
     uint64_t n;
-    uint64_t flip;                    // 1<<63 for int64 and float64, 0 for uint64
+    uint64_t flip;                    // 1<<63 for int64 and float64, 1<<31 for int32, 0 for unsigned
     uint64_t fneg;                    // all ones for float64, 0 otherwise (see okey)
+    uint32_t ew;                      // element bytes of the column: 8, or 4 for 32-bit keys
+    uint32_t cap;                     // keys per bucket of the paper's table (4, or 8 for 32-bit keys)
+    void* uniq_out;                   // 32-bit keys: the caller's distinct-key array (uniq is internal)
     uint32_t in_head;                 // 1 if in is 8- but not 16-byte aligned
     uint32_t out_head;
     uint32_t want_report;
@@ -271,8 +279,19 @@ __device__ __forceinline__ T g_load(const T* p) {
     return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Element i of a column of `ew`-byte keys, as the 64-bit value the kernels work on
+// (a 32-bit key zero-extended), and the converse store.
+__device__ __forceinline__ uint64_t load_key(const uint64_t* p, uint64_t i, uint32_t ew) {
+    return ew == 4 ? (uint64_t)gp(reinterpret_cast<const uint32_t*>(p))[i] : gp(p)[i];
+}
+__device__ __forceinline__ void store_key(uint64_t* p, uint64_t i, uint64_t v, uint32_t ew) {
+    if (ew == 4) gp(reinterpret_cast<uint32_t*>(p))[i] = (uint32_t)v;
+    else gp(p)[i] = v;
+}
+
 // Order key: the unsigned integer whose order is the column's order.  int64: bit 63
-// flipped; uint64: the bits themselves; float64 in IEEE 754 totalOrder (-NaN <
+// flipped; int32 (zero-extended): bit 31 flipped; uint64 and uint32: the bits
+// themselves; float64 in IEEE 754 totalOrder (-NaN <
 // -inf < ... < -0 < +0 < ... < +inf < +NaN): bit 63 flipped for a clear sign bit,
 // every bit flipped for a set one.  Equality stays on the raw bits.
 __device__ __forceinline__ uint64_t okey(uint64_t x, uint64_t flip, uint64_t fneg) {

@@ -55,6 +55,39 @@ __device__ __forceinline__ void phase2_body(const Args& a, uint32_t bid, uint32_
 #pragma unroll
     for (int j = 1; j < 8; ++j) key[j] = j < (int)nk ? key[j] : key[0];
     uint32_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // per lane: a lane sees < 2^32 elements
+    const uint32_t lane = __lane_id();
+    if (a.ew == 4) {
+        // 32-bit keys: each wave reads 64 * 16 consecutive keys per batch, one 4-byte
+        // load per lane and key (coalesced), the next batch's loads in flight
+        constexpr int UE = 16;
+        const CAFS_GLOBAL uint32_t* in32 = gp(reinterpret_cast<const uint32_t*>(a.in));
+        const uint64_t n = a.n;
+        const uint64_t step = gstride / 64 * 64 * UE;
+        uint64_t eb = gtid / 64 * 64 * UE;
+        uint32_t v32[UE];
+        auto load32 = [&](uint64_t b) {
+#pragma unroll
+            for (int u = 0; u < UE; ++u) {
+                const uint64_t e = b + (uint64_t)u * 64 + lane;
+                v32[u] = e < n ? in32[e] : 0u;
+            }
+        };
+        if (eb < n) load32(eb);
+        while (eb < n) {
+            uint32_t x32[UE];
+#pragma unroll
+            for (int u = 0; u < UE; ++u) x32[u] = v32[u];
+            const uint64_t cur = eb;
+            eb += step;
+            if (eb < n) load32(eb);
+#pragma unroll
+            for (int u = 0; u < UE; ++u) {
+                const bool ok = cur + (uint64_t)u * 64 + lane < n;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) cnt[j] += (ok && (uint64_t)x32[u] == key[j]) ? 1u : 0u;
+            }
+        }
+    } else {
     const uint32_t head = a.in_head;
     const uint64_t P = num_pairs(a.n, head);
     const uint64_t Pf = (a.n + head) / 2;
@@ -62,7 +95,6 @@ __device__ __forceinline__ void phase2_body(const Args& a, uint32_t bid, uint32_
     const uint64_t waves_total = gstride / 64;
     const uint64_t wave_id = gtid / 64;
     const uint64_t step = waves_total * 64 * U;
-    const uint32_t lane = __lane_id();
     const CAFS_GLOBAL uint64_t* in = gp(a.in);
     uint64_t v[2 * U];
     uint32_t okm = 0;
@@ -110,6 +142,7 @@ __device__ __forceinline__ void phase2_body(const Args& a, uint32_t bid, uint32_
                 for (int j = 0; j < 8; ++j) cnt[j] += (((m >> e) & 1u) && x[e] == key[j]) ? 1u : 0u;
         }
     }
+    }
     // one device-scope update per key and workgroup (per wave, thousands of them
     // queued on the same lines)
     __shared__ uint32_t s_cnt[8];
@@ -133,8 +166,10 @@ __device__ __noinline__ void set_overflow(Ctrl* c, uint32_t inplace, uint64_t* t
     if (atomicExch(&c->overflow, 1u) == 0) {
         if (inplace) {
             c->rj.dst_k = tmp_k;
+            c->rj.dst_ew = 8;
             c->rj.tmp_k = uniq;
             c->sorted = tmp_k;
+            c->sorted_ew = 8;
             c->deferred_copy = 1;
         }
         atomicExch(&c->radix_on, 1u);
@@ -626,7 +661,6 @@ __device__ __forceinline__ void part_scatter_body(const Args& a, uint32_t bid, u
     const uint64_t mul = a.table_mul;
     const GTable t = gtable(a);
     const uint64_t n = a.n;
-    const CAFS_GLOBAL uint64_t* in = gp(a.in);
     CAFS_GLOBAL uint64_t* pbuf = gp(a.pbuf);
     __shared__ uint64_t stage[kScatterChunk];
     __shared__ uint32_t lcnt[kMaxParts];
@@ -645,7 +679,7 @@ __device__ __forceinline__ void part_scatter_body(const Args& a, uint32_t bid, u
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t i = base + (uint64_t)u * kScatterThreads + tid;
-            x[u] = i < n ? in[i] : 0;
+            x[u] = i < n ? load_key(a.in, i, a.ew) : 0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -689,22 +723,22 @@ __device__ __forceinline__ void part_scatter_body(const Args& a, uint32_t bid, u
 }
 CAFS_KERNELS0(part_scatter, kScatterThreads)
 
-template <uint32_t W>
+template <uint32_t W, uint32_t EW>
 __device__ __forceinline__ void count_range(const Args& a, const GTable& t, uint64_t* skeys, uint32_t* scnt,
                                             uint32_t& s_ndef, uint32_t* s_sink, uint32_t* s_flag,
                                             const uint64_t* src, uint64_t n, uint32_t head, uint64_t p_begin,
                                             uint64_t p_end, uint32_t pl, CAFS_GLOBAL uint64_t* region,
                                             uint32_t region_cap);
 
-template <uint32_t W, bool PARTS>
+template <uint32_t W, bool PARTS, uint32_t EW>
 __device__ __forceinline__ void count_items(const Args& a, uint32_t bid, uint32_t nblk, uint64_t* skeys, uint32_t* scnt,
                                             uint32_t& s_ndef, uint32_t& s_flag, uint32_t* s_sink);
 
-// Two instances: the count without partitions (PARTS false: the partition bits are
-// the constant 0 in its hot loop) and the count over partition buckets, chosen once
-// at the top of the kernel.  The first also resolves the tiny branch (a tiny plan
-// has no partitions).
-template <bool PARTS>
+// Instances chosen once at the top of the kernel: the count without partitions
+// (PARTS false: the partition bits are the constant 0 in its hot loop) over a column
+// of EW-byte keys, and the count over the partition buckets (which hold 64-bit
+// keys).  The first also resolves the tiny branch (a tiny plan has no partitions).
+template <bool PARTS, uint32_t EW>
 __device__ __forceinline__ void hash_count_impl(const Args& a, uint32_t bid, uint32_t nblk, uint64_t* skeys,
                                                 uint32_t* scnt, uint32_t& s_ndef, uint32_t& s_flag, uint32_t* s_sink) {
     Ctrl* c = a.c;
@@ -738,8 +772,8 @@ __device__ __forceinline__ void hash_count_impl(const Args& a, uint32_t bid, uin
         return;
     }
 
-    if (c->lds_wide) count_items<4, PARTS>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
-    else count_items<2, PARTS>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
+    if (c->lds_wide) count_items<4, PARTS, EW>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
+    else count_items<2, PARTS, EW>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
 }
 __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uint32_t nblk) {
     __shared__ __attribute__((aligned(16))) uint64_t skeys[kLdsSlots];
@@ -747,12 +781,13 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
     __shared__ uint32_t s_ndef;
     __shared__ uint32_t s_flag;
     __shared__ uint32_t s_sink[64];  // target of the atomics of lanes without a hit
-    if (a.c->part_log2) hash_count_impl<true>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
-    else hash_count_impl<false>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
+    if (a.c->part_log2) hash_count_impl<true, 8>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
+    else if (a.ew == 4) hash_count_impl<false, 4>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
+    else hash_count_impl<false, 8>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
 }
 
 // This workgroup's work items (count_item_total) with LDS buckets of W keys.
-template <uint32_t W, bool PARTS>
+template <uint32_t W, bool PARTS, uint32_t EW>
 __device__ __forceinline__ void count_items(const Args& a, uint32_t bid, uint32_t nblk, uint64_t* skeys, uint32_t* scnt,
                                             uint32_t& s_ndef, uint32_t& s_flag, uint32_t* s_sink) {
     Ctrl* c = a.c;
@@ -765,7 +800,16 @@ __device__ __forceinline__ void count_items(const Args& a, uint32_t bid, uint32_
         const uint64_t* src;
         uint64_t ns, pb, pe, roff;  // roff: where the item's deferral region starts in tmp_k
         uint32_t head;
-        if (!PARTS) {
+        if (!PARTS && EW == 4) {
+            // ranges of elements (32-bit keys are loaded one per lane)
+            src = a.in;
+            ns = n;
+            head = 0;
+            const uint64_t ES = (n + nblk - 1) / nblk;
+            pb = (uint64_t)it * ES < n ? (uint64_t)it * ES : n;
+            pe = pb + ES < n ? pb + ES : n;
+            roff = pb;
+        } else if (!PARTS) {
             src = a.in;
             ns = n;
             head = a.in_head;
@@ -788,23 +832,24 @@ __device__ __forceinline__ void count_items(const Args& a, uint32_t bid, uint32_
         // the region holds every element of the item (tmp_k covers the column and
         // every bucket), so a deferral always finds room
         CAFS_GLOBAL uint64_t* region = gp(a.tmp_k) + roff;
-        const uint32_t region_cap = (uint32_t)(2 * (pe - pb));
+        const uint32_t region_cap = (uint32_t)((EW == 4 ? 1 : 2) * (pe - pb));
         for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
             skeys[i] = kEmpty;
             scnt[i] = 0;
         }
         if (threadIdx.x == 0) s_ndef = 0;
         __syncthreads();
-        count_range<W>(a, t, skeys, scnt, s_ndef, s_sink, &s_flag, src, ns, head, pb, pe, pl, region, region_cap);
+        count_range<W, EW>(a, t, skeys, scnt, s_ndef, s_sink, &s_flag, src, ns, head, pb, pe, pl, region, region_cap);
         __syncthreads();
     }
 }
 
 // The count over pairs [p_begin, p_end) of src[0..n) (head: src is 8- but not
-// 16-byte aligned) with buckets of W keys (the LDS table is cleared): the first pass
-// with its deferrals, the flush, the second pass over the deferred elements and its
-// flush.  Called by every thread of the workgroup.
-template <uint32_t W>
+// 16-byte aligned), or for EW = 4 (32-bit keys) over elements [p_begin, p_end),
+// with buckets of W keys (the LDS table is cleared): the first pass with its
+// deferrals, the flush, the second pass over the deferred elements and its flush.
+// Called by every thread of the workgroup.
+template <uint32_t W, uint32_t EW>
 __device__ __forceinline__ void count_range(const Args& a, const GTable& t, uint64_t* skeys, uint32_t* scnt,
                                             uint32_t& s_ndef, uint32_t* s_sink, uint32_t* s_flag,
                                             const uint64_t* src_, uint64_t n, uint32_t head, uint64_t p_begin,
@@ -820,11 +865,24 @@ __device__ __forceinline__ void count_range(const Args& a, const GTable& t, uint
     const uint64_t p_full = p_end < Pf ? p_end : Pf;
     constexpr int U = 4;                 // pairs per thread per step
     constexpr int NE = 2 * U;
-    const uint64_t span = (uint64_t)blockDim.x * U;
+    const uint64_t span = (uint64_t)blockDim.x * (EW == 4 ? NE : U);  // elements for EW = 4, pairs otherwise
     uint64_t base = p_begin;
     uint64_t v[NE];
     uint32_t okm = 0;  // bit e: element e of the batch is in range
     auto load = [&](uint64_t b) {
+        if constexpr (EW == 4) {
+            // 32-bit keys: element b + u * blockDim + thread, zero-extended
+            const CAFS_GLOBAL uint32_t* in32 = reinterpret_cast<const CAFS_GLOBAL uint32_t*>(in);
+            okm = 0;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const uint64_t i = b + (uint64_t)e * blockDim.x + threadIdx.x;
+                const bool o = i < p_end;
+                v[e] = o ? (uint64_t)in32[i] : 0;
+                okm |= (o ? 1u : 0u) << e;
+            }
+            return;
+        }
         if (b >= head && b + span <= p_full) {
             // interior batch: every pair is two aligned in-range elements
             const CAFS_GLOBAL u64x2* src = reinterpret_cast<const CAFS_GLOBAL u64x2*>(in + 2 * (b + threadIdx.x) - head);
@@ -871,7 +929,8 @@ __device__ __forceinline__ void count_range(const Args& a, const GTable& t, uint
             want &= is_empty_key ? ~(1u << e) : ~0u;
         }
         uint32_t add[NE];
-        const bool rle = run_lengths<NE>(x, want, add);
+        // (run detection follows the pair layout of 64-bit keys)
+        const bool rle = EW == 8 && run_lengths<NE>(x, want, add);
         if (rle) {
             // merged elements are counted by their run's head
 #pragma unroll
@@ -1002,6 +1061,7 @@ __device__ __forceinline__ void gather_pairs(const Args& a, Ctrl* c, uint32_t cl
         j.tmp_k = a.gkeys; j.tmp_v = a.gcnt;
         j.n = K;
         j.has_vals = 1;
+        j.src_ew = 8; j.dst_ew = 8;
         c->fold_k = a.uniq;
         c->fold_v = a.cnt;
         c->pair_sort = 1;
@@ -1033,6 +1093,7 @@ __device__ __forceinline__ void gather_spill(const Args& a, Ctrl* c, uint32_t cl
         j.tmp_k = a.tmp_k; j.tmp_v = a.off;  // (the offsets are written by the fold, after the sort)
         j.n = nspill + claimed + (ecount ? 1u : 0u);
         j.has_vals = 1;
+        j.src_ew = 8; j.dst_ew = 8;
         c->fold_k = a.spill_k;
         c->fold_v = a.spill_v;
         c->pair_sort = 1;
@@ -1085,8 +1146,9 @@ __device__ __forceinline__ void offsets_and_guard_check(const Args& a, Ctrl* c, 
     for (uint32_t i = tid; i < K; i += blockDim.x) atomicAdd(&bc[phi_hash32(uq[i], lg)], 1u);
     __syncthreads();
     uint32_t over = 0, over_b = 0;
-    for (uint32_t i = tid; i < K; i += blockDim.x) over += bc[phi_hash32(uq[i], lg)] > kBucketCap;
-    for (uint32_t i = tid; i < M; i += blockDim.x) over_b += bc[i] > kBucketCap;
+    const uint32_t cap = a.cap;
+    for (uint32_t i = tid; i < K; i += blockDim.x) over += bc[phi_hash32(uq[i], lg)] > cap;
+    for (uint32_t i = tid; i < M; i += blockDim.x) over_b += bc[i] > cap;
     over = wave_sum_u32(over);
     over_b = wave_sum_u32(over_b);
     if (__lane_id() == 0 && over) atomicAdd(&s_nc, over);
@@ -1102,7 +1164,7 @@ __device__ __forceinline__ void offsets_and_guard_check(const Args& a, Ctrl* c, 
     if (tid == 0) s_nc = 0;
     __syncthreads();
     for (uint32_t i = tid; i < K; i += blockDim.x)
-        if (bc[phi_hash32(uq[i], lg)] > kBucketCap) a.clist[atomicAdd(&s_nc, 1u)] = i;
+        if (bc[phi_hash32(uq[i], lg)] > cap) a.clist[atomicAdd(&s_nc, 1u)] = i;
     if (tid == 0) {
         c->n_contested = nc;
         c->n_cbuckets = s_nb;

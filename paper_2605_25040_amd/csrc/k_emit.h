@@ -96,6 +96,45 @@ __device__ __forceinline__ void emit_tiles(const Args& a, uint32_t bid, uint32_t
         __syncthreads();
     }
 }
+// The tile emit for 32-bit keys: the same tiles counted in elements (4096 per
+// tile), each element stored as 4 bytes (a wave writes 256 consecutive bytes per
+// store instruction).
+__device__ __forceinline__ void emit_tiles32(const Args& a, uint32_t bid, uint32_t nblk, uint64_t* s_off,
+                                             uint64_t* s_key, uint64_t* s_j) {
+    Ctrl* c = a.c;
+    const uint64_t n = a.n;
+    const uint64_t K = c->K;
+    constexpr uint64_t T = 2 * kEmitTilePairs;
+    const uint64_t tiles = (n + T - 1) / T;
+    const uint64_t* __restrict__ off = a.off;
+    const uint64_t* __restrict__ uq = a.uniq;
+    CAFS_GLOBAL uint32_t* y = gp(reinterpret_cast<uint32_t*>(a.out));
+    for (uint64_t t = bid; t < tiles; t += nblk) {
+        const uint64_t e_lo = t * T;
+        const uint64_t e_hi = e_lo + T < n ? e_lo + T : n;  // exclusive
+        if (threadIdx.x == 0) {
+            const uint64_t j0 = run_of(off, 0, K - 1, e_lo);
+            s_j[0] = j0;
+            s_j[1] = run_of(off, j0, K - 1, e_hi - 1);
+        }
+        __syncthreads();
+        const uint64_t j0 = s_j[0], j1 = s_j[1];
+        if (j0 == j1) {
+            const uint32_t v = (uint32_t)uq[j0];
+            for (uint64_t e = e_lo + threadIdx.x; e < e_hi; e += blockDim.x) y[e] = v;
+        } else if (j1 - j0 + 1 <= kEmitLdsRuns) {
+            const uint32_t R = (uint32_t)(j1 - j0 + 1);
+            for (uint32_t i = threadIdx.x; i <= R; i += blockDim.x) s_off[i] = off[j0 + i];
+            for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) s_key[i] = uq[j0 + i];
+            __syncthreads();
+            for (uint64_t e = e_lo + threadIdx.x; e < e_hi; e += blockDim.x) y[e] = (uint32_t)s_key[run_of(s_off, 0, R - 1, e)];
+        } else {
+            for (uint64_t e = e_lo + threadIdx.x; e < e_hi; e += blockDim.x) y[e] = (uint32_t)uq[run_of(off, j0, j1, e)];
+        }
+        __syncthreads();
+    }
+}
+
 // `mode`: 0 main instance (batched launches, which have no row emit), 1 after the
 // pair sort.
 __device__ __forceinline__ void emit_body(const Args& a, uint32_t mode, uint32_t bid, uint32_t nblk) {
@@ -104,7 +143,8 @@ __device__ __forceinline__ void emit_body(const Args& a, uint32_t mode, uint32_t
     __shared__ uint64_t s_j[2];
     __shared__ uint64_t s_off[kEmitLdsRuns + 1];
     __shared__ uint64_t s_key[kEmitLdsRuns];
-    emit_tiles(a, bid, nblk, s_off, s_key, s_j);
+    if (a.ew == 4) emit_tiles32(a, bid, nblk, s_off, s_key, s_j);
+    else emit_tiles(a, bid, nblk, s_off, s_key, s_j);
 }
 CAFS_KERNELS1(emit, kEmitThreads, uint32_t, mode)
 
@@ -168,6 +208,14 @@ __device__ __forceinline__ bool rows_take(const Args& a, const Ctrl* c) {
 __device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!c->emit_main) return;
+    if (a.ew == 4) {
+        // 32-bit keys: the element tile emit over this launch's workgroups
+        __shared__ uint64_t t_j[2];
+        __shared__ uint64_t t_off[kEmitLdsRuns + 1];
+        __shared__ uint64_t t_key[kEmitLdsRuns];
+        emit_tiles32(a, bid, nblk, t_off, t_key, t_j);
+        return;
+    }
     const uint64_t n = a.n;
     const uint64_t K64 = c->K;
     __shared__ uint32_t soff[kEmitRowsMaxK + 1];
@@ -373,7 +421,7 @@ __device__ __forceinline__ void copy_mono_body(const Args& a, uint32_t bid, uint
     if (c->path != P_MONOTONE || a.in == a.out) return;
     const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
     const uint64_t gstride = (uint64_t)nblk * blockDim.x;
-    for (uint64_t i = gtid; i < a.n; i += gstride) a.out[i] = a.in[i];
+    for (uint64_t i = gtid; i < a.n; i += gstride) store_key(a.out, i, load_key(a.in, i, a.ew), a.ew);
 }
 CAFS_KERNELS0(copy_mono, 256)
 
@@ -390,7 +438,8 @@ __device__ __forceinline__ void rle_count_body(const Args& a, uint32_t bid, uint
     Ctrl* c = a.c;
     if (!rle_needed(a, c)) return;
     const uint64_t n = a.n;
-    const CAFS_GLOBAL uint64_t* __restrict__ y = gp(c->sorted);
+    const uint64_t* y = c->sorted;
+    const uint32_t yw = c->sorted_ew;
     const uint64_t tiles = (n + kRleTile - 1) / kRleTile;
     __shared__ uint32_t s_cnt;
     __shared__ uint32_t s_last;
@@ -401,7 +450,8 @@ __device__ __forceinline__ void rle_count_body(const Args& a, uint32_t bid, uint
         const uint64_t b = t * kRleTile;
         const uint64_t e = (b + kRleTile < n) ? b + kRleTile : n;
         uint32_t local = 0;
-        for (uint64_t i = b + threadIdx.x; i < e; i += blockDim.x) local += (i == 0) || (y[i] != y[i - 1]);
+        for (uint64_t i = b + threadIdx.x; i < e; i += blockDim.x)
+            local += (i == 0) || (load_key(y, i, yw) != load_key(y, i - 1, yw));
         local = wave_sum_u32(local);
         if (__lane_id() == 0) atomicAdd(&s_cnt, local);
         __syncthreads();
@@ -453,7 +503,8 @@ __device__ __forceinline__ void rle_write_body(const Args& a, uint32_t bid, uint
     Ctrl* c = a.c;
     if (!rle_needed(a, c)) return;
     const uint64_t n = a.n;
-    const CAFS_GLOBAL uint64_t* __restrict__ y = gp(c->sorted);
+    const uint64_t* y = c->sorted;
+    const uint32_t yw = c->sorted_ew;
     CAFS_GLOBAL uint64_t* __restrict__ uq = gp(a.uniq);
     CAFS_GLOBAL uint64_t* __restrict__ off = gp(a.off);
     const uint64_t tiles = (n + kRleTile - 1) / kRleTile;
@@ -464,8 +515,8 @@ __device__ __forceinline__ void rle_write_body(const Args& a, uint32_t bid, uint
     for (uint64_t t = bid; t < tiles; t += nblk) {
         const uint64_t b = t * kRleTile;
         const uint32_t cnt = (uint32_t)(n - b < kRleTile ? n - b : kRleTile);
-        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) sy[i + 1] = y[b + i];
-        if (threadIdx.x == 0) sy[0] = b > 0 ? y[b - 1] : ~y[0];  // element 0 always starts a run
+        for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) sy[i + 1] = load_key(y, b + i, yw);
+        if (threadIdx.x == 0) sy[0] = b > 0 ? load_key(y, b - 1, yw) : ~load_key(y, 0, yw);  // element 0 starts a run
         __syncthreads();
         const uint32_t l0 = threadIdx.x * per;
         uint32_t flags = 0;
@@ -519,10 +570,23 @@ __device__ __forceinline__ void copy_deferred_body(const Args& a, uint32_t bid, 
     const Ctrl* c = a.c;
     if (!c->deferred_copy) return;
     const uint64_t* src = c->sorted;
+    const uint32_t sw = c->sorted_ew;
     const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
     const uint64_t gstride = (uint64_t)nblk * blockDim.x;
-    for (uint64_t i = gtid; i < a.n; i += gstride) a.out[i] = src[i];
+    for (uint64_t i = gtid; i < a.n; i += gstride) store_key(a.out, i, load_key(src, i, sw), a.ew);
 }
 CAFS_KERNELS0(copy_deferred, 256)
+
+// 32-bit keys: the distinct keys, kept as 64-bit values in the workspace, into the
+// caller's 32-bit array.
+__device__ __forceinline__ void uniq_out_body(const Args& a, uint32_t bid, uint32_t nblk) {
+    if (a.ew != 4 || !a.uniq_out) return;
+    const uint64_t K = a.c->K;
+    const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
+    const uint64_t gstride = (uint64_t)nblk * blockDim.x;
+    CAFS_GLOBAL uint32_t* dst = gp(static_cast<uint32_t*>(a.uniq_out));
+    for (uint64_t j = gtid; j < K; j += gstride) dst[j] = (uint32_t)gp(a.uniq)[j];
+}
+CAFS_KERNELS0(uniq_out, 256)
 
 }  // namespace cafs

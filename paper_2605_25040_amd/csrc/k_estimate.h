@@ -20,11 +20,12 @@ struct Chao1Result {
     uint64_t small[8];
 };
 
-// Sample threadIdx.x of the column (0 when there is none): element tid * stride.
-__device__ __forceinline__ uint64_t chao1_sample(const uint64_t* x, uint64_t n) {
+// Sample threadIdx.x of the column of `ew`-byte keys (0 when there is none):
+// element tid * stride.
+__device__ __forceinline__ uint64_t chao1_sample(const uint64_t* x, uint64_t n, uint32_t ew) {
     const uint64_t stride = n / kSamples > 1 ? n / kSamples : 1;
     const uint64_t ns = n < kSamples ? n : kSamples;
-    return threadIdx.x < ns ? gp(x)[threadIdx.x * stride] : 0;
+    return threadIdx.x < ns ? load_key(x, threadIdx.x * stride, ew) : 0;
 }
 
 __device__ void chao1_block(uint64_t v_mine, uint64_t n, uint64_t flip, uint64_t fneg, Chao1Result* res) {
@@ -106,10 +107,11 @@ __device__ void chao1_block(uint64_t v_mine, uint64_t n, uint64_t flip, uint64_t
     }
 }
 
-// Eq. Msize with cap = 4: M = bit_ceil(8 K^ / 4) clamped to [8, bit_ceil(N / 4)].
-__device__ __forceinline__ uint64_t paper_table_M(uint64_t k_hat, uint64_t n) {
-    uint64_t m = bit_ceil64(8 * k_hat / kBucketCap);
-    const uint64_t hi = bit_ceil64(n / kBucketCap);
+// Eq. Msize: M = bit_ceil(8 K^ / cap) clamped to [8, bit_ceil(N / cap)], cap = 4 for
+// 64-bit keys and 8 for 32-bit keys.
+__device__ __forceinline__ uint64_t paper_table_M(uint64_t k_hat, uint64_t n, uint32_t cap) {
+    uint64_t m = bit_ceil64(8 * k_hat / cap);
+    const uint64_t hi = bit_ceil64(n / cap);
     if (m > hi) m = hi;
     if (m < 8) m = 8;
     return m;
@@ -139,7 +141,7 @@ __device__ void plan_block(const Args& a) {
     c->lds_wide = 0;
     if (path == P_TINY || path == P_MAIN) {
         const uint64_t kh = c->k_hat;
-        c->table_M = paper_table_M(kh, n);
+        c->table_M = paper_table_M(kh, n, a.cap);
         // the hash count: partitions of about part_keys estimated keys each (at most
         // 2^kMaxPartLog2), LDS buckets of 4 keys when a partition's share of the
         // estimate reaches wide_min
@@ -210,14 +212,19 @@ __device__ void plan_block(const Args& a) {
     j.has_vals = 0;
     j.n_active = 0;
     j.copy_mode = 0;
+    j.src_ew = a.ew;
+    j.dst_ew = a.ew;
     c->sorted = a.out;
+    c->sorted_ew = a.ew;
     c->deferred_copy = 0;
     if (path == P_MAIN && engine == E_RADIX && a.in == a.out) {
         // in place on the main path: the guard still reads the input after the sort,
         // so sort into scratch (ping-pong with the dense key array, written later)
         j.dst_k = a.tmp_k;
+        j.dst_ew = 8;
         j.tmp_k = a.uniq;
         c->sorted = a.tmp_k;
+        c->sorted_ew = 8;
         c->deferred_copy = 1;
     }
 }
@@ -229,18 +236,17 @@ __device__ __forceinline__ void pre_body(const Args& a, uint32_t bid, uint32_t n
     __shared__ Chao1Result s_res;
     // the sample and the order-check prefix are loaded together, so that their
     // latencies overlap
-    const uint64_t v_sample = chao1_sample(a.in, a.n);
+    const uint64_t v_sample = chao1_sample(a.in, a.n, a.ew);
     if (threadIdx.x == 0) s_inv = 0;
     __syncthreads();
     const uint64_t lim = a.n < kMonoPrefix ? a.n : kMonoPrefix;
-    const CAFS_GLOBAL uint64_t* in = gp(a.in);
     uint32_t inv = 0;
     constexpr uint32_t kPer = kMonoPrefix / 1024;  // elements per thread (blockDim.x = 1024)
     uint64_t pv[kPer + 1];
 #pragma unroll
     for (uint32_t k = 0; k <= kPer; ++k) {
         const uint64_t i = (uint64_t)threadIdx.x * kPer + k;
-        pv[k] = i < lim ? okey(in[i], a.flip, a.fneg) : 0;
+        pv[k] = i < lim ? okey(load_key(a.in, i, a.ew), a.flip, a.fneg) : 0;
     }
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
@@ -267,11 +273,11 @@ __device__ __forceinline__ void pre_body(const Args& a, uint32_t bid, uint32_t n
 }
 CAFS_KERNELS0(pre, 1024)
 
-// Standalone estimate (cafs_estimate).
-__global__ __launch_bounds__(1024) void k_estimate_only(const uint64_t* x, uint64_t n,
+// Standalone estimate (cafs_estimate) of a column of `ew`-byte keys.
+__global__ __launch_bounds__(1024) void k_estimate_only(const uint64_t* x, uint64_t n, uint32_t ew,
                                                         cafs_estimate_t* out) {
     __shared__ Chao1Result s_res;
-    chao1_block(chao1_sample(x, n), n, 0, 0, &s_res);
+    chao1_block(chao1_sample(x, n, ew), n, 0, 0, &s_res);
     if (threadIdx.x == 0) {
         cafs_estimate_t e;
         e.k_hat = s_res.k_hat; e.u = s_res.u; e.f1 = s_res.f1; e.f2 = s_res.f2;
@@ -296,7 +302,7 @@ __device__ __forceinline__ void mono_full_body(const Args& a, uint32_t bid, uint
         uint32_t inv = 0;
         const uint64_t end = (base + chunk < n - 1) ? base + chunk : n - 1;  // pairs (i, i+1), i < end
         for (uint64_t i = base + threadIdx.x; i < end; i += 256)
-            inv |= okey(a.in[i], a.flip, a.fneg) > okey(a.in[i + 1], a.flip, a.fneg);
+            inv |= okey(load_key(a.in, i, a.ew), a.flip, a.fneg) > okey(load_key(a.in, i + 1, a.ew), a.flip, a.fneg);
         if (__any(inv) && __lane_id() == 0) atomicOr(&c->inversion, 1u);
         __syncthreads();
     }

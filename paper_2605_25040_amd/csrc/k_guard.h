@@ -1,19 +1,19 @@
 // Exact spill of the paper's bucket table, computed from the (key, count) pairs.
 //
 // In Alg. 1 a bucket never evicts and its counters only grow, so a bucket keeps
-// the first four distinct keys that hash to it (Eq. hash over M buckets, Eq.
-// Msize) in order of first occurrence, and every occurrence of any later key of
-// that bucket goes to the spill (counted in elements; the RLE step of Sec. 4.4
-// does not change that count).  Hence
-//     |spill| = sum over buckets with more than 4 distinct keys of the counts of
-//               the keys whose first occurrence is not among the bucket's first four.
+// the first cap distinct keys that hash to it (Eq. hash over M buckets, Eq. Msize;
+// cap = 4 for 64-bit keys, 8 for 32-bit keys) in order of first occurrence, and
+// every occurrence of any later key of that bucket goes to the spill (counted in
+// elements; the RLE step of Sec. 4.4 does not change that count).  Hence
+//     |spill| = sum over buckets with more than cap distinct keys of the counts of
+//               the keys whose first occurrence is not among the bucket's first cap.
 // The guard of Alg. 4 fires when |spill| > N/2 (tested as 2 |spill| > N).
 //
 // The GPU computes it in these steps, all skipped when no bucket is over-full:
 //   (the order kernel counts the buckets in LDS and lists the keys of over-full,
 //    "contested", buckets when K <= 8192, M <= 16384 and at most 2048 are contested;
 //    otherwise the three general kernels below do it from the dense pairs)
-//   k_guard_prep    clear bucket counters and the four per-bucket minima (general)
+//   k_guard_prep    clear bucket counters and the cap per-bucket minima (general)
 //   k_guard_bucket  distinct keys per bucket (general)
 //   k_guard_mark    list the contested keys (general); reset their first occurrences
 //   k_guard_first   first occurrence of each contested key: one pass over the
@@ -21,8 +21,8 @@
 //                   key has been seen (later chunks cannot hold a first occurrence)
 //   k_guard_resolve at most 2048 contested keys: rank them by first occurrence
 //                   within their bucket in LDS and sum the spilled counts
-//   k_guard_round   otherwise, r = 0..3: the r-th smallest first occurrence per bucket
-//   k_guard_final   and the sum of the counts of keys later than the 4th
+//   k_guard_round   otherwise, r = 0..cap-1: the r-th smallest first occurrence per bucket
+//   k_guard_final   and the sum of the counts of keys later than the cap-th
 #pragma once
 #include "cafs_dev.h"
 
@@ -60,7 +60,7 @@ __device__ __forceinline__ void guard_prep_body(const Args& a, uint32_t bid, uin
     const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     for (uint64_t i = gtid; i < M; i += gstride) {
         a.dcount[i] = 0;
-        for (int r = 0; r < 4; ++r) a.bmin[r * a.m_ws + i] = kNoIndex;
+        for (uint32_t r = 0; r < a.cap; ++r) a.bmin[r * a.m_ws + i] = kNoIndex;
     }
     const uint32_t lg = guard_index_log2(a, c);
     if (gtid == 0) c->gidx_log2 = lg;
@@ -93,7 +93,7 @@ __device__ __forceinline__ void guard_mark_body(const Args& a, uint32_t bid, uin
     uint32_t nb = 0;
     for (uint64_t b = gtid; b < M; b += gstride) {
         a.bfound[b] = 0;
-        if (c->guard_general) nb += a.dcount[b] > kBucketCap;
+        if (c->guard_general) nb += a.dcount[b] > a.cap;
     }
     nb = wave_sum_u32(nb);
     if (__lane_id() == 0 && nb) atomicAdd((unsigned long long*)&c->n_cbuckets, (unsigned long long)nb);
@@ -103,7 +103,7 @@ __device__ __forceinline__ void guard_mark_body(const Args& a, uint32_t bid, uin
         const uint32_t glg = c->gidx_log2;
         uint32_t* tab = guard_index(a);
         for (uint64_t j = gtid; j < K; j += gstride) {
-            const bool cont = a.dcount[phi_hash(a.uniq[j], lg)] > kBucketCap;
+            const bool cont = a.dcount[phi_hash(a.uniq[j], lg)] > a.cap;
             // list places: one update of the shared counter per wave (one per key
             // serialised on its address)
             const uint64_t m = __ballot(cont);
@@ -160,8 +160,8 @@ __device__ __forceinline__ uint64_t index_find(const Args& a, uint32_t glg, uint
 // First occurrences of the contested keys.  Chunks of the input are claimed in
 // increasing order and every claimed chunk is finished, so the minima found so far
 // are exact for every key seen in a claimed chunk.  A workgroup stops claiming
-// once every contested bucket has seen four of its keys: a key first seen in a
-// later chunk occurs after those four and cannot be among the bucket's first four,
+// once every contested bucket has seen cap of its keys: a key first seen in a
+// later chunk occurs after those and cannot be among the bucket's first cap,
 // so its first occurrence (left at the maximum) does not change the spill.  With at
 // most kGuardLdsKeys contested keys each workgroup keeps them in an LDS hash table
 // with per-key minima that it merges into the global minima after each chunk;
@@ -241,7 +241,7 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
 #pragma unroll
         for (uint32_t u = 0; u < PER; ++u) {
             const uint64_t i = b0 + threadIdx.x + (uint64_t)u * blockDim.x;
-            vv[u] = i < e0 ? gp(a.in)[i] : 0;
+            vv[u] = i < e0 ? load_key(a.in, i, a.ew) : 0;
         }
         if (kPhased && !small) {
             const CAFS_GLOBAL uint32_t* tab = gp(guard_index(a));
@@ -255,7 +255,7 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
             }
             if (glg) {
 #pragma unroll
-                for (uint32_t u = 0; u < PER; ++u) jt[u] = dc[u] > kBucketCap ? tab[phi_hash(vv[u], glg)] : kNoIndex;
+                for (uint32_t u = 0; u < PER; ++u) jt[u] = dc[u] > a.cap ? tab[phi_hash(vv[u], glg)] : kNoIndex;
                 uint64_t kk[PER];
 #pragma unroll
                 for (uint32_t u = 0; u < PER; ++u) kk[u] = jt[u] != kNoIndex ? a.uniq[jt[u]] : 0;
@@ -266,7 +266,7 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
             } else {
 #pragma unroll
                 for (uint32_t u = 0; u < PER; ++u)
-                    jt[u] = dc[u] > kBucketCap ? (uint32_t)find_key(a.uniq, K, vv[u], flip, a.fneg) : kNoIndex;
+                    jt[u] = dc[u] > a.cap ? (uint32_t)find_key(a.uniq, K, vv[u], flip, a.fneg) : kNoIndex;
             }
             uint32_t fi[PER];
 #pragma unroll
@@ -276,7 +276,7 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
                 const uint64_t i = b0 + threadIdx.x + (uint64_t)u * blockDim.x;
                 if (jt[u] >= K || fi[u] <= (uint32_t)i) continue;
                 const uint32_t old = atomicMin(&a.first_idx[jt[u]], (uint32_t)i);
-                if (old == kNoIndex && atomicAdd(&a.bfound[bb[u]], 1u) == kBucketCap - 1) ++newly;
+                if (old == kNoIndex && atomicAdd(&a.bfound[bb[u]], 1u) == a.cap - 1) ++newly;
             }
         } else {
 #pragma unroll
@@ -285,7 +285,7 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
             if (i >= e0) continue;
             const uint64_t v = vv[u];
             const uint32_t b = phi_hash32(v, lg);
-            const bool cont = bits ? ((bflag[b >> 5] >> (b & 31)) & 1u) : (a.dcount[b] > kBucketCap);
+            const bool cont = bits ? ((bflag[b >> 5] >> (b & 31)) & 1u) : (a.dcount[b] > a.cap);
             if (!cont) continue;
             if (small && v != kEmpty) {
                 uint32_t h = phi_hash32(v, 12);
@@ -299,12 +299,12 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
                     if (tk == kEmpty) break;  // unreachable: contested keys are all in the table
                     h = (h + 1) & (TS - 1);
                 }
-            } else if (bits || a.dcount[b] > kBucketCap) {
+            } else if (bits || a.dcount[b] > a.cap) {
                 const uint64_t jj = glg ? index_find(a, glg, v) : find_key(a.uniq, K, v, flip, a.fneg);
                 if (jj >= K) continue;  // not reached: every key of a contested bucket is indexed
                 if (g_load(&a.first_idx[jj]) <= (uint32_t)i) continue;
                 const uint32_t old = atomicMin(&a.first_idx[jj], (uint32_t)i);
-                if (old == kNoIndex && atomicAdd(&a.bfound[b], 1u) == kBucketCap - 1) ++newly;
+                if (old == kNoIndex && atomicAdd(&a.bfound[b], 1u) == a.cap - 1) ++newly;
             }
         }
         }
@@ -316,12 +316,12 @@ __device__ __forceinline__ void guard_first_body(const Args& a, uint32_t bid, ui
                     lsent[li] = m;
                     const uint32_t j = a.clist[li];
                     const uint32_t old = atomicMin(&a.first_idx[j], m);
-                    if (old == kNoIndex && atomicAdd(&a.bfound[phi_hash32(a.uniq[j], lg)], 1u) == kBucketCap - 1)
+                    if (old == kNoIndex && atomicAdd(&a.bfound[phi_hash32(a.uniq[j], lg)], 1u) == a.cap - 1)
                         ++newly;
                 }
             }
         }
-        newly = wave_sum_u32(newly);  // buckets that now know four keys
+        newly = wave_sum_u32(newly);  // buckets that now know cap keys
         if (__lane_id() == 0 && newly)
             atomicAdd((unsigned long long*)&c->buckets_done, (unsigned long long)newly);
         __syncthreads();
@@ -335,8 +335,9 @@ __global__ __launch_bounds__(256) void kb_guard_first(BatchGrid g) {
 
 // Rank of each contested key within its bucket by first occurrence, for at most
 // kGuardLdsKeys contested keys: sort (bucket, first occurrence) in LDS; position p
-// is the 5th or later key of its bucket exactly when position p - 4 holds the same
-// bucket.  The spill is the sum of those keys' counts.  One workgroup.
+// is past the bucket's first cap keys (cap = 4, or 8 for 32-bit keys) exactly when
+// position p - cap holds the same bucket.  The spill is the sum of those keys'
+// counts.  One workgroup.
 __device__ __forceinline__ void guard_resolve_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (c->path != P_MAIN || !c->guard_on) return;
@@ -383,7 +384,7 @@ __device__ __forceinline__ void guard_resolve_body(const Args& a, uint32_t bid, 
     }
     unsigned long long local = 0;
     for (uint32_t p = threadIdx.x; p < nc; p += blockDim.x)
-        if (p >= 4 && (sk[p - 4] >> 32) == (sk[p] >> 32)) local += sv[p];
+        if (p >= a.cap && (sk[p - a.cap] >> 32) == (sk[p] >> 32)) local += sv[p];
     local = wave_sum_u64(local);
     if (__lane_id() == 0 && local) atomicAdd(&s_spill, local);
     __syncthreads();
@@ -395,9 +396,10 @@ __device__ __forceinline__ void guard_resolve_body(const Args& a, uint32_t bid, 
 }
 CAFS_KERNELS0(guard_resolve, 1024)
 
+// Round r (r < cap, one launch each): the r-th smallest first occurrence per bucket.
 __device__ __forceinline__ void guard_round_body(const Args& a, uint32_t r, uint32_t bid, uint32_t nblk) {
     const Ctrl* c = a.c;
-    if (!guard_active(c) || !c->guard_rounds) return;
+    if (!guard_active(c) || !c->guard_rounds || r >= a.cap) return;
     // The rounds run in general mode only, where the contested list holds every key
     // of an over-full bucket: walk it (not all K keys), four keys per thread with
     // their loads in flight together.
@@ -447,7 +449,7 @@ __device__ __forceinline__ void guard_final_body(const Args& a, uint32_t bid, ui
             f[u] = in ? a.first_idx[j[u]] : 0u;
         }
 #pragma unroll
-        for (uint32_t u = 0; u < U; ++u) m4[u] = l0 + u * gstride < nc ? a.bmin[3 * a.m_ws + b[u]] : kNoIndex;
+        for (uint32_t u = 0; u < U; ++u) m4[u] = l0 + u * gstride < nc ? a.bmin[(a.cap - 1) * a.m_ws + b[u]] : kNoIndex;
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u)
             if (l0 + u * gstride < nc && f[u] > m4[u]) local += a.cnt[j[u]];

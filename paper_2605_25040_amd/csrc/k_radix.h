@@ -29,7 +29,8 @@ __device__ __forceinline__ void radix_hist_body(const Args& a, uint32_t bid, uin
     if (!c->radix_on) return;
     const RadixJob& j = c->rj;
     const uint64_t n = j.n;
-    const CAFS_GLOBAL uint64_t* __restrict__ src = gp(j.src_k);
+    const uint64_t* src = j.src_k;
+    const uint32_t sw = j.src_ew;
     const uint64_t flip = a.flip, fneg = a.fneg;
     __shared__ uint32_t lh[8][256];
     __shared__ uint32_t s_last;
@@ -48,7 +49,7 @@ __device__ __forceinline__ void radix_hist_body(const Args& a, uint32_t bid, uin
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t i = (it * U + u) * gstride + gtid;
-            vv[u] = i < n ? src[i] : 0;
+            vv[u] = i < n ? load_key(src, i, sw) : 0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -127,12 +128,14 @@ __device__ __forceinline__ void radix_hist_body(const Args& a, uint32_t bid, uin
         const uint32_t shift = (inplace && (np & 1u)) ? 1u : 0u;
         const uint64_t* ck = jw.src_k;
         const uint64_t* cv = jw.src_v;
+        uint32_t cw = jw.src_ew;
         for (uint32_t i = 0; i < np; ++i) {
             const bool to_dst = ((np - 1 - i + shift) % 2) == 0;
-            jw.ps_k[i] = ck; jw.ps_v[i] = cv;
+            jw.ps_k[i] = ck; jw.ps_v[i] = cv; jw.ps_w[i] = cw;
             jw.pd_k[i] = to_dst ? jw.dst_k : jw.tmp_k;
             jw.pd_v[i] = to_dst ? jw.dst_v : jw.tmp_v;
-            ck = jw.pd_k[i]; cv = jw.pd_v[i];
+            jw.pd_w[i] = to_dst ? jw.dst_ew : 8u;  // the scratch holds 8-byte keys
+            ck = jw.pd_k[i]; cv = jw.pd_v[i]; cw = jw.pd_w[i];
         }
         if (np == 0) jw.copy_mode = inplace ? 0u : 1u;
         else jw.copy_mode = shift ? 2u : 0u;
@@ -166,10 +169,11 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
     const uint64_t n = j.n;
     const uint32_t d = j.digit[pass];
     const uint64_t flip = a.flip, fneg = a.fneg;
-    const CAFS_GLOBAL uint64_t* __restrict__ sk = gp(j.ps_k[pass]);
+    const uint64_t* sk = j.ps_k[pass];
     const CAFS_GLOBAL uint64_t* __restrict__ sv = gp(j.ps_v[pass]);
-    CAFS_GLOBAL uint64_t* __restrict__ dk = gp(j.pd_k[pass]);
+    uint64_t* dk = j.pd_k[pass];
     CAFS_GLOBAL uint64_t* __restrict__ dv = gp(j.pd_v[pass]);
+    const uint32_t skw = j.ps_w[pass], dkw = j.pd_w[pass];
     const uint64_t tiles = (n + kRadixTile - 1) / kRadixTile;
     uint64_t* status = a.status + (pass & 1u) * a.status_slot;
     CAFS_GLOBAL uint64_t* status_next = gp(a.status) + ((pass + 1) & 1u) * a.status_slot;
@@ -213,7 +217,7 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
         for (int i = 0; i < kRadixItems; ++i) {
             const uint64_t pos = base + (uint64_t)wave * (64 * kRadixItems) + (uint64_t)i * 64 + lane;
             const bool ok = pos < n;
-            key[i] = ok ? sk[pos] : 0;
+            key[i] = ok ? load_key(sk, pos, skw) : 0;
             if constexpr (VALS) val[i] = ok ? sv[pos] : 0;
             okm |= (ok ? 1u : 0u) << i;
         }
@@ -292,7 +296,7 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
             const uint64_t k = lk[q];
             const uint64_t g = gofs[digit_of(k, flip, fneg, d)] + q;
             if (g < n) {  // always true when the look-back prefixes are consistent
-                dk[g] = k;
+                store_key(dk, g, k, dkw);
                 if constexpr (VALS) dv[g] = lv[q];
             }
         }
@@ -313,16 +317,17 @@ __device__ __forceinline__ void radix_copy_body(const Args& a, uint32_t bid, uin
     if (!c->radix_on) return;
     const RadixJob& j = c->rj;
     if (j.copy_mode == 0) return;
-    const CAFS_GLOBAL uint64_t* sk = gp(j.copy_mode == 1 ? j.src_k : j.tmp_k);
+    const uint64_t* sk = j.copy_mode == 1 ? j.src_k : j.tmp_k;
     const CAFS_GLOBAL uint64_t* sv = gp(j.copy_mode == 1 ? j.src_v : j.tmp_v);
-    CAFS_GLOBAL uint64_t* dk = gp(j.dst_k);
+    const uint32_t skw = j.copy_mode == 1 ? j.src_ew : 8u;
+    uint64_t* dk = j.dst_k;
     CAFS_GLOBAL uint64_t* dv = gp(j.dst_v);
     const bool vals = j.has_vals != 0;
     const uint64_t n = j.n;
     const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
     const uint64_t gstride = (uint64_t)nblk * blockDim.x;
     for (uint64_t i = gtid; i < n; i += gstride) {
-        dk[i] = sk[i];
+        store_key(dk, i, load_key(sk, i, skw), j.dst_ew);
         if (vals) dv[i] = sv[i];
     }
 }

@@ -77,8 +77,14 @@ def test_overlap_and_alignment_errors(ctx):
     # unknown dtype (radix API and estimate)
     assert ctx._lib.cafs_radix_sort(ctx._h, p, p + 2 * n * 8, n, 7, ws.data_ptr(), need, _stream()) == EINVAL
     est = torch.zeros(64, dtype=torch.uint8, device="cuda:0")
-    assert ctx._lib.cafs_estimate(ctx._h, p, n, 3, est.data_ptr(), _stream()) == EINVAL
+    assert ctx._lib.cafs_estimate(ctx._h, p, n, 7, est.data_ptr(), _stream()) == EINVAL
     assert ctx._lib.cafs_estimate(ctx._h, p + 4, n, 0, est.data_ptr(), _stream()) == EINVAL
+    # 32-bit keys need 4-byte alignment only, but not 2
+    assert _sort(ctx, p + 2, p + 2 * n * 8, n, ws.data_ptr(), need, fn="cafs_sort_i32") == EINVAL
+    assert _sort(ctx, p, p + 2 * n * 8 + 2, n, ws.data_ptr(), need, fn="cafs_sort_u32") == EINVAL
+    assert ctx._lib.cafs_estimate(ctx._h, p + 2, n, 3, est.data_ptr(), _stream()) == EINVAL
+    # a 32-bit output overlapping the input by one key
+    assert _sort(ctx, p, p + 4, n, ws.data_ptr(), need, fn="cafs_sort_i32") == EINVAL
     torch.cuda.synchronize()
     assert bool((buf[n:] == 0).all()), "a rejected call wrote memory"
     # in place is allowed
