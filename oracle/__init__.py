@@ -65,6 +65,10 @@ def _load():
         for name in ("oracle_table_M", "oracle_table_M32"):
             getattr(lib, name).argtypes = [u64, u64]
             getattr(lib, name).restype = u64
+        for name in ("oracle_sort_kv_i64", "oracle_sort_kv_u64", "oracle_sort_kv_f64", "oracle_sort_kv_i32",
+                     "oracle_sort_kv_u32"):
+            getattr(lib, name).argtypes = [p, p, u64, p, p]
+            getattr(lib, name).restype = None
         lib.oracle_hash.argtypes = [u64, u64]
         lib.oracle_hash.restype = u64
         for name in ("oracle_spill", "oracle_spill32"):
@@ -100,6 +104,19 @@ def sort(x, dtype=np.int64):
     y = np.empty_like(a)
     getattr(_load(), "oracle_sort_" + _kind(dtype))(_ptr(a), a.size, _ptr(y))
     return y
+
+
+def sort_kv(x, v, dtype=np.int64):
+    """Stable key-value sort: (keys in ``dtype``'s order, the 64-bit payloads ``v``
+    moved with their keys, equal keys in input order)."""
+    a = _arr(x, dtype)
+    vals = np.ascontiguousarray(v).view(np.uint64)
+    if vals.shape != a.shape:
+        raise ValueError("one 64-bit payload per key")
+    y = np.empty_like(a)
+    w = np.empty_like(vals)
+    getattr(_load(), "oracle_sort_kv_" + _kind(dtype))(_ptr(a), _ptr(vals), a.size, _ptr(y), _ptr(w))
+    return y, w
 
 
 def std_sort_i64(x):

@@ -25,7 +25,8 @@
 //   2*spill > N; M is clamped to [8, bit_ceil(N/4)] with integer N/4.
 //
 // Parity status: every function here is pinned by the CPU tests (library
-// sort, brute force over small alphabets, closed forms of Eq. chao1, Eq. hash
+// sort, library stable argsort for the key-value sort, brute force over small
+// alphabets, closed forms of Eq. chao1, Eq. hash
 // and Eq. Msize with the paper's worked sizes, crafted bucket collisions with
 // hand-derived spill counts, a Poisson check of the bucket model).  The float64
 // order (TotalF64) is pinned to the IEEE 754 totalOrder of signed zeros,
@@ -83,6 +84,24 @@ void sort_by_map(const T* x, uint64_t n, T* y) {
     uint64_t p = 0;
     for (const auto& kv : m)
         for (uint64_t c = 0; c < kv.second; ++c) y[p++] = kv.first;
+}
+
+// Key-value variant (a payload per key, for the post-group-by sort the paper names
+// as an integration target, Sec. Future directions): the keys come out as in the
+// keys-only sort and each payload goes with its key; equal keys keep their input
+// order (a stable sort).  Written out as a map from each key to the list of its
+// payloads in input order, emitted in key order.
+template <class T>
+void sort_kv_by_map(const T* x, const uint64_t* v, uint64_t n, T* y, uint64_t* w) {
+    std::map<T, std::vector<uint64_t>> m;
+    for (uint64_t i = 0; i < n; ++i) m[x[i]].push_back(v[i]);
+    uint64_t p = 0;
+    for (const auto& kv : m)
+        for (uint64_t val : kv.second) {
+            y[p] = kv.first;
+            w[p] = val;
+            ++p;
+        }
 }
 
 template <class T>
@@ -335,6 +354,26 @@ int oracle_is_monotone_f64(const uint64_t* x, uint64_t n) {
     return is_monotone(v.data(), n) ? 1 : 0;
 }
 void oracle_report_u64(const uint64_t* x, uint64_t n, uint64_t* out) { flatten(dispatch(x, x, n, kBucketCap), out); }
+
+// Key-value sorts (stable; payloads are opaque 64-bit words).
+void oracle_sort_kv_i64(const int64_t* x, const uint64_t* v, uint64_t n, int64_t* y, uint64_t* w) {
+    sort_kv_by_map(x, v, n, y, w);
+}
+void oracle_sort_kv_u64(const uint64_t* x, const uint64_t* v, uint64_t n, uint64_t* y, uint64_t* w) {
+    sort_kv_by_map(x, v, n, y, w);
+}
+void oracle_sort_kv_f64(const uint64_t* x, const uint64_t* v, uint64_t n, uint64_t* y, uint64_t* w) {
+    const std::vector<TotalF64> a = as_total(x, n);
+    std::vector<TotalF64> b(n);
+    sort_kv_by_map(a.data(), v, n, b.data(), w);
+    if (n) std::memcpy(y, b.data(), n * sizeof(uint64_t));
+}
+void oracle_sort_kv_i32(const int32_t* x, const uint64_t* v, uint64_t n, int32_t* y, uint64_t* w) {
+    sort_kv_by_map(x, v, n, y, w);
+}
+void oracle_sort_kv_u32(const uint32_t* x, const uint64_t* v, uint64_t n, uint32_t* y, uint64_t* w) {
+    sort_kv_by_map(x, v, n, y, w);
+}
 
 // 32-bit keys (the paper's int32 specialization, Sec. 4.2, and its unsigned twin).
 // Equality, the estimate, the tiny check and the spill simulation act on each key's

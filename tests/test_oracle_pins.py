@@ -502,3 +502,80 @@ def test_report32_reads_patterns_and_cap8():
     # with 64-bit keys of the same values the buckets hold four: keys 5..12 spill
     r64 = oracle.report(x, np.uint64)
     assert r64["spill_elems"] == 8 * 100 and r64["table_M"] == 8
+
+
+# ---- key-value sort (stable; payloads move with their keys) -----------------
+
+def _order_key_f64(bits):
+    """totalOrder as an unsigned order: flip every bit of a pattern with the sign
+    set, flip only the sign bit otherwise (IEEE 754-2008, Sec. 5.10)."""
+    b = bits.view(np.uint64)
+    neg = (b >> np.uint64(63)) != 0
+    return np.where(neg, ~b, b ^ np.uint64(1 << 63))
+
+
+@pytest.mark.parametrize("dtype", [np.int64, np.uint64, np.int32, np.uint32, np.float64])
+@pytest.mark.parametrize("n,k", [(1, 1), (50_000, 3), (50_000, 700), (30_000, 30_000)])
+def test_sort_kv_equals_numpy_stable_argsort(dtype, n, k):
+    """The key-value sort is numpy's stable argsort applied to keys and payloads."""
+    rng = np.random.default_rng(n + k)
+    if dtype == np.float64:
+        pal = rng.normal(size=k) * 10.0 ** rng.uniform(-20, 20, size=k)
+        x = pal[rng.integers(0, k, size=n)]
+        order = np.argsort(_order_key_f64(x), kind="stable")
+    else:
+        info = np.iinfo(dtype)
+        pal = rng.integers(info.min, info.max, size=k, dtype=dtype, endpoint=True)
+        x = pal[rng.integers(0, k, size=n)]
+        order = np.argsort(x, kind="stable")
+    v = rng.integers(0, 2**64 - 1, size=n, dtype=np.uint64, endpoint=True)
+    y, w = oracle.sort_kv(x, v, dtype)
+    assert np.array_equal(y.view(np.uint8), x[order].view(np.uint8))
+    assert np.array_equal(w, v[order])
+
+
+def test_sort_kv_bruteforce_small_alphabets():
+    """Every sequence of up to 7 keys over three values (one of them negative),
+    payloads = positions: the keys equal the keys-only sort, each payload points at
+    an input position holding its key, and within equal keys the positions rise."""
+    for dtype in (np.int64, np.int32, np.uint32):
+        alphabet = np.array([-3, 0, 5], dtype=np.int64).astype(dtype)
+        for L in range(0, 8):
+            for combo in itertools.product(range(3), repeat=L):
+                x = alphabet[list(combo)] if L else np.zeros(0, dtype=dtype)
+                v = np.arange(L, dtype=np.uint64)
+                y, w = oracle.sort_kv(x, v, dtype)
+                assert np.array_equal(y, oracle.sort(x, dtype))
+                assert sorted(w.tolist()) == list(range(L))
+                assert np.array_equal(x[w.astype(np.int64)], y)
+                for i in range(1, L):
+                    if y[i] == y[i - 1]:
+                        assert w[i] > w[i - 1]
+
+
+def test_sort_kv_f64_bits_are_keys():
+    """float64 keys: -0 and +0, and NaNs with different payloads, are different keys
+    in totalOrder; payloads follow them."""
+    bits = np.array([0x0000000000000000, 0x8000000000000000, 0x7FF8000000000001, 0x7FF8000000000000,
+                     0x8000000000000000, 0xFFF0000000000000, 0x0000000000000000], dtype=np.uint64)
+    v = np.arange(bits.size, dtype=np.uint64) * np.uint64(10)
+    y, w = oracle.sort_kv(bits.view(np.float64), v, np.float64)
+    assert y.view(np.uint64).tolist() == [0xFFF0000000000000, 0x8000000000000000, 0x8000000000000000,
+                                          0x0000000000000000, 0x0000000000000000, 0x7FF8000000000000,
+                                          0x7FF8000000000001]
+    assert w.tolist() == [50, 10, 40, 0, 60, 30, 20]
+
+
+def test_sort_kv_planted_mistakes_are_caught():
+    """The pins above fail for the mistakes a key-value sort can plausibly make:
+    an unstable order within a key and payloads left in input order."""
+    rng = np.random.default_rng(5)
+    x = rng.integers(0, 4, size=200).astype(np.int64)
+    v = np.arange(200, dtype=np.uint64)
+    y, w = oracle.sort_kv(x, v, np.int64)
+    order = np.argsort(x, kind="stable")
+    unstable = np.argsort(x, kind="quicksort")[::-1]
+    unstable = unstable[np.argsort(x[unstable], kind="stable")]  # keys sorted, ties reversed
+    assert not np.array_equal(v[unstable], v[order])
+    assert np.array_equal(w, v[order])
+    assert not np.array_equal(w, v)
