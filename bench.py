@@ -228,8 +228,9 @@ def bench_structured(ctx, n=1 << 28, steps=10):
 
 def bench_variants(ctx, n=1 << 28, k=1000, steps=10):
     """The headline column shape (N = 2^28, K = 1000, Zipf(1.0)) as float64 keys
-    (IEEE 754 totalOrder; a palette of normal doubles over the same rank stream) and
-    as int64 keys through a context with a seeded count-table hash."""
+    (IEEE 754 totalOrder; a palette of normal doubles over the same rank stream), as
+    int64 keys through a context with a seeded count-table hash, as int64 keys with
+    int64 row-id payloads (key-value sort), and as int32 keys."""
     import numpy as np
     import torch
 
@@ -254,6 +255,42 @@ def bench_variants(ctx, n=1 << 28, k=1000, steps=10):
         return {"n": n, "ms": round(ms, 4), "gkeys_s": round(n / ms / 1e6, 2), "path": r["path"],
                 "k_exact": r["k_exact"]}
 
+    def timed_kv(keys, steps_kv=5):
+        """Key-value sort with row-id payloads; torch's stable sort with a gather of
+        the payloads is timed beside it (the library way to do the same)."""
+        vals = torch.arange(n, dtype=torch.int64, device="cuda")
+        ko, vo = torch.empty_like(keys), torch.empty_like(vals)
+        ws = ctx.workspace(ctx.workspace_bytes(n))
+        for _ in range(2):
+            _, _, rep, _, _ = ctx.sort_kv(keys, vals, out_keys=ko, out_vals=vo, ws=ws)
+        torch.cuda.synchronize()
+        r = cafs.parse_report(rep)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps_kv):
+            ctx.sort_kv(keys, vals, out_keys=ko, out_vals=vo, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps_kv
+        del ko, vo
+        sk, idx = torch.sort(keys, stable=True)
+        _ = vals[idx]
+        del sk, idx, _
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(2):
+            sk, idx = torch.sort(keys, stable=True)
+            g = vals[idx]
+            del sk, idx, g
+        e1.record()
+        torch.cuda.synchronize()
+        t_ms = e0.elapsed_time(e1) / 2
+        del vals
+        torch.cuda.empty_cache()
+        return {"n": n, "ms": round(ms, 4), "gkeys_s": round(n / ms / 1e6, 2), "path": r["path"],
+                "k_exact": r["k_exact"], "payload": "int64 row ids",
+                "torch_stable_sort_gather_ms": round(t_ms, 4), "vs_torch": round(t_ms / ms, 2)}
+
     res = {}
     codes = torch.empty(n, dtype=torch.int64, device="cuda")
     gen.column_device(codes, k, dist="zipf", s=1.0, palette="codes")
@@ -269,7 +306,13 @@ def bench_variants(ctx, n=1 << 28, k=1000, steps=10):
         res["seeded_hash_k%d" % k] = timed(x)
     finally:
         ctx.set_hash_seed(0)
+    res["key_value_k%d" % k] = timed_kv(x)
+    # 32-bit keys: the low halves of the same values (K stays 1000)
+    x32 = (x & 0xFFFFFFFF).to(torch.int32)
     del x
+    torch.cuda.empty_cache()
+    res["int32_k%d" % k] = timed(x32)
+    del x32
     ctx._ws = None
     torch.cuda.empty_cache()
     return res

@@ -191,6 +191,27 @@ cafs_status_t cafs_sort_f64(cafs_ctx_t* ctx, const double* d_in, double* d_out, 
                             double* d_uniq, uint64_t* d_counts, cafs_report_t* d_report,
                             void* d_ws, size_t ws_bytes, void* stream);
 
+/* Key-value sort: keys of any dtype with one opaque 64-bit payload each (a row id
+ * or a value), for the post-group-by sort of a query engine that the paper names as
+ * an integration target (Sec. Future directions).
+ *   d_keys_in   n keys of `dtype` (device, 4- or 8-byte aligned by width)
+ *   d_keys_out  n keys: the keys in the dtype's order, as cafs_sort_* writes them
+ *   d_vals_in   n payloads (device, 8-byte aligned)
+ *   d_vals_out  n payloads: each input payload at its key's output position; equal
+ *               keys keep their input order (the sort is stable)
+ * d_uniq, d_counts, d_report, d_ws and ws_bytes (cafs_workspace_bytes(n)) as for
+ * cafs_sort_*; the report is the keys-only report of the same keys.  Neither output
+ * may share a byte with another of the four buffers (no in-place sort; the two
+ * inputs may overlap, they are only read): CAFS_EINVAL otherwise, as for
+ * null buffers with n > 0, misalignment, n >= 2^32 or an unknown dtype; nothing is
+ * enqueued then.  On the count paths the payloads are placed by a stable sort on
+ * the digits of each key's rank among the distinct keys (one pass of 8-bit digits
+ * per byte of K - 1); on the radix engine's paths they move with the keys. */
+cafs_status_t cafs_sort_kv(cafs_ctx_t* ctx, const void* d_keys_in, void* d_keys_out,
+                           const uint64_t* d_vals_in, uint64_t* d_vals_out, uint64_t n,
+                           cafs_dtype_t dtype, void* d_uniq, uint64_t* d_counts,
+                           cafs_report_t* d_report, void* d_ws, size_t ws_bytes, void* stream);
+
 /* For callers that cannot allocate device memory or pass a workspace (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation): the
  * sort of cafs_sort_i64 / _u64 / _f64 (dtype selects which) with the same buffer

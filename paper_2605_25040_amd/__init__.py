@@ -22,7 +22,7 @@ STAGES = ("pre", "count", "order", "emit", "tail")
 
 EXPORTS = ("cafs_ctx_create", "cafs_ctx_destroy", "cafs_ctx_enable_timing", "cafs_ctx_stage_ms",
            "cafs_workspace_bytes", "cafs_estimate",
-           "cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64", "cafs_sort_i32", "cafs_sort_u32", "cafs_sort_noalloc", "cafs_radix_sort", "cafs_batched_workspace_bytes",
+           "cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64", "cafs_sort_i32", "cafs_sort_u32", "cafs_sort_kv", "cafs_sort_noalloc", "cafs_radix_sort", "cafs_batched_workspace_bytes",
            "cafs_sort_batched", "cafs_ctx_set_batch_tuning", "cafs_autotune_batched", "cafs_ctx_set_hash_seed", "cafs_ctx_set_count_geometry", "cafs_ctx_get_tuning",
            "cafs_server_create", "cafs_server_destroy", "cafs_server_reserve", "cafs_server_submit",
            "cafs_server_poll", "cafs_server_release", "cafs_server_stats",
@@ -79,6 +79,8 @@ def load():
     for name in ("cafs_sort_i64", "cafs_sort_u64", "cafs_sort_f64", "cafs_sort_i32", "cafs_sort_u32"):
         getattr(lib, name).argtypes = [p, p, p, u64, p, p, p, p, ctypes.c_size_t, p]
         getattr(lib, name).restype = i32
+    lib.cafs_sort_kv.argtypes = [p, p, p, p, p, u64, i32, p, p, p, p, ctypes.c_size_t, p]
+    lib.cafs_sort_kv.restype = i32
     lib.cafs_sort_noalloc.argtypes = [p, p, p, u64, i32, p, p, p, p]
     lib.cafs_sort_noalloc.restype = i32
     lib.cafs_radix_sort.argtypes = [p, p, p, u64, i32, p, ctypes.c_size_t, p]
@@ -219,6 +221,30 @@ class Context:
         _check(fn(self._h, _ptr(x), _ptr(out), n, _ptr(uq), _ptr(ct), _ptr(rep), _ptr(ws), ws.numel(),
                   _stream(self.device)))
         return out, rep, uq, ct
+
+    def sort_kv(self, keys, vals, unsigned=False, out_keys=None, out_vals=None, counts=False, report=True,
+                ws=None):
+        """Stable key-value sort: ``keys`` (int64, int32 or float64; ``unsigned`` as
+        for ``sort``) with one 64-bit payload each in ``vals`` (an int64 tensor).
+        Returns (keys_out, vals_out, report_tensor, uniq, counts)."""
+        n = keys.numel()
+        if keys.dtype not in (torch.int64, torch.float64, torch.int32) or not keys.is_cuda:
+            raise CafsError("sort_kv takes a CUDA int64, int32 or float64 key tensor")
+        if vals.numel() != n or vals.element_size() != 8 or not vals.is_cuda:
+            raise CafsError("sort_kv takes one 64-bit payload per key")
+        if out_keys is None:
+            out_keys = torch.empty_like(keys)
+        if out_vals is None:
+            out_vals = torch.empty_like(vals)
+        rep = torch.zeros(ctypes.sizeof(Report), dtype=torch.uint8, device=self.device) if (report or counts) else None
+        uq = torch.empty_like(keys) if counts else None
+        ct = torch.empty(n, dtype=torch.int64, device=keys.device) if counts else None
+        if ws is None:
+            ws = self.workspace(self.workspace_bytes(n))
+        _check(self._lib.cafs_sort_kv(self._h, _ptr(keys), _ptr(out_keys), _ptr(vals), _ptr(out_vals), n,
+                                      _dtype_code(keys, unsigned), _ptr(uq), _ptr(ct), _ptr(rep), _ptr(ws),
+                                      ws.numel(), _stream(self.device)))
+        return out_keys, out_vals, rep, uq, ct
 
     def radix_sort(self, x, unsigned=False, out=None, ws=None):
         n = x.numel()

@@ -21,6 +21,7 @@
 #include "k_emit.h"
 #include "k_estimate.h"
 #include "k_guard.h"
+#include "k_kv.h"
 #include "k_radix.h"
 
 struct cafs_ctx {
@@ -271,6 +272,7 @@ cafs::Args make_args(const cafs_ctx* ctx, const Layout& L, const void* in, void*
     a.spill_v = at<uint64_t>(ws, L.spill_v);
     a.pbuf = at<uint64_t>(ws, L.pbuf);
     a.pbuf_elems = L.pbuf_elems;
+    a.kv_tab_log2 = log2_host(L.pbuf_elems / 2 + 1);  // (floor: pbuf_elems / 2 16-byte slots fit)
     a.part_keys = ctx ? ctx->part_keys : cafs::kPartKeys;
     a.wide_min = ctx ? ctx->wide_min : cafs::kLdsWideMinKhat;
     a.table_slots = ctx ? ctx->table_slots : cafs::kTableSlotsPerKey;
@@ -289,9 +291,15 @@ cafs_status_t check_buffers(const void* in, const void* out, uint64_t n, uint32_
     return CAFS_OK;
 }
 
+// Byte ranges [a, a + na) and [b, b + nb) share a byte.
+bool ranges_meet(const void* a, uint64_t na, const void* b, uint64_t nb) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return na > 0 && nb > 0 && x < y + nb && y < x + na;
+}
+
 cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, cafs_dtype_t dt, void* uniq,
                         uint64_t* counts, cafs_report_t* report, void* ws, size_t ws_bytes, void* stream,
-                        bool may_time = true) {
+                        bool may_time = true, const uint64_t* vin = nullptr, uint64_t* vout = nullptr) {
     if (!ctx) return CAFS_EINVAL;
     if (!dtype_ok(dt)) return CAFS_EINVAL;
     cafs_status_t st = check_buffers(in, out, n, elem_bytes(dt));
@@ -306,7 +314,10 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     }
     const Layout L = make_layout(n);
     if (!ws || ws_bytes < L.total || reinterpret_cast<uintptr_t>(ws) % kAlign) return CAFS_EWORKSPACE;
-    const cafs::Args a = make_args(ctx, L, in, out, n, dt, uniq, counts, report, ws);
+    cafs::Args a = make_args(ctx, L, in, out, n, dt, uniq, counts, report, ws);
+    a.vin = vin;
+    a.vout = vout;
+    const bool kv = vin != nullptr;
     const int cus = ctx->cus;
     std::vector<hipEvent_t> evs;
     if (ctx->timing && may_time) {
@@ -359,7 +370,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     if (countable && !inplace) cafs::k_emit_rows<<<std::min<uint32_t>(g_emit, cus), cafs::kEmitRowsThreads, 0, s>>>(a);
     mark(4);
     // (K > 32768 is emitted by the tile emit after the pair sort on the side stream)
-    launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2, countable);
+    launch_radix(a, std::max<uint64_t>(n, countable ? cap_ws : 0), cus, s2, countable || kv);
     if (countable) {
         // (a spill can reach the pair sort at any N)
         const uint32_t g_scan = std::min<uint32_t>(cus * 2, cafs::kMaxCountBlocks);
@@ -367,6 +378,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
         cafs::k_fold_write<<<g_scan, 1024, 0, s2>>>(a);
     }
     cafs::k_copy_mono<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s2>>>(a);
+    if (kv) cafs::k_kv_copy_mono<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s2>>>(a);
     const uint32_t g_rle = grid_for(n, cafs::kRleTile, cus * 4);
     cafs::k_rle_count<<<g_rle, 256, 0, s2>>>(a);
     cafs::k_rle_write<<<g_rle, 256, 0, s2>>>(a);
@@ -388,6 +400,28 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     (void)hipStreamWaitEvent(s, ctx->join, 0);
     if (countable && inplace)
         cafs::k_emit_rows<<<std::min<uint32_t>(g_emit, cus), cafs::kEmitRowsThreads, 0, s>>>(a);
+    if (kv && countable) {
+        // payload placement on the count paths (the kernels return at once elsewhere):
+        // `units` upsweep workgroups, kKvUnitsPerChunk of them per placement workgroup
+        const uint64_t tiles = (n + cafs::kKvTile - 1) / cafs::kKvTile;
+        const uint64_t want = (tiles + cafs::kKvUnitsPerChunk - 1) / cafs::kKvUnitsPerChunk;
+        const uint32_t chunks =
+            (uint32_t)std::min<uint64_t>(want, std::min<uint32_t>((uint32_t)cus * 2, cafs::kKvMaxChunks));
+        const uint32_t units = chunks * cafs::kKvUnitsPerChunk;
+        cafs::k_kv_setup<<<1, 64, 0, s>>>(a);
+        cafs::k_kv_clear<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s>>>(a);
+        cafs::k_kv_build<<<grid_for(n, 256 * 4, cus * 2), 256, 0, s>>>(a);
+        for (uint32_t p = 0; p < 4; ++p) {
+            if (p == 0) {
+                cafs::k_kv_up0_lds<<<units, cafs::kKvThreads, 0, s>>>(a);
+                cafs::k_kv_up0_mem<<<units, cafs::kKvThreads, 0, s>>>(a);
+            } else {
+                cafs::k_kv_up<<<units, cafs::kKvThreads, 0, s>>>(a, p);
+            }
+            cafs::k_kv_scan<<<256, 1024, 0, s>>>(a, p, units);
+            cafs::k_kv_down<<<chunks, cafs::kKvThreads, 0, s>>>(a, p);
+        }
+    }
     if (a.uniq_out) cafs::k_uniq_out<<<grid_for(n, 256 * 8, cus * 4), 256, 0, s>>>(a);
     cafs::k_finalize<<<1, 64, 0, s>>>(a);
     mark(5);
@@ -527,6 +561,30 @@ cafs_status_t cafs_estimate(cafs_ctx_t* ctx, const void* d_keys, uint64_t n, caf
                                                                             elem_bytes(dtype), d_out);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? CAFS_OK : hip_fail(e, "launch");
+}
+
+cafs_status_t cafs_sort_kv(cafs_ctx_t* ctx, const void* d_keys_in, void* d_keys_out, const uint64_t* d_vals_in,
+                           uint64_t* d_vals_out, uint64_t n, cafs_dtype_t dtype, void* d_uniq, uint64_t* d_counts,
+                           cafs_report_t* d_report, void* d_ws, size_t ws_bytes, void* stream) {
+    if (!ctx || !dtype_ok(dtype)) return CAFS_EINVAL;
+    const uint32_t ew = elem_bytes(dtype);
+    cafs_status_t st = check_buffers(d_keys_in, d_keys_out, n, ew);
+    if (st != CAFS_OK) return st;
+    if (n > 0) {
+        if (!d_vals_in || !d_vals_out) return CAFS_EINVAL;
+        if ((reinterpret_cast<uintptr_t>(d_vals_in) | reinterpret_cast<uintptr_t>(d_vals_out)) % 8) return CAFS_EINVAL;
+        // no output may share a byte with another buffer (the keys are read again
+        // after the sorted keys are written); the inputs are only read
+        const uint64_t kb = n * ew, vb = n * 8;
+        if (ranges_meet(d_keys_in, kb, d_keys_out, kb) || ranges_meet(d_vals_in, vb, d_vals_out, vb) ||
+            ranges_meet(d_keys_in, kb, d_vals_out, vb) || ranges_meet(d_keys_out, kb, d_vals_in, vb) ||
+            ranges_meet(d_keys_out, kb, d_vals_out, vb))
+            return CAFS_EINVAL;
+    }
+    if (n == 0) return sort_impl(ctx, d_keys_in, d_keys_out, n, dtype, d_uniq, d_counts, d_report, d_ws, ws_bytes,
+                                 stream);
+    return sort_impl(ctx, d_keys_in, d_keys_out, n, dtype, d_uniq, d_counts, d_report, d_ws, ws_bytes, stream, true,
+                     d_vals_in, d_vals_out);
 }
 
 cafs_status_t cafs_sort_i64(cafs_ctx_t* ctx, const int64_t* d_in, int64_t* d_out, uint64_t n, int64_t* d_uniq,

@@ -168,6 +168,11 @@ struct Ctrl {
     alignas(128) uint32_t chunk_ctr;
     alignas(128) uint32_t guard_done;
     uint64_t spill;
+    // key-value variant: payload placement by rank digits (count paths)
+    uint32_t kv_on;
+    uint32_t kv_passes;               // 8-bit digits of the largest rank (0 when K = 1)
+    uint32_t kv_slots_log2;           // rank lookup table size
+    uint32_t kv_mode;                 // lookup: 0 table in LDS, 1 table in memory, 2 binary search
 };
 
 // Everything a kernel needs to know about the call; passed by value.
@@ -225,6 +230,10 @@ struct Args {
     // the column scattered into hash-partition buckets (pbuf_elems entries in all)
     uint64_t* pbuf;
     uint64_t pbuf_elems;
+    // key-value variant: one 64-bit payload per key (null for a keys-only sort)
+    const uint64_t* vin;
+    uint64_t* vout;
+    uint32_t kv_tab_log2;             // largest rank lookup table the workspace holds (16-byte slots)
 };
 
 // Block table of a batched launch: block b works on column col[b] as block

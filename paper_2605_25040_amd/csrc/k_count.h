@@ -801,14 +801,16 @@ __device__ __forceinline__ void count_items(const Args& a, uint32_t bid, uint32_
         uint64_t ns, pb, pe, roff;  // roff: where the item's deferral region starts in tmp_k
         uint32_t head;
         if (!PARTS && EW == 4) {
-            // ranges of elements (32-bit keys are loaded one per lane)
+            // ranges of quads: quad q holds elements 4q - head .. 4q - head + 3 (head:
+            // the column's offset in its first 16 bytes, in keys), read by one
+            // 16-byte load when all four are in the column
             src = a.in;
             ns = n;
-            head = 0;
-            const uint64_t ES = (n + nblk - 1) / nblk;
-            pb = (uint64_t)it * ES < n ? (uint64_t)it * ES : n;
-            pe = pb + ES < n ? pb + ES : n;
-            roff = pb;
+            head = (uint32_t)((reinterpret_cast<uintptr_t>(a.in) >> 2) & 3u);
+            const uint64_t Q = (n + head + 3) / 4, QS = (Q + nblk - 1) / nblk;
+            pb = (uint64_t)it * QS < Q ? (uint64_t)it * QS : Q;
+            pe = pb + QS < Q ? pb + QS : Q;
+            roff = 4 * pb;
         } else if (!PARTS) {
             src = a.in;
             ns = n;
@@ -832,7 +834,7 @@ __device__ __forceinline__ void count_items(const Args& a, uint32_t bid, uint32_
         // the region holds every element of the item (tmp_k covers the column and
         // every bucket), so a deferral always finds room
         CAFS_GLOBAL uint64_t* region = gp(a.tmp_k) + roff;
-        const uint32_t region_cap = (uint32_t)((EW == 4 ? 1 : 2) * (pe - pb));
+        const uint32_t region_cap = (uint32_t)((EW == 4 ? 4 : 2) * (pe - pb));
         for (uint32_t i = threadIdx.x; i < S; i += blockDim.x) {
             skeys[i] = kEmpty;
             scnt[i] = 0;
@@ -861,25 +863,47 @@ __device__ __forceinline__ void count_range(const Args& a, const GTable& t, uint
     const uint32_t lane = __lane_id();
     const uint64_t mul = t.mul;
     uint32_t ecnt = 0;
-    const uint64_t Pf = (n + head) / 2;  // pairs [head, Pf) hold two in-range elements
+    // pairs [head, Pf) hold two in-range elements; for EW = 4, quads [first, Qf)
+    // hold four
+    const uint64_t Pf = EW == 4 ? (n + head) / 4 : (n + head) / 2;
     const uint64_t p_full = p_end < Pf ? p_end : Pf;
-    constexpr int U = 4;                 // pairs per thread per step
-    constexpr int NE = 2 * U;
-    const uint64_t span = (uint64_t)blockDim.x * (EW == 4 ? NE : U);  // elements for EW = 4, pairs otherwise
+    const uint64_t p_first = EW == 4 ? (head ? 1u : 0u) : head;
+    constexpr int U = EW == 4 ? 2 : 4;   // 16-byte groups per thread per step
+    constexpr int NE = 8;
+    const uint64_t span = (uint64_t)blockDim.x * U;  // groups
     uint64_t base = p_begin;
     uint64_t v[NE];
     uint32_t okm = 0;  // bit e: element e of the batch is in range
     auto load = [&](uint64_t b) {
         if constexpr (EW == 4) {
-            // 32-bit keys: element b + u * blockDim + thread, zero-extended
+            // 32-bit keys, zero-extended: quad q = b + u * blockDim + thread
             const CAFS_GLOBAL uint32_t* in32 = reinterpret_cast<const CAFS_GLOBAL uint32_t*>(in);
-            okm = 0;
+            if (b >= p_first && b + span <= p_full) {
+                // interior batch: every quad is four aligned in-range elements
+                const CAFS_GLOBAL u64x2* src =
+                    reinterpret_cast<const CAFS_GLOBAL u64x2*>(in32 + 4 * (b + threadIdx.x) - head);
 #pragma unroll
-            for (int e = 0; e < NE; ++e) {
-                const uint64_t i = b + (uint64_t)e * blockDim.x + threadIdx.x;
-                const bool o = i < p_end;
-                v[e] = o ? (uint64_t)in32[i] : 0;
-                okm |= (o ? 1u : 0u) << e;
+                for (int u = 0; u < U; ++u) {
+                    const u64x2 w = src[(uint64_t)u * blockDim.x];
+                    v[4 * u] = w.x & 0xFFFFFFFFull;
+                    v[4 * u + 1] = w.x >> 32;
+                    v[4 * u + 2] = w.y & 0xFFFFFFFFull;
+                    v[4 * u + 3] = w.y >> 32;
+                }
+                okm = (1u << NE) - 1;
+            } else {
+                okm = 0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint64_t q = b + (uint64_t)u * blockDim.x + threadIdx.x;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int64_t e = (int64_t)(4 * q + j) - (int64_t)head;
+                        const bool o = q < p_end && e >= 0 && (uint64_t)e < n;
+                        v[4 * u + j] = o ? (uint64_t)in32[e] : 0;
+                        okm |= (o ? 1u : 0u) << (4 * u + j);
+                    }
+                }
             }
             return;
         }

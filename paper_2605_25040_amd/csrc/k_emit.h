@@ -153,11 +153,12 @@ CAFS_KERNELS1(emit, kEmitThreads, uint32_t, mode)
 // TB/s when 256 workgroups sweep the output in rows, whether as one sweep or as up
 // to 32 sweeps over separate segments, against 5.2-5.8 TB/s when each workgroup
 // streams its own tiles or chunk).  The output is cut into segments of about
-// kEmitSegRuns runs each (segment i starts at the 4 KB-aligned pair at or before
-// the first element of run i * kEmitSegRuns); each segment gets workgroups in
-// proportion to its pairs, and they sweep it in rows of (workgroups * blockDim)
-// pairs, each writing blockDim consecutive pairs of every row, kEmitRowsUnroll
-// rows per step.  A workgroup stages its segment's runs in LDS (offsets relative
+// R runs each (segment i starts at the 4 KB-aligned group at or before the first
+// element of run i * R); each segment gets workgroups in
+// proportion to its groups, and they sweep it in rows of (workgroups * blockDim)
+// groups, each writing blockDim consecutive groups of every row, kEmitRowsUnroll
+// rows per step.  A group is the 16 bytes of one store: two 64-bit keys or four
+// 32-bit keys.  A workgroup stages its segment's runs in LDS (offsets relative
 // to the segment start) with an index of the run holding every 2^s-th position of
 // the segment (at most kEmitIdxSlots entries); an element's run is that entry's
 // run, or a short binary search when run boundaries fall inside the span.
@@ -165,8 +166,10 @@ constexpr uint32_t kEmitRowsMaxK = 4088;   // runs one workgroup stages (64 KB o
                                            // workgroup per CU leaves room for the side stream's kernels)
 constexpr uint32_t kEmitIdxSlots = 4096;
 constexpr uint32_t kEmitAlignPairs = 256;  // segment starts: multiples of 4 KB of output
-constexpr uint32_t kEmitSegRuns = kEmitRowsMaxK - 2 * kEmitAlignPairs;  // runs starting in a segment
-constexpr uint32_t kEmitMaxSegs = (kRankMax + kEmitSegRuns - 1) / kEmitSegRuns;  // segments for K <= kRankMax
+// runs starting in a segment: kEmitRowsMaxK - G * kEmitAlignPairs for groups of G keys
+// per 16-byte store (2 for 64-bit keys, 4 for 32-bit keys); the fewest is for G = 4
+constexpr uint32_t kEmitSegRunsMin = kEmitRowsMaxK - 4 * kEmitAlignPairs;
+constexpr uint32_t kEmitMaxSegs = (kRankMax + kEmitSegRunsMin - 1) / kEmitSegRunsMin;  // segments for K <= kRankMax
 constexpr uint32_t kEmitRowsThreads = 256;
 constexpr int kEmitRowsUnroll = 8;
 
@@ -205,48 +208,70 @@ __device__ __forceinline__ bool rows_take(const Args& a, const Ctrl* c) {
     return c->K >= 1 && c->K <= kRankMax;  // (columns hold fewer than 2^32 keys)
 }
 
-__device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint32_t nblk) {
-    Ctrl* c = a.c;
-    if (!c->emit_main) return;
-    if (a.ew == 4) {
-        // 32-bit keys: the element tile emit over this launch's workgroups
-        __shared__ uint64_t t_j[2];
-        __shared__ uint64_t t_off[kEmitLdsRuns + 1];
-        __shared__ uint64_t t_key[kEmitLdsRuns];
-        emit_tiles32(a, bid, nblk, t_off, t_key, t_j);
-        return;
+// LDS of the row emit.
+struct EmitRowsLds {
+    uint32_t soff[kEmitRowsMaxK + 1];
+    uint64_t skey[kEmitRowsMaxK];
+    uint32_t sidx[kEmitIdxSlots + 2];
+    uint32_t swave[kEmitRowsThreads / 64];
+    uint64_t s_rng[2];
+    uint64_t s_pb[kEmitMaxSegs + 1];  // first group of each segment, and the group count
+    uint32_t s_seg[3];
+};
+
+// Four 32-bit keys of group p (elements 4p - head .. 4p - head + 3): one 16-byte
+// store when all four are in the column.
+__device__ __forceinline__ void store_quad(uint64_t* __restrict__ y64, uint64_t n, uint32_t head, uint64_t p,
+                                           const uint32_t* v) {
+    uint32_t* y = reinterpret_cast<uint32_t*>(y64);
+    const int64_t e0 = (int64_t)(4 * p) - (int64_t)head;
+    if (e0 >= 0 && (uint64_t)e0 + 3 < n) {
+        u64x2 w;
+        w.x = (uint64_t)v[0] | ((uint64_t)v[1] << 32);
+        w.y = (uint64_t)v[2] | ((uint64_t)v[3] << 32);
+        __builtin_nontemporal_store(w, reinterpret_cast<u64x2*>(y + e0));
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (e0 + j >= 0 && (uint64_t)(e0 + j) < n) y[e0 + j] = v[j];
     }
+}
+
+template <uint32_t G>
+__device__ __forceinline__ void emit_rows_impl(const Args& a, uint32_t bid, uint32_t nblk, EmitRowsLds& L) {
+    Ctrl* c = a.c;
     const uint64_t n = a.n;
     const uint64_t K64 = c->K;
-    __shared__ uint32_t soff[kEmitRowsMaxK + 1];
-    __shared__ uint64_t skey[kEmitRowsMaxK];
-    __shared__ uint32_t sidx[kEmitIdxSlots + 2];
-    __shared__ uint32_t swave[kEmitRowsThreads / 64];
-    __shared__ uint64_t s_rng[2];
-    __shared__ uint64_t s_pb[kEmitMaxSegs + 1];  // first pair of each segment, and P
-    __shared__ uint32_t s_seg[3];
+    uint32_t* soff = L.soff;
+    uint64_t* skey = L.skey;
+    uint32_t* sidx = L.sidx;
+    uint32_t* swave = L.swave;
+    uint64_t* s_rng = L.s_rng;
+    uint64_t* s_pb = L.s_pb;
+    uint32_t* s_seg = L.s_seg;
     if (!rows_take(a, c) || bid >= a.row_blocks) return;  // the sweep takes row_blocks workgroups
     nblk = a.row_blocks < nblk ? a.row_blocks : nblk;
     const uint32_t K = (uint32_t)K64;
-    const uint32_t head = a.out_head;
-    const uint64_t P = num_pairs(n, head);
+    // slots of the first group before element 0 (the output's offset in its 16 bytes)
+    const uint32_t head = G == 2 ? a.out_head : (uint32_t)((reinterpret_cast<uintptr_t>(a.out) >> 2) & 3u);
+    const uint64_t P = (n + head + G - 1) / G;  // groups
     const uint32_t tid = threadIdx.x;
     const CAFS_GLOBAL uint64_t* off = gp(a.off);
     const CAFS_GLOBAL uint64_t* uq = gp(a.uniq);
-    // segments by run count: segment i starts at the pair holding the first element
+    // segments by run count: segment i starts at the group holding the first element
     // of run i * R, so it holds runs i * R - 1 .. (i + 1) * R - 1 at most
-    // (rounded down to a multiple of kEmitAlignPairs pairs, so that the stores stay
-    // aligned to whole cache lines; the rounding adds at most 2 * kEmitAlignPairs - 1
+    // (rounded down to a multiple of kEmitAlignPairs groups, so that the stores stay
+    // aligned to whole cache lines; the rounding adds at most G * kEmitAlignPairs - 1
     // elements, so at most that many runs, in front)
-    constexpr uint32_t R = kEmitSegRuns;
+    constexpr uint32_t R = kEmitRowsMaxK - G * kEmitAlignPairs;  // runs starting in a segment
     uint32_t S = (K + R - 1) / R;
     if (S > nblk) S = 1;  // (tiny grids) one segment, searched in global memory below
     if (tid < S)
-        s_pb[tid + 1] = tid + 1 == S ? P : (off[(tid + 1) * R] + head) / 2 / kEmitAlignPairs * kEmitAlignPairs;
+        s_pb[tid + 1] = tid + 1 == S ? P : (off[(tid + 1) * R] + head) / G / kEmitAlignPairs * kEmitAlignPairs;
     if (tid == 0) s_pb[0] = 0;
     __syncthreads();
     if (tid == 0) {
-        // workgroups per segment in proportion to its pairs, at least one each
+        // workgroups per segment in proportion to its groups, at least one each
         uint32_t acc = 0;
         s_seg[0] = S;  // none
         for (uint32_t i = 0; i < S; ++i) {
@@ -268,9 +293,9 @@ __device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint
     const uint64_t sp0 = s_pb[seg], sp1 = s_pb[seg + 1];
     if (sp0 >= sp1) return;
     // the segment's elements [e_first, e_last] and the runs holding them
-    const int64_t ef_s = (int64_t)(2 * sp0) - (int64_t)head;
+    const int64_t ef_s = (int64_t)(G * sp0) - (int64_t)head;
     const uint64_t e_first = ef_s < 0 ? 0 : (uint64_t)ef_s;
-    const uint64_t el_s = 2 * sp1 - 1 - head;
+    const uint64_t el_s = G * sp1 - 1 - head;
     const uint64_t e_last = el_s < n - 1 ? el_s : n - 1;
     if (S == 1) {  // the whole column
         if (tid == 0) {
@@ -282,7 +307,7 @@ __device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint
         // i * R, so its first run is at most that many runs before; it ends at most
         // 2 * kEmitAlignPairs elements before run (i + 1) * R, so its last run is at
         // most that many runs before that one (wave 0 finds the first, wave 1 the last)
-        constexpr uint32_t back = 2 * kEmitAlignPairs;
+        constexpr uint32_t back = G * kEmitAlignPairs;
         if (tid < 64) {
             const uint32_t a1 = seg * R, a0 = a1 > back ? a1 - back : 0u;
             const uint64_t jl = wave_run_of(a.off, a0, a1, e_first);
@@ -303,11 +328,22 @@ __device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint
         // too many runs to stage (one segment on a tiny grid): each pair searches the
         // global offsets
         for (uint64_t p = sp0 + (uint64_t)w * blockDim.x + tid; p < sp1; p += row) {
-            const int64_t e0s = (int64_t)(2 * p) - (int64_t)head;
-            const uint64_t e0 = e0s < 0 ? 0 : (uint64_t)e0s;
-            const uint64_t r0 = run_of(a.off, j_lo, j_hi, e0);
-            const uint64_t r1 = (r0 + 1 <= j_hi && (int64_t)off[r0 + 1] <= e0s + 1) ? r0 + 1 : r0;
-            store_pair(a.out, n, head, p, uq[r0], uq[r1]);
+            const int64_t e0s = (int64_t)(G * p) - (int64_t)head;
+            if constexpr (G == 2) {
+                const uint64_t e0 = e0s < 0 ? 0 : (uint64_t)e0s;
+                const uint64_t r0 = run_of(a.off, j_lo, j_hi, e0);
+                const uint64_t r1 = (r0 + 1 <= j_hi && (int64_t)off[r0 + 1] <= e0s + 1) ? r0 + 1 : r0;
+                store_pair(a.out, n, head, p, uq[r0], uq[r1]);
+            } else {
+                uint32_t v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t e = e0s + j;
+                    const uint64_t ec = e < 0 ? 0 : ((uint64_t)e < n ? (uint64_t)e : n - 1);
+                    v[j] = (uint32_t)uq[run_of(a.off, j_lo, j_hi, ec)];
+                }
+                store_quad(a.out, n, head, p, v);
+            }
         }
         return;
     }
@@ -364,54 +400,108 @@ __device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint
     __syncthreads();
 
     constexpr int U = kEmitRowsUnroll;
-    // U rows per step.  Fast case: the index span of the element holds at most one
-    // run boundary (hi <= lo + 1), so the pair's keys follow from that boundary's
-    // offset and the keys of runs lo and lo + 1: two LDS round trips for all U rows,
-    // no loop.  Spans with more boundaries take a binary search.
-    for (uint64_t p = sp0 + (uint64_t)w * blockDim.x + tid; p < sp1; p += U * row) {
-        int64_t e0s[U];  // first element of the pair, relative to e_first (-1: before the column)
-        uint32_t e0[U], lo[U], hi[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t pu = p + u * row;
-            e0s[u] = (int64_t)(2 * pu) - (int64_t)head - (int64_t)e_first;
-            e0[u] = (pu < sp1 && e0s[u] > 0) ? (uint32_t)e0s[u] : 0u;
-            const uint32_t q = e0[u] >> s;
-            lo[u] = sidx[q];
-            hi[u] = sidx[q + 1];
-        }
-        uint32_t nb[U];
-        uint64_t k0[U], k1[U];
-        bool slow = false;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            nb[u] = soff[lo[u] + 1];
-            k0[u] = skey[lo[u]];
-            k1[u] = skey[lo[u] + 1 < Ks ? lo[u] + 1 : lo[u]];
-            slow |= hi[u] > lo[u] + 1;
-        }
-        if (slow) {
-#pragma unroll
+    if constexpr (G == 2) {
+        constexpr int U = kEmitRowsUnroll;
+        // U rows per step.  Fast case: the index span of the element holds at most one
+        // run boundary (hi <= lo + 1), so the pair's keys follow from that boundary's
+        // offset and the keys of runs lo and lo + 1: two LDS round trips for all U rows,
+        // no loop.  Spans with more boundaries take a binary search.
+        for (uint64_t p = sp0 + (uint64_t)w * blockDim.x + tid; p < sp1; p += U * row) {
+            int64_t e0s[U];  // first element of the pair, relative to e_first (-1: before the column)
+            uint32_t e0[U], lo[U], hi[U];
+    #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (hi[u] <= lo[u] + 1) continue;
-                uint32_t l = lo[u], h = hi[u];
-                while (l < h) {
-                    const uint32_t mid = (l + h + 1) >> 1;
-                    if (soff[mid] <= e0[u]) l = mid; else h = mid - 1;
+                const uint64_t pu = p + u * row;
+                e0s[u] = (int64_t)(2 * pu) - (int64_t)head - (int64_t)e_first;
+                e0[u] = (pu < sp1 && e0s[u] > 0) ? (uint32_t)e0s[u] : 0u;
+                const uint32_t q = e0[u] >> s;
+                lo[u] = sidx[q];
+                hi[u] = sidx[q + 1];
+            }
+            uint32_t nb[U];
+            uint64_t k0[U], k1[U];
+            bool slow = false;
+    #pragma unroll
+            for (int u = 0; u < U; ++u) {
+                nb[u] = soff[lo[u] + 1];
+                k0[u] = skey[lo[u]];
+                k1[u] = skey[lo[u] + 1 < Ks ? lo[u] + 1 : lo[u]];
+                slow |= hi[u] > lo[u] + 1;
+            }
+            if (slow) {
+    #pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (hi[u] <= lo[u] + 1) continue;
+                    uint32_t l = lo[u], h = hi[u];
+                    while (l < h) {
+                        const uint32_t mid = (l + h + 1) >> 1;
+                        if (soff[mid] <= e0[u]) l = mid; else h = mid - 1;
+                    }
+                    // as in the fast case, from the run holding the first element
+                    nb[u] = soff[l + 1];
+                    k0[u] = skey[l];
+                    k1[u] = skey[l + 1 < Ks ? l + 1 : l];
                 }
-                // as in the fast case, from the run holding the first element
-                nb[u] = soff[l + 1];
-                k0[u] = skey[l];
-                k1[u] = skey[l + 1 < Ks ? l + 1 : l];
+            }
+    #pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t v0 = (int64_t)e0[u] >= (int64_t)nb[u] ? k1[u] : k0[u];
+                const uint64_t v1 = e0s[u] + 1 >= (int64_t)nb[u] ? k1[u] : k0[u];
+                if (p + u * row < sp1) store_pair(a.out, n, head, p + u * row, v0, v1);
             }
         }
+    } else {
+        // groups of four 32-bit keys: the index spans around the first and the last
+        // element of the group; at most one run boundary between them is the fast
+        // case, otherwise each element searches
+        for (uint64_t p = sp0 + (uint64_t)w * blockDim.x + tid; p < sp1; p += U * row) {
+            int64_t e0s[U];
+            uint32_t e0[U], lo[U], hi[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t v0 = (int64_t)e0[u] >= (int64_t)nb[u] ? k1[u] : k0[u];
-            const uint64_t v1 = e0s[u] + 1 >= (int64_t)nb[u] ? k1[u] : k0[u];
-            if (p + u * row < sp1) store_pair(a.out, n, head, p + u * row, v0, v1);
+            for (int u = 0; u < U; ++u) {
+                const uint64_t pu = p + u * row;
+                e0s[u] = (int64_t)(4 * pu) - (int64_t)head - (int64_t)e_first;
+                e0[u] = (pu < sp1 && e0s[u] > 0) ? (uint32_t)e0s[u] : 0u;
+                const uint32_t q3 = (e0[u] + 3) >> s;
+                lo[u] = sidx[e0[u] >> s];
+                hi[u] = sidx[(q3 < qn ? q3 : qn) + 1];  // (entries from qn on hold the last run)
+            }
+            uint32_t nb[U];
+            uint64_t k0[U], k1[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                nb[u] = soff[lo[u] + 1];
+                k0[u] = skey[lo[u]];
+                k1[u] = skey[lo[u] + 1 < Ks ? lo[u] + 1 : lo[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (p + u * row >= sp1) continue;
+                uint32_t v[4];
+                if (hi[u] <= lo[u] + 1) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int64_t e = e0s[u] + j;
+                        v[j] = (uint32_t)(e >= (int64_t)nb[u] ? k1[u] : k0[u]);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int64_t e = e0s[u] + j;
+                        const uint32_t ec = e < 0 ? 0u : (e < (int64_t)len ? (uint32_t)e : len - 1);
+                        v[j] = (uint32_t)skey[run_in(sidx, soff, s, ec)];
+                    }
+                }
+                store_quad(a.out, n, head, p + u * row, v);
+            }
         }
     }
+}
+__device__ __forceinline__ void emit_rows_body(const Args& a, uint32_t bid, uint32_t nblk) {
+    if (!a.c->emit_main) return;
+    __shared__ EmitRowsLds L;
+    if (a.ew == 4) emit_rows_impl<4>(a, bid, nblk, L);
+    else emit_rows_impl<2>(a, bid, nblk, L);
 }
 CAFS_KERNELS0(emit_rows, kEmitRowsThreads)
 

@@ -205,11 +205,11 @@ __device__ void plan_block(const Args& a) {
     c->guard_done = 0;
     c->spill = 0;
     RadixJob& j = c->rj;
-    j.src_k = a.in; j.src_v = nullptr;
-    j.dst_k = a.out; j.dst_v = nullptr;
-    j.tmp_k = a.tmp_k; j.tmp_v = nullptr;
+    j.src_k = a.in; j.src_v = a.vin;
+    j.dst_k = a.out; j.dst_v = a.vout;
+    j.tmp_k = a.tmp_k; j.tmp_v = a.spill_v;  // (the spill list is not used when the radix engine sorts the column)
     j.n = n;
-    j.has_vals = 0;
+    j.has_vals = a.vin ? 1u : 0u;
     j.n_active = 0;
     j.copy_mode = 0;
     j.src_ew = a.ew;
