@@ -340,6 +340,12 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     mark(0);
     cafs::k_pre<<<1, 1024, 0, s>>>(a);
     if (n > cafs::kMonoPrefix) cafs::k_mono_full<<<grid_for(n, 256 * 16, cus * 4), 256, 0, s>>>(a);
+    if (n >= cafs::kReplanMinN) {
+        // heavy-tailed estimates: the count's geometry from a larger sample
+        cafs::k_sample2_clear<<<128, 256, 0, s>>>(a);
+        cafs::k_sample2<<<cafs::kSamples2 / 256, 256, 0, s>>>(a);
+        cafs::k_replan<<<(1u << cafs::kSample2SlotsLog2) / (256 * 4), 256, 0, s>>>(a);
+    }
     const bool countable = n >= cafs::kSmallN;  // tiny and main need N >= 2048
     if (countable)
         cafs::k_phase2<<<grid_for(std::max<uint64_t>(n / 2, cap_ws), 256 * 4, cus * 4), 256, 0, s>>>(a);

@@ -51,6 +51,14 @@ constexpr uint32_t kScatterChunk = kScatterThreads * 8;  // elements staged per 
 constexpr uint32_t kXcds = 8;                  // accelerator dies
 constexpr uint32_t kSpillFracDiv = 4;          // the radix engine takes over when the spill passes N / this
 constexpr uint32_t kMinTableLog2 = 12;         // smallest global table (4096 slots)
+// Engine planning from a larger sample, for long columns whose estimate shows a
+// heavy tail (many singletons among the 1024 samples): the hash count's geometry
+// then follows Chao1 over kSamples2 strided samples (the reported estimate, path
+// and table M stay the paper's).
+constexpr uint64_t kReplanMinN = 1ull << 22;
+constexpr uint32_t kReplanMinF1 = 128;
+constexpr uint32_t kSamples2 = 65536;
+constexpr uint32_t kSample2SlotsLog2 = 18;     // hash set of the large sample (load <= 1/4)
 constexpr uint32_t kMaxTableLog2 = 22;         // largest global table (4M slots, 64 MiB)
 constexpr uint32_t kTableFloorLog2 = 16;       // global table never smaller (64K slots) when the workspace allows
 constexpr uint32_t kRankMax = 32768;           // K ordered by ranking (larger K: pair radix sort)
@@ -120,6 +128,9 @@ struct Ctrl {
     uint32_t cap_log2;                // GPU global table size (log2 slots)
     uint32_t cap_limit;               // claimed slots allowed; keys arriving later spill
     uint32_t part_log2;               // hash partitions of the count workgroups (log2)
+    uint32_t replan;                  // plan the count again from the larger sample
+    uint32_t s2acc[3 + kMaxParts];    // the larger sample: u, f1, f2, elements per 16 partitions
+    uint32_t s2done;
     uint32_t lds_wide;                // LDS buckets of 4 keys (else 2)
     // tiny count: each key's counter on a line of its own (every workgroup adds to them)
     alignas(128) uint64_t tiny_cnt[8][16];
@@ -132,8 +143,11 @@ struct Ctrl {
     alignas(128) uint64_t ecount;     // elements equal to kEmpty
     alignas(128) uint64_t nspill;     // (key, count) pairs on the spill list
     uint64_t spill_limit;             // past this many the radix engine takes over
-    uint64_t pcap;                    // elements each partition's bucket holds
-    alignas(128) uint32_t pfill[kMaxParts][32];  // elements scattered to each bucket (one line each)
+    // partition buckets in pbuf: bucket q is [pbase[q], pbase[q + 1]); the overflow
+    // area after the last bucket, [pbase[P], pbase[P + 1]), takes what a full bucket
+    // cannot (its keys are of any partition)
+    uint64_t pbase[kMaxParts + 2];
+    alignas(128) uint32_t pfill[kMaxParts + 1][32];  // elements sent to each bucket and the overflow area
     // where the sorted column is when the radix engine ran (the output, or scratch
     // when sorting in place on the main path, copied out after the guard)
     uint64_t* sorted;

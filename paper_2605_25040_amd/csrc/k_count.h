@@ -564,16 +564,6 @@ __device__ __forceinline__ bool run_lengths(const uint64_t (&x)[NE], uint32_t wa
     return any;
 }
 
-// The count's work items: with P = 2^pl partitions, item i is the range s of S of
-// bucket q = i mod P, s = i div P, with S = max(1, nblk / P); workgroup b takes items
-// b, b + nblk, ...  Without partitions item b is the b-th of nblk ranges of the
-// column.  Ranges are whole 16-byte pairs of their array.
-__device__ __forceinline__ uint32_t count_item_total(uint32_t pl, uint32_t nblk) {
-    const uint32_t P = 1u << pl;
-    const uint32_t S = nblk / P > 1 ? nblk / P : 1u;
-    return pl ? P * S : nblk;
-}
-
 // Each range of a workgroup's region of the deferred-element scratch (tmp_k) holds
 // 2 ceil(pairs / nblk) elements (tmp_k has room for n + 2 + 2 * kMaxCountBlocks
 // keys); deferrals past it go to the global table directly.
@@ -651,13 +641,14 @@ __device__ __forceinline__ bool block_overflow(const Ctrl* c, uint32_t* s_flag) 
 // partition (a wave matches equal partitions by ballots and takes one LDS counter
 // update per partition), staged in LDS in partition order, given a place in each
 // bucket by one atomic per partition and chunk, and written out as runs of
-// consecutive elements.  A bucket holds pcap elements (an eighth more than an even
-// share, plus a chunk); elements past it go to the spill list.
+// consecutive elements.  A bucket holds a sixteenth more than its planned share
+// plus a chunk; elements past it go to the overflow area (a reservation per
+// partition and chunk), and past that to the spill list.
 __device__ __forceinline__ void part_scatter_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (c->engine != E_HASH || c->part_log2 == 0) return;
     const uint32_t pl = c->part_log2;
-    const uint64_t pcap = c->pcap;
+    const uint32_t P = 1u << pl;
     const uint64_t mul = a.table_mul;
     const GTable t = gtable(a);
     const uint64_t n = a.n;
@@ -666,6 +657,10 @@ __device__ __forceinline__ void part_scatter_body(const Args& a, uint32_t bid, u
     __shared__ uint32_t lcnt[kMaxParts];
     __shared__ uint32_t loff[kMaxParts];
     __shared__ uint64_t gbase[kMaxParts];
+    __shared__ uint64_t pb0[kMaxParts + 2];   // the bucket bounds
+    __shared__ uint32_t ofirst[kMaxParts];    // first chunk-local index of a bucket that overflows
+    __shared__ uint64_t obase[kMaxParts];     // its place in the overflow area
+    if (threadIdx.x < P + 2) pb0[threadIdx.x] = c->pbase[threadIdx.x];
     const uint32_t tid = threadIdx.x, lane = __lane_id();
     const uint64_t lt = (1ull << lane) - 1;
     const uint64_t chunks = (n + kScatterChunk - 1) / kScatterChunk;
@@ -700,7 +695,16 @@ __device__ __forceinline__ void part_scatter_body(const Args& a, uint32_t bid, u
                 run += lcnt[qq];
             }
         }
-        if (tid < (1u << pl)) gbase[tid] = lcnt[tid] ? atomicAdd(&c->pfill[tid][0], lcnt[tid]) : 0u;
+        if (tid < P) {
+            const uint32_t lc = lcnt[tid];
+            const uint64_t g = lc ? atomicAdd(&c->pfill[tid][0], lc) : 0u;
+            const uint64_t cap = pb0[tid + 1] - pb0[tid];
+            gbase[tid] = g;
+            // elements past the bucket's capacity go to the overflow area
+            const uint64_t fit = g >= cap ? 0 : (cap - g < lc ? cap - g : lc);
+            ofirst[tid] = (uint32_t)fit;
+            obase[tid] = fit < lc ? atomicAdd(&c->pfill[kMaxParts][0], (uint32_t)(lc - fit)) : 0u;
+        }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -713,10 +717,13 @@ __device__ __forceinline__ void part_scatter_body(const Args& a, uint32_t bid, u
             const bool ok = i < cnt;
             const uint64_t v = ok ? stage[i] : 0;
             const uint32_t qq = mul_hash32(v, 32, mul) >> (32 - pl);
-            const uint64_t dst = ok ? gbase[qq] + (i - loff[qq]) : 0;
-            const bool fits = dst < pcap;
-            if (ok && fits) pbuf[qq * pcap + dst] = v;
-            spill_pairs(t, ok && !fits, v, 1);
+            const uint32_t li = ok ? i - loff[qq] : 0u;
+            const bool in_bucket = li < ofirst[qq];
+            const uint64_t odst = obase[qq] + (li - ofirst[qq]);
+            const bool in_over = !in_bucket && odst < pb0[P + 1] - pb0[P];
+            if (ok && in_bucket) pbuf[pb0[qq] + gbase[qq] + li] = v;
+            if (ok && in_over) pbuf[pb0[P] + odst] = v;
+            spill_pairs(t, ok && !in_bucket && !in_over, v, 1);
         }
         __syncthreads();
     }
@@ -786,7 +793,49 @@ __device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uin
     else hash_count_impl<false, 8>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
 }
 
-// This workgroup's work items (count_item_total) with LDS buckets of W keys.
+// The contents of the partition buckets and the overflow area, taken as one
+// sequence (each part's length rounded up to even, so that pairs stay aligned),
+// split evenly over the items in multiples of 64 elements: item `it` counts its
+// share, one contiguous range of a part at a time, each range with a cleared LDS
+// table and its deferrals at the same place in tmp_k as the range in pbuf.
+template <uint32_t W>
+__device__ __forceinline__ void count_parts(const Args& a, const GTable& t, uint64_t* skeys, uint32_t* scnt,
+                                            uint32_t& s_ndef, uint32_t& s_flag, uint32_t* s_sink, uint32_t it,
+                                            uint32_t items, uint32_t pl) {
+    Ctrl* c = a.c;
+    const uint32_t P = 1u << pl;
+    uint64_t len[kMaxParts + 1];
+    uint64_t total = 0;
+    for (uint32_t q = 0; q <= P; ++q) {
+        const uint64_t cap = c->pbase[q + 1] - c->pbase[q];
+        const uint64_t fill = c->pfill[q == P ? kMaxParts : q][0];
+        len[q] = fill < cap ? fill : cap;
+        total += (len[q] + 1) & ~1ull;
+    }
+    const uint64_t per = ((total + items - 1) / items + 63) & ~63ull;
+    const uint64_t v0 = (uint64_t)it * per, v1 = v0 + per < total ? v0 + per : total;
+    uint64_t f = 0;  // start of part q in the sequence
+    for (uint32_t q = 0; q <= P && f < v1; ++q) {
+        const uint64_t lv = (len[q] + 1) & ~1ull;
+        const uint64_t s0 = v0 > f ? v0 - f : 0, s1 = v1 - f < lv ? v1 - f : lv;
+        if (s0 < s1) {
+            const uint64_t base = c->pbase[q];  // a multiple of 32 elements
+            CAFS_GLOBAL uint64_t* region = gp(a.tmp_k) + base + s0;
+            for (uint32_t i = threadIdx.x; i < kLdsSlots; i += blockDim.x) {
+                skeys[i] = kEmpty;
+                scnt[i] = 0;
+            }
+            if (threadIdx.x == 0) s_ndef = 0;
+            __syncthreads();
+            count_range<W, 8>(a, t, skeys, scnt, s_ndef, s_sink, &s_flag, a.pbuf + base, len[q], 0, s0 / 2, s1 / 2,
+                              pl, region, (uint32_t)(s1 - s0));
+            __syncthreads();
+        }
+        f += lv;
+    }
+}
+
+// This workgroup's work items with LDS buckets of W keys.
 template <uint32_t W, bool PARTS, uint32_t EW>
 __device__ __forceinline__ void count_items(const Args& a, uint32_t bid, uint32_t nblk, uint64_t* skeys, uint32_t* scnt,
                                             uint32_t& s_ndef, uint32_t& s_flag, uint32_t* s_sink) {
@@ -795,7 +844,7 @@ __device__ __forceinline__ void count_items(const Args& a, uint32_t bid, uint32_
     const GTable t = gtable(a);
     const uint64_t n = a.n;
     const uint32_t pl = PARTS ? c->part_log2 : 0u;
-    const uint32_t items = PARTS ? count_item_total(pl, nblk) : nblk;
+    const uint32_t items = nblk;
     for (uint32_t it = bid; it < items; it += nblk) {  // uniform over the workgroup
         const uint64_t* src;
         uint64_t ns, pb, pe, roff;  // roff: where the item's deferral region starts in tmp_k
@@ -820,16 +869,8 @@ __device__ __forceinline__ void count_items(const Args& a, uint32_t bid, uint32_
             pe = pb + PS < P ? pb + PS : P;
             roff = 2 * pb;
         } else {
-            const uint32_t P = 1u << pl, Sn = items / P;
-            const uint32_t q = it % P, sidx = it / P;
-            const uint64_t fill = c->pfill[q][0];
-            ns = fill < c->pcap ? fill : c->pcap;
-            src = a.pbuf + (uint64_t)q * c->pcap;  // 256-byte aligned buckets (pcap is a multiple of 32)
-            head = 0;
-            const uint64_t Pq = num_pairs(ns, 0), PS = (Pq + Sn - 1) / Sn;
-            pb = (uint64_t)sidx * PS < Pq ? (uint64_t)sidx * PS : Pq;
-            pe = pb + PS < Pq ? pb + PS : Pq;
-            roff = (uint64_t)q * c->pcap + 2 * pb;
+            count_parts<W>(a, t, skeys, scnt, s_ndef, s_flag, s_sink, it, items, pl);
+            continue;
         }
         // the region holds every element of the item (tmp_k covers the column and
         // every bucket), so a deferral always finds room

@@ -516,11 +516,16 @@ __device__ __forceinline__ void copy_mono_body(const Args& a, uint32_t bid, uint
 CAFS_KERNELS0(copy_mono, 256)
 
 // Run-length pass over the sorted output, needed when the column was not counted
-// (monotone input, radix engine) but the report, the counts or the guard need
-// the (key, count) pairs.
+// (monotone input, radix engine) but the report needs K, or the counts or the
+// guard need the (key, count) pairs.  The first pass alone gives K; the pairs are
+// written only when they are needed.
 __device__ __forceinline__ bool rle_needed(const Args& a, const Ctrl* c) {
     if (c->dense_ready && !c->overflow) return false;
     return a.want_report || a.want_counts || (c->path == P_MAIN);
+}
+__device__ __forceinline__ bool rle_pairs_needed(const Args& a, const Ctrl* c) {
+    if (c->dense_ready && !c->overflow) return false;
+    return a.want_counts || (c->path == P_MAIN);
 }
 
 // Pass 1: runs starting in each tile; the last workgroup scans the tile counts.
@@ -540,8 +545,19 @@ __device__ __forceinline__ void rle_count_body(const Args& a, uint32_t bid, uint
         const uint64_t b = t * kRleTile;
         const uint64_t e = (b + kRleTile < n) ? b + kRleTile : n;
         uint32_t local = 0;
-        for (uint64_t i = b + threadIdx.x; i < e; i += blockDim.x)
-            local += (i == 0) || (load_key(y, i, yw) != load_key(y, i - 1, yw));
+        constexpr uint32_t G = kRleTile / 256;  // elements per thread, loads all in flight
+        uint64_t cur[G], prv[G];
+#pragma unroll
+        for (uint32_t u = 0; u < G; ++u) {
+            const uint64_t i = b + (uint64_t)u * blockDim.x + threadIdx.x;
+            cur[u] = i < e ? load_key(y, i, yw) : 0;
+            prv[u] = (i < e && i > 0) ? load_key(y, i - 1, yw) : ~cur[u];  // element 0 starts a run
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < G; ++u) {
+            const uint64_t i = b + (uint64_t)u * blockDim.x + threadIdx.x;
+            local += (i < e && cur[u] != prv[u]) ? 1u : 0u;
+        }
         local = wave_sum_u32(local);
         if (__lane_id() == 0) atomicAdd(&s_cnt, local);
         __syncthreads();
@@ -591,7 +607,7 @@ CAFS_KERNELS0(rle_count, 256)
 // back with coalesced stores (their places in the output are consecutive).
 __device__ __forceinline__ void rle_write_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
-    if (!rle_needed(a, c)) return;
+    if (!rle_pairs_needed(a, c)) return;
     const uint64_t n = a.n;
     const uint64_t* y = c->sorted;
     const uint32_t yw = c->sorted_ew;
@@ -646,7 +662,7 @@ CAFS_KERNELS0(rle_write, 256)
 // Pass 3: counts from consecutive offsets; marks the pairs ready for the guard.
 __device__ __forceinline__ void rle_counts_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
-    if (!rle_needed(a, c)) return;
+    if (!rle_pairs_needed(a, c)) return;
     const uint64_t K = c->K;
     const uint64_t gtid = (uint64_t)bid * blockDim.x + threadIdx.x;
     const uint64_t gstride = (uint64_t)nblk * blockDim.x;

@@ -117,6 +117,86 @@ __device__ __forceinline__ uint64_t paper_table_M(uint64_t k_hat, uint64_t n, ui
     return m;
 }
 
+// Partition buckets: each a sixteenth more than its share of the column plus a
+// scatter chunk, rounded to 32 elements (256 bytes); the rest of pbuf is the
+// overflow area.  Shares are even, or `mass` (sampled elements per partition,
+// summing to `total`) when given.  False when the buckets do not fit.
+__device__ bool set_buckets(const Args& a, Ctrl* c, uint32_t pl, const uint32_t* mass, uint64_t total = 0) {
+    const uint32_t P = 1u << pl;
+    uint64_t at = 0;
+    for (uint32_t q = 0; q < P; ++q) {
+        const uint64_t share = mass ? (uint64_t)((double)a.n * mass[q] / (double)total) : (a.n >> pl);
+        const uint64_t cap = (share + share / 16 + kScatterChunk + 31) / 32 * 32;
+        c->pbase[q] = at;
+        at += cap;
+    }
+    c->pbase[P] = at;
+    if (at + a.n / 32 > a.pbuf_elems) return false;
+    c->pbase[P + 1] = a.pbuf_elems / 32 * 32;
+    return true;
+}
+
+// The hash count's geometry for an estimate kh of K: partitions of about part_keys
+// estimated keys each (at most 2^kMaxPartLog2), LDS buckets of 4 keys when a
+// partition's share reaches wide_min, a global table of table_slots kh slots (half
+// of them may be claimed; keys past that spill).  Returns the engine: the radix
+// engine when kh is more than the partitions' LDS tables or the global table hold
+// (the estimate is close to K for flat frequencies, and there most elements of the
+// keys beyond would spill).
+__device__ uint32_t plan_count(const Args& a, Ctrl* c, uint64_t kh, uint32_t engine) {
+    const uint64_t n = a.n;
+    // (no partitions up to twice part_keys: one LDS table holds that many keys, and
+    // partitions cost a scatter pass over the column)
+    const uint64_t parts = kh <= 2 * a.part_keys ? 1 : (kh + a.part_keys - 1) / a.part_keys;
+    uint32_t pl = parts <= 1 ? 0u : log2_pow2(bit_ceil64(parts));
+    if (pl > kMaxPartLog2) pl = kMaxPartLog2;
+    if (pl && !set_buckets(a, c, pl, nullptr)) pl = 0;
+    c->part_log2 = pl;
+    c->lds_wide = (kh >> pl) >= a.wide_min ? 1u : 0u;
+    uint32_t lg = log2_pow2(bit_ceil64(a.table_slots * kh));
+    if (lg < kMinTableLog2) lg = kMinTableLog2;
+    const uint32_t floor_lg = kTableFloorLog2 < a.cap_ws_log2 ? kTableFloorLog2 : a.cap_ws_log2;
+    if (lg < floor_lg) lg = floor_lg;
+    if (lg > a.cap_ws_log2) lg = a.cap_ws_log2;
+    if (kh > (a.part_keys << (kMaxPartLog2 + 1)) || 2 * kh > (1ull << a.cap_ws_log2)) engine = E_RADIX;
+    c->cap_log2 = lg;
+    c->cap_limit = (uint32_t)((1ull << lg) / 2);  // linear probing stays short up to half load
+    return engine;
+}
+
+// Engine-dependent state: which later stages run, and the radix job (the column,
+// or scratch when sorting in place on the main path).
+__device__ void plan_engine_state(const Args& a, Ctrl* c, int32_t path, uint32_t engine) {
+    c->engine = engine;
+    c->radix_on = (engine == E_RADIX);
+    c->guard_on = (path == P_MAIN && engine == E_RADIX);
+    c->guard_general = c->guard_on;
+    RadixJob& j = c->rj;
+    j.src_k = a.in; j.src_v = a.vin;
+    j.dst_k = a.out; j.dst_v = a.vout;
+    j.tmp_k = a.tmp_k; j.tmp_v = a.spill_v;  // (the spill list is not used when the radix engine sorts the column)
+    j.n = a.n;
+    j.has_vals = a.vin ? 1u : 0u;
+    j.n_active = 0;
+    j.copy_mode = 0;
+    j.src_ew = a.ew;
+    j.dst_ew = a.ew;
+    c->sorted = a.out;
+    c->sorted_ew = a.ew;
+    c->deferred_copy = 0;
+    if (path == P_MAIN && engine == E_RADIX && a.in == a.out) {
+        // in place on the main path: the guard still reads the input after the sort,
+        // so sort into scratch (ping-pong with the dense key array, written later)
+        j.dst_k = a.tmp_k;
+        j.dst_ew = 8;
+        j.tmp_k = a.uniq;
+        c->sorted = a.tmp_k;
+        c->sorted_ew = 8;
+        c->deferred_copy = 1;
+    }
+}
+
+
 // Dispatcher (Alg. 3): picks the path and the engine and resets the counters
 // of the later stages.  Called by every thread of one workgroup once the order
 // check is settled: by the pre kernel when its prefix already shows an inversion
@@ -137,45 +217,14 @@ __device__ void plan_block(const Args& a) {
     c->table_M = 0;
     c->cap_log2 = kMinTableLog2;
     c->part_log2 = 0;
-    c->pcap = 0;
     c->lds_wide = 0;
     if (path == P_TINY || path == P_MAIN) {
-        const uint64_t kh = c->k_hat;
-        c->table_M = paper_table_M(kh, n, a.cap);
-        // the hash count: partitions of about part_keys estimated keys each (at most
-        // 2^kMaxPartLog2), LDS buckets of 4 keys when a partition's share of the
-        // estimate reaches wide_min
-        // (no partitions up to twice part_keys: one LDS table holds that many keys,
-        // and partitions cost a scatter pass over the column)
-        const uint64_t parts = kh <= 2 * a.part_keys ? 1 : (kh + a.part_keys - 1) / a.part_keys;
-        uint32_t pl = parts <= 1 ? 0u : log2_pow2(bit_ceil64(parts));
-        if (pl > kMaxPartLog2) pl = kMaxPartLog2;
-        // each bucket: an eighth more than an even share and a scatter chunk, a
-        // multiple of 32 elements (256 bytes)
-        const uint64_t share = n >> pl;
-        const uint64_t pcap = (share + share / 8 + kScatterChunk + 31) / 32 * 32;
-        if (pl && (pcap << pl) > a.pbuf_elems) pl = 0;
-        c->part_log2 = pl;
-        c->pcap = pcap;
-        c->lds_wide = (kh >> pl) >= a.wide_min ? 1u : 0u;
-        // the global table: table_slots K^ slots (half of them may be claimed); keys
-        // past that spill
-        uint32_t lg = log2_pow2(bit_ceil64(a.table_slots * kh));
-        if (lg < kMinTableLog2) lg = kMinTableLog2;
-        const uint32_t floor_lg = kTableFloorLog2 < a.cap_ws_log2 ? kTableFloorLog2 : a.cap_ws_log2;
-        if (lg < floor_lg) lg = floor_lg;
-        if (lg > a.cap_ws_log2) lg = a.cap_ws_log2;
-        // more keys than the partitions' LDS tables or the global table hold (the
-        // estimate is close to K for flat frequencies, and there most elements of
-        // the keys beyond would spill): the radix engine sorts instead
-        if (kh > (a.part_keys << (kMaxPartLog2 + 1)) || 2 * kh > (1ull << a.cap_ws_log2)) engine = E_RADIX;
-        c->cap_log2 = lg;
+        c->table_M = paper_table_M(c->k_hat, n, a.cap);
+        engine = plan_count(a, c, c->k_hat, engine);
     }
-    const uint64_t cap = 1ull << c->cap_log2;
-    c->cap_limit = (uint32_t)(cap / 2);  // linear probing stays short up to half load
     c->nspill = 0;
     c->spill_limit = n / kSpillFracDiv;
-    for (uint32_t q = 0; q < kMaxParts; ++q) c->pfill[q][0] = 0;
+    for (uint32_t q = 0; q <= kMaxParts; ++q) c->pfill[q][0] = 0;
     c->path = path;
     c->engine = engine;
     c->tiny_miss = 0;
@@ -189,9 +238,6 @@ __device__ void plan_block(const Args& a) {
     c->emit_main = 0;
     c->dense_ready = 0;
     c->pair_sort = 0;
-    c->radix_on = (engine == E_RADIX);
-    c->guard_on = (path == P_MAIN && engine == E_RADIX);
-    c->guard_general = c->guard_on;
     c->guard_rounds = 0;
     c->hist_done = 0;
     c->rle_done = 0;
@@ -204,29 +250,10 @@ __device__ void plan_block(const Args& a) {
     c->chunk_ctr = 0;
     c->guard_done = 0;
     c->spill = 0;
-    RadixJob& j = c->rj;
-    j.src_k = a.in; j.src_v = a.vin;
-    j.dst_k = a.out; j.dst_v = a.vout;
-    j.tmp_k = a.tmp_k; j.tmp_v = a.spill_v;  // (the spill list is not used when the radix engine sorts the column)
-    j.n = n;
-    j.has_vals = a.vin ? 1u : 0u;
-    j.n_active = 0;
-    j.copy_mode = 0;
-    j.src_ew = a.ew;
-    j.dst_ew = a.ew;
-    c->sorted = a.out;
-    c->sorted_ew = a.ew;
-    c->deferred_copy = 0;
-    if (path == P_MAIN && engine == E_RADIX && a.in == a.out) {
-        // in place on the main path: the guard still reads the input after the sort,
-        // so sort into scratch (ping-pong with the dense key array, written later)
-        j.dst_k = a.tmp_k;
-        j.dst_ew = 8;
-        j.tmp_k = a.uniq;
-        c->sorted = a.tmp_k;
-        c->sorted_ew = 8;
-        c->deferred_copy = 1;
-    }
+    c->replan = (path == P_MAIN && engine == E_HASH && n >= kReplanMinN && c->f1 >= kReplanMinF1) ? 1u : 0u;
+    for (uint32_t i = 0; i < 3 + kMaxParts; ++i) c->s2acc[i] = 0;
+    c->s2done = 0;
+    plan_engine_state(a, c, path, engine);
 }
 
 // First kernel of a sort: order check of a prefix and the Chao1 estimate.
@@ -343,6 +370,124 @@ __device__ __forceinline__ void finalize_body(const Args& a, uint32_t bid, uint3
     *a.report = r;
 }
 CAFS_KERNELS0(finalize, 64)
+
+// The larger sample: kSamples2 strided keys counted in a hash set in the deferral
+// scratch (free until the count): keys at tmp_k[0, S), counts after them.
+__device__ __forceinline__ uint32_t* sample2_counts(const Args& a) {
+    return reinterpret_cast<uint32_t*>(a.tmp_k + (1ull << kSample2SlotsLog2));
+}
+__device__ __forceinline__ void sample2_clear_body(const Args& a, uint32_t bid, uint32_t nblk) {
+    if (!a.c->replan) return;
+    const uint32_t S = 1u << kSample2SlotsLog2;
+    uint32_t* cnt = sample2_counts(a);
+    for (uint32_t i = bid * blockDim.x + threadIdx.x; i < S; i += nblk * blockDim.x) {
+        gp(a.tmp_k)[i] = kEmpty;
+        gp(cnt)[i] = 0;
+    }
+}
+CAFS_KERNELS0(sample2_clear, 256)
+
+// 256 samples per workgroup, merged in LDS first (a heavy key takes one update of
+// the shared set per workgroup instead of one per sample).
+__device__ __forceinline__ void sample2_body(const Args& a, uint32_t bid, uint32_t nblk) {
+    if (!a.c->replan) return;
+    constexpr uint32_t LS = 1024;  // LDS set of 256 samples
+    __shared__ uint64_t lk[LS];
+    __shared__ uint32_t lc[LS];
+    for (uint32_t i = threadIdx.x; i < LS; i += blockDim.x) {
+        lk[i] = kEmpty;
+        lc[i] = 0;
+    }
+    __syncthreads();
+    const uint64_t stride = a.n / kSamples2;
+    const uint32_t s = bid * blockDim.x + threadIdx.x;  // (grid * block == kSamples2)
+    const uint64_t v = load_key(a.in, (uint64_t)s * stride, a.ew);
+    if (v != kEmpty) {  // (planning only: that one key is left out)
+        uint32_t h = phi_hash(v, 10);
+        for (uint32_t probe = 0; probe < LS; ++probe) {
+            const unsigned long long old =
+                atomicCAS((unsigned long long*)&lk[h], (unsigned long long)kEmpty, (unsigned long long)v);
+            if (old == kEmpty || old == v) {
+                atomicAdd(&lc[h], 1u);
+                break;
+            }
+            h = (h + 1) & (LS - 1);
+        }
+    }
+    __syncthreads();
+    const uint32_t mask = (1u << kSample2SlotsLog2) - 1;
+    uint32_t* cnt = sample2_counts(a);
+    for (uint32_t i = threadIdx.x; i < LS; i += blockDim.x) {
+        const uint32_t cn = lc[i];
+        if (!cn) continue;
+        const uint64_t key = lk[i];
+        uint32_t h = phi_hash(key, kSample2SlotsLog2);
+        for (uint32_t probe = 0; probe <= mask; ++probe) {
+            const uint64_t old = g_cas(&a.tmp_k[h], kEmpty, key);
+            if (old == kEmpty || old == key) {
+                g_add(&cnt[h], cn);
+                break;
+            }
+            h = (h + 1) & mask;
+        }
+    }
+}
+CAFS_KERNELS0(sample2, 256)
+
+// Chao1 of the larger sample (same formula as the paper's estimate) and the sampled
+// elements per 16 partitions (the partitions of fewer bits are their unions), by
+// every workgroup over its slots of the set; the last workgroup plans the hash count
+// for that estimate when it is above the paper's, with the partition buckets sized
+// by the sample (a few heavy keys can make one partition far larger than an even
+// share).
+__device__ __forceinline__ void replan_body(const Args& a, uint32_t bid, uint32_t nblk) {
+    Ctrl* c = a.c;
+    if (!c->replan) return;
+    const uint32_t S = 1u << kSample2SlotsLog2;
+    const CAFS_GLOBAL uint32_t* cnt = gp(sample2_counts(a));
+    const CAFS_GLOBAL uint64_t* keys = gp(a.tmp_k);
+    __shared__ uint32_t s_acc[3 + kMaxParts];  // u, f1, f2, mass of each of 16 partitions
+    __shared__ uint32_t s_last;
+    if (threadIdx.x < 3 + kMaxParts) s_acc[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t lu = 0, l1 = 0, l2 = 0;
+    for (uint32_t i = bid * blockDim.x + threadIdx.x; i < S; i += nblk * blockDim.x) {
+        const uint32_t cn = cnt[i];
+        lu += cn > 0;
+        l1 += cn == 1;
+        l2 += cn == 2;
+        if (cn) atomicAdd(&s_acc[3 + (mul_hash32(keys[i], 32, a.table_mul) >> (32 - kMaxPartLog2))], cn);
+    }
+    lu = wave_sum_u32(lu); l1 = wave_sum_u32(l1); l2 = wave_sum_u32(l2);
+    if (__lane_id() == 0) { atomicAdd(&s_acc[0], lu); atomicAdd(&s_acc[1], l1); atomicAdd(&s_acc[2], l2); }
+    __syncthreads();
+    if (threadIdx.x < 3 + kMaxParts && s_acc[threadIdx.x]) atomicAdd(&c->s2acc[threadIdx.x], s_acc[threadIdx.x]);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(&c->s2done, 1u) == nblk - 1);
+    __syncthreads();
+    if (!s_last || threadIdx.x != 0) return;
+    __threadfence();
+    uint32_t acc[3 + kMaxParts];
+    for (uint32_t i = 0; i < 3 + kMaxParts; ++i) acc[i] = atomic_load_agent(&c->s2acc[i]);
+    const uint64_t u = acc[0], f1 = acc[1], f2 = acc[2];
+    const uint64_t k2 = u >= kSamples2 ? a.n : u + (f1 * f1) / (2 * (f2 + 1));
+    if (k2 <= c->k_hat) return;
+    const uint32_t engine = plan_count(a, c, k2, E_HASH);
+    plan_engine_state(a, c, c->path, engine);
+    const uint32_t pl = c->part_log2;
+    if (engine != E_HASH || pl == 0) return;
+    uint32_t mass[kMaxParts];
+    uint64_t total = 0;
+    const uint32_t span = 1u << (kMaxPartLog2 - pl);  // 16-partition cells per partition
+    for (uint32_t q = 0; q < (1u << pl); ++q) {
+        mass[q] = 0;
+        for (uint32_t j = 0; j < span; ++j) mass[q] += acc[3 + q * span + j];
+        total += mass[q];
+    }
+    if (total > 0 && !set_buckets(a, c, pl, mass, total)) set_buckets(a, c, pl, nullptr);
+}
+CAFS_KERNELS0(replan, 256)
 
 // Report of an empty column (n = 0): path MONOTONE, everything else zero.
 __global__ void k_report_empty(cafs_report_t* r) {
