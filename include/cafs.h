@@ -102,7 +102,13 @@ typedef struct {
  * send to the spill, counted in elements) are set on MAIN and GUARD only.
  * k_exact is the exact number of distinct keys.  engine is a cafs_engine_t.
  * flags: bit 0 = the GPU hash table overflowed and the radix engine sorted the
- * column instead; bit 1 = the guard needed the first-occurrence pass. */
+ * column instead; bit 1 = the guard needed the first-occurrence pass; bit 2 =
+ * some keys went to the spill list, which was sorted and folded.
+ * Every field up to k_exact is a function of the column alone.  engine and flags
+ * describe what ran: which keys claim a slot of the global table first is
+ * decided by timing, so a column near the table's limits can take the spill
+ * list, or the radix engine, on one call and not on the next (the sorted output,
+ * counts and the fields above are the same either way). */
 typedef struct {
     cafs_estimate_t est;
     int32_t path;
@@ -124,7 +130,8 @@ void cafs_ctx_destroy(cafs_ctx_t* ctx);
 /* Per-stage timing.  While enabled, every cafs_sort_i64/u64/f64 call on the context
  * records HIP events on its stream at the stage boundaries:
  *   0 pre    order check, Chao1 estimate, dispatch, table
- *            initialisation and tiny count                 (Alg. 2, Alg. 3, Sec. 4.4)
+ *            initialisation, tiny count, and the hash-partition
+ *            scatter of columns estimated above 12000 keys (Alg. 2, Alg. 3, Sec. 4.4)
  *   1 count  hash count with run-length injection, and its pass over
  *            deferred elements (one kernel)                (Sec. 4.4)
  *   2 order  ranking of up to 32768 distinct keys, run offsets and the guard's

@@ -375,3 +375,10 @@ def parse_report_bytes(raw):
 
 def report_size():
     return ctypes.sizeof(Report)
+
+
+def report_fixed_bytes():
+    """Bytes of a report that are a function of the column alone (the estimate, path,
+    tiny miss, table M, spill and K); the engine and flags words after them record
+    what ran."""
+    return Report.engine.offset

@@ -340,20 +340,22 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     mark(0);
     cafs::k_pre<<<1, 1024, 0, s>>>(a);
     if (n > cafs::kMonoPrefix) cafs::k_mono_full<<<grid_for(n, 256 * 16, cus * 4), 256, 0, s>>>(a);
-    if (n >= cafs::kReplanMinN) {
-        // heavy-tailed estimates: the count's geometry from a larger sample
-        cafs::k_sample2_clear<<<128, 256, 0, s>>>(a);
-        cafs::k_sample2<<<cafs::kSamples2 / 256, 256, 0, s>>>(a);
-        cafs::k_replan<<<(1u << cafs::kSample2SlotsLog2) / (256 * 4), 256, 0, s>>>(a);
-    }
+    if (n >= cafs::kReplanMinN)  // heavy-tailed estimates: the count's geometry from a larger sample
+        cafs::k_sample2<<<cafs::kSamples2 / cafs::kSamples2Block, cafs::kSamples2Block, 0, s>>>(a);
     const bool countable = n >= cafs::kSmallN;  // tiny and main need N >= 2048
     if (countable)
         cafs::k_phase2<<<grid_for(std::max<uint64_t>(n / 2, cap_ws), 256 * 4, cus * 4), 256, 0, s>>>(a);
-    mark(1);
+    if (countable)
+        cafs::k_part_scatter<<<grid_for(n, cafs::kScatterChunk * 4, cus * 2), cafs::kScatterThreads, 0, s>>>(a);
+    mark(1);  // (the count stage brackets the hash count kernel alone)
     const uint32_t g_count = count_grid(n, cus);
     if (countable) {
-        cafs::k_part_scatter<<<grid_for(n, cafs::kScatterChunk * 4, cus * 2), cafs::kScatterThreads, 0, s>>>(a);
-        cafs::k_hash_count<<<g_count, cafs::kCountThreads, 0, s>>>(a);
+        if (a.ew == 4) cafs::k_hash_count32<<<g_count, cafs::kCountThreads, 0, s>>>(a);
+        else cafs::k_hash_count<<<g_count, cafs::kCountThreads, 0, s>>>(a);
+        // partitions need an estimate above twice part_keys, at most N / 2 on the
+        // main path, or the larger sample's estimate
+        if (n > 4 * a.part_keys || n >= cafs::kReplanMinN)
+            cafs::k_hash_count_parts<<<g_count, cafs::kCountThreads, 0, s>>>(a);
     }
     mark(2);
     if (countable) {
@@ -736,8 +738,15 @@ cafs_status_t check_columns(const cafs_column_t* cols, uint32_t n_cols, std::vec
 // Enqueues one batch.  col_ws[i] is column i's workspace (make_layout(n_i).total
 // bytes, 256-byte aligned); hdr_dev receives the header, staged through hdr_host
 // (pinned, at least P.header bytes, not reused before this upload has run).
+// A second stream with its fork and join events: the batch's partitioned count runs
+// there beside the other count variants.
+struct SideLane {
+    hipStream_t s;
+    hipEvent_t fork, join;
+};
+
 cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uint32_t n_cols, void* const* col_ws,
-                           const BatchShape& P, void* hdr_dev, void* hdr_host, hipStream_t s) {
+                           const BatchShape& P, void* hdr_dev, void* hdr_host, hipStream_t s, const SideLane& side) {
     char* h = static_cast<char*>(hdr_host);
     cafs::Args* args = reinterpret_cast<cafs::Args*>(h + P.off_args);
     for (uint32_t i = 0; i < n_cols; ++i) {
@@ -762,7 +771,24 @@ cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uin
     cafs::kb_mono_full<<<TP, 256, 0, s>>>(gp);
     cafs::kb_phase2<<<TP, 256, 0, s>>>(gp);
     cafs::kb_part_scatter<<<TP, cafs::kScatterThreads, 0, s>>>(gp);
-    cafs::kb_hash_count<<<TH, cafs::kCountThreads, 0, s>>>(gh);
+    // the count variants present in the batch (partitions need an estimate above
+    // twice part_keys, at most N / 2 on the main path)
+    bool any32 = false, any64 = false, any_parts = false;
+    for (uint32_t i = 0; i < n_cols; ++i) {
+        (elem_bytes((cafs_dtype_t)cols[i].dtype) == 4 ? any32 : any64) = true;
+        any_parts |= cols[i].n > 4 * args[i].part_keys;
+    }
+    // (a column's workgroups leave every variant's launch but one at once, so the
+    // partitioned count overlaps the others on the side stream)
+    if (any_parts) {
+        (void)hipEventRecord(side.fork, s);
+        (void)hipStreamWaitEvent(side.s, side.fork, 0);
+        cafs::kb_hash_count_parts<<<TH, cafs::kCountThreads, 0, side.s>>>(gh);
+        (void)hipEventRecord(side.join, side.s);
+    }
+    if (any64) cafs::kb_hash_count<<<TH, cafs::kCountThreads, 0, s>>>(gh);
+    if (any32) cafs::kb_hash_count32<<<TH, cafs::kCountThreads, 0, s>>>(gh);
+    if (any_parts) (void)hipStreamWaitEvent(s, side.join, 0);
     cafs::kb_rank<<<TP, 1024, 0, s>>>(gp);
     cafs::kb_compact_order<<<C, 1024, 0, s>>>(g1);
     cafs::kb_radix_hist<<<TP, 256, 0, s>>>(gp);
@@ -893,7 +919,7 @@ cafs_status_t cafs_sort_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols, ui
         }
         host = ctx->staging;
     }
-    st = launch_batch(ctx, h_cols, n_cols, col_ws.data(), P, d_ws, host, s);
+    st = launch_batch(ctx, h_cols, n_cols, col_ws.data(), P, d_ws, host, s, SideLane{ctx->side, ctx->fork, ctx->join});
     if (st != CAFS_OK) return st;
     if (cap == hipStreamCaptureStatusNone) {
         hipError_t e = hipEventRecord(ctx->staged, s);
@@ -1002,6 +1028,8 @@ struct cafs_server {
     std::deque<uint64_t> finished;
     struct Slot {
         hipStream_t s = nullptr;
+        hipStream_t side = nullptr;  // the slot's second stream (partitioned count)
+        hipEvent_t fork = nullptr, join = nullptr;
         hipEvent_t done = nullptr;
         void* hdr_dev = nullptr;
         void* hdr_host = nullptr;
@@ -1076,6 +1104,9 @@ cafs_status_t cafs_server_create(cafs_ctx_t* ctx, size_t hbm_budget, uint32_t n_
     const size_t hb = header_bound(max_batch);
     for (auto& sl : sv->slots) {
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.join, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
         if (e == hipSuccess) e = hipMalloc(&sl.hdr_dev, hb);
         if (e == hipSuccess) e = hipHostMalloc(&sl.hdr_host, hb, hipHostMallocDefault);
@@ -1095,9 +1126,13 @@ void cafs_server_destroy(cafs_server_t* sv) {
     DeviceGuard dg(sv->ctx->device);
     for (auto& sl : sv->slots) {
         if (sl.s) (void)hipStreamSynchronize(sl.s);
+        if (sl.side) (void)hipStreamSynchronize(sl.side);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.fork) (void)hipEventDestroy(sl.fork);
+        if (sl.join) (void)hipEventDestroy(sl.join);
         if (sl.hdr_dev) (void)hipFree(sl.hdr_dev);
         if (sl.hdr_host) (void)hipHostFree(sl.hdr_host);
+        if (sl.side) (void)hipStreamDestroy(sl.side);
         if (sl.s) (void)hipStreamDestroy(sl.s);
     }
     for (auto& kv : sv->reqs)
@@ -1205,7 +1240,8 @@ cafs_status_t cafs_server_poll(cafs_server_t* sv, uint64_t* h_tickets, uint32_t 
             r.state = 2;
         }
         const BatchShape P = shape_batch(ns.data(), m, sv->ctx->batch_per_block, sv->ctx->batch_per_hash_block);
-        cafs_status_t st = launch_batch(sv->ctx, cols.data(), m, ws.data(), P, sl.hdr_dev, sl.hdr_host, sl.s);
+        cafs_status_t st = launch_batch(sv->ctx, cols.data(), m, ws.data(), P, sl.hdr_dev, sl.hdr_host, sl.s,
+                                        SideLane{sl.side, sl.fork, sl.join});
         if (st != CAFS_OK) return st;
         hipError_t e = hipEventRecord(sl.done, sl.s);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");

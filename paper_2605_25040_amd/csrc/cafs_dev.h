@@ -58,6 +58,7 @@ constexpr uint32_t kMinTableLog2 = 12;         // smallest global table (4096 sl
 constexpr uint64_t kReplanMinN = 1ull << 22;
 constexpr uint32_t kReplanMinF1 = 128;
 constexpr uint32_t kSamples2 = 65536;
+constexpr uint32_t kSamples2Block = 1024;      // samples (and threads) per workgroup of the larger sample
 constexpr uint32_t kSample2SlotsLog2 = 18;     // hash set of the large sample (load <= 1/4)
 constexpr uint32_t kMaxTableLog2 = 22;         // largest global table (4M slots, 64 MiB)
 constexpr uint32_t kTableFloorLog2 = 16;       // global table never smaller (64K slots) when the workspace allows
@@ -129,7 +130,6 @@ struct Ctrl {
     uint32_t cap_limit;               // claimed slots allowed; keys arriving later spill
     uint32_t part_log2;               // hash partitions of the count workgroups (log2)
     uint32_t replan;                  // plan the count again from the larger sample
-    uint32_t s2acc[3 + kMaxParts];    // the larger sample: u, f1, f2, elements per 16 partitions
     uint32_t s2done;
     uint32_t lds_wide;                // LDS buckets of 4 keys (else 2)
     // tiny count: each key's counter on a line of its own (every workgroup adds to them)

@@ -782,16 +782,6 @@ __device__ __forceinline__ void hash_count_impl(const Args& a, uint32_t bid, uin
     if (c->lds_wide) count_items<4, PARTS, EW>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
     else count_items<2, PARTS, EW>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
 }
-__device__ __forceinline__ void hash_count_body(const Args& a, uint32_t bid, uint32_t nblk) {
-    __shared__ __attribute__((aligned(16))) uint64_t skeys[kLdsSlots];
-    __shared__ uint32_t scnt[kLdsSlots];
-    __shared__ uint32_t s_ndef;
-    __shared__ uint32_t s_flag;
-    __shared__ uint32_t s_sink[64];  // target of the atomics of lanes without a hit
-    if (a.c->part_log2) hash_count_impl<true, 8>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
-    else if (a.ew == 4) hash_count_impl<false, 4>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
-    else hash_count_impl<false, 8>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
-}
 
 // The contents of the partition buckets and the overflow area, taken as one
 // sequence (each part's length rounded up to even, so that pairs stay aligned),
@@ -804,19 +794,21 @@ __device__ __forceinline__ void count_parts(const Args& a, const GTable& t, uint
                                             uint32_t items, uint32_t pl) {
     Ctrl* c = a.c;
     const uint32_t P = 1u << pl;
-    uint64_t len[kMaxParts + 1];
-    uint64_t total = 0;
-    for (uint32_t q = 0; q <= P; ++q) {
+    // (each part's length is read again where it is needed: an array indexed by
+    // the part would live in scratch memory)
+    auto part_len = [&](uint32_t q) -> uint64_t {
         const uint64_t cap = c->pbase[q + 1] - c->pbase[q];
         const uint64_t fill = c->pfill[q == P ? kMaxParts : q][0];
-        len[q] = fill < cap ? fill : cap;
-        total += (len[q] + 1) & ~1ull;
-    }
+        return fill < cap ? fill : cap;
+    };
+    uint64_t total = 0;
+    for (uint32_t q = 0; q <= P; ++q) total += (part_len(q) + 1) & ~1ull;
     const uint64_t per = ((total + items - 1) / items + 63) & ~63ull;
     const uint64_t v0 = (uint64_t)it * per, v1 = v0 + per < total ? v0 + per : total;
     uint64_t f = 0;  // start of part q in the sequence
     for (uint32_t q = 0; q <= P && f < v1; ++q) {
-        const uint64_t lv = (len[q] + 1) & ~1ull;
+        const uint64_t lq = part_len(q);
+        const uint64_t lv = (lq + 1) & ~1ull;
         const uint64_t s0 = v0 > f ? v0 - f : 0, s1 = v1 - f < lv ? v1 - f : lv;
         if (s0 < s1) {
             const uint64_t base = c->pbase[q];  // a multiple of 32 elements
@@ -827,7 +819,7 @@ __device__ __forceinline__ void count_parts(const Args& a, const GTable& t, uint
             }
             if (threadIdx.x == 0) s_ndef = 0;
             __syncthreads();
-            count_range<W, 8>(a, t, skeys, scnt, s_ndef, s_sink, &s_flag, a.pbuf + base, len[q], 0, s0 / 2, s1 / 2,
+            count_range<W, 8>(a, t, skeys, scnt, s_ndef, s_sink, &s_flag, a.pbuf + base, lq, 0, s0 / 2, s1 / 2,
                               pl, region, (uint32_t)(s1 - s0));
             __syncthreads();
         }
@@ -1088,7 +1080,42 @@ __device__ __forceinline__ void count_range(const Args& a, const GTable& t, uint
     if (block_overflow(c, s_flag)) return;
     flush_table<W>(t, skeys, scnt);
 }
-CAFS_KERNELS0(hash_count, kCountThreads)
+// One kernel per variant (the 64-bit and 32-bit columns without partitions, chosen
+// by the host from the dtype, and the partitioned count, which returns at once
+// unless the plan has partitions), so that each is register-allocated alone: the
+// partitioned variant needs more registers than the others and would otherwise
+// make the common count loop spill.  The batched kernels take the same split, each
+// launched over the whole block table; a column's workgroups leave every launch
+// but the one of its variant at once.
+template <bool PARTS, uint32_t EW>
+__device__ __forceinline__ void hash_count_variant(const Args& a, uint32_t bid, uint32_t nblk) {
+    __shared__ __attribute__((aligned(16))) uint64_t skeys[kLdsSlots];
+    __shared__ uint32_t scnt[kLdsSlots];
+    __shared__ uint32_t s_ndef;
+    __shared__ uint32_t s_flag;
+    __shared__ uint32_t s_sink[64];
+    if ((a.c->part_log2 != 0) != PARTS) return;
+    hash_count_impl<PARTS, EW>(a, bid, nblk, skeys, scnt, s_ndef, s_flag, s_sink);
+}
+__global__ __launch_bounds__(kCountThreads) void k_hash_count(Args a) {
+    hash_count_variant<false, 8>(a, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kCountThreads) void k_hash_count32(Args a) {
+    hash_count_variant<false, 4>(a, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kCountThreads) void k_hash_count_parts(Args a) {
+    hash_count_variant<true, 8>(a, blockIdx.x, gridDim.x);
+}
+template <bool PARTS, uint32_t EW>
+__device__ __forceinline__ void hash_count_batch(const BatchGrid& g) {
+    const uint32_t col = g.col[blockIdx.x];
+    const Args& a = g.args[col];
+    if (!PARTS && a.ew != EW) return;
+    hash_count_variant<PARTS, EW>(a, blockIdx.x - g.first[col], g.count[col]);
+}
+__global__ __launch_bounds__(kCountThreads) void kb_hash_count(BatchGrid g) { hash_count_batch<false, 8>(g); }
+__global__ __launch_bounds__(kCountThreads) void kb_hash_count32(BatchGrid g) { hash_count_batch<false, 4>(g); }
+__global__ __launch_bounds__(kCountThreads) void kb_hash_count_parts(BatchGrid g) { hash_count_batch<true, 8>(g); }
 
 // ---------------------------------------------------------------------------
 // Order of the distinct keys (Alg. 4, steps "collect non-empty bucket slots" and

@@ -250,8 +250,9 @@ __device__ void plan_block(const Args& a) {
     c->chunk_ctr = 0;
     c->guard_done = 0;
     c->spill = 0;
-    c->replan = (path == P_MAIN && engine == E_HASH && n >= kReplanMinN && c->f1 >= kReplanMinF1) ? 1u : 0u;
-    for (uint32_t i = 0; i < 3 + kMaxParts; ++i) c->s2acc[i] = 0;
+    // (not after a full order check: the set is cleared beside that check)
+    c->replan = (path == P_MAIN && engine == E_HASH && n >= kReplanMinN && c->f1 >= kReplanMinF1 && !c->mono_full)
+                    ? 1u : 0u;
     c->s2done = 0;
     plan_engine_state(a, c, path, engine);
 }
@@ -314,11 +315,34 @@ __global__ __launch_bounds__(1024) void k_estimate_only(const uint64_t* x, uint6
     }
 }
 
+// The larger sample (engine planning for long heavy-tailed columns) is counted in
+// a hash set in the deferral scratch, free until the count: keys at tmp_k[0, S),
+// 32-bit counts after them.  The full order check's workgroups clear it when the
+// prefix already settled the order (the only case that plans from that sample).
+__device__ __forceinline__ uint32_t* sample2_counts(const Args& a) {
+    return reinterpret_cast<uint32_t*>(a.tmp_k + (1ull << kSample2SlotsLog2));
+}
+// Rows of the per-workgroup sums (3 + kMaxParts words each), after the counts.
+__device__ __forceinline__ uint32_t* sample2_rows(const Args& a) {
+    return sample2_counts(a) + (1u << kSample2SlotsLog2);
+}
+__device__ __forceinline__ void sample2_clear(const Args& a, uint32_t bid, uint32_t nblk) {
+    const uint32_t S = 1u << kSample2SlotsLog2;
+    uint32_t* cnt = sample2_counts(a);
+    for (uint32_t i = bid * blockDim.x + threadIdx.x; i < S; i += nblk * blockDim.x) {
+        gp(a.tmp_k)[i] = kEmpty;
+        gp(cnt)[i] = 0;
+    }
+}
+
 // Full order check, only when the prefix was in order (IsMonotone, Alg. 3).  Exits
 // early once any workgroup has found an inversion.
 __device__ __forceinline__ void mono_full_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
-    if (!c->mono_full) return;
+    if (!c->mono_full) {
+        if (c->replan) sample2_clear(a, bid, nblk);
+        return;
+    }
     const uint64_t n = a.n;
     const uint64_t chunk = 256 * 16;
     __shared__ uint32_t s_stop, s_last;
@@ -371,39 +395,39 @@ __device__ __forceinline__ void finalize_body(const Args& a, uint32_t bid, uint3
 }
 CAFS_KERNELS0(finalize, 64)
 
-// The larger sample: kSamples2 strided keys counted in a hash set in the deferral
-// scratch (free until the count): keys at tmp_k[0, S), counts after them.
-__device__ __forceinline__ uint32_t* sample2_counts(const Args& a) {
-    return reinterpret_cast<uint32_t*>(a.tmp_k + (1ull << kSample2SlotsLog2));
-}
-__device__ __forceinline__ void sample2_clear_body(const Args& a, uint32_t bid, uint32_t nblk) {
-    if (!a.c->replan) return;
-    const uint32_t S = 1u << kSample2SlotsLog2;
-    uint32_t* cnt = sample2_counts(a);
-    for (uint32_t i = bid * blockDim.x + threadIdx.x; i < S; i += nblk * blockDim.x) {
-        gp(a.tmp_k)[i] = kEmpty;
-        gp(cnt)[i] = 0;
-    }
-}
-CAFS_KERNELS0(sample2_clear, 256)
-
-// 256 samples per workgroup, merged in LDS first (a heavy key takes one update of
-// the shared set per workgroup instead of one per sample).
+// kSamples2Block samples per workgroup, merged in LDS first (a heavy key takes one
+// update of the shared set per workgroup instead of one per sample), then added to
+// the set, each thread's updates issued together.  Chao1's u, f1 and f2 of the
+// whole sample are kept as they grow: an add that takes a slot's count from o to
+// o + m changes u by [o = 0], f1 by [o + m = 1] - [o = 1] and f2 by
+// [o + m = 2] - [o = 2], and these changes telescope along each slot's chain of
+// adds to its final count whatever the order of the adds.  Each workgroup stores
+// its changes and its sampled elements per partition in its own row; the last
+// workgroup sums the rows and plans the hash count for that estimate when it is
+// above the paper's, with the partition buckets sized by the sampled elements of
+// each partition (a few heavy keys can make one partition far larger than an even
+// share).
 __device__ __forceinline__ void sample2_body(const Args& a, uint32_t bid, uint32_t nblk) {
-    if (!a.c->replan) return;
-    constexpr uint32_t LS = 1024;  // LDS set of 256 samples
+    Ctrl* c = a.c;
+    if (!c->replan) return;
+    constexpr uint32_t LS = 4 * kSamples2Block;  // LDS set (load <= 1/4)
+    constexpr uint32_t R = 3 + kMaxParts;        // u, f1, f2 changes; sampled elements per 16 partitions
+    constexpr uint32_t PER = LS / kSamples2Block;  // set slots per thread
     __shared__ uint64_t lk[LS];
     __shared__ uint32_t lc[LS];
+    __shared__ uint32_t s_acc[R];
+    __shared__ uint32_t s_last;
     for (uint32_t i = threadIdx.x; i < LS; i += blockDim.x) {
         lk[i] = kEmpty;
         lc[i] = 0;
     }
+    if (threadIdx.x < R) s_acc[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t stride = a.n / kSamples2;
-    const uint32_t s = bid * blockDim.x + threadIdx.x;  // (grid * block == kSamples2)
-    const uint64_t v = load_key(a.in, (uint64_t)s * stride, a.ew);
+    const uint32_t smp = bid * blockDim.x + threadIdx.x;  // (grid * block == kSamples2)
+    const uint64_t v = load_key(a.in, (uint64_t)smp * stride, a.ew);
     if (v != kEmpty) {  // (planning only: that one key is left out)
-        uint32_t h = phi_hash(v, 10);
+        uint32_t h = phi_hash(v, 12);
         for (uint32_t probe = 0; probe < LS; ++probe) {
             const unsigned long long old =
                 atomicCAS((unsigned long long*)&lk[h], (unsigned long long)kEmpty, (unsigned long long)v);
@@ -417,60 +441,64 @@ __device__ __forceinline__ void sample2_body(const Args& a, uint32_t bid, uint32
     __syncthreads();
     const uint32_t mask = (1u << kSample2SlotsLog2) - 1;
     uint32_t* cnt = sample2_counts(a);
-    for (uint32_t i = threadIdx.x; i < LS; i += blockDim.x) {
-        const uint32_t cn = lc[i];
-        if (!cn) continue;
-        const uint64_t key = lk[i];
-        uint32_t h = phi_hash(key, kSample2SlotsLog2);
-        for (uint32_t probe = 0; probe <= mask; ++probe) {
-            const uint64_t old = g_cas(&a.tmp_k[h], kEmpty, key);
-            if (old == kEmpty || old == key) {
-                g_add(&cnt[h], cn);
-                break;
-            }
-            h = (h + 1) & mask;
+    uint64_t key[PER];
+    uint32_t cn[PER], slot[PER];
+    uint64_t found[PER];
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+        const uint32_t i = threadIdx.x + j * blockDim.x;
+        cn[j] = lc[i];
+        key[j] = lk[i];
+        slot[j] = phi_hash(key[j], kSample2SlotsLog2);
+        if (cn[j]) atomicAdd(&s_acc[3 + (mul_hash32(key[j], 32, a.table_mul) >> (32 - kMaxPartLog2))], cn[j]);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) found[j] = cn[j] ? g_cas(&a.tmp_k[slot[j]], kEmpty, key[j]) : kEmpty;
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+        // another key holds the home slot (rare at this load): probe on
+        for (uint32_t probe = 1; cn[j] && found[j] != kEmpty && found[j] != key[j] && probe <= mask; ++probe) {
+            slot[j] = (slot[j] + 1) & mask;
+            found[j] = g_cas(&a.tmp_k[slot[j]], kEmpty, key[j]);
         }
     }
-}
-CAFS_KERNELS0(sample2, 256)
-
-// Chao1 of the larger sample (same formula as the paper's estimate) and the sampled
-// elements per 16 partitions (the partitions of fewer bits are their unions), by
-// every workgroup over its slots of the set; the last workgroup plans the hash count
-// for that estimate when it is above the paper's, with the partition buckets sized
-// by the sample (a few heavy keys can make one partition far larger than an even
-// share).
-__device__ __forceinline__ void replan_body(const Args& a, uint32_t bid, uint32_t nblk) {
-    Ctrl* c = a.c;
-    if (!c->replan) return;
-    const uint32_t S = 1u << kSample2SlotsLog2;
-    const CAFS_GLOBAL uint32_t* cnt = gp(sample2_counts(a));
-    const CAFS_GLOBAL uint64_t* keys = gp(a.tmp_k);
-    __shared__ uint32_t s_acc[3 + kMaxParts];  // u, f1, f2, mass of each of 16 partitions
-    __shared__ uint32_t s_last;
-    if (threadIdx.x < 3 + kMaxParts) s_acc[threadIdx.x] = 0;
-    __syncthreads();
-    uint32_t lu = 0, l1 = 0, l2 = 0;
-    for (uint32_t i = bid * blockDim.x + threadIdx.x; i < S; i += nblk * blockDim.x) {
-        const uint32_t cn = cnt[i];
-        lu += cn > 0;
-        l1 += cn == 1;
-        l2 += cn == 2;
-        if (cn) atomicAdd(&s_acc[3 + (mul_hash32(keys[i], 32, a.table_mul) >> (32 - kMaxPartLog2))], cn);
+    uint32_t o[PER];
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) o[j] = cn[j] ? g_add(&cnt[slot[j]], cn[j]) : 0u;
+    int32_t du = 0, d1 = 0, d2 = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+        if (!cn[j]) continue;
+        du += o[j] == 0;
+        d1 += (int32_t)(o[j] + cn[j] == 1) - (int32_t)(o[j] == 1);
+        d2 += (int32_t)(o[j] + cn[j] == 2) - (int32_t)(o[j] == 2);
     }
-    lu = wave_sum_u32(lu); l1 = wave_sum_u32(l1); l2 = wave_sum_u32(l2);
-    if (__lane_id() == 0) { atomicAdd(&s_acc[0], lu); atomicAdd(&s_acc[1], l1); atomicAdd(&s_acc[2], l2); }
+    du = (int32_t)wave_sum_u32((uint32_t)du);
+    d1 = (int32_t)wave_sum_u32((uint32_t)d1);
+    d2 = (int32_t)wave_sum_u32((uint32_t)d2);
+    if (__lane_id() == 0) {
+        atomicAdd(&s_acc[0], (uint32_t)du);
+        atomicAdd(&s_acc[1], (uint32_t)d1);
+        atomicAdd(&s_acc[2], (uint32_t)d2);
+    }
     __syncthreads();
-    if (threadIdx.x < 3 + kMaxParts && s_acc[threadIdx.x]) atomicAdd(&c->s2acc[threadIdx.x], s_acc[threadIdx.x]);
+    // (the changes are added modulo 2^32; the totals are counts, so they come out right)
+    uint32_t* rows = sample2_rows(a);
+    if (threadIdx.x < R) gp(rows)[bid * R + threadIdx.x] = s_acc[threadIdx.x];
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) s_last = (atomicAdd(&c->s2done, 1u) == nblk - 1);
     __syncthreads();
-    if (!s_last || threadIdx.x != 0) return;
+    if (!s_last) return;
     __threadfence();
-    uint32_t acc[3 + kMaxParts];
-    for (uint32_t i = 0; i < 3 + kMaxParts; ++i) acc[i] = atomic_load_agent(&c->s2acc[i]);
-    const uint64_t u = acc[0], f1 = acc[1], f2 = acc[2];
+    if (threadIdx.x < R) {
+        uint32_t t = 0;
+        for (uint32_t w = 0; w < nblk; ++w) t += atomic_load_agent(&rows[w * R + threadIdx.x]);
+        s_acc[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const uint64_t u = s_acc[0], f1 = s_acc[1], f2 = s_acc[2];
     const uint64_t k2 = u >= kSamples2 ? a.n : u + (f1 * f1) / (2 * (f2 + 1));
     if (k2 <= c->k_hat) return;
     const uint32_t engine = plan_count(a, c, k2, E_HASH);
@@ -482,12 +510,12 @@ __device__ __forceinline__ void replan_body(const Args& a, uint32_t bid, uint32_
     const uint32_t span = 1u << (kMaxPartLog2 - pl);  // 16-partition cells per partition
     for (uint32_t q = 0; q < (1u << pl); ++q) {
         mass[q] = 0;
-        for (uint32_t j = 0; j < span; ++j) mass[q] += acc[3 + q * span + j];
+        for (uint32_t j = 0; j < span; ++j) mass[q] += s_acc[3 + q * span + j];
         total += mass[q];
     }
     if (total > 0 && !set_buckets(a, c, pl, mass, total)) set_buckets(a, c, pl, nullptr);
 }
-CAFS_KERNELS0(replan, 256)
+CAFS_KERNELS0(sample2, kSamples2Block)
 
 // Report of an empty column (n = 0): path MONOTONE, everything else zero.
 __global__ void k_report_empty(cafs_report_t* r) {

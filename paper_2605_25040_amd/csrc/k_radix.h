@@ -59,7 +59,9 @@ __device__ __forceinline__ void radix_hist_body(const Args& a, uint32_t bid, uin
         if (act == 0) continue;
         for (uint32_t d = 0; d < 8; ++d) {
             const uint32_t dg = digit_of(v, flip, fneg, d);
-            const uint32_t first = __shfl(dg, (int)(__ffsll((unsigned long long)act) - 1), 64);
+            // lane 0's digit, read as a scalar (no cross-lane LDS instruction); if lane
+            // 0 is out of range and its digit differs, the lanes take the per-lane atomics
+            const uint32_t first = __builtin_amdgcn_readfirstlane(dg);
             const uint64_t same = __ballot(ok && dg == first);
             if (same == act) {
                 // wave-uniform digit: one atomic for the wave (skewed and low-K data)
