@@ -30,6 +30,9 @@ WORKLOADS = {
     "hbm_k1000_uniform": (1 << 28, 1000, "uniform", 1.1, "random"),
     "hbm_k4000_uniform": (1 << 28, 4000, "uniform", 1.1, "random"),
     "hbm_k10000_uniform": (1 << 28, 10_000, "uniform", 1.1, "random"),
+    # the tiny branch beside the main path at the dispatcher sweep's length
+    "sweep_tiny_k8": (30_000_000, 8, "uniform", 1.1, "random"),
+    "sweep_main_k200": (30_000_000, 200, "uniform", 1.1, "random"),
 }
 # algorithmic bytes per key of each single-kernel stage
 STAGE_BYTES_PER_KEY = {"count": 8.0, "emit": 8.0}
@@ -468,16 +471,18 @@ def main():
     ap.add_argument("--radix-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--serve-low-rate", type=float, default=4000.0,
-                    help="second serving replay at this rate (req/s; 0: skip)")
+    ap.add_argument("--serve-sustained-rate", type=float, default=7000.0,
+                    help="second serving replay at this rate (req/s; 0: skip), one the GPU sustains")
+    ap.add_argument("--serve-sustained-seconds", type=float, default=20.0)
     ap.add_argument("--no-structured", action="store_true",
                     help="skip the run-shaped, float64 and seeded-hash columns")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the input (counter calibration under a profiler)")
     ap.add_argument("--sweep", action="store_true",
                     help="run the dispatcher sweep (checked against the oracle) instead of the bench line")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
-                    help="length of the Poisson serving replay (the configured workload is 60 s); 0 skips it")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the Poisson serving replay at 10^4 req/s (the configured workload); 0 skips "
+                         "both serving replays")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -651,11 +656,11 @@ def main():
         line["batched"] = bench_batched(ctx)
     if args.serve_seconds > 0:
         line["serving"] = bench_serving(args.serve_seconds)
-        if args.serve_low_rate > 0:
+        if args.serve_sustained_rate > 0:
             # the same request law at a rate the GPU sustains: request latency without
             # the queue that grows at 10^4 req/s
-            line["serving_low_rate"] = bench_serving(min(args.serve_seconds, 5.0), rate=args.serve_low_rate,
-                                                     fifo_seconds=0.5)
+            line["serving_sustained"] = bench_serving(args.serve_sustained_seconds, rate=args.serve_sustained_rate,
+                                                      fifo_seconds=0.5)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x_np, 20)
     print(json.dumps(line), flush=True)

@@ -197,10 +197,11 @@ cafs_status_t launch_radix(const cafs::Args& a, uint64_t n_max, int cus, hipStre
     const uint64_t tiles = (n_max + cafs::kRadixTile - 1) / cafs::kRadixTile;
     const uint32_t g_hist = grid_for(n_max, 256 * 16, cus * 4);
     cafs::k_radix_hist<<<g_hist, 256, 0, s>>>(a);
-    // resident workgroups per CU: three keys-only (LDS, registers), two key-value
-    const uint32_t g_keys = grid_for(tiles, 1, cus * 3), g_kv = grid_for(tiles, 1, cus * 2);
+    // resident workgroups per CU (LDS): two keys-only (tiles of twice kRadixTile),
+    // two key-value
+    const uint32_t g_keys = grid_for(tiles / 2 + 1, 1, cus * 2), g_kv = grid_for(tiles, 1, cus * 2);
     for (uint32_t p = 0; p < 8; ++p) {
-        cafs::k_radix_pass<<<g_keys, cafs::kRadixThreads, 0, s>>>(a, p);
+        cafs::k_radix_pass<<<g_keys, cafs::kRadixKeysThreads, 0, s>>>(a, p);
         if (pairs) cafs::k_radix_pass_kv<<<g_kv, cafs::kRadixThreads, 0, s>>>(a, p);
     }
     cafs::k_radix_copy<<<grid_for(n_max, 256 * 8, cus * 4), 256, 0, s>>>(a);
@@ -341,7 +342,7 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
     cafs::k_pre<<<1, 1024, 0, s>>>(a);
     if (n > cafs::kMonoPrefix) cafs::k_mono_full<<<grid_for(n, 256 * 16, cus * 4), 256, 0, s>>>(a);
     if (n >= cafs::kReplanMinN)  // heavy-tailed estimates: the count's geometry from a larger sample
-        cafs::k_sample2<<<cafs::kSamples2 / cafs::kSamples2Block, cafs::kSamples2Block, 0, s>>>(a);
+        cafs::k_sample2<<<cafs::kSamples2 / cafs::kSamples2Block, cafs::kSamples2Threads, 0, s>>>(a);
     const bool countable = n >= cafs::kSmallN;  // tiny and main need N >= 2048
     if (countable)
         cafs::k_phase2<<<grid_for(std::max<uint64_t>(n / 2, cap_ws), 256 * 4, cus * 4), 256, 0, s>>>(a);
@@ -792,10 +793,16 @@ cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uin
     cafs::kb_rank<<<TP, 1024, 0, s>>>(gp);
     cafs::kb_compact_order<<<C, 1024, 0, s>>>(g1);
     cafs::kb_radix_hist<<<TP, 256, 0, s>>>(gp);
+    // a column's radix job is keys-only or key-value, so the two chains of passes
+    // (different columns) run side by side
+    (void)hipEventRecord(side.fork, s);
+    (void)hipStreamWaitEvent(side.s, side.fork, 0);
     for (uint32_t p = 0; p < 8; ++p) {
-        cafs::kb_radix_pass<<<TP, cafs::kRadixThreads, 0, s>>>(gp, p);
-        cafs::kb_radix_pass_kv<<<TP, cafs::kRadixThreads, 0, s>>>(gp, p);
+        cafs::kb_radix_pass<<<TP, cafs::kRadixKeysThreads, 0, s>>>(gp, p);
+        cafs::kb_radix_pass_kv<<<TP, cafs::kRadixThreads, 0, side.s>>>(gp, p);
     }
+    (void)hipEventRecord(side.join, side.s);
+    (void)hipStreamWaitEvent(s, side.join, 0);
     cafs::kb_radix_copy<<<TP, 256, 0, s>>>(gp);
     cafs::kb_fold_sums<<<TP, 1024, 0, s>>>(gp);
     cafs::kb_fold_write<<<TP, 1024, 0, s>>>(gp);
@@ -954,8 +961,10 @@ cafs_status_t cafs_autotune_batched(cafs_ctx_t* ctx, const cafs_column_t* h_cols
     double best = 1e30;
     // stage 1: workgroups per column (elements per block of the general kernels and of
     // the hash count)
-    const uint64_t per[] = {1ull << 15, 1ull << 16, 1ull << 17, 1ull << 18};
-    const uint64_t per_h[] = {1ull << 17, 1ull << 18, 1ull << 19, 1ull << 20};
+    // (few elements per block give a long column of a batch more workgroups; many
+    // give fewer idle launches to the short ones)
+    const uint64_t per[] = {1ull << 13, 1ull << 14, 1ull << 15, 1ull << 16, 1ull << 17};
+    const uint64_t per_h[] = {1ull << 15, 1ull << 16, 1ull << 17, 1ull << 18, 1ull << 19};
     uint64_t bp = ctx->batch_per_block, bh = ctx->batch_per_hash_block;
     for (uint64_t p : per) {
         for (uint64_t q : per_h) {

@@ -58,7 +58,9 @@ constexpr uint32_t kMinTableLog2 = 12;         // smallest global table (4096 sl
 constexpr uint64_t kReplanMinN = 1ull << 22;
 constexpr uint32_t kReplanMinF1 = 128;
 constexpr uint32_t kSamples2 = 65536;
-constexpr uint32_t kSamples2Block = 1024;      // samples (and threads) per workgroup of the larger sample
+constexpr uint32_t kSamples2Block = 4096;      // samples per workgroup of the larger sample
+constexpr uint32_t kSamples2Threads = 1024;    // threads per workgroup of the larger sample
+constexpr uint32_t kSample2LdsLog2 = 13;       // its LDS set: 2 * kSamples2Block slots
 constexpr uint32_t kSample2SlotsLog2 = 18;     // hash set of the large sample (load <= 1/4)
 constexpr uint32_t kMaxTableLog2 = 22;         // largest global table (4M slots, 64 MiB)
 constexpr uint32_t kTableFloorLog2 = 16;       // global table never smaller (64K slots) when the workspace allows
@@ -68,7 +70,8 @@ constexpr uint32_t kRankTile = 8192;           // keys staged in LDS at a time w
 constexpr uint32_t kRankBudgetLog2 = 24;       // compares per ranking workgroup before a pair sort wins
 constexpr uint32_t kRankBudgetBatchLog2 = 20;  // the same in a batch, where total work counts more than latency
 constexpr uint32_t kGuardLdsBuckets = 16384;   // guard bucket counts kept in LDS up to this M
-constexpr int kRadixThreads = 256;             // radix workgroup (4 waves)
+constexpr int kRadixThreads = 256;             // key-value radix pass workgroup (4 waves)
+constexpr int kRadixKeysThreads = 512;         // keys-only radix pass workgroup (8 waves)
 constexpr int kRadixItems = 16;                // keys per thread per tile
 constexpr uint32_t kRadixTile = kRadixThreads * kRadixItems;  // 4096 keys per tile
 constexpr uint32_t kRleTile = 4096;            // elements per run-detection tile

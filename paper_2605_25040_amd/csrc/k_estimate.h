@@ -395,7 +395,8 @@ __device__ __forceinline__ void finalize_body(const Args& a, uint32_t bid, uint3
 }
 CAFS_KERNELS0(finalize, 64)
 
-// kSamples2Block samples per workgroup, merged in LDS first (a heavy key takes one
+// kSamples2Block samples per workgroup (kSamples2 / kSamples2Block workgroups, so
+// that a heavy key's set slot takes few same-address updates), merged in LDS first (a heavy key takes one
 // update of the shared set per workgroup instead of one per sample), then added to
 // the set, each thread's updates issued together.  Chao1's u, f1 and f2 of the
 // whole sample are kept as they grow: an add that takes a slot's count from o to
@@ -410,9 +411,10 @@ CAFS_KERNELS0(finalize, 64)
 __device__ __forceinline__ void sample2_body(const Args& a, uint32_t bid, uint32_t nblk) {
     Ctrl* c = a.c;
     if (!c->replan) return;
-    constexpr uint32_t LS = 4 * kSamples2Block;  // LDS set (load <= 1/4)
+    constexpr uint32_t LS = 2 * kSamples2Block;  // LDS set (load <= 1/2)
     constexpr uint32_t R = 3 + kMaxParts;        // u, f1, f2 changes; sampled elements per 16 partitions
-    constexpr uint32_t PER = LS / kSamples2Block;  // set slots per thread
+    constexpr uint32_t SPT = kSamples2Block / kSamples2Threads;  // samples per thread
+    constexpr uint32_t PER = LS / kSamples2Threads;              // set slots per thread
     __shared__ uint64_t lk[LS];
     __shared__ uint32_t lc[LS];
     __shared__ uint32_t s_acc[R];
@@ -424,10 +426,15 @@ __device__ __forceinline__ void sample2_body(const Args& a, uint32_t bid, uint32
     if (threadIdx.x < R) s_acc[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t stride = a.n / kSamples2;
-    const uint32_t smp = bid * blockDim.x + threadIdx.x;  // (grid * block == kSamples2)
-    const uint64_t v = load_key(a.in, (uint64_t)smp * stride, a.ew);
-    if (v != kEmpty) {  // (planning only: that one key is left out)
-        uint32_t h = phi_hash(v, 12);
+    uint64_t sv[SPT];
+#pragma unroll
+    for (uint32_t j = 0; j < SPT; ++j)  // (grid * kSamples2Block == kSamples2)
+        sv[j] = load_key(a.in, (uint64_t)(bid * kSamples2Block + j * kSamples2Threads + threadIdx.x) * stride, a.ew);
+#pragma unroll
+    for (uint32_t j = 0; j < SPT; ++j) {
+        const uint64_t v = sv[j];
+        if (v == kEmpty) continue;  // (planning only: that one key is left out)
+        uint32_t h = phi_hash(v, kSample2LdsLog2);
         for (uint32_t probe = 0; probe < LS; ++probe) {
             const unsigned long long old =
                 atomicCAS((unsigned long long*)&lk[h], (unsigned long long)kEmpty, (unsigned long long)v);
@@ -452,8 +459,17 @@ __device__ __forceinline__ void sample2_body(const Args& a, uint32_t bid, uint32
         slot[j] = phi_hash(key[j], kSample2SlotsLog2);
         if (cn[j]) atomicAdd(&s_acc[3 + (mul_hash32(key[j], 32, a.table_mul) >> (32 - kMaxPartLog2))], cn[j]);
     }
+    // a slot that already holds the key (the heavy keys, after the first workgroup)
+    // is taken without a compare-and-swap: same-address atomics of every workgroup
+    // would queue on it
 #pragma unroll
-    for (uint32_t j = 0; j < PER; ++j) found[j] = cn[j] ? g_cas(&a.tmp_k[slot[j]], kEmpty, key[j]) : kEmpty;
+    for (uint32_t j = 0; j < PER; ++j) found[j] = cn[j] ? g_load(&a.tmp_k[slot[j]]) : kEmpty;
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j)
+        if (cn[j] && found[j] != key[j]) found[j] = g_cas(&a.tmp_k[slot[j]], kEmpty, key[j]);
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j)
+        if (found[j] == key[j]) found[j] = kEmpty;  // (the slot is the key's: no probe)
 #pragma unroll
     for (uint32_t j = 0; j < PER; ++j) {
         // another key holds the home slot (rare at this load): probe on
@@ -484,8 +500,10 @@ __device__ __forceinline__ void sample2_body(const Args& a, uint32_t bid, uint32
     __syncthreads();
     // (the changes are added modulo 2^32; the totals are counts, so they come out right)
     uint32_t* rows = sample2_rows(a);
-    if (threadIdx.x < R) gp(rows)[bid * R + threadIdx.x] = s_acc[threadIdx.x];
-    __threadfence();
+    if (threadIdx.x < R) {
+        gp(rows)[bid * R + threadIdx.x] = s_acc[threadIdx.x];
+        __threadfence();  // (only the row's writers release it: a fence waits for the wave's stores)
+    }
     __syncthreads();
     if (threadIdx.x == 0) s_last = (atomicAdd(&c->s2done, 1u) == nblk - 1);
     __syncthreads();
@@ -515,7 +533,7 @@ __device__ __forceinline__ void sample2_body(const Args& a, uint32_t bid, uint32
     }
     if (total > 0 && !set_buckets(a, c, pl, mass, total)) set_buckets(a, c, pl, nullptr);
 }
-CAFS_KERNELS0(sample2, kSamples2Block)
+CAFS_KERNELS0(sample2, kSamples2Threads)
 
 // Report of an empty column (n = 0): path MONOTONE, everything else zero.
 __global__ void k_report_empty(cafs_report_t* r) {

@@ -164,6 +164,12 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t dg, uint64_t act) {
 // are separate kernels so that the keys-only one keeps fewer registers and less LDS.
 template <bool VALS>
 __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, uint32_t bid, uint32_t nblk) {
+    // keys-only passes: workgroups of 512 threads and tiles of 8192 keys (digit runs
+    // of 32 keys on average, so fewer partly written cache lines, and half the
+    // look-backs); key-value passes: 256 threads, tiles of 4096
+    constexpr uint32_t THREADS = VALS ? kRadixThreads : kRadixKeysThreads;
+    constexpr uint32_t NW = THREADS / 64;
+    constexpr uint32_t TILE = THREADS * kRadixItems;
     Ctrl* c = a.c;
     if (!c->radix_on) return;
     const RadixJob& j = c->rj;
@@ -176,17 +182,17 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
     uint64_t* dk = j.pd_k[pass];
     CAFS_GLOBAL uint64_t* __restrict__ dv = gp(j.pd_v[pass]);
     const uint32_t skw = j.ps_w[pass], dkw = j.pd_w[pass];
-    const uint64_t tiles = (n + kRadixTile - 1) / kRadixTile;
+    const uint64_t tiles = (n + TILE - 1) / TILE;  // (the status words are sized for kRadixTile)
     uint64_t* status = a.status + (pass & 1u) * a.status_slot;
     CAFS_GLOBAL uint64_t* status_next = gp(a.status) + ((pass + 1) & 1u) * a.status_slot;
 
-    __shared__ uint64_t lk[kRadixTile];
-    __shared__ uint64_t lv[VALS ? kRadixTile : 1];
-    __shared__ uint32_t wcnt[kRadixThreads / 64][256];
+    __shared__ uint64_t lk[TILE];
+    __shared__ uint64_t lv[VALS ? TILE : 1];
+    __shared__ uint32_t wcnt[NW][256];
     __shared__ uint32_t toff[256];
     __shared__ uint64_t gofs[256];
     __shared__ uint32_t s_tile;
-    __shared__ uint32_t scan_tmp[8];
+    __shared__ uint32_t scan_tmp[NW + 1];
     __shared__ uint64_t sbase[256];  // the digit's global bases, read once per workgroup
     for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) sbase[i] = c->hist[d][i];
 
@@ -205,11 +211,11 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
 
     while (true) {
         if (tid == 0) s_tile = atomicAdd(&c->tile_ctr[pass], 1u);
-        for (uint32_t i = tid; i < (kRadixThreads / 64) * 256; i += blockDim.x) (&wcnt[0][0])[i] = 0;
+        for (uint32_t i = tid; i < NW * 256; i += blockDim.x) (&wcnt[0][0])[i] = 0;
         __syncthreads();
         const uint64_t t = s_tile;
         if (t >= tiles) break;
-        const uint64_t base = t * kRadixTile;
+        const uint64_t base = t * TILE;
         // load: wave w owns positions base + w*1024 + i*64 + lane, i = 0..15 (in order)
         uint64_t key[kRadixItems];
         uint64_t val[VALS ? kRadixItems : 1];
@@ -239,11 +245,11 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
         }
         __syncthreads();
         // per digit: tile total and per-wave exclusive prefix
-        uint32_t run = 0;  // this thread's digit: count in the tile
-        {
-            const uint32_t dd = tid;  // 256 threads, one digit each
+        uint32_t run = 0;  // this thread's digit: count in the tile (threads past 256: none)
+        if (tid < 256) {
+            const uint32_t dd = tid;  // one digit per thread
 #pragma unroll
-            for (int w = 0; w < kRadixThreads / 64; ++w) {
+            for (uint32_t w = 0; w < NW; ++w) {
                 const uint32_t cw = wcnt[w][dd];
                 wcnt[w][dd] = run;
                 run += cw;
@@ -275,9 +281,9 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
         {
             uint32_t total;
             const uint32_t ex = block_exclusive_scan<uint32_t>(run, scan_tmp, &total);
-            toff[tid] = ex;
+            if (tid < 256) toff[tid] = ex;
             __syncthreads();
-            gofs[tid] -= ex;  // global position = gofs[digit] + local position
+            if (tid < 256) gofs[tid] -= ex;  // global position = gofs[digit] + local position
         }
         __syncthreads();
         // reorder the tile in LDS by digit (stable)
@@ -286,14 +292,14 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
             if ((okm >> i) & 1u) {
                 const uint32_t dg = digit_of(key[i], flip, fneg, d);
                 const uint32_t q = toff[dg] + wcnt[wave][dg] + ((rank2[i >> 1] >> (16 * (i & 1))) & 0xFFFFu);
-                if (q < kRadixTile) {  // always true when the ranks are consistent
+                if (q < TILE) {  // always true when the ranks are consistent
                     lk[q] = key[i];
                     if constexpr (VALS) lv[q] = val[i];
                 }
             }
         }
         __syncthreads();
-        const uint32_t cnt = (uint32_t)((n - base) < kRadixTile ? (n - base) : kRadixTile);
+        const uint32_t cnt = (uint32_t)((n - base) < TILE ? (n - base) : TILE);
         for (uint32_t q = tid; q < cnt; q += blockDim.x) {
             const uint64_t k = lk[q];
             const uint64_t g = gofs[digit_of(k, flip, fneg, d)] + q;
@@ -311,7 +317,15 @@ __device__ __forceinline__ void radix_pass_body(const Args& a, uint32_t pass, ui
 __device__ __forceinline__ void radix_pass_kv_body(const Args& a, uint32_t pass, uint32_t bid, uint32_t nblk) {
     radix_pass_impl<true>(a, pass, bid, nblk);
 }
-CAFS_KERNELS1(radix_pass, kRadixThreads, uint32_t, pass)
+// (the keys-only pass asks for four waves per SIMD, two workgroups per CU, which
+// its LDS allows: at most 128 registers)
+__global__ __launch_bounds__(kRadixKeysThreads, 4) void k_radix_pass(Args a, uint32_t pass) {
+    radix_pass_body(a, pass, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kRadixKeysThreads, 4) void kb_radix_pass(BatchGrid g, uint32_t pass) {
+    const uint32_t col = g.col[blockIdx.x];
+    radix_pass_body(g.args[col], pass, blockIdx.x - g.first[col], g.count[col]);
+}
 CAFS_KERNELS1(radix_pass_kv, kRadixThreads, uint32_t, pass)
 
 __device__ __forceinline__ void radix_copy_body(const Args& a, uint32_t bid, uint32_t nblk) {
