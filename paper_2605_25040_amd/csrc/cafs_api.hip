@@ -798,7 +798,7 @@ cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uin
     (void)hipEventRecord(side.fork, s);
     (void)hipStreamWaitEvent(side.s, side.fork, 0);
     for (uint32_t p = 0; p < 8; ++p) {
-        cafs::kb_radix_pass<<<TP, cafs::kRadixKeysThreads, 0, s>>>(gp, p);
+        cafs::kb_radix_pass<<<TP, cafs::kRadixThreads, 0, s>>>(gp, p);
         cafs::kb_radix_pass_kv<<<TP, cafs::kRadixThreads, 0, side.s>>>(gp, p);
     }
     (void)hipEventRecord(side.join, side.s);

@@ -65,7 +65,8 @@ constexpr uint32_t kSample2SlotsLog2 = 18;     // hash set of the large sample (
 constexpr uint32_t kMaxTableLog2 = 22;         // largest global table (4M slots, 64 MiB)
 constexpr uint32_t kTableFloorLog2 = 16;       // global table never smaller (64K slots) when the workspace allows
 constexpr uint32_t kRankMax = 32768;           // K ordered by ranking (larger K: pair radix sort)
-constexpr uint32_t kRankKeysPerBlock = 64;     // keys ranked by one workgroup (16 threads each)
+constexpr uint32_t kRankKeysPerBlock = 64;     // keys ranked by one workgroup (16 waves)
+constexpr uint32_t kRankKeysPerWave = 4;       // keys ranked by one wave, held in registers
 constexpr uint32_t kRankTile = 8192;           // keys staged in LDS at a time while ranking
 constexpr uint32_t kRankBudgetLog2 = 24;       // compares per ranking workgroup before a pair sort wins
 constexpr uint32_t kRankBudgetBatchLog2 = 20;  // the same in a batch, where total work counts more than latency

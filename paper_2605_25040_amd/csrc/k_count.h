@@ -1288,26 +1288,46 @@ __device__ __forceinline__ void rank_body(const Args& a, uint32_t bid, uint32_t 
     if ((uint64_t)bid * kRankKeysPerBlock >= K) return;
     const uint64_t flip = a.flip, fneg = a.fneg;
     __shared__ uint64_t sk[kRankTile];
-    const uint32_t part = threadIdx.x % 16;
+    // each wave ranks kRankKeysPerWave keys held in registers: its 64 lanes read the
+    // staged keys once between them and compare each with all of the wave's keys, so
+    // the LDS reads per key ranked are K / 64 wave loads
+    constexpr uint32_t Q = kRankKeysPerWave;
+    static_assert(Q * 16 == kRankKeysPerBlock, "16 waves of 1024 threads");
+    const uint32_t wave = threadIdx.x >> 6, lane = __lane_id();
     for (uint32_t i0 = bid * kRankKeysPerBlock; i0 < K; i0 += nblk * kRankKeysPerBlock) {  // uniform
-        const uint32_t i = i0 + threadIdx.x / 16;
-        const bool have = i < K;
-        const uint64_t ki = okey(have ? table_key(a, i, claimed) : 0, flip, fneg);
-        uint32_t r = 0;
+        uint64_t ki[Q];
+        uint32_t r[Q];
+#pragma unroll
+        for (uint32_t q = 0; q < Q; ++q) {
+            const uint32_t i = i0 + wave * Q + q;
+            ki[q] = okey(i < K ? table_key(a, i, claimed) : 0, flip, fneg);
+            r[q] = 0;
+        }
         for (uint32_t j0 = 0; j0 < K; j0 += kRankTile) {
             const uint32_t jn = K - j0 < kRankTile ? K - j0 : kRankTile;
             __syncthreads();
             for (uint32_t j = threadIdx.x; j < jn; j += blockDim.x) sk[j] = okey(table_key(a, j0 + j, claimed), flip, fneg);
             __syncthreads();
-            for (uint32_t j = part; j < jn; j += 16) r += sk[j] < ki ? 1u : 0u;
+            for (uint32_t j = lane; j < jn; j += 64) {
+                const uint64_t v = sk[j];
+#pragma unroll
+                for (uint32_t q = 0; q < Q; ++q) r[q] += v < ki[q] ? 1u : 0u;
+            }
         }
-        r += __shfl_xor(r, 8, 16);
-        r += __shfl_xor(r, 4, 16);
-        r += __shfl_xor(r, 2, 16);
-        r += __shfl_xor(r, 1, 16);
-        if (have && part == 0) {
-            gp(a.uniq)[r] = okey_inv(ki, flip, fneg);
-            gp(a.cnt)[r] = i < claimed ? gp(a.gcnt)[gp(a.claimed)[i]] : ecount;
+#pragma unroll
+        for (uint32_t q = 0; q < Q; ++q) r[q] = wave_sum_u32(r[q]);
+        // lane q writes key q of the wave (the keys are distinct, so the ranks are)
+        uint32_t rq = r[0];
+        uint64_t kq = ki[0];
+#pragma unroll
+        for (uint32_t q = 1; q < Q; ++q) {
+            rq = lane == q ? r[q] : rq;
+            kq = lane == q ? ki[q] : kq;
+        }
+        const uint32_t i = i0 + wave * Q + lane;
+        if (lane < Q && i < K) {
+            gp(a.uniq)[rq] = okey_inv(kq, flip, fneg);
+            gp(a.cnt)[rq] = i < claimed ? gp(a.gcnt)[gp(a.claimed)[i]] : ecount;
         }
     }
 }

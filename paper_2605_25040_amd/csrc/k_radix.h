@@ -162,12 +162,13 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t dg, uint64_t act) {
 // ranks within the tile by wave matching, tile offsets by decoupled look-back, a
 // reorder through LDS and a scatter of digit runs.  Keys-only and key-value passes
 // are separate kernels so that the keys-only one keeps fewer registers and less LDS.
-template <bool VALS>
+// THREADS threads, tiles of 16 keys per thread: the single-column keys-only pass
+// takes 512 (tiles of 8192 keys: digit runs of 32 keys on average, so fewer partly
+// written cache lines, and half the look-backs); key-value passes and the batched
+// keys-only pass take 256 (a batched launch spans every column's blocks, most of
+// them idle, and 256-thread workgroups start three to a CU instead of two).
+template <bool VALS, uint32_t THREADS>
 __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, uint32_t bid, uint32_t nblk) {
-    // keys-only passes: workgroups of 512 threads and tiles of 8192 keys (digit runs
-    // of 32 keys on average, so fewer partly written cache lines, and half the
-    // look-backs); key-value passes: 256 threads, tiles of 4096
-    constexpr uint32_t THREADS = VALS ? kRadixThreads : kRadixKeysThreads;
     constexpr uint32_t NW = THREADS / 64;
     constexpr uint32_t TILE = THREADS * kRadixItems;
     Ctrl* c = a.c;
@@ -311,20 +312,17 @@ __device__ __forceinline__ void radix_pass_impl(const Args& a, uint32_t pass, ui
         __syncthreads();
     }
 }
-__device__ __forceinline__ void radix_pass_body(const Args& a, uint32_t pass, uint32_t bid, uint32_t nblk) {
-    radix_pass_impl<false>(a, pass, bid, nblk);
-}
 __device__ __forceinline__ void radix_pass_kv_body(const Args& a, uint32_t pass, uint32_t bid, uint32_t nblk) {
-    radix_pass_impl<true>(a, pass, bid, nblk);
+    radix_pass_impl<true, kRadixThreads>(a, pass, bid, nblk);
 }
 // (the keys-only pass asks for four waves per SIMD, two workgroups per CU, which
 // its LDS allows: at most 128 registers)
 __global__ __launch_bounds__(kRadixKeysThreads, 4) void k_radix_pass(Args a, uint32_t pass) {
-    radix_pass_body(a, pass, blockIdx.x, gridDim.x);
+    radix_pass_impl<false, kRadixKeysThreads>(a, pass, blockIdx.x, gridDim.x);
 }
-__global__ __launch_bounds__(kRadixKeysThreads, 4) void kb_radix_pass(BatchGrid g, uint32_t pass) {
+__global__ __launch_bounds__(kRadixThreads) void kb_radix_pass(BatchGrid g, uint32_t pass) {
     const uint32_t col = g.col[blockIdx.x];
-    radix_pass_body(g.args[col], pass, blockIdx.x - g.first[col], g.count[col]);
+    radix_pass_impl<false, kRadixThreads>(g.args[col], pass, blockIdx.x - g.first[col], g.count[col]);
 }
 CAFS_KERNELS1(radix_pass_kv, kRadixThreads, uint32_t, pass)
 
