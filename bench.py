@@ -41,6 +41,15 @@ KERNEL_SOURCES = ["paper_2605_25040_amd/csrc/cafs_dev.h", "paper_2605_25040_amd/
                   "paper_2605_25040_amd/csrc/k_emit.h", "paper_2605_25040_amd/csrc/cafs_api.hip"]
 
 
+def progress(msg):
+    """A progress line on stderr (the bench line itself is the only stdout output)."""
+    sys.stderr.write("bench: %s (%.0f s)\n" % (msg, time.time() - _T0))
+    sys.stderr.flush()
+
+
+_T0 = time.time()
+
+
 def sources_hash():
     """Hash of the kernel sources' code: line comments, trailing blanks and empty
     lines are left out, so that an edit of the comments keeps the counter runs valid."""
@@ -546,6 +555,7 @@ def main():
         assert r[f] == v, ("report field", f, r[f], v)
     pool.shutdown()
     del got_out
+    progress("checked call matches the oracle")
 
     for _ in range(args.warmup):
         step()
@@ -649,18 +659,23 @@ def main():
     del x, out, ws
     ctx._ws = None
     torch.cuda.empty_cache()
+    progress("headline timed")
     if not args.no_structured:
         line["structured"] = bench_structured(ctx)
         line["variants"] = bench_variants(ctx)
+        progress("structured columns and variants timed")
     if not args.no_batched:
         line["batched"] = bench_batched(ctx)
+        progress("batched workload timed")
     if args.serve_seconds > 0:
         line["serving"] = bench_serving(args.serve_seconds)
+        progress("serving replay at 10^4 req/s done")
         if args.serve_sustained_rate > 0:
             # the same request law at a rate the GPU sustains: request latency without
             # the queue that grows at 10^4 req/s
             line["serving_sustained"] = bench_serving(args.serve_sustained_seconds, rate=args.serve_sustained_rate,
                                                       fifo_seconds=0.5)
+            progress("sustained serving replay done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x_np, 20)
     print(json.dumps(line), flush=True)
