@@ -668,7 +668,7 @@ constexpr uint32_t kBatchMaxBlocks = 64;  // per column and kernel
 struct BatchShape {
     std::vector<uint32_t> bp, bh;  // blocks per column: general kernels, hash count
     uint32_t total_p = 0, total_h = 0;
-    size_t off_args = 0, off_m1 = 0, off_mp = 0, off_mh = 0, header = 0;
+    size_t off_args = 0, off_m1 = 0, off_mp = 0, off_mh = 0, off_rl = 0, header = 0;
 };
 
 uint32_t blocks_for(uint64_t n, uint64_t per) {
@@ -693,12 +693,14 @@ BatchShape shape_batch(const uint64_t* ns, uint32_t n_cols, uint64_t per_block, 
     P.off_m1 = take(4ull * (n_cols + 2ull * n_cols));   // col[total], first[n_cols], count[n_cols]
     P.off_mp = take(4ull * (P.total_p + 2ull * n_cols));
     P.off_mh = take(4ull * (P.total_h + 2ull * n_cols));
+    P.off_rl = take(cafs::radix_list_bytes(n_cols));  // (filled on the device, after its capacity)
     P.header = o;
     return P;
 }
 
 size_t header_bound(uint32_t n_cols) {
-    return align_up(sizeof(cafs::Args) * (size_t)n_cols) + 3 * align_up(4ull * (kBatchMaxBlocks + 2ull) * n_cols);
+    return align_up(sizeof(cafs::Args) * (size_t)n_cols) + 3 * align_up(4ull * (kBatchMaxBlocks + 2ull) * n_cols) +
+           align_up(cafs::radix_list_bytes(n_cols));
 }
 
 void fill_table(uint32_t* dst, uint32_t n_cols, const std::vector<uint32_t>* per_col, uint32_t total) {
@@ -761,6 +763,11 @@ cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uin
     fill_table(reinterpret_cast<uint32_t*>(h + P.off_m1), n_cols, nullptr, n_cols);
     fill_table(reinterpret_cast<uint32_t*>(h + P.off_mp), n_cols, &P.bp, P.total_p);
     fill_table(reinterpret_cast<uint32_t*>(h + P.off_mh), n_cols, &P.bh, P.total_h);
+    {
+        cafs::RadixList* rl = reinterpret_cast<cafs::RadixList*>(h + P.off_rl);
+        std::memset(rl, 0, sizeof(cafs::RadixList));
+        rl->cap = n_cols;
+    }
     (void)hipGetLastError();
     hipError_t e = hipMemcpyAsync(hdr_dev, hdr_host, P.header, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
@@ -793,13 +800,16 @@ cafs_status_t launch_batch(const cafs_ctx_t* ctx, const cafs_column_t* cols, uin
     cafs::kb_rank<<<TP, 1024, 0, s>>>(gp);
     cafs::kb_compact_order<<<C, 1024, 0, s>>>(g1);
     cafs::kb_radix_hist<<<TP, 256, 0, s>>>(gp);
-    // a column's radix job is keys-only or key-value, so the two chains of passes
-    // (different columns) run side by side
+    // the radix jobs as one list per kind, worked through by fixed grids; a column's
+    // job is keys-only or key-value, so the two chains of passes (different columns)
+    // run side by side
+    cafs::RadixList* rl = at<cafs::RadixList>(hdr_dev, P.off_rl);
+    cafs::kb_radix_list<<<1, 1024, 0, s>>>(g1.args, n_cols, rl);
     (void)hipEventRecord(side.fork, s);
     (void)hipStreamWaitEvent(side.s, side.fork, 0);
     for (uint32_t p = 0; p < 8; ++p) {
-        cafs::kb_radix_pass<<<TP, cafs::kRadixThreads, 0, s>>>(gp, p);
-        cafs::kb_radix_pass_kv<<<TP, cafs::kRadixThreads, 0, side.s>>>(gp, p);
+        cafs::kbl_radix_pass<<<ctx->cus * 3, cafs::kRadixThreads, 0, s>>>(g1.args, rl, p);
+        cafs::kbl_radix_pass_kv<<<ctx->cus * 2, cafs::kRadixThreads, 0, side.s>>>(g1.args, rl, p);
     }
     (void)hipEventRecord(side.join, side.s);
     (void)hipStreamWaitEvent(s, side.join, 0);

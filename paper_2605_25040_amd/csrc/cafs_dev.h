@@ -256,6 +256,34 @@ struct Args {
 
 // Block table of a batched launch: block b works on column col[b] as block
 // b - first[col[b]] of count[col[b]] blocks given to that column.
+// The radix jobs of a batch (built on the device once the histograms have planned
+// them): for each kind (0 keys-only, 1 key-value) the columns and the first item of
+// each (an item is a tile of kRadixTile keys), and one item counter per pass.  The
+// arrays follow the struct: cols[kind][cap], then start[kind][cap + 1].
+struct RadixList {
+    uint32_t total[2];
+    uint32_t ncols[2];
+    uint32_t cap;
+    uint32_t pad[3];
+    uint32_t next[2][8];
+};
+constexpr uint32_t kNoCol = 0xFFFFFFFFu;
+__host__ __device__ inline size_t radix_list_bytes(uint32_t cap) {
+    return sizeof(RadixList) + 4ull * (2ull * cap + 2ull * (cap + 1ull));
+}
+__device__ __forceinline__ uint32_t* radix_list_cols(RadixList* R, uint32_t kind) {
+    return reinterpret_cast<uint32_t*>(R + 1) + (size_t)kind * R->cap;
+}
+__device__ __forceinline__ const uint32_t* radix_list_cols(const RadixList* R, uint32_t kind) {
+    return reinterpret_cast<const uint32_t*>(R + 1) + (size_t)kind * R->cap;
+}
+__device__ __forceinline__ uint32_t* radix_list_start(RadixList* R, uint32_t kind) {
+    return reinterpret_cast<uint32_t*>(R + 1) + 2ull * R->cap + (size_t)kind * (R->cap + 1ull);
+}
+__device__ __forceinline__ const uint32_t* radix_list_start(const RadixList* R, uint32_t kind) {
+    return reinterpret_cast<const uint32_t*>(R + 1) + 2ull * R->cap + (size_t)kind * (R->cap + 1ull);
+}
+
 struct BatchGrid {
     const Args* args;
     const uint32_t* col;
