@@ -50,7 +50,13 @@ def check_cols(cols, label):
         dt = np.uint64 if c["unsigned"] else np.int64
         x = c["src"].view(dt)
         y = c["out"].cpu().numpy().view(dt)
-        assert np.array_equal(y, oracle.sort(x, dt)), "%s col %d output" % (label, i)
+        want = oracle.sort(x, dt)
+        if not np.array_equal(y, want):
+            # what the column took on the GPU, and where the output first differs
+            r = cafs.parse_report(c["report"]) if c["report"] is not None else None
+            bad = np.flatnonzero(y != want) if y.size == want.size else np.array([-1])
+            raise AssertionError("%s col %d output: n=%d, report %r, first difference at %d of %d differing" %
+                                 (label, i, x.size, r, int(bad[0]), bad.size))
         if c["report"] is not None:
             r = cafs.parse_report(c["report"])
             ro = oracle.report(x, dt)
