@@ -436,11 +436,20 @@ __device__ __forceinline__ void sample2_body(const Args& a, uint32_t bid, uint32
         if (v == kEmpty) continue;  // (planning only: that one key is left out)
         uint32_t h = phi_hash(v, kSample2LdsLog2);
         for (uint32_t probe = 0; probe < LS; ++probe) {
-            const unsigned long long old =
-                atomicCAS((unsigned long long*)&lk[h], (unsigned long long)kEmpty, (unsigned long long)v);
-            if (old == kEmpty || old == v) {
+            // a slot that already holds the key takes the add alone (a heavy key's
+            // samples would otherwise queue twice on one LDS address)
+            const uint64_t k = lk[h];
+            if (k == v) {
                 atomicAdd(&lc[h], 1u);
                 break;
+            }
+            if (k == kEmpty) {
+                const unsigned long long old =
+                    atomicCAS((unsigned long long*)&lk[h], (unsigned long long)kEmpty, (unsigned long long)v);
+                if (old == kEmpty || old == v) {
+                    atomicAdd(&lc[h], 1u);
+                    break;
+                }
             }
             h = (h + 1) & (LS - 1);
         }
@@ -509,11 +518,11 @@ __device__ __forceinline__ void sample2_body(const Args& a, uint32_t bid, uint32
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    if (threadIdx.x < R) {
-        uint32_t t = 0;
-        for (uint32_t w = 0; w < nblk; ++w) t += atomic_load_agent(&rows[w * R + threadIdx.x]);
-        s_acc[threadIdx.x] = t;
-    }
+    // the rows' words, one device-scope load per thread (loads of one thread, one
+    // after the other, would each wait on memory)
+    if (threadIdx.x < R) s_acc[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nblk * R; i += blockDim.x) atomicAdd(&s_acc[i % R], atomic_load_agent(&rows[i]));
     __syncthreads();
     if (threadIdx.x != 0) return;
     const uint64_t u = s_acc[0], f1 = s_acc[1], f2 = s_acc[2];
