@@ -33,6 +33,8 @@ WORKLOADS = {
     # the tiny branch beside the main path at the dispatcher sweep's length
     "sweep_tiny_k8": (30_000_000, 8, "uniform", 1.1, "random"),
     "sweep_main_k200": (30_000_000, 200, "uniform", 1.1, "random"),
+    # a heavy-tailed column of the sweep whose count geometry follows the larger sample
+    "sweep_main_zipf11_k130000": (30_000_000, 130_000, "zipf", 1.1, "random"),
 }
 # algorithmic bytes per key of each single-kernel stage
 STAGE_BYTES_PER_KEY = {"count": 8.0, "emit": 8.0}
