@@ -397,7 +397,8 @@ cafs_status_t sort_impl(cafs_ctx_t* ctx, const void* in, void* out, uint64_t n, 
         cafs::k_guard_prep<<<grid_for(L.m_ws, 256 * 8, cus * 4), 256, 0, s2>>>(a);
         cafs::k_guard_bucket<<<g, 256, 0, s2>>>(a);
         cafs::k_guard_mark<<<g, 256, 0, s2>>>(a);
-        cafs::k_guard_first<<<grid_for(n, cafs::kGuardChunk, cus), 256, 0, s2>>>(a);
+        // (two workgroups per CU: each one's chunk loop is a chain of dependent loads)
+        cafs::k_guard_first<<<grid_for(n, cafs::kGuardChunk, cus * 2), 256, 0, s2>>>(a);
         cafs::k_guard_resolve<<<1, 1024, 0, s2>>>(a);
         for (uint32_t r = 0; r < a.cap; ++r) cafs::k_guard_round<<<g, 256, 0, s2>>>(a, r);
         cafs::k_guard_final<<<g, 256, 0, s2>>>(a);
